@@ -1,0 +1,821 @@
+/*
+ * femoracle.c -- plain, slow, obviously correct FP64 reference for the
+ * Laplace / Jacobi-PCG solve path.  TEST INFRASTRUCTURE ONLY: it is loaded by
+ * the tests, by the smoke check and by the CPU-baseline leg of the benchmark,
+ * never by the library.  It shares no code, header or table with the HIP
+ * library.
+ *
+ * What it computes, step by step, with the passage each step follows:
+ *
+ *  1. DOF numbering.  P1: the mesh vertices.  P2: the vertices, then one DOF
+ *     per mesh edge, edges ordered by their (min, max) vertex pair.  The
+ *     paper's Table 7 (Sect. 4.2, "polynomial basis") varies the FEM degree;
+ *     a DOF on a boundary facet whose vertices are all flagged is a Dirichlet
+ *     DOF (Sect. 2.2: u = f on the boundary).
+ *  2. Element matrices K^e_ij = integral over T of grad(phi_i).grad(phi_j).
+ *     P1 is written in gradient form, |T| grad(l_i).grad(l_j), and separately
+ *     in the paper's cotangent form (Sect. 2.2: w(i,j) = (1/6) sum l_k cot a_k
+ *     for tetrahedra, (cot a + cot b)/2 for triangles), where K_ij = -w(i,j)
+ *     and K_ii = sum_j w(i,j).  The sign is flipped with respect to the
+ *     paper's A(i,j) so that K is positive semi-definite.  P2 is integrated
+ *     with a quadrature rule exact for the quadratic integrand.
+ *  3. Assembly: coordinate triplets, stable counting sort by column and then
+ *     by row, duplicates summed in element order.  The structural pattern
+ *     (every DOF pair sharing an element) is kept, zeros included.
+ *  4. Dirichlet lifting with zero source: A = K_II, b = -K_ID g_D.
+ *  5. Jacobi-preconditioned CG (Sect. 2.1, preconditioned system with
+ *     M = diag(A)), one column at a time, zero initial guess, stopping test
+ *     of Eq. (2) on the recursive residual, then the true residual
+ *     ||b - A x|| / ||b||; if that exceeds tol the solve restarts from x
+ *     (at most 3 times).  Iterations count the products A p.
+ *  6. Eq. (1) error and Eq. (2) residual helpers.
+ *
+ * Every function returns 0 on success and a negative code on failure.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_EINVAL -1
+#define ORC_ENOMEM -2
+#define ORC_EMESH -3
+#define ORC_EBREAK -4
+
+/* ------------------------------------------------------------------------- */
+/* small dense helpers                                                        */
+/* ------------------------------------------------------------------------- */
+
+/* Jacobian J[r][c] = x_{c+1}[r] - x_0[r]; returns det J and writes the
+ * gradients of the barycentric coordinates, G[i][r] = d l_i / d x_r. */
+static double bary_gradients(int dim, const double *X, double *G)
+{
+    double J[3][3], inv[3][3], det;
+    for (int r = 0; r < dim; r++)
+        for (int c = 0; c < dim; c++)
+            J[r][c] = X[(c + 1) * dim + r] - X[r];
+    if (dim == 2) {
+        det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        inv[0][0] = J[1][1] / det;
+        inv[0][1] = -J[0][1] / det;
+        inv[1][0] = -J[1][0] / det;
+        inv[1][1] = J[0][0] / det;
+    } else {
+        det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1])
+            - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0])
+            + J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+        inv[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+        inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+        inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+        inv[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+        inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+        inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+        inv[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+        inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+        inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+    }
+    /* lambda_{c+1}(x) = (J^{-1} (x - x_0))_c, so grad lambda_{c+1} = row c */
+    for (int r = 0; r < dim; r++) G[0 * dim + r] = 0.0;
+    for (int c = 0; c < dim; c++)
+        for (int r = 0; r < dim; r++) {
+            G[(c + 1) * dim + r] = inv[c][r];
+            G[0 * dim + r] -= inv[c][r];
+        }
+    return det;
+}
+
+static double simplex_measure(int dim, double det)
+{
+    return dim == 2 ? det / 2.0 : det / 6.0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* element matrices                                                           */
+/* ------------------------------------------------------------------------- */
+
+/* P1 gradient form: K_ij = |T| grad(l_i) . grad(l_j). */
+int orc_p1_element(int dim, const double *X, double *K)
+{
+    double G[12];
+    if (dim != 2 && dim != 3) return ORC_EINVAL;
+    double det = bary_gradients(dim, X, G);
+    if (!(det > 0.0)) return ORC_EMESH;
+    double vol = simplex_measure(dim, det);
+    int nl = dim + 1;
+    for (int i = 0; i < nl; i++)
+        for (int j = 0; j < nl; j++) {
+            double s = 0.0;
+            for (int r = 0; r < dim; r++) s += G[i * dim + r] * G[j * dim + r];
+            K[i * nl + j] = vol * s;
+        }
+    return 0;
+}
+
+static void sub3(const double *a, const double *b, double *o)
+{
+    o[0] = a[0] - b[0]; o[1] = a[1] - b[1]; o[2] = a[2] - b[2];
+}
+static double dot3(const double *a, const double *b)
+{
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+static void cross3(const double *a, const double *b, double *o)
+{
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* P1 cotangent form (the paper's Laplacian weights, Sect. 2.2).
+ * Triangle: w_ij = cot(angle at the third vertex) / 2.
+ * Tetrahedron: w_ij = l_kl cot(theta_kl) / 6, where (k,l) is the edge opposite
+ * to (i,j), l_kl its length and theta_kl the dihedral angle along it.
+ * K_ij = -w_ij (i != j), K_ii = sum_{j != i} w_ij. */
+int orc_p1_element_cot(int dim, const double *X, double *K)
+{
+    int nl = dim + 1;
+    if (dim != 2 && dim != 3) return ORC_EINVAL;
+    for (int i = 0; i < nl * nl; i++) K[i] = 0.0;
+    for (int i = 0; i < nl; i++)
+        for (int j = i + 1; j < nl; j++) {
+            double w;
+            if (dim == 2) {
+                int l = 3 - i - j;
+                double a[2] = {X[i * 2] - X[l * 2], X[i * 2 + 1] - X[l * 2 + 1]};
+                double b[2] = {X[j * 2] - X[l * 2], X[j * 2 + 1] - X[l * 2 + 1]};
+                double cr = a[0] * b[1] - a[1] * b[0];
+                double dt = a[0] * b[0] + a[1] * b[1];
+                if (cr == 0.0) return ORC_EMESH;
+                w = 0.5 * dt / fabs(cr);
+            } else {
+                int kl[2], c = 0;
+                for (int t = 0; t < 4; t++)
+                    if (t != i && t != j) kl[c++] = t;
+                const double *xk = X + 3 * kl[0], *xl = X + 3 * kl[1];
+                double e[3], a[3], b[3], u[3], v[3], uxv[3];
+                sub3(xl, xk, e);
+                sub3(X + 3 * i, xk, a);
+                sub3(X + 3 * j, xk, b);
+                double len = sqrt(dot3(e, e));
+                double eh[3] = {e[0] / len, e[1] / len, e[2] / len};
+                double ae = dot3(a, eh), be = dot3(b, eh);
+                for (int r = 0; r < 3; r++) {
+                    u[r] = a[r] - ae * eh[r];
+                    v[r] = b[r] - be * eh[r];
+                }
+                cross3(u, v, uxv);
+                double sn = sqrt(dot3(uxv, uxv));
+                if (sn == 0.0) return ORC_EMESH;
+                w = len * (dot3(u, v) / sn) / 6.0;
+            }
+            K[i * nl + j] = -w;
+            K[j * nl + i] = -w;
+            K[i * nl + i] += w;
+            K[j * nl + j] += w;
+        }
+    return 0;
+}
+
+/* local P2 numbering: vertices 0..d, then the edges (a,b), a<b, in
+ * lexicographic order */
+static int p2_local_edges(int dim, int E[6][2])
+{
+    int c = 0;
+    for (int a = 0; a <= dim; a++)
+        for (int b = a + 1; b <= dim; b++) {
+            E[c][0] = a;
+            E[c][1] = b;
+            c++;
+        }
+    return c;
+}
+
+/* Gradients of the P2 basis at barycentric point L:
+ * vertex i: phi = l_i (2 l_i - 1), grad = (4 l_i - 1) grad l_i;
+ * edge (a,b): phi = 4 l_a l_b, grad = 4 (l_a grad l_b + l_b grad l_a). */
+static void p2_grads(int dim, const double *G, const double *L, double *out)
+{
+    int E[6][2];
+    int ne = p2_local_edges(dim, E);
+    int nv = dim + 1;
+    for (int i = 0; i < nv; i++)
+        for (int r = 0; r < dim; r++)
+            out[i * dim + r] = (4.0 * L[i] - 1.0) * G[i * dim + r];
+    for (int e = 0; e < ne; e++) {
+        int a = E[e][0], b = E[e][1];
+        for (int r = 0; r < dim; r++)
+            out[(nv + e) * dim + r] = 4.0 * (L[a] * G[b * dim + r] + L[b] * G[a * dim + r]);
+    }
+}
+
+/* P2: K_ij = integral of grad(phi_i).grad(phi_j); the integrand is a
+ * quadratic polynomial, integrated exactly by
+ *   triangle: the three edge midpoints, weight |T|/3 each;
+ *   tetrahedron: the symmetric 4-point rule with barycentric coordinates
+ *   (a,b,b,b), a = (5 + 3 sqrt 5)/20, b = (5 - sqrt 5)/20, weight |T|/4. */
+int orc_p2_element(int dim, const double *X, double *K)
+{
+    double G[12], Q[10 * 3];
+    if (dim != 2 && dim != 3) return ORC_EINVAL;
+    double det = bary_gradients(dim, X, G);
+    if (!(det > 0.0)) return ORC_EMESH;
+    double vol = simplex_measure(dim, det);
+    int nl = dim == 2 ? 6 : 10;
+    int nq = dim == 2 ? 3 : 4;
+    double pts[4][4];
+    if (dim == 2) {
+        double m[3][3] = {{0.5, 0.5, 0.0}, {0.0, 0.5, 0.5}, {0.5, 0.0, 0.5}};
+        for (int q = 0; q < 3; q++)
+            for (int i = 0; i < 3; i++) pts[q][i] = m[q][i];
+    } else {
+        double a = (5.0 + 3.0 * sqrt(5.0)) / 20.0, b = (5.0 - sqrt(5.0)) / 20.0;
+        for (int q = 0; q < 4; q++)
+            for (int i = 0; i < 4; i++) pts[q][i] = (i == q) ? a : b;
+    }
+    for (int i = 0; i < nl * nl; i++) K[i] = 0.0;
+    for (int q = 0; q < nq; q++) {
+        p2_grads(dim, G, pts[q], Q);
+        double w = vol / nq;
+        for (int i = 0; i < nl; i++)
+            for (int j = 0; j < nl; j++) {
+                double s = 0.0;
+                for (int r = 0; r < dim; r++) s += Q[i * dim + r] * Q[j * dim + r];
+                K[i * nl + j] += w * s;
+            }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* the assembled system                                                       */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    int dim, order;
+    int64_t nverts, ncells, nedges, ndofs, nfree;
+    int nloc;
+    int32_t *cell_dofs;  /* [ncells][nloc] global DOF of each local DOF */
+    double *dof_coords;  /* [ndofs][dim] */
+    uint8_t *dirichlet;  /* [ndofs] */
+    int64_t *dof2free;   /* [ndofs], -1 on Dirichlet DOFs */
+    int64_t *free2dof;   /* [nfree] */
+    /* full stiffness K (structural pattern) */
+    int64_t nnz;
+    int64_t *rowptr;
+    int32_t *col;
+    double *val;
+    /* A = K_II in free numbering */
+    int64_t a_nnz;
+    int64_t *a_rowptr;
+    int32_t *a_col;
+    double *a_val;
+    double *a_diag;
+    int64_t n_bad_cells;
+} orc_system;
+
+static int cmp_i64(const void *a, const void *b)
+{
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+typedef struct { int32_t v[3]; } face3;
+static int cmp_face(const void *a, const void *b)
+{
+    const face3 *x = a, *y = b;
+    for (int i = 0; i < 3; i++) {
+        if (x->v[i] < y->v[i]) return -1;
+        if (x->v[i] > y->v[i]) return 1;
+    }
+    return 0;
+}
+
+static int64_t find_key(const int64_t *keys, int64_t n, int64_t key)
+{
+    int64_t lo = 0, hi = n - 1;
+    while (lo <= hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (keys[mid] == key) return mid;
+        if (keys[mid] < key) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    return -1;
+}
+
+void orc_free(orc_system *s)
+{
+    if (!s) return;
+    free(s->cell_dofs);
+    free(s->dof_coords);
+    free(s->dirichlet);
+    free(s->dof2free);
+    free(s->free2dof);
+    free(s->rowptr);
+    free(s->col);
+    free(s->val);
+    free(s->a_rowptr);
+    free(s->a_col);
+    free(s->a_val);
+    free(s->a_diag);
+    free(s);
+}
+
+static void sort3(int32_t *a)
+{
+    for (int i = 0; i < 3; i++)
+        for (int j = i + 1; j < 3; j++)
+            if (a[j] < a[i]) { int32_t t = a[i]; a[i] = a[j]; a[j] = t; }
+}
+
+/* Build DOFs, element matrices, K and the lifted A.  *err receives a code. */
+orc_system *orc_build(int dim, int64_t nverts, const double *coords, int64_t ncells,
+                      const int32_t *cells, const uint8_t *on_boundary, int order, int *err)
+{
+    *err = 0;
+    if ((dim != 2 && dim != 3) || (order != 1 && order != 2) || nverts <= 0 || ncells <= 0) {
+        *err = ORC_EINVAL;
+        return NULL;
+    }
+    orc_system *s = calloc(1, sizeof(orc_system));
+    if (!s) { *err = ORC_ENOMEM; return NULL; }
+    s->dim = dim;
+    s->order = order;
+    s->nverts = nverts;
+    s->ncells = ncells;
+    int nv = dim + 1;
+    int ne_loc = dim == 2 ? 3 : 6;
+    s->nloc = order == 1 ? nv : nv + ne_loc;
+    int nloc = s->nloc;
+
+    /* ---- DOFs ---- */
+    int64_t *ekeys = NULL, *uniq = NULL;
+    int64_t nek = 0, nuniq = 0;
+    if (order == 2) {
+        int E[6][2];
+        p2_local_edges(dim, E);
+        nek = ncells * ne_loc;
+        ekeys = malloc(sizeof(int64_t) * nek);
+        if (!ekeys) goto nomem;
+        for (int64_t c = 0; c < ncells; c++)
+            for (int e = 0; e < ne_loc; e++) {
+                int64_t a = cells[c * nv + E[e][0]], b = cells[c * nv + E[e][1]];
+                int64_t lo = a < b ? a : b, hi = a < b ? b : a;
+                ekeys[c * ne_loc + e] = lo * nverts + hi;
+            }
+        uniq = malloc(sizeof(int64_t) * nek);
+        if (!uniq) goto nomem;
+        memcpy(uniq, ekeys, sizeof(int64_t) * nek);
+        qsort(uniq, nek, sizeof(int64_t), cmp_i64);
+        for (int64_t i = 0; i < nek; i++)
+            if (i == 0 || uniq[i] != uniq[i - 1]) uniq[nuniq++] = uniq[i];
+        s->nedges = nuniq;
+    }
+    s->ndofs = nverts + s->nedges;
+    s->dof_coords = malloc(sizeof(double) * s->ndofs * dim);
+    s->dirichlet = calloc(s->ndofs, 1);
+    s->cell_dofs = malloc(sizeof(int32_t) * ncells * nloc);
+    if (!s->dof_coords || !s->dirichlet || !s->cell_dofs) goto nomem;
+    memcpy(s->dof_coords, coords, sizeof(double) * nverts * dim);
+    for (int64_t v = 0; v < nverts; v++) s->dirichlet[v] = on_boundary[v] ? 1 : 0;
+    for (int64_t e = 0; e < s->nedges; e++) {
+        int64_t a = uniq[e] / nverts, b = uniq[e] % nverts;
+        for (int r = 0; r < dim; r++)
+            s->dof_coords[(nverts + e) * dim + r] = 0.5 * (coords[a * dim + r] + coords[b * dim + r]);
+    }
+    for (int64_t c = 0; c < ncells; c++) {
+        for (int i = 0; i < nv; i++) s->cell_dofs[c * nloc + i] = cells[c * nv + i];
+        if (order == 2)
+            for (int e = 0; e < ne_loc; e++) {
+                int64_t idx = find_key(uniq, nuniq, ekeys[c * ne_loc + e]);
+                s->cell_dofs[c * nloc + nv + e] = (int32_t)(nverts + idx);
+            }
+    }
+    /* Dirichlet edges: edges of boundary facets (facets in exactly one cell)
+     * whose two vertices are flagged */
+    if (order == 2) {
+        if (dim == 2) {
+            /* facets are edges: count occurrences in the sorted key list */
+            int64_t *cnt = calloc(nuniq, sizeof(int64_t));
+            if (!cnt) goto nomem;
+            for (int64_t i = 0; i < nek; i++) cnt[find_key(uniq, nuniq, ekeys[i])]++;
+            for (int64_t e = 0; e < nuniq; e++) {
+                int64_t a = uniq[e] / nverts, b = uniq[e] % nverts;
+                if (cnt[e] == 1 && on_boundary[a] && on_boundary[b]) s->dirichlet[nverts + e] = 1;
+            }
+            free(cnt);
+        } else {
+            int64_t nf = ncells * 4;
+            face3 *f = malloc(sizeof(face3) * nf);
+            if (!f) goto nomem;
+            for (int64_t c = 0; c < ncells; c++)
+                for (int o = 0; o < 4; o++) {
+                    int q = 0;
+                    for (int t = 0; t < 4; t++)
+                        if (t != o) f[c * 4 + o].v[q++] = cells[c * 4 + t];
+                    sort3(f[c * 4 + o].v);
+                }
+            qsort(f, nf, sizeof(face3), cmp_face);
+            for (int64_t i = 0; i < nf;) {
+                int64_t j = i;
+                while (j < nf && cmp_face(&f[i], &f[j]) == 0) j++;
+                if (j - i == 1) {
+                    const int32_t *v = f[i].v;
+                    if (on_boundary[v[0]] && on_boundary[v[1]] && on_boundary[v[2]]) {
+                        int pr[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+                        for (int p = 0; p < 3; p++) {
+                            int64_t key = (int64_t)v[pr[p][0]] * nverts + v[pr[p][1]];
+                            int64_t idx = find_key(uniq, nuniq, key);
+                            s->dirichlet[nverts + idx] = 1;
+                        }
+                    }
+                }
+                i = j;
+            }
+            free(f);
+        }
+    }
+    free(ekeys);
+    ekeys = NULL;
+    free(uniq);
+    uniq = NULL;
+
+    /* ---- element matrices into coordinate triplets ---- */
+    {
+        int64_t ncoo = ncells * (int64_t)nloc * nloc;
+        int32_t *ri = malloc(sizeof(int32_t) * ncoo);
+        int32_t *ci = malloc(sizeof(int32_t) * ncoo);
+        double *vv = malloc(sizeof(double) * ncoo);
+        if (!ri || !ci || !vv) { free(ri); free(ci); free(vv); goto nomem; }
+        double Ke[100], X[4 * 3];
+        for (int64_t c = 0; c < ncells; c++) {
+            for (int i = 0; i < nv; i++)
+                for (int r = 0; r < dim; r++) X[i * dim + r] = coords[(int64_t)cells[c * nv + i] * dim + r];
+            int rc = order == 1 ? orc_p1_element(dim, X, Ke) : orc_p2_element(dim, X, Ke);
+            if (rc) { s->n_bad_cells++; continue; }
+            for (int i = 0; i < nloc; i++)
+                for (int j = 0; j < nloc; j++) {
+                    int64_t t = (c * nloc + i) * nloc + j;
+                    ri[t] = s->cell_dofs[c * nloc + i];
+                    ci[t] = s->cell_dofs[c * nloc + j];
+                    vv[t] = Ke[i * nloc + j];
+                }
+        }
+        if (s->n_bad_cells) {
+            free(ri); free(ci); free(vv);
+            *err = ORC_EMESH;
+            orc_free(s);
+            return NULL;
+        }
+        /* stable counting sort by column, then by row: triplets end up
+         * ordered by (row, col, element order) */
+        int64_t n = s->ndofs;
+        int64_t *cnt = calloc(n + 1, sizeof(int64_t));
+        int32_t *r2 = malloc(sizeof(int32_t) * ncoo);
+        int32_t *c2 = malloc(sizeof(int32_t) * ncoo);
+        double *v2 = malloc(sizeof(double) * ncoo);
+        if (!cnt || !r2 || !c2 || !v2) {
+            free(ri); free(ci); free(vv); free(cnt); free(r2); free(c2); free(v2);
+            goto nomem;
+        }
+        for (int64_t t = 0; t < ncoo; t++) cnt[ci[t] + 1]++;
+        for (int64_t i = 0; i < n; i++) cnt[i + 1] += cnt[i];
+        for (int64_t t = 0; t < ncoo; t++) {
+            int64_t d = cnt[ci[t]]++;
+            r2[d] = ri[t]; c2[d] = ci[t]; v2[d] = vv[t];
+        }
+        memset(cnt, 0, sizeof(int64_t) * (n + 1));
+        for (int64_t t = 0; t < ncoo; t++) cnt[r2[t] + 1]++;
+        for (int64_t i = 0; i < n; i++) cnt[i + 1] += cnt[i];
+        for (int64_t t = 0; t < ncoo; t++) {
+            int64_t d = cnt[r2[t]]++;
+            ri[d] = r2[t]; ci[d] = c2[t]; vv[d] = v2[t];
+        }
+        free(r2); free(c2); free(v2); free(cnt);
+        /* sum duplicates */
+        s->rowptr = calloc(n + 1, sizeof(int64_t));
+        int64_t nnz = 0;
+        for (int64_t t = 0; t < ncoo; t++)
+            if (t == 0 || ri[t] != ri[t - 1] || ci[t] != ci[t - 1]) nnz++;
+        s->col = malloc(sizeof(int32_t) * nnz);
+        s->val = malloc(sizeof(double) * nnz);
+        if (!s->rowptr || !s->col || !s->val) { free(ri); free(ci); free(vv); goto nomem; }
+        int64_t w = -1;
+        for (int64_t t = 0; t < ncoo; t++) {
+            if (t == 0 || ri[t] != ri[t - 1] || ci[t] != ci[t - 1]) {
+                w++;
+                s->col[w] = ci[t];
+                s->val[w] = vv[t];
+                s->rowptr[ri[t] + 1]++;
+            } else {
+                s->val[w] += vv[t];
+            }
+        }
+        for (int64_t i = 0; i < n; i++) s->rowptr[i + 1] += s->rowptr[i];
+        s->nnz = nnz;
+        free(ri); free(ci); free(vv);
+    }
+
+    /* ---- lifting: A = K_II ---- */
+    {
+        int64_t n = s->ndofs;
+        s->dof2free = malloc(sizeof(int64_t) * n);
+        if (!s->dof2free) goto nomem;
+        int64_t nf = 0;
+        for (int64_t d = 0; d < n; d++) s->dof2free[d] = s->dirichlet[d] ? -1 : nf++;
+        s->nfree = nf;
+        s->free2dof = malloc(sizeof(int64_t) * (nf ? nf : 1));
+        s->a_rowptr = calloc(nf + 1, sizeof(int64_t));
+        s->a_diag = calloc(nf ? nf : 1, sizeof(double));
+        if (!s->free2dof || !s->a_rowptr || !s->a_diag) goto nomem;
+        for (int64_t d = 0; d < n; d++)
+            if (s->dof2free[d] >= 0) s->free2dof[s->dof2free[d]] = d;
+        int64_t annz = 0;
+        for (int64_t f = 0; f < nf; f++) {
+            int64_t d = s->free2dof[f];
+            for (int64_t t = s->rowptr[d]; t < s->rowptr[d + 1]; t++)
+                if (s->dof2free[s->col[t]] >= 0) annz++;
+            s->a_rowptr[f + 1] = annz;
+        }
+        s->a_col = malloc(sizeof(int32_t) * (annz ? annz : 1));
+        s->a_val = malloc(sizeof(double) * (annz ? annz : 1));
+        if (!s->a_col || !s->a_val) goto nomem;
+        int64_t w = 0;
+        for (int64_t f = 0; f < nf; f++) {
+            int64_t d = s->free2dof[f];
+            for (int64_t t = s->rowptr[d]; t < s->rowptr[d + 1]; t++) {
+                int64_t cf = s->dof2free[s->col[t]];
+                if (cf >= 0) {
+                    s->a_col[w] = (int32_t)cf;
+                    s->a_val[w] = s->val[t];
+                    if (cf == f) s->a_diag[f] = s->val[t];
+                    w++;
+                }
+            }
+        }
+        s->a_nnz = annz;
+    }
+    return s;
+nomem:
+    free(ekeys);
+    free(uniq);
+    orc_free(s);
+    *err = ORC_ENOMEM;
+    return NULL;
+}
+
+/* sizes: ndofs, nedges, nfree, nnz(K), nnz(A), nloc */
+int orc_sizes(const orc_system *s, int64_t *out)
+{
+    out[0] = s->ndofs;
+    out[1] = s->nedges;
+    out[2] = s->nfree;
+    out[3] = s->nnz;
+    out[4] = s->a_nnz;
+    out[5] = s->nloc;
+    return 0;
+}
+
+int orc_copy_dofs(const orc_system *s, double *coords, uint8_t *dirichlet, int64_t *free2dof)
+{
+    if (coords) memcpy(coords, s->dof_coords, sizeof(double) * s->ndofs * s->dim);
+    if (dirichlet) memcpy(dirichlet, s->dirichlet, s->ndofs);
+    if (free2dof) memcpy(free2dof, s->free2dof, sizeof(int64_t) * s->nfree);
+    return 0;
+}
+
+int orc_copy_K(const orc_system *s, int64_t *rowptr, int32_t *col, double *val)
+{
+    memcpy(rowptr, s->rowptr, sizeof(int64_t) * (s->ndofs + 1));
+    memcpy(col, s->col, sizeof(int32_t) * s->nnz);
+    memcpy(val, s->val, sizeof(double) * s->nnz);
+    return 0;
+}
+
+int orc_copy_A(const orc_system *s, int64_t *rowptr, int32_t *col, double *val)
+{
+    memcpy(rowptr, s->a_rowptr, sizeof(int64_t) * (s->nfree + 1));
+    memcpy(col, s->a_col, sizeof(int32_t) * s->a_nnz);
+    memcpy(val, s->a_val, sizeof(double) * s->a_nnz);
+    return 0;
+}
+
+/* b = -K_ID g_D for k columns; g is [ndofs][k], B is [nfree][k]. */
+int orc_rhs(const orc_system *s, const double *g, int k, double *B)
+{
+    if (k <= 0) return ORC_EINVAL;
+    for (int64_t f = 0; f < s->nfree; f++) {
+        int64_t d = s->free2dof[f];
+        for (int j = 0; j < k; j++) {
+            double acc = 0.0;
+            for (int64_t t = s->rowptr[d]; t < s->rowptr[d + 1]; t++) {
+                int32_t c = s->col[t];
+                if (s->dirichlet[c]) acc += s->val[t] * g[(int64_t)c * k + j];
+            }
+            B[f * k + j] = -acc;
+        }
+    }
+    return 0;
+}
+
+/* y = A x for k interleaved columns ([nfree][k]) */
+int orc_spmv(const orc_system *s, const double *x, int k, double *y)
+{
+    for (int64_t i = 0; i < s->nfree; i++)
+        for (int j = 0; j < k; j++) {
+            double acc = 0.0;
+            for (int64_t t = s->a_rowptr[i]; t < s->a_rowptr[i + 1]; t++)
+                acc += s->a_val[t] * x[(int64_t)s->a_col[t] * k + j];
+            y[i * k + j] = acc;
+        }
+    return 0;
+}
+
+/* ---- single-column kernels of the PCG ---- */
+
+typedef struct {
+    int64_t n;
+    const int64_t *rowptr;
+    const int32_t *col;
+    const double *val;
+    const double *diag;
+} csr_view;
+
+static csr_view view_A(const orc_system *s)
+{
+    csr_view v = {s->nfree, s->a_rowptr, s->a_col, s->a_val, s->a_diag};
+    return v;
+}
+
+static void spmv1(const csr_view *A, const double *x, double *y)
+{
+    for (int64_t i = 0; i < A->n; i++) {
+        double acc = 0.0;
+        for (int64_t t = A->rowptr[i]; t < A->rowptr[i + 1]; t++)
+            acc += A->val[t] * x[A->col[t]];
+        y[i] = acc;
+    }
+}
+
+static double dot1(int64_t n, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; i++) s += a[i] * b[i];
+    return s;
+}
+
+/* Eq. (2) for k interleaved columns: relres[j] = ||b_j - A x_j|| / ||b_j||
+ * (0 when b_j = 0 and x_j = 0). */
+int orc_relres(const orc_system *s, const double *B, const double *X, int k, double *relres)
+{
+    int64_t n = s->nfree;
+    double *x = malloc(sizeof(double) * (n ? n : 1));
+    double *ax = malloc(sizeof(double) * (n ? n : 1));
+    if (!x || !ax) { free(x); free(ax); return ORC_ENOMEM; }
+    csr_view A = view_A(s);
+    for (int j = 0; j < k; j++) {
+        for (int64_t i = 0; i < n; i++) x[i] = X[i * k + j];
+        spmv1(&A, x, ax);
+        double rr = 0.0, bb = 0.0;
+        for (int64_t i = 0; i < n; i++) {
+            double b = B[i * k + j], r = b - ax[i];
+            rr += r * r;
+            bb += b * b;
+        }
+        relres[j] = bb > 0.0 ? sqrt(rr / bb) : sqrt(rr);
+    }
+    free(x);
+    free(ax);
+    return 0;
+}
+
+/* Jacobi-PCG, one column at a time (Sect. 2.1 with M = diag(A); exit test
+ * Eq. (2)).  B, X are [nfree][k]; X is overwritten (zero initial guess).
+ * iters[j] = number of products A p; relres[j] = true residual of Eq. (2);
+ * restarts[j] = restarts after a drifted recursive residual.
+ * Returns 0, or 1 if some column hit max_iter, or ORC_EBREAK on p.Ap <= 0. */
+static int pcg_csr(const csr_view *A, const double *B, int k, double tol, int64_t max_iter,
+                   double *X, int64_t *iters, double *relres, int32_t *restarts)
+{
+    int64_t n = A->n;
+    int status = 0;
+    size_t bytes = sizeof(double) * (n ? n : 1);
+    double *b = malloc(bytes), *x = malloc(bytes), *r = malloc(bytes), *z = malloc(bytes);
+    double *p = malloc(bytes), *q = malloc(bytes);
+    if (!b || !x || !r || !z || !p || !q) {
+        free(b); free(x); free(r); free(z); free(p); free(q);
+        return ORC_ENOMEM;
+    }
+    for (int j = 0; j < k; j++) {
+        for (int64_t i = 0; i < n; i++) b[i] = B[i * k + j];
+        double bnorm = sqrt(dot1(n, b, b));
+        int64_t its = 0;
+        int rs = 0;
+        for (int64_t i = 0; i < n; i++) x[i] = 0.0;
+        if (bnorm == 0.0) {
+            iters[j] = 0;
+            relres[j] = 0.0;
+            if (restarts) restarts[j] = 0;
+            for (int64_t i = 0; i < n; i++) X[i * k + j] = 0.0;
+            continue;
+        }
+        double rel = 0.0;
+        for (;;) {
+            /* (re)start from x: r = b - A x, z = D^-1 r, p = z */
+            spmv1(A, x, q);
+            for (int64_t i = 0; i < n; i++) r[i] = b[i] - q[i];
+            for (int64_t i = 0; i < n; i++) z[i] = r[i] / A->diag[i];
+            for (int64_t i = 0; i < n; i++) p[i] = z[i];
+            double rho = dot1(n, r, z);
+            double rnorm = sqrt(dot1(n, r, r));
+            while (rnorm > tol * bnorm && its < max_iter) {
+                spmv1(A, p, q);
+                double pq = dot1(n, p, q);
+                if (!(pq > 0.0) || !isfinite(pq)) {
+                    status = ORC_EBREAK;
+                    break;
+                }
+                double alpha = rho / pq;
+                for (int64_t i = 0; i < n; i++) x[i] += alpha * p[i];
+                for (int64_t i = 0; i < n; i++) r[i] -= alpha * q[i];
+                its++;
+                rnorm = sqrt(dot1(n, r, r));
+                if (rnorm <= tol * bnorm) break;
+                for (int64_t i = 0; i < n; i++) z[i] = r[i] / A->diag[i];
+                double rho_new = dot1(n, r, z);
+                double beta = rho_new / rho;
+                rho = rho_new;
+                for (int64_t i = 0; i < n; i++) p[i] = z[i] + beta * p[i];
+            }
+            /* true residual */
+            spmv1(A, x, q);
+            double rr = 0.0;
+            for (int64_t i = 0; i < n; i++) {
+                double t = b[i] - q[i];
+                rr += t * t;
+            }
+            rel = sqrt(rr) / bnorm;
+            if (status == ORC_EBREAK || rel <= tol || its >= max_iter || rs >= 3) break;
+            rs++;
+        }
+        if (its >= max_iter && rel > tol && status == 0) status = 1;
+        iters[j] = its;
+        relres[j] = rel;
+        if (restarts) restarts[j] = rs;
+        for (int64_t i = 0; i < n; i++) X[i * k + j] = x[i];
+        if (status == ORC_EBREAK) break;
+    }
+    free(b); free(x); free(r); free(z); free(p); free(q);
+    return status;
+}
+
+int orc_pcg(const orc_system *s, const double *B, int k, double tol, int64_t max_iter,
+            double *X, int64_t *iters, double *relres, int32_t *restarts)
+{
+    csr_view A = view_A(s);
+    return pcg_csr(&A, B, k, tol, max_iter, X, iters, relres, restarts);
+}
+
+/* The same PCG on a caller-given CSR matrix (used by tests that plant a
+ * defect, e.g. an indefinite matrix, into an oracle-built system). */
+int orc_pcg_csr(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                const double *B, int k, double tol, int64_t max_iter, double *X, int64_t *iters,
+                double *relres, int32_t *restarts)
+{
+    double *diag = malloc(sizeof(double) * (n ? n : 1));
+    if (!diag) return ORC_ENOMEM;
+    for (int64_t i = 0; i < n; i++) {
+        diag[i] = 0.0;
+        for (int64_t t = rowptr[i]; t < rowptr[i + 1]; t++)
+            if (col[t] == i) diag[i] = val[t];
+    }
+    csr_view A = {n, rowptr, col, val, diag};
+    int rc = pcg_csr(&A, B, k, tol, max_iter, X, iters, relres, restarts);
+    free(diag);
+    return rc;
+}
+
+/* Count of the nonzeros of the paper's regular-grid matrix read as a
+ * 7-point finite-difference stencil (w(i,j) = 1, Sect. 2.2) on an m^3 grid
+ * with one identity row per Dirichlet node (Table 1 row counts = m^3). */
+int64_t orc_fd7_identity_nnz(int64_t m)
+{
+    int64_t nnz = 0;
+    for (int64_t l = 0; l < m; l++)
+        for (int64_t j = 0; j < m; j++)
+            for (int64_t i = 0; i < m; i++) {
+                int bnd = i == 0 || j == 0 || l == 0 || i == m - 1 || j == m - 1 || l == m - 1;
+                if (bnd) {
+                    nnz += 1;
+                } else {
+                    int nb = 0;
+                    int64_t d[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+                    for (int t = 0; t < 6; t++) {
+                        int64_t a = i + d[t][0], b = j + d[t][1], c = l + d[t][2];
+                        if (a >= 0 && a < m && b >= 0 && b < m && c >= 0 && c < m) nb++;
+                    }
+                    nnz += 1 + nb;
+                }
+            }
+    return nnz;
+}
