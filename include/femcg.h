@@ -1,0 +1,241 @@
+/*
+ * femcg.h -- C ABI of the MI355X (gfx950) Jacobi-PCG library for the
+ * P1/P2 finite-element Laplace systems of "Evaluating Accuracy and
+ * Efficiency of HPC Solvers for Sparse Linear Systems with Applications to
+ * PDEs" (Galizia, Cammarasana, Clematis, Patane).
+ *
+ * Problem (Sect. 2.2): the Laplace equation with Dirichlet data u = f on the
+ * boundary of a 2D/3D domain, discretised on a regular or irregular simplicial
+ * mesh, gives a sparse system A u = b whose right-hand side encodes the
+ * boundary condition.  Several right-hand sides known a priori form the block
+ * system A X = B of Eq. (3) (Sect. 4.3).  Iterations stop when Eq. (2),
+ * ||A x - b||_2 / ||b||_2 <= eps, holds; Eq. (1) is the error metric.
+ *
+ * Conventions shared by every call:
+ *  - Plain C types only; no exception crosses the ABI.
+ *  - Return value: 0 = ok, > 0 = warning, < 0 = error (FEMCG_E*).  The text of
+ *    the last error of the calling thread is fem_last_error().
+ *  - "host" pointers are CPU memory owned by the caller; "device" pointers are
+ *    HIP device memory (e.g. from a torch CUDA tensor) owned by the caller.
+ *    The library never frees caller memory.
+ *  - Dense blocks B and X are row-major [n][k] with the k right-hand sides of
+ *    a row contiguous ("interleaved"), in the public DOF order below.
+ *  - Public DOF order: mesh vertices in mesh order, then (order 2) one DOF per
+ *    mesh edge in lexicographic order of its (min, max) vertex pair.  Solver
+ *    vectors hold the free (non-Dirichlet) DOFs in increasing DOF index.
+ *    Internal row permutations of the sparse formats are never visible.
+ *  - "stream" is a hipStream_t (NULL = the null stream).  Device work is
+ *    enqueued on it; calls that must inspect device state synchronise it.
+ */
+#ifndef FEMCG_H
+#define FEMCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FEMCG_OK 0
+#define FEMCG_WARN_MAXITER 1     /* some column hit max_iter; stats hold its residual */
+#define FEMCG_EINVAL (-1)        /* invalid argument */
+#define FEMCG_EMESH (-2)         /* invalid mesh: non-positive element measure, bad index */
+#define FEMCG_ENOMEM (-3)        /* host or device allocation failed */
+#define FEMCG_EBREAKDOWN (-4)    /* p.Ap <= 0 or a non-finite scalar in some column */
+#define FEMCG_EUNSUPPORTED (-5)  /* unsupported order, dimension, k or format */
+#define FEMCG_EDEVICE (-6)       /* a HIP runtime call failed */
+#define FEMCG_EADMIT (-7)        /* serving: request does not fit the memory budget */
+
+#define FEMCG_MAX_K 64           /* right-hand sides per solve */
+
+/* Sparse formats of the solver copy of A. */
+#define FEM_FORMAT_CSR 0
+#define FEM_FORMAT_SELL 1        /* SELL-C-sigma, rows sorted by length in windows of sigma */
+#define FEM_FORMAT_AUTO 2        /* chosen by the autotuner (fem_tune) */
+
+/* Arithmetic of the Krylov iteration. */
+#define PCG_FP64 0               /* FP64 values, vectors and dots */
+#define PCG_MIXED 1              /* FP32 inner PCG (FP64 dots) inside FP64 iterative refinement */
+
+/* A simplicial mesh (Sect. 2.2 input domain).  All arrays are host memory,
+ * read during fem_assemble only. */
+typedef struct {
+    int32_t dim;                  /* 2 (triangles) or 3 (tetrahedra) */
+    int64_t nverts;
+    const double *coords;         /* [nverts][dim] */
+    int64_t ncells;
+    const int32_t *cells;         /* [ncells][dim+1], positively oriented */
+    const uint8_t *on_boundary;   /* [nverts], 1 = Dirichlet vertex */
+} fem_mesh;
+
+/* Opaque assembled system; owns its host and device buffers. */
+typedef struct fem_matrix fem_matrix;
+
+typedef struct {
+    double tol;            /* Eq. (2) threshold eps (per column) */
+    int64_t max_iter;      /* cap on products A p per column; 0 = 20 sqrt(n) log2(n) + 100 */
+    int32_t precision;     /* PCG_FP64 or PCG_MIXED */
+    double inner_eta;      /* PCG_MIXED: relative residual reduction of each inner solve */
+    int32_t check_every;   /* iterations per device graph replay between host polls */
+    int32_t use_x0;        /* 1: X holds the initial guess; 0: start from zero */
+    int32_t max_restarts;  /* restarts after the true residual misses tol (drift) */
+    int32_t max_outer;     /* PCG_MIXED: cap on refinement steps */
+    int32_t use_graph;     /* 1: replay the iterations as a HIP graph */
+} pcg_opts;
+
+typedef struct {
+    int64_t n;             /* free DOFs (rows of A) */
+    int64_t nnz;           /* structural nonzeros of A */
+    int64_t nnz_nonzero;   /* entries kept by the solver copy (numerically nonzero) */
+    int64_t nnz_stored;    /* entries stored, padding included */
+    int32_t k;             /* right-hand sides of the last solve */
+    int32_t status;        /* return code of the last solve */
+    int32_t precision;
+    int32_t format;
+    int32_t outer;         /* refinement steps (PCG_MIXED) or restarts + 1 (PCG_FP64) */
+    int32_t graph_replays;
+    int64_t iters[FEMCG_MAX_K];     /* products A p per column (inner ones for PCG_MIXED) */
+    double relres[FEMCG_MAX_K];     /* true FP64 residual of Eq. (2) per column */
+    double setup_s;        /* fem_assemble wall time */
+    double solve_s;        /* pcg_solve wall time, entry to converged result */
+    double bytes;          /* algorithmic HBM bytes of the iterations */
+    double gbps;           /* bytes / solve_s / 1e9 */
+    double gflops;         /* algorithmic flops / solve_s / 1e9 */
+    double footprint_mb;   /* device memory held by the matrix and its workspaces */
+} pcg_stats_t;
+
+/* Fill opts with defaults: tol 1e-8, precision FP64, inner_eta 1e-4,
+ * check_every 32, use_x0 0, max_restarts 3, max_outer 30, use_graph 1. */
+void pcg_default_opts(pcg_opts *opts);
+
+/* Assemble the stiffness matrix K_ij = integral grad(phi_i).grad(phi_j) of
+ * the P1 (order 1) or P2 (order 2) Lagrange basis on the mesh -- the sign-
+ * flipped, symmetric counterpart of the paper's Laplacian matrix (Sect. 2.2:
+ * cotangent weights w(i,j), diagonal -sum w) -- and eliminate the Dirichlet
+ * DOFs (zero source): A = K_II, b = -K_ID g_D.  Builds the solver copy
+ * (entries with |a| <= 4 eps64 max_row|a| dropped, FP64 and FP32 values,
+ * inverse diagonal) in `format` and uploads it to the current device.
+ * Mesh arrays are copied; *out is owned by the caller until fem_free.
+ * Errors: FEMCG_EINVAL, FEMCG_EMESH (non-positive element), FEMCG_ENOMEM,
+ * FEMCG_EUNSUPPORTED, FEMCG_EDEVICE. */
+int fem_assemble(const fem_mesh *mesh, int32_t order, int32_t format, fem_matrix **out);
+
+/* Sizes and DOF data.  Any output pointer may be NULL.
+ * dof_coords: host [n_all][dim]; dirichlet: host [n_all]; free2dof: host
+ * [n_free] (the DOF index of each solver row). */
+int fem_dofs(const fem_matrix *A, int64_t *n_all, int64_t *n_free, double *dof_coords,
+             uint8_t *dirichlet, int64_t *free2dof);
+
+/* Host copy of the assembled A = K_II (structural pattern, unpruned, FP64)
+ * in CSR with columns ascending: rowptr [n_free+1], col [nnz], val [nnz].
+ * Pass NULL arrays to query nnz only. */
+int fem_csr(const fem_matrix *A, int64_t *nnz, int64_t *rowptr, int32_t *col, double *val);
+
+/* B = -K_ID g_D (Sect. 2.2: b encodes the boundary condition).
+ * g_all: host [n_all][k], Dirichlet data at every DOF (only Dirichlet DOFs
+ * are read).  B: device [n_free][k], FP64.  Enqueued on stream. */
+int fem_rhs(const fem_matrix *A, const double *g_all, int32_t k, double *B, void *stream);
+
+/* Y = A X for k interleaved columns (Sect. 3.2's MatMult, here as SpMM).
+ * X, Y: device [n_free][k] FP64, public order.  Enqueued on stream. */
+int fem_spmv(fem_matrix *A, const double *X, double *Y, int32_t k, void *stream);
+
+/* Solve A X = B column by column with Jacobi-preconditioned CG (Sect. 2.1's
+ * preconditioned system with M = diag(A)), stopping each column when Eq. (2)
+ * holds for its recursive residual and then confirming it with the true FP64
+ * residual (restart from X when it drifted).  B, X: device [n_free][k] FP64
+ * (X: initial guess when opts->use_x0, else overwritten).  opts NULL =
+ * defaults with opts.tol = tol.  Blocks the host until the solve has
+ * converged or stopped; X is ready when stream reaches the end of the call.
+ * Returns 0, FEMCG_WARN_MAXITER, or an error (FEMCG_EBREAKDOWN, ...). */
+int pcg_solve(fem_matrix *A, const double *B, double *X, int32_t k, double tol,
+              const pcg_opts *opts, void *stream);
+
+/* Many independent systems in one batch: every CG phase of every system runs
+ * in one persistent kernel launch (systems are independent; results do not
+ * depend on which other systems share the batch).  Arrays of length nsys;
+ * all systems use opts->precision.  Status per system in status[]. */
+int pcg_solve_batch(int32_t nsys, fem_matrix *const *A, const double *const *B, double *const *X,
+                    const int32_t *k, const double *tol, const pcg_opts *opts, int32_t *status,
+                    void *stream);
+
+/* Statistics of the last solve on this matrix. */
+int pcg_stats(const fem_matrix *A, pcg_stats_t *out);
+
+/* Autotune the solver copy for k right-hand sides: times SpMM over candidate
+ * formats (CSR; SELL with C in {16,32,64}, sigma in {1, 64, 1024}) on the
+ * device and keeps the fastest.  Returns the chosen format; C_out and sigma_out
+ * may be NULL. */
+int fem_tune(fem_matrix *A, int32_t k, int32_t precision, int32_t *C_out, int32_t *sigma_out,
+             void *stream);
+
+/* Rebuild the solver copy in an explicit format (SELL: slice height C in
+ * {8,16,32,64}, sorting window sigma >= 1). */
+int fem_set_format(fem_matrix *A, int32_t format, int32_t C, int32_t sigma);
+
+/* Time one hot kernel of the iteration on the workspace of the last solve
+ * (same launch configuration as inside the solve), `reps` launches bracketed
+ * by HIP events on `stream`.  kernel: 0 = SpMM + p.q, 1 = fused update,
+ * 2 = p-update.  Writes the mean duration in ms and the algorithmic bytes of
+ * one launch. */
+int pcg_time_kernel(fem_matrix *A, int32_t kernel, int32_t reps, void *stream, double *ms,
+                    double *bytes);
+
+void fem_free(fem_matrix *A);
+
+/* Thread-local text of the last error ("" if none). */
+const char *fem_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of solve requests (Sect. 4.3's multiple
+ * independent systems, arriving over time).  A server owns a device memory
+ * budget; requests are admitted while their footprint fits, run as slots of
+ * the persistent batched kernels, and retire when converged, freeing their
+ * memory for waiting requests.
+ * ------------------------------------------------------------------------- */
+typedef struct fem_server fem_server;
+
+typedef struct {
+    int64_t id;
+    int32_t status;         /* solve status */
+    int32_t k;
+    int64_t n;
+    int64_t iters_max;      /* max over columns */
+    double t_submit;        /* seconds on the server clock */
+    double t_ready;         /* host assembly finished */
+    double t_admit;         /* admitted to the device */
+    double t_done;
+    double relres_max;
+} fem_request_info;
+
+/* budget_bytes: device memory the server may hold for admitted requests.
+ * max_slots: systems resident at once.  precision: PCG_FP64 or PCG_MIXED. */
+int serve_create(double budget_bytes, int32_t max_slots, int32_t precision, int32_t check_every,
+                 fem_server **out);
+
+/* Submit a request: the server assembles it (host), queues it and admits it
+ * when memory frees up.  g_all: host [n_all][k].  Returns the request id
+ * (>= 0) or an error.  The server takes ownership of nothing the caller
+ * passes (arrays are copied). */
+int64_t serve_submit(fem_server *s, const fem_mesh *mesh, int32_t order, const double *g_all,
+                     int32_t k, double tol);
+
+/* Advance the server by one tick: admit what fits, run check_every
+ * iterations of every resident system as one batched graph replay, retire
+ * converged systems.  Returns the number of requests still queued or running. */
+int serve_step(fem_server *s);
+
+/* 1 if request id is done; then X (host [n_free][k], may be NULL) and info
+ * are filled and the request's memory is released. */
+int serve_poll(fem_server *s, int64_t id, double *X, fem_request_info *info);
+
+/* Server clock (seconds since serve_create). */
+double serve_clock(const fem_server *s);
+
+void serve_destroy(fem_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FEMCG_H */

@@ -1,0 +1,508 @@
+// assemble.cpp -- host-side FEM assembly of the library (mesh -> A = K_II,
+// lifting operator K_ID, solver copy).
+//
+// The stiffness matrix is K_ij = integral grad(phi_i).grad(phi_j) for the P1
+// or P2 Lagrange basis: the sign-flipped, symmetric counterpart of the
+// paper's Laplacian matrix (Sect. 2.2: off-diagonal cotangent weights w(i,j),
+// diagonal -sum_j w(i,j)).  Element matrices use the closed-form simplex
+// moments  integral l^a = |T| d! a! / (d + |a|)!  of the barycentric
+// coordinates l, so no quadrature is involved:
+//   integral l_a       = |T| / (d+1)
+//   integral l_a l_b   = |T| (1 + [a=b]) / ((d+1)(d+2))
+// With g_a = grad l_a, the P2 basis is l_a(2 l_a - 1) at vertices and
+// 4 l_a l_b at edges, whose gradients are (4 l_a - 1) g_a and
+// 4 (l_a g_b + l_b g_a); products of these integrate with the moments above.
+//
+// Dirichlet lifting with zero source (Sect. 2.2, u = f on the boundary;
+// b encodes the boundary condition): A = K_II, b = -K_ID g_D.
+#include <algorithm>
+#include <array>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <thread>
+
+#include "assemble.h"
+
+namespace femcg {
+
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &fn)
+{
+    unsigned hw = std::thread::hardware_concurrency();
+    int nt = (int)std::min<unsigned>(hw ? hw : 1, 16);
+    if (n < 4096 || nt <= 1) {
+        fn(0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    const int64_t chunk = (n + nt - 1) / nt;
+    for (int t = 0; t < nt; ++t) {
+        const int64_t b = t * chunk, e = std::min(n, b + chunk);
+        if (b >= e) break;
+        th.emplace_back([&fn, b, e] { fn(b, e); });
+    }
+    for (auto &x : th) x.join();
+}
+
+// barycentric gradients g[a][r] and the measure |T| of one simplex
+static bool simplex_grads(int dim, const double *P, double g[4][3], double *meas)
+{
+    if (dim == 2) {
+        const double x1 = P[2] - P[0], y1 = P[3] - P[1];
+        const double x2 = P[4] - P[0], y2 = P[5] - P[1];
+        const double det = x1 * y2 - x2 * y1;
+        if (!(det > 0.0)) return false;
+        // inverse of [[x1 x2][y1 y2]]: rows are grad l_1, grad l_2
+        g[1][0] = y2 / det;
+        g[1][1] = -x2 / det;
+        g[2][0] = -y1 / det;
+        g[2][1] = x1 / det;
+        g[0][0] = -g[1][0] - g[2][0];
+        g[0][1] = -g[1][1] - g[2][1];
+        *meas = 0.5 * det;
+        return true;
+    }
+    double e[3][3];
+    for (int c = 0; c < 3; ++c)
+        for (int r = 0; r < 3; ++r) e[c][r] = P[(c + 1) * 3 + r] - P[r];
+    // grad l_{c+1} = (e_{c+1} x e_{c+2}) / det  (cyclic), det = e1 . (e2 x e3)
+    double cr[3][3];
+    for (int c = 0; c < 3; ++c) {
+        const double *u = e[(c + 1) % 3], *v = e[(c + 2) % 3];
+        cr[c][0] = u[1] * v[2] - u[2] * v[1];
+        cr[c][1] = u[2] * v[0] - u[0] * v[2];
+        cr[c][2] = u[0] * v[1] - u[1] * v[0];
+    }
+    const double det = e[0][0] * cr[0][0] + e[0][1] * cr[0][1] + e[0][2] * cr[0][2];
+    if (!(det > 0.0)) return false;
+    for (int c = 0; c < 3; ++c)
+        for (int r = 0; r < 3; ++r) g[c + 1][r] = cr[c][r] / det;
+    for (int r = 0; r < 3; ++r) g[0][r] = -(g[1][r] + g[2][r] + g[3][r]);
+    *meas = det / 6.0;
+    return true;
+}
+
+static int local_edges(int dim, int E[6][2])
+{
+    int c = 0;
+    for (int a = 0; a <= dim; ++a)
+        for (int b = a + 1; b <= dim; ++b) {
+            E[c][0] = a;
+            E[c][1] = b;
+            ++c;
+        }
+    return c;
+}
+
+bool element_matrix(int dim, int order, const double *P, double *K)
+{
+    double g[4][3] = {}, T;
+    if (!simplex_grads(dim, P, g, &T)) return false;
+    const int nv = dim + 1;
+    double G[4][4];
+    for (int a = 0; a < nv; ++a)
+        for (int b = 0; b < nv; ++b) {
+            double s = 0.0;
+            for (int r = 0; r < dim; ++r) s += g[a][r] * g[b][r];
+            G[a][b] = s;
+        }
+    if (order == 1) {
+        for (int a = 0; a < nv; ++a)
+            for (int b = 0; b < nv; ++b) K[a * nv + b] = T * G[a][b];
+        return true;
+    }
+    const double m1 = T / (dim + 1);                           // integral l_a
+    const double m2o = T / ((dim + 1.0) * (dim + 2.0));        // integral l_a l_b, a != b
+    auto m2 = [&](int a, int b) { return a == b ? 2.0 * m2o : m2o; };
+    int E[6][2];
+    const int ne = local_edges(dim, E);
+    const int nl = nv + ne;
+    // vertex-vertex: (g_a.g_b) integral (4 l_a - 1)(4 l_b - 1)
+    for (int a = 0; a < nv; ++a)
+        for (int b = 0; b < nv; ++b)
+            K[a * nl + b] = G[a][b] * (16.0 * m2(a, b) - 8.0 * m1 + T);
+    // vertex-edge: integral (4 l_v - 1) g_v . 4 (l_a g_b + l_b g_a)
+    for (int v = 0; v < nv; ++v)
+        for (int e = 0; e < ne; ++e) {
+            const int a = E[e][0], b = E[e][1];
+            const double val = 4.0 * (G[v][b] * (4.0 * m2(v, a) - m1) + G[v][a] * (4.0 * m2(v, b) - m1));
+            K[v * nl + nv + e] = val;
+            K[(nv + e) * nl + v] = val;
+        }
+    // edge-edge: 16 integral (l_a g_b + l_b g_a).(l_c g_d + l_d g_c)
+    for (int e = 0; e < ne; ++e)
+        for (int f = 0; f < ne; ++f) {
+            const int a = E[e][0], b = E[e][1], c = E[f][0], d = E[f][1];
+            K[(nv + e) * nl + nv + f] =
+                16.0 * (m2(a, c) * G[b][d] + m2(a, d) * G[b][c] + m2(b, c) * G[a][d] + m2(b, d) * G[a][c]);
+        }
+    return true;
+}
+
+struct Face {
+    int32_t v[3];
+    bool operator<(const Face &o) const
+    {
+        return v[0] != o.v[0] ? v[0] < o.v[0] : (v[1] != o.v[1] ? v[1] < o.v[1] : v[2] < o.v[2]);
+    }
+    bool operator==(const Face &o) const { return v[0] == o.v[0] && v[1] == o.v[1] && v[2] == o.v[2]; }
+};
+
+int assemble_host(const fem_mesh *mesh, int order, HostSystem &hs, std::string &err)
+{
+    const int dim = mesh->dim;
+    if ((dim != 2 && dim != 3) || (order != 1 && order != 2)) {
+        err = "unsupported dimension or order";
+        return FEMCG_EUNSUPPORTED;
+    }
+    if (mesh->nverts <= 0 || mesh->ncells <= 0 || !mesh->coords || !mesh->cells || !mesh->on_boundary) {
+        err = "empty mesh or NULL array";
+        return FEMCG_EINVAL;
+    }
+    if (mesh->nverts >= (int64_t)1 << 30) {
+        err = "too many vertices for int32 indices";
+        return FEMCG_EUNSUPPORTED;
+    }
+    const int64_t nv = mesh->nverts, nc = mesh->ncells;
+    const int nvl = dim + 1;
+    for (int64_t i = 0; i < nc * nvl; ++i)
+        if (mesh->cells[i] < 0 || mesh->cells[i] >= nv) {
+            err = "cell vertex index out of range";
+            return FEMCG_EMESH;
+        }
+    hs.dim = dim;
+    hs.order = order;
+    hs.nverts = nv;
+    hs.ncells = nc;
+    int E[6][2];
+    const int nel = local_edges(dim, E);
+    const int nl = order == 1 ? nvl : nvl + nel;
+    hs.nloc = nl;
+
+    // ---- DOFs: vertices, then edges in (min, max) order ----
+    std::vector<uint64_t> ekey;
+    std::vector<uint64_t> edges;
+    if (order == 2) {
+        ekey.resize(nc * nel);
+        for (int64_t c = 0; c < nc; ++c)
+            for (int e = 0; e < nel; ++e) {
+                uint64_t a = (uint64_t)mesh->cells[c * nvl + E[e][0]];
+                uint64_t b = (uint64_t)mesh->cells[c * nvl + E[e][1]];
+                if (a > b) std::swap(a, b);
+                ekey[c * nel + e] = (a << 32) | b;
+            }
+        edges = ekey;
+        std::sort(edges.begin(), edges.end());
+        edges.erase(std::unique(edges.begin(), edges.end()), edges.end());
+    }
+    hs.nedges = (int64_t)edges.size();
+    hs.ndofs = nv + hs.nedges;
+    if (hs.ndofs >= (int64_t)1 << 31) {
+        err = "too many DOFs for int32 indices";
+        return FEMCG_EUNSUPPORTED;
+    }
+    hs.dof_coords.resize(hs.ndofs * dim);
+    std::memcpy(hs.dof_coords.data(), mesh->coords, sizeof(double) * nv * dim);
+    for (int64_t e = 0; e < hs.nedges; ++e) {
+        const int64_t a = (int64_t)(edges[e] >> 32), b = (int64_t)(edges[e] & 0xffffffffu);
+        for (int r = 0; r < dim; ++r)
+            hs.dof_coords[(nv + e) * dim + r] = 0.5 * (mesh->coords[a * dim + r] + mesh->coords[b * dim + r]);
+    }
+    hs.cell_dofs.resize(nc * nl);
+    parallel_for(nc, [&](int64_t c0, int64_t c1) {
+        for (int64_t c = c0; c < c1; ++c) {
+            for (int i = 0; i < nvl; ++i) hs.cell_dofs[c * nl + i] = mesh->cells[c * nvl + i];
+            if (order == 2)
+                for (int e = 0; e < nel; ++e) {
+                    auto it = std::lower_bound(edges.begin(), edges.end(), ekey[c * nel + e]);
+                    hs.cell_dofs[c * nl + nvl + e] = (int32_t)(nv + (it - edges.begin()));
+                }
+        }
+    });
+
+    // ---- Dirichlet DOFs ----
+    hs.dirichlet.assign(hs.ndofs, 0);
+    for (int64_t v = 0; v < nv; ++v) hs.dirichlet[v] = mesh->on_boundary[v] ? 1 : 0;
+    if (order == 2) {
+        auto bnd = [&](uint64_t key) {
+            return mesh->on_boundary[key >> 32] && mesh->on_boundary[key & 0xffffffffu];
+        };
+        if (dim == 2) {
+            // boundary facets are the edges of exactly one triangle
+            std::vector<uint64_t> all = ekey;
+            std::sort(all.begin(), all.end());
+            for (size_t i = 0; i < all.size();) {
+                size_t j = i;
+                while (j < all.size() && all[j] == all[i]) ++j;
+                if (j - i == 1 && bnd(all[i])) {
+                    const int64_t idx = std::lower_bound(edges.begin(), edges.end(), all[i]) - edges.begin();
+                    hs.dirichlet[nv + idx] = 1;
+                }
+                i = j;
+            }
+        } else {
+            std::vector<Face> faces(nc * 4);
+            for (int64_t c = 0; c < nc; ++c)
+                for (int o = 0; o < 4; ++o) {
+                    Face f;
+                    int q = 0;
+                    for (int t = 0; t < 4; ++t)
+                        if (t != o) f.v[q++] = mesh->cells[c * 4 + t];
+                    std::sort(f.v, f.v + 3);
+                    faces[c * 4 + o] = f;
+                }
+            std::sort(faces.begin(), faces.end());
+            for (size_t i = 0; i < faces.size();) {
+                size_t j = i;
+                while (j < faces.size() && faces[j] == faces[i]) ++j;
+                if (j - i == 1) {
+                    const int32_t *v = faces[i].v;
+                    if (mesh->on_boundary[v[0]] && mesh->on_boundary[v[1]] && mesh->on_boundary[v[2]]) {
+                        const int pr[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+                        for (auto &p : pr) {
+                            const uint64_t key = ((uint64_t)v[p[0]] << 32) | (uint64_t)v[p[1]];
+                            const int64_t idx = std::lower_bound(edges.begin(), edges.end(), key) - edges.begin();
+                            hs.dirichlet[nv + idx] = 1;
+                        }
+                    }
+                }
+                i = j;
+            }
+        }
+    }
+    hs.dof2free.assign(hs.ndofs, -1);
+    hs.dof2dir.assign(hs.ndofs, -1);
+    hs.free2dof.clear();
+    hs.dir2dof.clear();
+    for (int64_t d = 0; d < hs.ndofs; ++d) {
+        if (hs.dirichlet[d]) {
+            hs.dof2dir[d] = (int64_t)hs.dir2dof.size();
+            hs.dir2dof.push_back(d);
+        } else {
+            hs.dof2free[d] = (int64_t)hs.free2dof.size();
+            hs.free2dof.push_back(d);
+        }
+    }
+    hs.nfree = (int64_t)hs.free2dof.size();
+    hs.ndir = (int64_t)hs.dir2dof.size();
+
+    // ---- element matrices (parallel over cells) ----
+    std::vector<double> Ke((size_t)nc * nl * nl);
+    std::atomic<int64_t> bad{0};
+    parallel_for(nc, [&](int64_t c0, int64_t c1) {
+        double P[12];
+        for (int64_t c = c0; c < c1; ++c) {
+            for (int i = 0; i < nvl; ++i)
+                for (int r = 0; r < dim; ++r) P[i * dim + r] = mesh->coords[(int64_t)mesh->cells[c * nvl + i] * dim + r];
+            if (!element_matrix(dim, order, P, &Ke[(size_t)c * nl * nl])) bad.fetch_add(1);
+        }
+    });
+    if (bad.load()) {
+        err = "mesh has " + std::to_string(bad.load()) + " cells with non-positive measure";
+        return FEMCG_EMESH;
+    }
+
+    // ---- DOF -> incident (cell, local index), cells ascending ----
+    const int64_t nd = hs.ndofs;
+    std::vector<int64_t> inc_ptr(nd + 1, 0);
+    for (int64_t i = 0; i < nc * nl; ++i) inc_ptr[hs.cell_dofs[i] + 1]++;
+    for (int64_t d = 0; d < nd; ++d) inc_ptr[d + 1] += inc_ptr[d];
+    std::vector<int64_t> inc(nc * nl);
+    {
+        std::vector<int64_t> fill(inc_ptr.begin(), inc_ptr.end() - 1);
+        for (int64_t i = 0; i < nc * nl; ++i) inc[fill[hs.cell_dofs[i]]++] = i;  // i = c*nl + a
+    }
+
+    // ---- rows of the free DOFs: pattern (all DOFs sharing a cell), values
+    //      summed in cell order; split into A (free cols) and K_ID ----
+    const int64_t nf = hs.nfree;
+    std::vector<int64_t> a_cnt(nf + 1, 0), l_cnt(nf + 1, 0);
+    std::vector<std::vector<int32_t>> dummy;
+    // pass 1: pattern sizes
+    parallel_for(nf, [&](int64_t f0, int64_t f1) {
+        std::vector<int32_t> cols;
+        for (int64_t f = f0; f < f1; ++f) {
+            const int64_t d = hs.free2dof[f];
+            cols.clear();
+            for (int64_t t = inc_ptr[d]; t < inc_ptr[d + 1]; ++t) {
+                const int64_t c = inc[t] / nl;
+                for (int b = 0; b < nl; ++b) cols.push_back(hs.cell_dofs[c * nl + b]);
+            }
+            std::sort(cols.begin(), cols.end());
+            cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+            int64_t na = 0, nl_ = 0;
+            for (int32_t cdof : cols) (hs.dirichlet[cdof] ? nl_ : na)++;
+            a_cnt[f + 1] = na;
+            l_cnt[f + 1] = nl_;
+        }
+    });
+    for (int64_t f = 0; f < nf; ++f) {
+        a_cnt[f + 1] += a_cnt[f];
+        l_cnt[f + 1] += l_cnt[f];
+    }
+    hs.a_rowptr = a_cnt;
+    hs.l_rowptr = l_cnt;
+    hs.a_col.resize(a_cnt[nf]);
+    hs.a_val.assign(a_cnt[nf], 0.0);
+    hs.l_col.resize(l_cnt[nf]);
+    hs.l_val.assign(l_cnt[nf], 0.0);
+    // pass 2: columns and values
+    parallel_for(nf, [&](int64_t f0, int64_t f1) {
+        std::vector<int32_t> cols;
+        std::vector<double> vals;
+        for (int64_t f = f0; f < f1; ++f) {
+            const int64_t d = hs.free2dof[f];
+            cols.clear();
+            for (int64_t t = inc_ptr[d]; t < inc_ptr[d + 1]; ++t) {
+                const int64_t c = inc[t] / nl;
+                for (int b = 0; b < nl; ++b) cols.push_back(hs.cell_dofs[c * nl + b]);
+            }
+            std::sort(cols.begin(), cols.end());
+            cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+            vals.assign(cols.size(), 0.0);
+            for (int64_t t = inc_ptr[d]; t < inc_ptr[d + 1]; ++t) {
+                const int64_t c = inc[t] / nl, a = inc[t] % nl;
+                const double *Kc = &Ke[(size_t)c * nl * nl + a * nl];
+                for (int b = 0; b < nl; ++b) {
+                    const int32_t cd = hs.cell_dofs[c * nl + b];
+                    const size_t pos = std::lower_bound(cols.begin(), cols.end(), cd) - cols.begin();
+                    vals[pos] += Kc[b];
+                }
+            }
+            int64_t pa = hs.a_rowptr[f], pl = hs.l_rowptr[f];
+            for (size_t i = 0; i < cols.size(); ++i) {
+                const int32_t cd = cols[i];
+                if (hs.dirichlet[cd]) {
+                    hs.l_col[pl] = (int32_t)hs.dof2dir[cd];
+                    hs.l_val[pl++] = vals[i];
+                } else {
+                    hs.a_col[pa] = (int32_t)hs.dof2free[cd];
+                    hs.a_val[pa++] = vals[i];
+                }
+            }
+        }
+    });
+    hs.cell_dofs.clear();
+    hs.cell_dofs.shrink_to_fit();
+    return FEMCG_OK;
+}
+
+// Solver copy: drop |a| <= 4 eps max_row|a| (never the diagonal), permute rows
+// symmetrically so that rows sorted by length (within windows of sigma rows)
+// share SELL slices.
+int build_solver_copy(const HostSystem &hs, int format, int C, int sigma, SolverCopy &sc,
+                      std::string &err)
+{
+    const int64_t n = hs.nfree;
+    sc.n = n;
+    sc.format = format;
+    sc.C = C;
+    sc.sigma = std::max(1, sigma);
+    // pruned rows in free order
+    std::vector<int64_t> rp(n + 1, 0);
+    std::vector<int32_t> len(n);
+    std::vector<uint8_t> keep(hs.a_col.size());
+    sc.diag.assign(n, 0.0);
+    for (int64_t i = 0; i < n; ++i) {
+        double mx = 0.0;
+        for (int64_t t = hs.a_rowptr[i]; t < hs.a_rowptr[i + 1]; ++t) mx = std::max(mx, std::fabs(hs.a_val[t]));
+        const double thr = 4.0 * 2.220446049250313e-16 * mx;
+        int32_t c = 0;
+        for (int64_t t = hs.a_rowptr[i]; t < hs.a_rowptr[i + 1]; ++t) {
+            const bool diag = hs.a_col[t] == i;
+            if (diag) sc.diag[i] = hs.a_val[t];
+            keep[t] = diag || std::fabs(hs.a_val[t]) > thr;
+            c += keep[t];
+        }
+        len[i] = c;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        if (!(sc.diag[i] > 0.0)) {
+            err = "non-positive diagonal in A";
+            return FEMCG_EMESH;
+        }
+    // permutation
+    sc.perm.resize(n);
+    for (int64_t i = 0; i < n; ++i) sc.perm[i] = (int32_t)i;
+    if (format == FEM_FORMAT_SELL && sc.sigma > 1) {
+        for (int64_t w = 0; w < n; w += sc.sigma) {
+            const int64_t e = std::min(n, w + sc.sigma);
+            std::stable_sort(sc.perm.begin() + w, sc.perm.begin() + e,
+                             [&](int32_t a, int32_t b) { return len[a] > len[b]; });
+        }
+    }
+    std::vector<int32_t> iperm(n);
+    for (int64_t i = 0; i < n; ++i) iperm[sc.perm[i]] = (int32_t)i;
+    // internal CSR (columns in internal numbering, ascending)
+    sc.rowptr.assign(n + 1, 0);
+    for (int64_t i = 0; i < n; ++i) sc.rowptr[i + 1] = sc.rowptr[i] + len[sc.perm[i]];
+    const int64_t nnz = sc.rowptr[n];
+    if (nnz >= ((int64_t)1 << 31)) {
+        err = "too many nonzeros for int32 row pointers";
+        return FEMCG_EUNSUPPORTED;
+    }
+    sc.nnz = nnz;
+    sc.col.resize(nnz);
+    sc.val.resize(nnz);
+    parallel_for(n, [&](int64_t i0, int64_t i1) {
+        std::vector<std::pair<int32_t, double>> row;
+        for (int64_t i = i0; i < i1; ++i) {
+            const int64_t src = sc.perm[i];
+            row.clear();
+            for (int64_t t = hs.a_rowptr[src]; t < hs.a_rowptr[src + 1]; ++t)
+                if (keep[t]) row.emplace_back(iperm[hs.a_col[t]], hs.a_val[t]);
+            std::sort(row.begin(), row.end(), [](auto &a, auto &b) { return a.first < b.first; });
+            int64_t p = sc.rowptr[i];
+            for (auto &e : row) {
+                sc.col[p] = e.first;
+                sc.val[p++] = e.second;
+            }
+        }
+    });
+    sc.dinv.resize(n);
+    for (int64_t i = 0; i < n; ++i) sc.dinv[i] = 1.0 / sc.diag[sc.perm[i]];
+    // SELL-C-sigma: slice s holds rows [s*C, s*C+C), entry e of row r at
+    // slice_ptr[s] + e*C + (r mod C); padding: column = own row, value 0
+    if (format == FEM_FORMAT_SELL) {
+        const int64_t ns = (n + C - 1) / C;
+        sc.slice_ptr.assign(ns + 1, 0);
+        sc.rowlen.resize(n);
+        for (int64_t s = 0; s < ns; ++s) {
+            int32_t mx = 0;
+            for (int64_t r = s * C; r < std::min(n, s * C + C); ++r) {
+                sc.rowlen[r] = (int32_t)(sc.rowptr[r + 1] - sc.rowptr[r]);
+                mx = std::max(mx, sc.rowlen[r]);
+            }
+            sc.slice_ptr[s + 1] = sc.slice_ptr[s] + (int64_t)mx * C;
+        }
+        const int64_t stored = sc.slice_ptr[ns];
+        sc.sell_col.assign(stored, 0);
+        sc.sell_val.assign(stored, 0.0);
+        parallel_for(ns, [&](int64_t s0, int64_t s1) {
+            for (int64_t s = s0; s < s1; ++s) {
+                const int64_t base = sc.slice_ptr[s];
+                const int64_t width = (sc.slice_ptr[s + 1] - base) / C;
+                for (int64_t r = s * C; r < s * C + C; ++r) {
+                    const int64_t lr = r - s * C;
+                    const int64_t own = r < n ? r : n - 1;
+                    for (int64_t e = 0; e < width; ++e) {
+                        const int64_t dst = base + e * C + lr;
+                        if (r < n && e < sc.rowlen[r]) {
+                            sc.sell_col[dst] = sc.col[sc.rowptr[r] + e];
+                            sc.sell_val[dst] = sc.val[sc.rowptr[r] + e];
+                        } else {
+                            sc.sell_col[dst] = (int32_t)own;
+                            sc.sell_val[dst] = 0.0;
+                        }
+                    }
+                }
+            }
+        });
+        sc.stored = stored;
+    } else {
+        sc.stored = nnz;
+    }
+    return FEMCG_OK;
+}
+
+}  // namespace femcg

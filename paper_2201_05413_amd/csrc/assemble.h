@@ -1,0 +1,52 @@
+// assemble.h -- host assembly of the library (not part of the public ABI).
+#pragma once
+
+#include <cstdint>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "femcg.h"
+
+namespace femcg {
+
+struct HostSystem {
+    int dim = 0, order = 0, nloc = 0;
+    int64_t nverts = 0, ncells = 0, nedges = 0, ndofs = 0, nfree = 0, ndir = 0;
+    std::vector<double> dof_coords;      // [ndofs][dim]
+    std::vector<uint8_t> dirichlet;      // [ndofs]
+    std::vector<int64_t> free2dof, dof2free, dir2dof, dof2dir;
+    std::vector<int32_t> cell_dofs;      // [ncells][nloc] (released after assembly)
+    // A = K_II, structural pattern, columns ascending (free numbering)
+    std::vector<int64_t> a_rowptr;
+    std::vector<int32_t> a_col;
+    std::vector<double> a_val;
+    // K_ID: free rows x Dirichlet columns (Dirichlet numbering)
+    std::vector<int64_t> l_rowptr;
+    std::vector<int32_t> l_col;
+    std::vector<double> l_val;
+};
+
+// Solver copy of A on the host, in internal (permuted) row order.
+struct SolverCopy {
+    int format = FEM_FORMAT_CSR, C = 64, sigma = 1;
+    int64_t n = 0, nnz = 0, stored = 0;
+    std::vector<int32_t> perm;           // internal row -> free row
+    std::vector<double> diag;            // free order
+    std::vector<int32_t> rowptr;         // internal CSR
+    std::vector<int32_t> col;
+    std::vector<double> val;
+    std::vector<double> dinv;            // internal order
+    std::vector<int64_t> slice_ptr;      // SELL
+    std::vector<int32_t> rowlen;
+    std::vector<int32_t> sell_col;
+    std::vector<double> sell_val;
+};
+
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &fn);
+bool element_matrix(int dim, int order, const double *P, double *K);
+int assemble_host(const fem_mesh *mesh, int order, HostSystem &hs, std::string &err);
+int build_solver_copy(const HostSystem &hs, int format, int C, int sigma, SolverCopy &sc,
+                      std::string &err);
+
+}  // namespace femcg

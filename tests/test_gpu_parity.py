@@ -1,0 +1,200 @@
+"""GPU parity of the HIP path against the oracle, through the C ABI.
+
+Bars (see the oracle's pins for what fixes the oracle itself):
+* assembly: identical structural pattern, max_row |dA| / max_row |A| <= 1e-12;
+  B = -K_ID g_D within 1e-12 norm-wise per column; DOF coordinates bit-equal;
+* SpMM: |y - y_oracle| <= 1e-13 (|A| |x|) row-wise (FP64; the solver copy
+  drops entries below 4 eps64 max_row|a|);
+* solve (R): the oracle recomputes ||b - A x|| / ||b|| with its own A: <= tol;
+* solve (S): at tol 1e-12 the solution is within 1e-8 relative L2 of the
+  oracle's solution at tol 1e-14 (or of the closed form where one exists).
+Sizes span several tiles and end in a ragged tail.
+"""
+import numpy as np
+import pytest
+
+import meshgen
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2201_05413_amd import femcg  # noqa: E402
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+class Case:
+    def __init__(self, dim, m, jit, order, k, seed=1, fmt=femcg.FEM_FORMAT_SELL, noise=0.0):
+        self.mesh = meshgen.make_mesh(dim, m, jit, seed)
+        self.order = order
+        self.k = k
+        self.orc = oracle.System(self.mesh, order)
+        self.A = femcg.Matrix(self.mesh, order, fmt)
+        coords, _, self.f2d = self.orc.dofs()
+        co = meshgen.random_coeffs(dim, k, seed + 100)
+        self.g = meshgen.harmonic_eval(co, coords)
+        if noise > 0:
+            self.g = self.g + meshgen.noise(seed + 200, self.g.size, noise).reshape(self.g.shape)
+        self.Bo = self.orc.rhs(self.g)
+
+    def B(self):
+        B = torch.empty((self.A.n_free, self.k), dtype=torch.float64, device="cuda")
+        femcg.fem_rhs(self.A, self.g, B)
+        return B
+
+    def solve(self, tol, **kw):
+        B = self.B()
+        X = torch.zeros_like(B)
+        o = femcg.default_opts(tol=tol, **kw)
+        rc = femcg.pcg_solve(self.A, B, X, tol, o)
+        torch.cuda.synchronize()
+        return rc, X.cpu().numpy(), self.A.stats()
+
+
+CASES = [
+    (2, 37, 0.3, 1), (2, 23, 0.25, 2), (3, 11, 0.3, 1), (3, 7, 0.2, 2), (2, 64, 0.0, 1), (3, 17, 0.0, 1),
+]
+
+
+@pytest.mark.parametrize("dim,m,jit,order", CASES)
+def test_assembly_matches_oracle(dim, m, jit, order):
+    c = Case(dim, m, jit, order, 2)
+    coords_l, dir_l, f2d_l = c.A.dofs()
+    coords_o, dir_o, f2d_o = c.orc.dofs()
+    assert np.array_equal(coords_l, coords_o)
+    assert np.array_equal(dir_l, dir_o) and np.array_equal(f2d_l, f2d_o)
+    rp, col, val = c.A.csr()
+    rpo, colo, valo = c.orc.A()
+    assert np.array_equal(rp, rpo) and np.array_equal(col, colo)
+    rowmax = np.maximum.reduceat(np.abs(valo), rpo[:-1])
+    dmax = np.maximum.reduceat(np.abs(val - valo), rpo[:-1])
+    assert (dmax / rowmax).max() <= 1e-12
+    B = c.B().cpu().numpy()
+    for j in range(c.k):
+        assert np.linalg.norm(B[:, j] - c.Bo[:, j]) <= 1e-12 * np.linalg.norm(c.Bo[:, j])
+
+
+@pytest.mark.parametrize("fmt", [femcg.FEM_FORMAT_CSR, femcg.FEM_FORMAT_SELL])
+@pytest.mark.parametrize("k", [1, 3, 8, 32])
+def test_spmm_matches_oracle(fmt, k):
+    c = Case(2, 45, 0.3, 2, 1, seed=3, fmt=fmt)
+    rng = np.random.default_rng(k)
+    X = rng.standard_normal((c.A.n_free, k))
+    Y = torch.zeros((c.A.n_free, k), dtype=torch.float64, device="cuda")
+    femcg.fem_spmv(c.A, dev(X), Y)
+    torch.cuda.synchronize()
+    Yo = c.orc.spmv(X)
+    rp, col, val = c.orc.A()
+    absAx = np.zeros_like(X)
+    for i in range(c.orc.nfree):
+        absAx[i] = np.abs(val[rp[i]:rp[i + 1]]) @ np.abs(X[col[rp[i]:rp[i + 1]]])
+    assert np.all(np.abs(Y.cpu().numpy() - Yo) <= 1e-13 * absAx)
+
+
+@pytest.mark.parametrize("dim,m,jit,order", CASES)
+@pytest.mark.parametrize("prec", [femcg.PCG_FP64, femcg.PCG_MIXED])
+def test_solve_matches_oracle(dim, m, jit, order, prec):
+    c = Case(dim, m, jit, order, 3, noise=0.01)
+    Xs, its_o, _, _, st = c.orc.pcg(c.Bo, 1e-14)
+    assert st == 0
+    # (R) at tol 1e-8 and (S) at tol 1e-12
+    for tol in (1e-8, 1e-12):
+        rc, X, stats = c.solve(tol, precision=prec)
+        assert rc == 0, stats
+        rel = c.orc.relres(c.Bo, X)
+        assert np.all(rel <= tol * 1.0001), (rel, stats)
+        if tol == 1e-12:
+            for j in range(c.k):
+                assert oracle.x_err(Xs[:, j], X[:, j]) <= 1e-8
+        if prec == femcg.PCG_FP64 and tol == 1e-8:
+            _, its_t, _, _, _ = c.orc.pcg(c.Bo, tol)
+            for j in range(c.k):
+                assert abs(stats["iters"][j] - its_t[j]) <= 0.02 * its_t[j] + 2, (stats["iters"], its_t)
+
+
+def test_c1_closed_form():
+    w = meshgen.c1()
+    A = femcg.Matrix(w.mesh, 1)
+    coords, _, f2d = A.dofs()
+    g = w.dirichlet(coords)
+    B = torch.empty((A.n_free, 1), dtype=torch.float64, device="cuda")
+    femcg.fem_rhs(A, g, B)
+    X = torch.zeros_like(B)
+    assert femcg.pcg_solve(A, B, X, 1e-10) == 0
+    x = X.cpu().numpy()
+    assert oracle.x_err(g[f2d], x) <= 1e-9
+    assert abs(A.stats()["iters"][0] - 197) <= 6
+
+
+def test_structured_3d_harmonic_cubics_closed_form():
+    c = Case(3, 24, 0.0, 1, 8, seed=3)
+    for prec in (femcg.PCG_FP64, femcg.PCG_MIXED):
+        rc, X, st = c.solve(1e-12, precision=prec)
+        assert rc == 0
+        for j in range(c.k):
+            assert oracle.x_err(c.g[c.f2d, j], X[:, j]) <= 1e-8
+
+
+def test_zero_rhs_column_and_odd_k():
+    c = Case(2, 30, 0.3, 1, 5, seed=7)
+    c.g[:, 2] = 0.0
+    c.Bo = c.orc.rhs(c.g)
+    rc, X, st = c.solve(1e-10)
+    assert rc == 0
+    assert st["iters"][2] == 0 and np.all(X[:, 2] == 0.0)
+    rel = c.orc.relres(c.Bo, X)
+    assert np.all(rel[[0, 1, 3, 4]] <= 1e-10)
+
+
+def test_max_iter_warning_and_initial_guess():
+    c = Case(2, 40, 0.3, 1, 1, seed=9)
+    rc, X, st = c.solve(1e-10, max_iter=7, check_every=4)
+    assert rc == femcg.FEMCG_WARN_MAXITER and st["iters"][0] == 7 and st["relres"][0] > 1e-10
+    # exact solution as the initial guess: converged at the first residual
+    Xs, _, _, _, _ = c.orc.pcg(c.Bo, 1e-14)
+    B = c.B()
+    X0 = dev(Xs)
+    o = femcg.default_opts(tol=1e-10, use_x0=1)
+    assert femcg.pcg_solve(c.A, B, X0, 1e-10, o) == 0
+    assert c.A.stats()["iters"][0] == 0
+
+
+def test_k_columns_equal_single_solves():
+    c = Case(2, 50, 0.3, 1, 4, seed=11)
+    rc, X, st = c.solve(1e-12)
+    for j in range(c.k):
+        B = c.B()[:, j:j + 1].contiguous()
+        Xj = torch.zeros_like(B)
+        assert femcg.pcg_solve(c.A, B, Xj, 1e-12) == 0
+        assert oracle.x_err(Xj.cpu().numpy()[:, 0], X[:, j]) <= 1e-9
+
+
+def test_batch_equals_alone_bitwise():
+    cases = [Case(2, 41, 0.3, 1, 2, seed=21), Case(3, 9, 0.2, 2, 5, seed=22), Case(2, 29, 0.0, 2, 1, seed=23),
+             Case(3, 13, 0.3, 1, 8, seed=24)]
+    alone = []
+    for c in cases:
+        rc, X, st = c.solve(1e-10)
+        assert rc == 0
+        alone.append(X)
+    Bs = [c.B() for c in cases]
+    Xs = [torch.zeros_like(b) for b in Bs]
+    st = femcg.pcg_solve_batch([c.A for c in cases], Bs, Xs, [1e-10] * len(cases))
+    torch.cuda.synchronize()
+    assert st == [0] * len(cases)
+    for X, Xa in zip(Xs, alone):
+        assert np.array_equal(X.cpu().numpy(), Xa)
+
+
+def test_format_and_tuner_agree():
+    c = Case(2, 33, 0.25, 2, 3, seed=31)
+    rc, X1, _ = c.solve(1e-12)
+    femcg.fem_set_format(c.A, femcg.FEM_FORMAT_CSR)
+    rc2, X2, _ = c.solve(1e-12)
+    f, cw, sg = femcg.fem_tune(c.A, 3)
+    rc3, X3, _ = c.solve(1e-12)
+    assert rc == rc2 == rc3 == 0
+    assert oracle.x_err(X1, X2) <= 1e-9 and oracle.x_err(X1, X3) <= 1e-9
