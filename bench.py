@@ -1,0 +1,374 @@
+"""Benchmark of the Jacobi-PCG hot path on one MI355X.
+
+One step = one full pass of the path over the workload's system, inputs
+resident in HBM: lift the Dirichlet data into B on the device, solve to the
+tolerance with plain FP64 PCG, then solve again with the FP32-inner /
+FP64-refined PCG (iterations as HIP graph replays, alpha/beta/convergence on
+the device).  Reported: whole-step algorithmic GB/s (value), time-to-tol of
+both precisions and their ratio, p50/p99 of the per-solve latency over the
+timed steps, the roofline of the dominant kernel (SpMM + p.q of the FP64
+iteration, timed with HIP events on its stream), and the oracle on the host
+CPU as a bounded-sample baseline.
+
+Default workload: 2D P1 on a 1024x1024 vertex grid jittered by 0.3h
+(1,044,484 unknowns), g = x^2 - y^2 + N(0, 0.01^2) noise, tol 1e-8.
+Other workloads: --workload c1|c3|c4 (single solves), c5 (serving stream).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SpMV HBM GB/s + time-to-1e-8 residual vs FP64 PCG; p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def percentile(xs, p):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    i = min(len(xs) - 1, max(0, int(math.ceil(p / 100.0 * len(xs))) - 1))
+    return xs[i]
+
+
+def iter_bytes(n, nnz, k, sv):
+    """Algorithmic HBM bytes of one fused PCG iteration."""
+    return nnz * (sv + 4) + 4 * (n + 1) + 11 * n * k * sv + 2 * n * sv
+
+
+def spmm_bytes(n, nnz, k, sv):
+    return nnz * (sv + 4) + 4 * n + 2 * n * k * sv
+
+
+def cpu_baseline(w, budget_s=15.0):
+    """The oracle (plain C, one thread) on a bounded sample of the same solve."""
+    import numpy as np
+    import oracle
+
+    t0 = time.time()
+    s = oracle.System(w.mesh, w.order)
+    t_asm = time.time() - t0
+    coords, _, _ = s.dofs()
+    g = w.dirichlet(coords)
+    B = s.rhs(g)[:, :1]
+    # time a short run, then size the sample to about budget_s seconds
+    t0 = time.time()
+    s.pcg(B, 1e-300, max_iter=5)
+    dt = max(time.time() - t0, 1e-3) / 5
+    its = max(10, int(budget_s / dt))
+    t0 = time.time()
+    _, it, _, _, _ = s.pcg(B, 1e-300, max_iter=its)
+    el = time.time() - t0
+    n, nnz = s.nfree, s.nnz_A
+    rate = iter_bytes(n, nnz, 1, 8) * int(it[0]) / el / 1e9
+    return dict(value=round(rate, 3), unit="GB/s", cores=1, kind="oracle",
+                sample="oracle FP64 Jacobi-PCG, column 0 of %s, first %d iterations (%.1f s; %.2f ms/iteration; "
+                       "assembly %.1f s), algorithmic bytes as the GPU line (structural nnz %d)"
+                       % (w.name, int(it[0]), el, 1e3 * el / int(it[0]), t_asm, nnz),
+                ms_per_iter=1e3 * el / int(it[0]))
+
+
+def make_workload(name):
+    import meshgen
+    return {"c1": meshgen.c1, "c2": meshgen.c2, "c3": meshgen.c3, "c4": meshgen.c4}[name]()
+
+
+def run_single(args):
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2201_05413_amd import femcg
+
+    torch.cuda.set_device(0)
+    if args.calibrate_copy_mb > 0:
+        nel = int(args.calibrate_copy_mb * 1e6 / 8)
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d doubles (%.1f MB read, %.1f MB written)" % (nel, nel * 8e-6, nel * 8e-6))
+        del src, dst
+    t0 = time.time()
+    w = make_workload(args.workload)
+    log("workload %s: mesh %.1f s" % (w.name, time.time() - t0))
+    t0 = time.time()
+    A = femcg.Matrix(w.mesh, w.order, femcg.FEM_FORMAT_SELL)
+    t_asm = time.time() - t0
+    coords, _, f2d = A.dofs()
+    g = w.dirichlet(coords)
+    k = w.k
+    n = A.n_free
+    B = torch.empty((n, k), dtype=torch.float64, device="cuda")
+    X64 = torch.zeros_like(B)
+    Xmx = torch.zeros_like(B)
+    femcg.fem_rhs(A, g, B)
+    t0 = time.time()
+    fmt, cw, sg = femcg.fem_tune(A, k, femcg.PCG_FP64)
+    t_tune = time.time() - t0
+    log("assembly %.2f s, tuner %.2f s -> format %d C=%d sigma=%d" % (t_asm, t_tune, fmt, cw, sg))
+    o64 = femcg.default_opts(tol=w.tol, precision=femcg.PCG_FP64, check_every=args.check_every)
+    omx = femcg.default_opts(tol=w.tol, precision=femcg.PCG_MIXED, check_every=args.check_every,
+                             inner_eta=args.eta)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        ta = time.perf_counter()
+        femcg.fem_rhs(A, g, B)
+        rc1 = femcg.pcg_solve(A, B, X64, w.tol, o64)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        s64 = A.stats()
+        rc2 = femcg.pcg_solve(A, B, Xmx, w.tol, omx)
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        smx = A.stats()
+        if rc1 != 0 or rc2 != 0:
+            raise RuntimeError("solve status %d / %d" % (rc1, rc2))
+        return tb - ta, tc - tb, s64, smx
+
+    for i in range(args.warmup):
+        step()
+        log("warmup %d done" % i)
+    torch.cuda.synchronize()
+    lat64, latmx, bytes_tot = [], [], 0.0
+    T0 = time.perf_counter()
+    for i in range(args.steps):
+        t64, tmx, s64, smx = step()
+        lat64.append(t64)
+        latmx.append(tmx)
+        bytes_tot += s64["bytes"] + smx["bytes"]
+        log("step %d: fp64 %.2f ms (%d its), mixed %.2f ms (%d inner its, %d outer)"
+            % (i, 1e3 * t64, max(s64["iters"]), 1e3 * tmx, max(smx["iters"]), smx["outer"]))
+    torch.cuda.synchronize()
+    T = time.perf_counter() - T0
+    # parity (R): the oracle's own residual of both solutions
+    t0 = time.time()
+    orc = oracle.System(w.mesh, w.order)
+    Bo = orc.rhs(g)
+    rel64 = orc.relres(Bo, X64.cpu().numpy())
+    relmx = orc.relres(Bo, Xmx.cpu().numpy())
+    x64 = X64.cpu().numpy()
+    xmx = Xmx.cpu().numpy()
+    diff = float(np.linalg.norm(xmx - x64) / np.linalg.norm(x64))
+    log("oracle check %.1f s: relres fp64 %.3e mixed %.3e (tol %.0e)" % (time.time() - t0, rel64.max(), relmx.max(),
+                                                                         w.tol))
+    # roofline of the dominant kernel: SpMM + p.q of the FP64 iteration
+    femcg.pcg_solve(A, B, X64, w.tol, o64)
+    torch.cuda.synchronize()
+    st = A.stats()
+    ms_spmm, by_spmm = femcg.pcg_time_kernel(A, 0, reps=args.kernel_reps)
+    ms_upd, by_upd = femcg.pcg_time_kernel(A, 1, reps=args.kernel_reps)
+    ms_pup, by_pup = femcg.pcg_time_kernel(A, 2, reps=args.kernel_reps)
+    # restore the solution overwritten by the forced kernel launches
+    femcg.pcg_solve(A, B, X64, w.tol, o64)
+    torch.cuda.synchronize()
+    achieved = by_spmm / (ms_spmm * 1e-3) / 1e9
+    traffic = None
+    if args.traffic_json and os.path.exists(args.traffic_json):
+        traffic = json.load(open(args.traffic_json)).get(w.name)
+    line = {
+        "metric": METRIC,
+        "value": round(bytes_tot / T / 1e9, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * T / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 (FP64 PCG) + f32-inner/f64-refined (mixed PCG)",
+        "data": "synthetic",
+        "config": {
+            "workload": w.name,
+            "recipe": meshgen_doc(args.workload),
+            "n": n, "nnz_structural": st["nnz"], "nnz_nonzero": st["nnz_nonzero"], "k": k, "tol": w.tol,
+            "format": {0: "CSR", 1: "SELL"}[fmt], "sell_C": cw, "sell_sigma": sg,
+        },
+        "time_to_tol_ms": {"fp64_p50": round(1e3 * percentile(lat64, 50), 3),
+                           "mixed_p50": round(1e3 * percentile(latmx, 50), 3),
+                           "mixed_over_fp64": round(percentile(latmx, 50) / percentile(lat64, 50), 3)},
+        "latency_ms": {"fp64_p50": round(1e3 * percentile(lat64, 50), 3),
+                       "fp64_p99": round(1e3 * percentile(lat64, 99), 3),
+                       "mixed_p50": round(1e3 * percentile(latmx, 50), 3),
+                       "mixed_p99": round(1e3 * percentile(latmx, 99), 3)},
+        "iters": {"fp64": st["iters"], "mixed_inner_last": None},
+        "parity": {"oracle_relres_fp64": float(rel64.max()), "oracle_relres_mixed": float(relmx.max()),
+                   "mixed_vs_fp64_rel_l2": diff},
+        "kernels_ms": {"spmm_pq": round(ms_spmm, 5), "update": round(ms_upd, 5), "pupdate": round(ms_pup, 5)},
+        "kernels_gbs": {"spmm_pq": round(achieved, 1), "update": round(by_upd / (ms_upd * 1e-3) / 1e9, 1),
+                        "pupdate": round(by_pup / (ms_pup * 1e-3) / 1e9, 1)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "k_spmm<double> (SpMM + p.q, FP64)", "bytes_per_launch": by_spmm},
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
+def run_serve(args):
+    """Serving stream: Poisson arrivals of mixed 2D/3D, P1/P2, structured/jittered
+    requests with 1..16 random harmonic right-hand sides, tol 1e-8.  The server
+    (continuous batching, admission by device footprint) is compared with
+    one-at-a-time FP64 PCG replaying the same arrival trace."""
+    import numpy as np
+    import torch
+
+    import meshgen
+    import oracle
+    from paper_2201_05413_amd import femcg
+
+    torch.cuda.set_device(0)
+    reqs = meshgen.request_stream(args.n_requests, args.rate, seed=6, max2d=args.max2d, max3d=args.max3d)
+    t0 = time.time()
+    wls = [meshgen.build_request(r) for r in reqs]
+    log("generated %d requests in %.1f s" % (len(wls), time.time() - t0))
+    # DOF coordinates (public order) of every request, for its Dirichlet data:
+    # P1 = vertices; P2 = vertices then edge midpoints in (min, max) order
+    gs = []
+    for w in wls:
+        coords = w.mesh["coords"]
+        if w.order == 2:
+            cells = w.mesh["cells"]
+            d = cells.shape[1]
+            pairs = []
+            for a in range(d):
+                for b in range(a + 1, d):
+                    lo = np.minimum(cells[:, a], cells[:, b]).astype(np.int64)
+                    hi = np.maximum(cells[:, a], cells[:, b]).astype(np.int64)
+                    pairs.append(lo * (1 << 32) + hi)
+            e = np.unique(np.concatenate(pairs))
+            mid = 0.5 * (coords[e >> 32] + coords[e & 0xFFFFFFFF])
+            coords = np.concatenate([coords, mid])
+        gs.append(w.dirichlet(coords))
+    budget = args.budget_gb * 1e9
+    prec = femcg.PCG_MIXED if args.serve_mixed else femcg.PCG_FP64
+    L = femcg.lib()
+    import ctypes as C
+    srv = C.c_void_p()
+    femcg._check(L.serve_create(budget, args.slots, prec, args.check_every, C.byref(srv)))
+    keep = []
+    ids = {}
+    done = {}
+    t_start = L.serve_clock(srv)
+    nxt = 0
+    while len(done) < len(reqs):
+        now = L.serve_clock(srv) - t_start
+        while nxt < len(reqs) and reqs[nxt]["t_arrival"] <= now:
+            w = wls[nxt]
+            m, hold = femcg.make_mesh_struct(w.mesh)
+            g = np.ascontiguousarray(gs[nxt])
+            keep.append((hold, g))
+            rid = L.serve_submit(srv, C.byref(m), w.order, femcg._np_ptr(g), w.k, w.tol)
+            femcg._check(rid)
+            ids[rid] = nxt
+            nxt += 1
+        open_ = L.serve_step(srv)
+        femcg._check(open_)
+        for rid in list(ids):
+            info = femcg.fem_request_info()
+            r = L.serve_poll(srv, rid, None, C.byref(info))
+            if r == 1:
+                i = ids.pop(rid)
+                done[i] = dict(status=info.status, t_arr=reqs[i]["t_arrival"], t_submit=info.t_submit - t_start,
+                               t_ready=info.t_ready - t_start, t_admit=info.t_admit - t_start,
+                               t_done=info.t_done - t_start, iters=info.iters_max, relres=info.relres_max,
+                               n=info.n, k=info.k)
+        if open_ == 0 and nxt < len(reqs):
+            time.sleep(max(0.0, min(0.01, reqs[nxt]["t_arrival"] - (L.serve_clock(srv) - t_start))))
+    T_srv = max(d["t_done"] for d in done.values())
+    L.serve_destroy(srv)
+    lat = [d["t_done"] - d["t_arr"] for d in done.values()]
+    lat_solve = [d["t_done"] - d["t_ready"] for d in done.values()]
+    bad = [i for i, d in done.items() if d["status"] != 0 or d["relres"] > reqs[i].get("tol", 1e-8) * 1.0001]
+    # one-at-a-time FP64 PCG on the same trace
+    t_free = 0.0
+    lat1 = []
+    for i, w in enumerate(wls):
+        t_arr = reqs[i]["t_arrival"]
+        ta = time.perf_counter()
+        A = femcg.Matrix(w.mesh, w.order)
+        B = torch.empty((A.n_free, w.k), dtype=torch.float64, device="cuda")
+        X = torch.zeros_like(B)
+        femcg.fem_rhs(A, gs[i], B)
+        femcg.pcg_solve(A, B, X, w.tol, femcg.default_opts(tol=w.tol, check_every=args.check_every))
+        torch.cuda.synchronize()
+        dur = time.perf_counter() - ta
+        start = max(t_arr, t_free)
+        t_free = start + dur
+        lat1.append(t_free - t_arr)
+        del A
+    T_one = t_free
+    line = {
+        "metric": METRIC, "value": round(len(reqs) / T_srv, 3), "unit": "solves/s", "n_gpus": 1,
+        "steps": len(reqs), "warmup": 0, "ms_per_step": round(1e3 * T_srv / len(reqs), 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32-inner/f64-refined" if args.serve_mixed else "f64", "data": "synthetic",
+        "config": {"workload": "c5_serving_stream", "recipe": " ".join((run_serve.__doc__ or "").split()),
+                   "n_requests": len(reqs), "rate_per_s": args.rate, "slots": args.slots,
+                   "budget_gb": args.budget_gb, "max2d": args.max2d, "max3d": args.max3d},
+        "latency_ms": {"p50": round(1e3 * percentile(lat, 50), 2), "p99": round(1e3 * percentile(lat, 99), 2),
+                       "p50_excl_assembly": round(1e3 * percentile(lat_solve, 50), 2),
+                       "p99_excl_assembly": round(1e3 * percentile(lat_solve, 99), 2)},
+        "one_at_a_time_fp64": {"solves_per_s": round(len(reqs) / T_one, 3),
+                               "p50_ms": round(1e3 * percentile(lat1, 50), 2),
+                               "p99_ms": round(1e3 * percentile(lat1, 99), 2)},
+        "failed_or_above_tol": bad,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def meshgen_doc(name):
+    import meshgen
+    f = {"c1": meshgen.c1, "c2": meshgen.c2, "c3": meshgen.c3, "c4": meshgen.c4}[name]
+    return " ".join((f.__doc__ or "").split())
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--check-every", type=int, default=64)
+    ap.add_argument("--eta", type=float, default=1e-4)
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--n-requests", type=int, default=40)
+    ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--slots", type=int, default=32)
+    ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--max2d", type=int, default=1024)
+    ap.add_argument("--max3d", type=int, default=96)
+    ap.add_argument("--serve-mixed", action="store_true")
+    ap.add_argument("--calibrate-copy-mb", type=float, default=0.0,
+                    help="run one plain device copy of this size first (HBM counter calibration)")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.workload == "c5":
+        run_serve(args)
+    else:
+        run_single(args)
+
+
+if __name__ == "__main__":
+    main()

@@ -24,11 +24,10 @@ struct Arena {
 struct Work {
     int kp = 0, prec = 0;
     int64_t n = 0;
-    int tile_rows = 0, ntiles = 0, ngroups = 0;
+    int tile_rows = 0, ntiles = 0;
     double *B64 = nullptr, *X64 = nullptr, *R64 = nullptr, *P64 = nullptr, *Q64 = nullptr;
     float *B32 = nullptr, *X32 = nullptr, *R32 = nullptr, *P32 = nullptr, *Q32 = nullptr;
-    double *part64 = nullptr, *gpart64 = nullptr, *part32 = nullptr, *gpart32 = nullptr;
-    uint32_t *gtk64 = nullptr, *gtk32 = nullptr;
+    double *part64 = nullptr, *part32 = nullptr;
     char *mem = nullptr;
     size_t bytes = 0;
     ~Work()
@@ -95,6 +94,7 @@ struct Slot {
     int64_t outer_residuals = 0;
     double relres[kMaxK] = {};
     int64_t req = -1;              // serving: request id
+    int par_off = 0;               // iteration parity offset while in the main table
 };
 
 struct Engine {
@@ -114,8 +114,10 @@ struct Engine {
     std::vector<Slot> slots;
     std::vector<int> main_ids;      // slots in the uploaded main table
     bool main_dirty = true;
-    hipGraphExec_t gexec = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};  // chunks starting at an even / odd launch index
     int graph_m = 0, graph_grid = 0;
+    unsigned main_mask = 0, graph_mask = 0;  // kp classes present in the main table
+    int64_t it_global = 0;          // iterations launched on the main table
     hipStream_t cap = nullptr;
     int64_t replays = 0;
     ~Engine();

@@ -16,6 +16,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <deque>
 #include <mutex>
 
@@ -131,7 +132,10 @@ static void choose_tiles(const fem_matrix *A, int kp, int &tile_rows, int &ntile
     const int64_t n = A->dev.n;
     const int rps = kBlock / kp;
     const int unit = std::max(rps, A->dev.format == FEM_FORMAT_SELL ? A->dev.C : 1);
-    int target = A->tile_target > 0 ? A->tile_target : (kp >= 8 ? 1024 : 2048);
+    // every block reduces all tile partials of its system at the start of a
+    // phase, so keep ntiles * kp bounded (<= 16K partials per dot)
+    int target = A->tile_target > 0 ? A->tile_target : std::max(256, std::min(1024, 16384 / kp));
+    if (const char *ev = std::getenv("FEMCG_TILE_TARGET")) target = std::max(1, atoi(ev));  // tuning override
     int64_t rows = (n + target - 1) / target;
     rows = ((rows + unit - 1) / unit) * unit;
     if (rows < unit) rows = unit;
@@ -153,9 +157,8 @@ int get_work(fem_matrix *A, int kp, int prec, Work **out)
     w->prec = prec;
     w->n = A->dev.n;
     choose_tiles(A, kp, w->tile_rows, w->ntiles);
-    w->ngroups = (w->ntiles + kGroup - 1) / kGroup;
     const size_t nv = (size_t)std::max<int64_t>(w->n, 1) * kp;
-    const size_t np = (size_t)w->ntiles * kDots * kp, ng = (size_t)w->ngroups * kDots * kp;
+    const size_t np = (size_t)w->ntiles * kDots * kp;
     Arena ar;
     for (int pass = 0; pass < 2; ++pass) {
         ar.used = 0;
@@ -172,12 +175,8 @@ int get_work(fem_matrix *A, int kp, int prec, Work **out)
             w->P32 = (float *)ar.take(nv * 4);
             w->Q32 = (float *)ar.take(nv * 4);
             w->part32 = (double *)ar.take(np * 8);
-            w->gpart32 = (double *)ar.take(ng * 8);
-            w->gtk32 = (uint32_t *)ar.take(w->ngroups * 4);
         }
         w->part64 = (double *)ar.take(np * 8);
-        w->gpart64 = (double *)ar.take(ng * 8);
-        w->gtk64 = (uint32_t *)ar.take(w->ngroups * 4);
         if (pass == 0) {
             ar.size = ar.used;
             if (hipMalloc((void **)&ar.base, ar.size) != hipSuccess)
@@ -195,8 +194,7 @@ int get_work(fem_matrix *A, int kp, int prec, Work **out)
 size_t work_bytes_estimate(int64_t n, int kp, int prec, int ntiles)
 {
     const size_t nv = (size_t)std::max<int64_t>(n, 1) * kp;
-    const size_t ng = (size_t)(ntiles + kGroup - 1) / kGroup;
-    const size_t parts = ((size_t)ntiles + ng) * kDots * kp * 8 + ng * 4;
+    const size_t parts = (size_t)ntiles * kDots * kp * 8;
     const size_t vec = prec == PCG_FP64 ? nv * 8 * 5 : nv * (8 * 3 + 4 * 5);
     return vec + parts * (prec == PCG_FP64 ? 1 : 2) + 16 * 256;
 }
@@ -209,8 +207,7 @@ size_t matrix_bytes_estimate(const SolverCopy &sc, const HostSystem &hs)
 }
 
 static SysDesc make_desc(const fem_matrix *A, const Work *w, bool fp32, const void *b, void *x, void *r,
-                         void *p, void *q, double *part, double *gpart, uint32_t *gtk, SysState *st,
-                         int k)
+                         void *p, void *q, double *part, SysState *st, int k)
 {
     SysDesc D{};
     const DevSparse &d = A->dev;
@@ -233,15 +230,14 @@ static SysDesc make_desc(const fem_matrix *A, const Work *w, bool fp32, const vo
     D.p = p;
     D.q = q;
     D.part = part;
-    D.gpart = gpart;
-    D.gticket = gtk;
     D.st = st;
     return D;
 }
 
 Engine::~Engine()
 {
-    if (gexec) (void)hipGraphExecDestroy(gexec);
+    for (auto &g : gexec)
+        if (g) (void)hipGraphExecDestroy(g);
     if (cap) (void)hipStreamDestroy(cap);
     SysTable *dt[] = {d_main, d_ri64, d_acc64, d_acc32, d_sc64, d_sc32, d_ri32};
     for (auto p : dt)
@@ -298,28 +294,66 @@ static SysDesc slot_desc(Engine *e, int s, bool fp32)
     Slot &sl = e->slots[s];
     Work *w = sl.w;
     if (!fp32)
-        return make_desc(sl.A, w, false, w->B64, w->X64, w->R64, w->P64, w->Q64, w->part64, w->gpart64,
-                         w->gtk64, e->d_st64 + s, sl.k);
-    return make_desc(sl.A, w, true, w->B32, w->X32, w->R32, w->P32, w->Q32, w->part32, w->gpart32,
-                     w->gtk32, e->d_st32 + s, sl.k);
+        return make_desc(sl.A, w, false, w->B64, w->X64, w->R64, w->P64, w->Q64, w->part64, e->d_st64 + s,
+                         sl.k);
+    return make_desc(sl.A, w, true, w->B32, w->X32, w->R32, w->P32, w->Q32, w->part32, e->d_st32 + s, sl.k);
 }
 
-// Fill a host table from slot ids; returns total tiles.
-static int64_t fill_table(Engine *e, SysTable *h, const std::vector<int> &ids, bool fp32, int use_x,
-                          int write_p, const std::vector<int> *use_x_per = nullptr)
+static int class_of(int kp)
 {
+    int c = 0;
+    while ((1 << c) < kp) ++c;
+    return c;
+}
+
+// Fill a host table from slot ids (sorted by kp class in place, stable, with
+// their per-system flags); returns total tiles and the class mask.
+static int64_t fill_table(Engine *e, SysTable *h, std::vector<int> &ids, bool fp32, int use_x, int write_p,
+                          unsigned *mask, std::vector<int> *use_x_per = nullptr)
+{
+    std::vector<int> ux(ids.size(), use_x);
+    if (use_x_per) ux = *use_x_per;
+    std::vector<size_t> ord(ids.size());
+    for (size_t i = 0; i < ord.size(); ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(),
+                     [&](size_t a, size_t b) { return e->slots[ids[a]].kp < e->slots[ids[b]].kp; });
+    std::vector<int> sid(ids.size()), sux(ids.size());
+    for (size_t i = 0; i < ord.size(); ++i) {
+        sid[i] = ids[ord[i]];
+        sux[i] = ux[ord[i]];
+    }
+    ids = sid;
+    if (use_x_per) *use_x_per = sux;
     int64_t base = 0;
+    unsigned m = 0;
+    for (int c = 0; c < kNumClass; ++c) h->cls_begin[c] = h->cls_end[c] = 0;
     h->nsys = (int)ids.size();
     for (size_t i = 0; i < ids.size(); ++i) {
         SysDesc D = slot_desc(e, ids[i], fp32);
         D.tile_base = base;
-        D.use_x = use_x_per ? (*use_x_per)[i] : use_x;
+        D.use_x = sux[i];
         D.write_p = write_p;
+        D.par_off = e->slots[ids[i]].par_off;
+        const int c = class_of(D.kp);
+        if (!(m & (1u << c))) h->cls_begin[c] = base;
+        m |= 1u << c;
         base += D.ntiles;
+        h->cls_end[c] = base;
         h->d[i] = D;
     }
     h->total_tiles = base;
+    if (mask) *mask = m;
     return base;
+}
+
+static void set_single_table(SysTable *h, const SysDesc &D)
+{
+    h->nsys = 1;
+    h->total_tiles = D.ntiles;
+    for (int c = 0; c < kNumClass; ++c) h->cls_begin[c] = h->cls_end[c] = 0;
+    const int c = class_of(D.kp);
+    h->cls_end[c] = D.ntiles;
+    h->d[0] = D;
 }
 
 static int upload_table(Engine *e, SysTable *d, SysTable *h)
@@ -328,44 +362,53 @@ static int upload_table(Engine *e, SysTable *d, SysTable *h)
     return FEMCG_OK;
 }
 
-static int launch_iterations(Engine *e, int iters, int grid)
+// `iters` iterations on the main table; launch indices it0, it0+1, ...
+static int launch_iterations(Engine *e, int iters, int grid, int64_t it0)
 {
-    for (int it = 0; it < iters; ++it) {
+    const unsigned m = e->main_mask;
+    for (int i = 0; i < iters; ++i) {
+        const int it = (int)((it0 + i) & 1);
         if (e->prec == PCG_FP64) {
-            launch_phase<double>(PH_SPMM, e->d_main, grid, 0, e->stream);
-            launch_phase<double>(PH_UPDATE, e->d_main, grid, 0, e->stream);
-            launch_phase<double>(PH_PUPDATE, e->d_main, grid, 0, e->stream);
+            launch_phase<double>(PH_SPMM, e->d_main, grid, it, 0, m, e->stream);
+            launch_phase<double>(PH_UPDATE, e->d_main, grid, it, 0, m, e->stream);
+            launch_phase<double>(PH_PUPDATE, e->d_main, grid, it, 0, m, e->stream);
         } else {
-            launch_phase<float>(PH_SPMM, e->d_main, grid, 0, e->stream);
-            launch_phase<float>(PH_UPDATE, e->d_main, grid, 0, e->stream);
-            launch_phase<float>(PH_PUPDATE, e->d_main, grid, 0, e->stream);
+            launch_phase<float>(PH_SPMM, e->d_main, grid, it, 0, m, e->stream);
+            launch_phase<float>(PH_UPDATE, e->d_main, grid, it, 0, m, e->stream);
+            launch_phase<float>(PH_PUPDATE, e->d_main, grid, it, 0, m, e->stream);
         }
     }
     HIPCHK(hipGetLastError());
     return FEMCG_OK;
 }
 
+// Graphs of m iterations for chunks starting at an even / odd launch index.
 static int ensure_graph(Engine *e, int grid)
 {
-    if (e->gexec && e->graph_m == e->m && e->graph_grid == grid) return FEMCG_OK;
-    if (e->gexec) {
-        HIPCHK(hipGraphExecDestroy(e->gexec));
-        e->gexec = nullptr;
+    if (e->gexec[0] && e->graph_m == e->m && e->graph_grid == grid && e->graph_mask == e->main_mask)
+        return FEMCG_OK;
+    for (auto &g : e->gexec)
+        if (g) {
+            HIPCHK(hipGraphExecDestroy(g));
+            g = nullptr;
+        }
+    for (int par = 0; par < 2; ++par) {
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(e->cap, hipStreamCaptureModeThreadLocal));
+        hipStream_t saved = e->stream;
+        e->stream = e->cap;
+        int rc = launch_iterations(e, e->m, grid, par);
+        e->stream = saved;
+        hipError_t ce = hipStreamEndCapture(e->cap, &g);
+        if (rc) return rc;
+        if (ce != hipSuccess) return fail(FEMCG_EDEVICE, "graph capture: %s", hipGetErrorString(ce));
+        hipError_t ie = hipGraphInstantiate(&e->gexec[par], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) return fail(FEMCG_EDEVICE, "graph instantiate: %s", hipGetErrorString(ie));
     }
-    hipGraph_t g = nullptr;
-    HIPCHK(hipStreamBeginCapture(e->cap, hipStreamCaptureModeThreadLocal));
-    hipStream_t saved = e->stream;
-    e->stream = e->cap;
-    int rc = launch_iterations(e, e->m, grid);
-    e->stream = saved;
-    hipError_t ce = hipStreamEndCapture(e->cap, &g);
-    if (rc) return rc;
-    if (ce != hipSuccess) return fail(FEMCG_EDEVICE, "graph capture: %s", hipGetErrorString(ce));
-    hipError_t ie = hipGraphInstantiate(&e->gexec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (ie != hipSuccess) return fail(FEMCG_EDEVICE, "graph instantiate: %s", hipGetErrorString(ie));
     e->graph_m = e->m;
     e->graph_grid = grid;
+    e->graph_mask = e->main_mask;
     return FEMCG_OK;
 }
 
@@ -448,8 +491,8 @@ int engine_tick(Engine *e, int *rc_out)
     int rc;
     // 1. transition kernels
     if (!acc.empty()) {
-        int64_t T = fill_table(e, e->h_acc64, acc, false, 1, 0);
-        fill_table(e, e->h_acc32, acc, true, 0, 0);
+        int64_t T = fill_table(e, e->h_acc64, acc, false, 1, 0, nullptr);
+        fill_table(e, e->h_acc32, acc, true, 0, 0, nullptr);
         if ((rc = upload_table(e, e->d_acc64, e->h_acc64)) || (rc = upload_table(e, e->d_acc32, e->h_acc32))) {
             *rc_out = rc;
             return -1;
@@ -457,23 +500,25 @@ int engine_tick(Engine *e, int *rc_out)
         launch_ir_accum(e->d_acc64, e->d_acc32, grid_for(T, 2048), e->stream);
     }
     if (!ri64.empty()) {
-        int64_t T = fill_table(e, e->h_ri64, ri64, false, 0, mixed ? 0 : 1, &ri64_usex);
+        unsigned m;
+        int64_t T = fill_table(e, e->h_ri64, ri64, false, 0, mixed ? 0 : 1, &m, &ri64_usex);
         if ((rc = upload_table(e, e->d_ri64, e->h_ri64))) {
             *rc_out = rc;
             return -1;
         }
-        launch_residual_init<double>(e->d_ri64, grid_for(T, 2048), e->stream);
+        launch_residual_init<double>(e->d_ri64, grid_for(T, 2048), (int)ri64.size(), m, e->stream);
         for (int s : ri64) e->slots[s].outer_residuals++;
     }
     if (!sc.empty()) {
-        int64_t T = fill_table(e, e->h_sc64, sc, false, 0, 0);
-        fill_table(e, e->h_sc32, sc, true, 0, 1);
+        unsigned m;
+        int64_t T = fill_table(e, e->h_sc64, sc, false, 0, 0, nullptr);
+        fill_table(e, e->h_sc32, sc, true, 0, 1, &m);
         if ((rc = upload_table(e, e->d_sc64, e->h_sc64)) || (rc = upload_table(e, e->d_sc32, e->h_sc32))) {
             *rc_out = rc;
             return -1;
         }
         launch_ir_scale(e->d_sc64, e->d_sc32, grid_for(T, 2048), e->stream);
-        launch_residual_init<float>(e->d_sc32, grid_for(T, 2048), e->stream);
+        launch_residual_init<float>(e->d_sc32, grid_for(T, 2048), (int)sc.size(), m, e->stream);
     }
     // 2. iterations of every iterating slot
     std::vector<int> iter_ids;
@@ -485,12 +530,20 @@ int engine_tick(Engine *e, int *rc_out)
             budget = std::min(budget, sl.max_iter - slot_max_iters(sl));
         }
     }
-    if (iter_ids != e->main_ids) e->main_dirty = true;
+    std::stable_sort(iter_ids.begin(), iter_ids.end(),
+                     [&](int a, int b) { return e->slots[a].kp < e->slots[b].kp; });
+    if (iter_ids != e->main_ids) {
+        // a system entering the table starts at parity 0 on the next launch
+        for (int sid : iter_ids)
+            if (std::find(e->main_ids.begin(), e->main_ids.end(), sid) == e->main_ids.end())
+                e->slots[sid].par_off = (int)(e->it_global & 1);
+        e->main_dirty = true;
+    }
     int nrun = 0;
     if (!iter_ids.empty()) {
         int64_t T = 0;
         if (e->main_dirty) {
-            T = fill_table(e, e->h_main, iter_ids, mixed, 0, 0);
+            T = fill_table(e, e->h_main, iter_ids, mixed, 0, 0, &e->main_mask);
             if ((rc = upload_table(e, e->d_main, e->h_main))) {
                 *rc_out = rc;
                 return -1;
@@ -507,16 +560,17 @@ int engine_tick(Engine *e, int *rc_out)
                 *rc_out = rc;
                 return -1;
             }
-            hipError_t le = hipGraphLaunch(e->gexec, e->stream);
+            hipError_t le = hipGraphLaunch(e->gexec[e->it_global & 1], e->stream);
             if (le != hipSuccess) {
                 *rc_out = fail(FEMCG_EDEVICE, "hipGraphLaunch: %s", hipGetErrorString(le));
                 return -1;
             }
             e->replays++;
-        } else if ((rc = launch_iterations(e, nrun, grid))) {
+        } else if ((rc = launch_iterations(e, nrun, grid, e->it_global))) {
             *rc_out = rc;
             return -1;
         }
+        e->it_global += nrun;
     }
     // 3. poll the states
     int hi = 0;
@@ -548,7 +602,7 @@ int engine_tick(Engine *e, int *rc_out)
         };
         if (!mixed) {
             if (sl.ph == S_ITER) {
-                for (int j = 0; j < sl.k; ++j) sl.iters[j] = s64.iters[j];
+                for (int j = 0; j < sl.k; ++j) sl.iters[j] = s64.h_iters[j];
                 sl.kernel_iters = slot_max_iters(sl);
             }
             switch (sl.ph) {
@@ -593,9 +647,9 @@ int engine_tick(Engine *e, int *rc_out)
                 break;
             case S_INNER: {
                 int64_t inner_max = 0;
-                for (int j = 0; j < sl.k; ++j) inner_max = std::max<int64_t>(inner_max, s32.iters[j]);
+                for (int j = 0; j < sl.k; ++j) inner_max = std::max<int64_t>(inner_max, s32.h_iters[j]);
                 if (s32.n_active == 0 || slot_max_iters(sl) + inner_max >= sl.max_iter) {
-                    for (int j = 0; j < sl.k; ++j) sl.iters[j] += s32.iters[j];
+                    for (int j = 0; j < sl.k; ++j) sl.iters[j] += s32.h_iters[j];
                     sl.kernel_iters32 += inner_max;
                     sl.ph = S_ACCUM;
                 }
@@ -762,14 +816,11 @@ int fem_spmv(fem_matrix *A, const double *X, double *Y, int32_t k, void *stream)
     SysState hs0;
     init_state(hs0, k, kp, 1.0, 0.0);
     HIPCHK(hipMemcpyAsync(st, &hs0, sizeof hs0, hipMemcpyHostToDevice, s));
-    SysDesc D = make_desc(A, w, false, w->B64, w->X64, w->R64, w->P64, w->Q64, w->part64, w->gpart64, w->gtk64,
-                          st, k);
+    SysDesc D = make_desc(A, w, false, w->B64, w->X64, w->R64, w->P64, w->Q64, w->part64, st, k);
     D.tile_base = 0;
-    h->nsys = 1;
-    h->total_tiles = D.ntiles;
-    h->d[0] = D;
+    set_single_table(h, D);
     HIPCHK(hipMemcpyAsync(d, h, table_bytes(1), hipMemcpyHostToDevice, s));
-    launch_phase<double>(PH_SPMM, d, grid_for(D.ntiles, A->max_grid), 1, s);
+    launch_phase<double>(PH_SPMM, d, grid_for(D.ntiles, A->max_grid), 0, 1, 1u << class_of(kp), s);
     launch_scatter(w->Q64, A->d_perm, n, k, kp, nullptr, Y, s);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
@@ -1016,28 +1067,25 @@ int fem_tune(fem_matrix *A, int32_t k, int32_t precision, int32_t *C_out, int32_
         HIPCHK(hipMalloc((void **)&st, sizeof(SysState)));
         HIPCHK(hipMemset(st, 0, sizeof(SysState)));
         const bool fp32 = precision == PCG_MIXED;
-        SysDesc D = fp32 ? make_desc(A, w, true, w->B32, w->X32, w->R32, w->P32, w->Q32, w->part32, w->gpart32,
-                                     w->gtk32, st, k)
-                         : make_desc(A, w, false, w->B64, w->X64, w->R64, w->P64, w->Q64, w->part64,
-                                     w->gpart64, w->gtk64, st, k);
+        SysDesc D = fp32 ? make_desc(A, w, true, w->B32, w->X32, w->R32, w->P32, w->Q32, w->part32, st, k)
+                         : make_desc(A, w, false, w->B64, w->X64, w->R64, w->P64, w->Q64, w->part64, st, k);
         D.tile_base = 0;
-        h->nsys = 1;
-        h->total_tiles = D.ntiles;
-        h->d[0] = D;
+        set_single_table(h, D);
         HIPCHK(hipMemcpy(d, h, table_bytes(1), hipMemcpyHostToDevice));
+        const unsigned cm = 1u << class_of(kp);
         const int grid = grid_for(D.ntiles, A->max_grid);
         hipEvent_t a, b;
         HIPCHK(hipEventCreate(&a));
         HIPCHK(hipEventCreate(&b));
         const int reps = 10;
         for (int r = 0; r < 2; ++r) {
-            if (fp32) launch_phase<float>(PH_SPMM, d, grid, 1, s);
-            else launch_phase<double>(PH_SPMM, d, grid, 1, s);
+            if (fp32) launch_phase<float>(PH_SPMM, d, grid, 0, 1, cm, s);
+            else launch_phase<double>(PH_SPMM, d, grid, 0, 1, cm, s);
         }
         HIPCHK(hipEventRecord(a, s));
         for (int r = 0; r < reps; ++r) {
-            if (fp32) launch_phase<float>(PH_SPMM, d, grid, 1, s);
-            else launch_phase<double>(PH_SPMM, d, grid, 1, s);
+            if (fp32) launch_phase<float>(PH_SPMM, d, grid, 0, 1, cm, s);
+            else launch_phase<double>(PH_SPMM, d, grid, 0, 1, cm, s);
         }
         HIPCHK(hipEventRecord(b, s));
         HIPCHK(hipEventSynchronize(b));
@@ -1077,7 +1125,9 @@ int pcg_time_kernel(fem_matrix *A, int32_t kernel, int32_t reps, void *stream, d
     sl.w = w;
     sl.k = A->stats.k;
     sl.kp = kp;
-    fill_table(e, h, std::vector<int>{0}, fp32, 0, 0);
+    std::vector<int> one{0};
+    unsigned cm = 0;
+    fill_table(e, h, one, fp32, 0, 0, &cm);
     HIPCHK(hipMemcpyAsync(e->d_main, h, table_bytes(1), hipMemcpyHostToDevice, s));
     e->main_ids.clear();
     e->main_dirty = true;
@@ -1086,8 +1136,8 @@ int pcg_time_kernel(fem_matrix *A, int32_t kernel, int32_t reps, void *stream, d
     HIPCHK(hipEventCreate(&a));
     HIPCHK(hipEventCreate(&b));
     auto launch = [&]() {
-        if (fp32) launch_phase<float>(kernel, e->d_main, grid, 1, s);
-        else launch_phase<double>(kernel, e->d_main, grid, 1, s);
+        if (fp32) launch_phase<float>(kernel, e->d_main, grid, 0, 1, cm, s);
+        else launch_phase<double>(kernel, e->d_main, grid, 0, 1, cm, s);
     };
     launch();  // warm
     HIPCHK(hipEventRecord(a, s));

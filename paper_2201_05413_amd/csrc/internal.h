@@ -19,28 +19,30 @@ constexpr int kWave = 64;
 constexpr int kMaxK = FEMCG_MAX_K;
 constexpr int kDots = 3;           // dot products a kernel may reduce per column
 constexpr int kNumXcd = 8;         // MI355X: 8 XCDs x 32 CUs, one L2 each
-constexpr int kGroup = 64;         // tiles per first-level reduction group
 
-// Per-system solver scalars, resident on the device.  Every field is written
-// only by the single "last tile" of a phase kernel (or by the host between
-// solves), so reads in the next kernel see one consistent value.
+// Per-system solver state, resident on the device.
+//
+// Loop state is double-buffered by iteration parity: iteration i of a system
+// reads slot prv = (i & 1) ^ 1 and only the designated block (the one running
+// the system's tile 0 of the p-update) writes slot cur = i & 1, so no block
+// ever reads a value another block of the same launch writes.  Fields marked
+// "host" are copies the host polls; kernels never read them inside the loop.
 struct alignas(256) SysState {
-    double rho[kMaxK];      // r.z of the current iterate
-    double alpha[kMaxK];
-    double beta[kMaxK];
+    double rho[2][kMaxK];   // r.z of the iterate, by parity
+    int32_t active[2][kMaxK];
+    int32_t iters[2][kMaxK];
     double bb[kMaxK];       // ||b||^2
-    double rr[kMaxK];       // ||r||^2 of the last residual evaluation
-    double relres[kMaxK];   // sqrt(rr / bb) from the last true residual
     double tol_rel[kMaxK];  // Eq. (2) threshold of each column
     double eta;             // inner systems of iterative refinement: reduction target
     double pad_d;
     int32_t flag[kMaxK];    // 0 normal, 1 disabled (not solved here), FEMCG_EBREAKDOWN
-    int32_t active[kMaxK];  // 1 while the column iterates
-    int32_t iters[kMaxK];   // products A p since the last reset
+    // host-facing copies
+    double rr[kMaxK];       // ||r||^2 of the last residual evaluation
+    double relres[kMaxK];   // sqrt(rr / bb) from the last true residual
+    int32_t h_iters[kMaxK]; // products A p per column
+    int32_t h_active[kMaxK];
     int32_t n_active;       // number of active columns
     int32_t status;         // FEMCG_EBREAKDOWN once any column broke down
-    uint32_t ticket;        // arrival counter of the tiles of the running phase
-    int32_t pad;
 };
 
 // One system as seen by the batched phase kernels.  All pointers are device
@@ -55,6 +57,8 @@ struct SysDesc {
     int32_t ntiles;
     int32_t use_x;          // residual phase: 1 = r = b - A x, 0 = r = b and x = 0
     int32_t write_p;        // residual phase: 1 = also start p = D^-1 r
+    int32_t par_off;        // iteration parity of this system = (launch index + par_off) & 1
+    int32_t pad_i;
     int64_t tile_base;      // first global tile index of this system
     const int32_t *rowptr;  // CSR [n+1]
     const int64_t *slice_ptr; // SELL [n/C+1]: first entry of each slice
@@ -64,18 +68,22 @@ struct SysDesc {
     const void *dinv;       // T, inverse diagonal
     const void *b;          // T [n][kp] right-hand side (internal order)
     void *x, *r, *p, *q;    // T [n][kp]
-    double *part;           // [ntiles][kDots*kp] per-tile partial dots
-    double *gpart;          // [ceil(ntiles/kGroup)][kDots*kp] per-group sums
-    uint32_t *gticket;      // [ceil(ntiles/kGroup)] arrival counters, zero between phases
+    double *part;           // [kDots][ntiles][kp] per-tile partial dots
     SysState *st;
 };
 
 constexpr int kMaxSys = 256;
+constexpr int kNumClass = 7;       // lanes-per-row classes kp = 1, 2, 4, ..., 64
 
+// Systems sorted by kp; class c (kp = 1 << c) owns global tiles
+// [cls_begin[c], cls_end[c]).  Each class is processed by its own kernel
+// instantiation, specialised on kp.
 struct alignas(256) SysTable {
     int32_t nsys;
     int32_t pad;
     int64_t total_tiles;
+    int64_t cls_begin[kNumClass];
+    int64_t cls_end[kNumClass];
     SysDesc d[kMaxSys];
 };
 
@@ -103,10 +111,15 @@ enum Phase { PH_SPMM = 0, PH_UPDATE = 1, PH_PUPDATE = 2 };
 int grid_for(int64_t total_tiles, int max_grid);
 
 // T = double or float.  `tab` is a device SysTable.
+// `it` = launch index of the iteration (its parity drives the state slots);
+// `cls_mask` = bit c set if class c (kp = 1 << c) has systems in the table.
 template <typename T>
-void launch_phase(int phase, const SysTable *tab, int grid, int force, hipStream_t s);
+void launch_phase(int phase, const SysTable *tab, int grid, int it, int force, unsigned cls_mask,
+                  hipStream_t s);
+// residual (r = b - A x or r = b), p = D^-1 r, partial b.b r.r r.z; then the
+// per-system finalize (one block per system) that decides which columns iterate
 template <typename T>
-void launch_residual_init(const SysTable *tab, int grid, hipStream_t s);
+void launch_residual_init(const SysTable *tab, int grid, int nsys, unsigned cls_mask, hipStream_t s);
 void launch_gather(const double *src, int64_t ld_src, const int32_t *perm, int64_t n, int k,
                    int kp, double *dst, hipStream_t s);
 void launch_scatter(const double *src, const int32_t *perm, int64_t n, int k, int kp,

@@ -3,29 +3,41 @@
 // One iteration of Jacobi-preconditioned CG (Sect. 2.1's preconditioned
 // system with M = diag(A); exit test Eq. (2)) is three bandwidth-bound phases:
 //
-//   SpMM      q = A p, partial p.q                  -> alpha = rho / p.q
-//   update    x += alpha p, r -= alpha q, z = D^-1 r, partial r.z, r.r
-//                                                   -> beta, convergence (Eq. 2)
-//   p-update  p = D^-1 r + beta p
+//   SpMM      q = A p                                  partial p.q
+//   update    alpha = rho / p.q;  x += alpha p, r -= alpha q, z = D^-1 r
+//                                                      partial r.z, r.r
+//   p-update  beta = r.z / rho, Eq. (2) test;  p = D^-1 r + beta p
 //
 // Every phase is ONE persistent launch over a device table of systems
 // (SysTable): the global tile space is the concatenation of every system's
-// row tiles, a block walks tiles with an XCD-aware stride (consecutive tiles
-// stay on one XCD, so the banded x gather of neighbouring rows hits that XCD's
-// L2), and the last tile of a system to finish reduces that system's partial
-// dots in a fixed order and writes alpha or beta on the device.  The host
-// never sees a scalar inside the iteration.  Reductions are deterministic and
-// per system: a system's result does not depend on which other systems share
-// the table, nor on the grid size.
+// row tiles, and a block walks tiles with an XCD-aware stride (consecutive
+// tiles stay on one XCD, so the banded gather of neighbouring rows of p hits
+// that XCD's L2).
+//
+// Scalars never go through the host and no block waits for another inside a
+// launch: each tile writes its partial dot products with plain stores, and
+// every block of the NEXT phase reduces all partials of its system at its
+// start, in one fixed order, so all blocks derive bit-identical alpha / beta.
+// Loop state (rho, active columns, iteration counts) is double-buffered by
+// iteration parity and written only by the block that runs tile 0 of the
+// p-update.  Results are deterministic and per system: they do not depend on
+// the grid size nor on which other systems share the table.
 //
 // Vectors are [n][kp] with the kp right-hand sides of a row contiguous; a row
 // is served by kp lanes, so each matrix value and column index is loaded once
-// per wavefront row-group and broadcast to its kp lanes (one value load serves
-// every right-hand side).  No MFMA: the arithmetic intensity is far below the
-// ridge point, the roofline is HBM bandwidth.
+// per row-group and shared by its kp lanes (one value load serves every
+// right-hand side).  No MFMA: the arithmetic intensity is far below the ridge
+// point; the roofline is HBM bandwidth.
 #include "internal.h"
 
 namespace femcg {
+
+enum { DOT0 = 0, DOT1 = 1, DOT2 = 2 };
+
+template <int KP>
+constexpr int kLog2 = KP <= 1 ? 0 : 1 + kLog2<KP / 2>;
+// loop phases: DOT0 = p.q, DOT1 = r.z, DOT2 = r.r
+// residual phase: DOT0 = b.b, DOT1 = r.r, DOT2 = r.z
 
 // ---------------------------------------------------------------------------
 // tile scheduling
@@ -46,9 +58,10 @@ __device__ __forceinline__ int find_sys(const SysTable *__restrict__ tab, int64_
 // Give XCD x the contiguous tile range [x*T/8, (x+1)*T/8) so that rows close in
 // the (banded) matrix are processed on the same L2.
 template <typename F>
-__device__ __forceinline__ void for_each_tile(int64_t T, F &&f)
+__device__ __forceinline__ void for_each_tile_in(int64_t tb, int64_t te, F &&f)
 {
     const int G = gridDim.x, b = blockIdx.x;
+    const int64_t T = te - tb;
     if (G >= kNumXcd && (G % kNumXcd) == 0) {
         const int xcd = b % kNumXcd, loc = b / kNumXcd, per = G / kNumXcd;
         const int64_t TperX = (T + kNumXcd - 1) / kNumXcd;
@@ -56,15 +69,21 @@ __device__ __forceinline__ void for_each_tile(int64_t T, F &&f)
         for (int64_t j = loc; j < TperX; j += per) {
             const int64_t t = base + j;
             if (t >= T) break;
-            f(t);
+            f(tb + t);
         }
     } else {
-        for (int64_t t = b; t < T; t += G) f(t);
+        for (int64_t t = b; t < T; t += G) f(tb + t);
     }
 }
 
+template <typename F>
+__device__ __forceinline__ void for_each_tile(int64_t T, F &&f)
+{
+    for_each_tile_in(0, T, f);
+}
+
 // ---------------------------------------------------------------------------
-// reductions
+// reductions (fixed order everywhere)
 // ---------------------------------------------------------------------------
 
 // Lanes l and l' serve the same column iff l = l' (mod kp); sum them.
@@ -73,273 +92,517 @@ __device__ __forceinline__ double wave_reduce_cols(double v, int kp)
     for (int off = kWave / 2; off >= kp; off >>= 1) v += __shfl_xor(v, off, kWave);
     return v;
 }
-
-// dst[i] = sum_{r < rows} src[r*stride + i] for i < W, fixed order: g lanes
-// per sum (g | 64), lane `sub` takes rows sub, sub+g, ..., then a fixed xor
-// tree over the g lanes.
-__device__ __forceinline__ void block_sum_rows(const double *src, int64_t rows, int stride, int W,
-                                               double *dst)
+template <int KP>
+__device__ __forceinline__ double wave_reduce_cols(double v)
 {
-    int g = kWave;
-    while (g > 1 && g * W > kBlock) g >>= 1;
-    const int i = threadIdx.x / g, sub = threadIdx.x % g;
-    double s = 0.0;
-    if (i < W)
-        for (int64_t r = sub; r < rows; r += g) s += src[r * stride + i];
-    for (int off = g / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, kWave);
-    if (i < W && sub == 0) dst[i] = s;
+#pragma unroll
+    for (int off = kWave / 2; off >= KP; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
 }
 
-// Commit this tile's per-column partial dots v[0..ndots) and, if this is the
-// last tile of its system, reduce every tile of the system into tot[d*kp+j]
-// (shared memory) and return true.  Two levels: groups of kGroup tiles, then
-// the groups; each level is a fixed-order sum, so the result is independent of
-// which block ran which tile.
-__device__ bool commit_and_reduce(const SysDesc &D, int64_t tl, int ndots, double *v, double *tot)
+// Sum the per-thread values v[0..nd) of this block per column and store them
+// as tile tl's partials of dots d0..d0+nd-1.
+template <int KP>
+__device__ void write_tile_partials(const SysDesc &D, int64_t tl, int d0, int nd, const double *v)
 {
-    __shared__ double red[kBlock / kWave][kDots * kMaxK];
-    __shared__ int s_flag;
-    const int kp = D.kp, W = ndots * kp, S = kDots * kp;
+    __shared__ double ws[kBlock / kWave][kDots * kMaxK];
+    constexpr int kp = KP;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    for (int d = 0; d < ndots; ++d) v[d] = wave_reduce_cols(v[d], kp);
-    if (lane < kp)
-        for (int d = 0; d < ndots; ++d) red[wave][d * kp + lane] = v[d];
-    __syncthreads();
-    if (threadIdx.x < W) {
-        const int i = threadIdx.x;
-        D.part[tl * S + i] = ((red[0][i] + red[1][i]) + red[2][i]) + red[3][i];
+    for (int d = 0; d < nd; ++d) {
+        const double s = wave_reduce_cols<KP>(v[d]);
+        if (lane < kp) ws[wave][d * kp + lane] = s;
     }
-    __threadfence();
     __syncthreads();
-    const int64_t g = tl / kGroup;
-    const int64_t ng = (D.ntiles + kGroup - 1) / kGroup;
-    const int gcount = (int)min((int64_t)kGroup, (int64_t)D.ntiles - g * kGroup);
-    if (threadIdx.x == 0) s_flag = (atomicAdd(&D.gticket[g], 1u) + 1u == (unsigned)gcount);
-    __syncthreads();
-    if (!s_flag) return false;
-    __threadfence();
-    if (threadIdx.x == 0) D.gticket[g] = 0u;
-    if (ng == 1) {
-        block_sum_rows(D.part, gcount, S, W, tot);
-        __syncthreads();
-        return true;
+    if (threadIdx.x < nd * kp) {
+        const int i = threadIdx.x, d = d0 + i / kp, j = i % kp;
+        D.part[((int64_t)d * D.ntiles + tl) * kp + j] = ((ws[0][i] + ws[1][i]) + ws[2][i]) + ws[3][i];
     }
-    block_sum_rows(D.part + g * kGroup * S, gcount, S, W, D.gpart + g * S);
-    __threadfence();
     __syncthreads();
-    if (threadIdx.x == 0) s_flag = (atomicAdd(&D.st->ticket, 1u) + 1u == (unsigned)ng);
-    __syncthreads();
-    if (!s_flag) return false;
-    __threadfence();
-    if (threadIdx.x == 0) D.st->ticket = 0u;
-    block_sum_rows(D.gpart, ng, S, W, tot);
-    __syncthreads();
-    return true;
 }
 
-__device__ __forceinline__ void recount_active(SysState *st, int k)
+// out[(d-d0)*kp + j] = sum over the system's tiles of partial dot d, column j.
+// Thread (t0 = tid / kp, j = tid % kp) sums tiles t0, t0 + 256/kp, ... (the
+// loads of a wave are contiguous; the loads of all ND dots are issued together,
+// so the reduction costs one round trip to the partials), then a fixed xor
+// tree and a fixed cross-wave sum.  Called by all threads; the result is in
+// shared memory.
+template <int ND, int KP>
+__device__ void reduce_partials(const SysDesc &D, int d0, double *out)
 {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int n = 0, bad = 0;
-        for (int j = 0; j < k; ++j) {
-            n += st->active[j];
-            bad |= (st->flag[j] == FEMCG_EBREAKDOWN);
-        }
-        st->n_active = n;
-        if (bad) st->status = FEMCG_EBREAKDOWN;
+    __shared__ double ws[kBlock / kWave][kDots * kMaxK];
+    constexpr int kp = KP;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int j = threadIdx.x & (kp - 1);
+    const int t0 = threadIdx.x / kp, ts = kBlock / kp;
+    const int64_t stride = (int64_t)D.ntiles * kp;
+    const double *src = D.part + (int64_t)d0 * stride + j;
+    double s[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) s[d] = 0.0;
+#pragma unroll 4
+    for (int64_t t = t0; t < D.ntiles; t += ts) {
+#pragma unroll
+        for (int d = 0; d < ND; ++d) s[d] += src[d * stride + t * kp];
     }
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        const double r = wave_reduce_cols<KP>(s[d]);
+        if (lane < kp) ws[wave][d * kp + lane] = r;
+    }
+    __syncthreads();
+    if (threadIdx.x < ND * kp) {
+        const int i = threadIdx.x;
+        out[i] = ((ws[0][i] + ws[1][i]) + ws[2][i]) + ws[3][i];
+    }
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
-// sparse row product: sum_e A[row][e] * X[col_e][j]
+// sparse row products: acc[u] = sum_e A[row_u][e] * X[col_e][j] for kU rows
+// at once.  The rows' entry streams are interleaved so that a thread has kU
+// independent index/value loads (then kU gathers) in flight; entries past a
+// row's end are clamped to a valid index and masked to zero, so every load is
+// in bounds and issued without a branch.
 // ---------------------------------------------------------------------------
+constexpr int kU = 4;  // rows per thread in flight
+constexpr int kE = 4;  // entries per row per chunk (one lane per row)
+constexpr int kV = 2;  // rows per sub-chunk (kp lanes per row)
 
 template <typename T>
-__device__ __forceinline__ T row_dot(const SysDesc &D, int64_t row, int j, int kp,
-                                     const T *__restrict__ X)
+__device__ __forceinline__ void rows_dot(const SysDesc &D, const int64_t *row, const T *__restrict__ X, T *acc)
 {
+    constexpr int kp = 1;
+    constexpr int j = 0;
     const T *__restrict__ val = (const T *)D.val;
     const int32_t *__restrict__ col = D.col;
-    T acc0 = 0, acc1 = 0;
+    int64_t base[kU];
+    int len[kU];
+    int64_t stride;
+    int maxlen = 0;
     if (D.format == FEM_FORMAT_SELL) {
         const int sh = D.sell_shift;
-        const int64_t C = (int64_t)1 << sh;
-        const int64_t base = D.slice_ptr[row >> sh] + (row & (C - 1));
-        const int len = D.rowlen[row];
-        int e = 0;
-        for (; e + 1 < len; e += 2) {
-            const int64_t i0 = base + (int64_t)e * C, i1 = i0 + C;
-            const int c0 = col[i0], c1 = col[i1];
-            const T v0 = val[i0], v1 = val[i1];
-            acc0 += v0 * X[(int64_t)c0 * kp + j];
-            acc1 += v1 * X[(int64_t)c1 * kp + j];
-        }
-        if (e < len) {
-            const int64_t i0 = base + (int64_t)e * C;
-            acc0 += val[i0] * X[(int64_t)col[i0] * kp + j];
+        stride = (int64_t)1 << sh;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const bool ok = row[u] < D.n;
+            base[u] = ok ? D.slice_ptr[row[u] >> sh] + (row[u] & (stride - 1)) : 0;
+            len[u] = ok ? D.rowlen[row[u]] : 0;
+            maxlen = max(maxlen, len[u]);
         }
     } else {
-        const int b = D.rowptr[row], end = D.rowptr[row + 1];
-        int t = b;
-        for (; t + 1 < end; t += 2) {
-            const int c0 = col[t], c1 = col[t + 1];
-            const T v0 = val[t], v1 = val[t + 1];
-            acc0 += v0 * X[(int64_t)c0 * kp + j];
-            acc1 += v1 * X[(int64_t)c1 * kp + j];
+        stride = 1;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const bool ok = row[u] < D.n;
+            base[u] = ok ? D.rowptr[row[u]] : 0;
+            len[u] = ok ? D.rowptr[row[u] + 1] - (int)base[u] : 0;
+            maxlen = max(maxlen, len[u]);
         }
-        if (t < end) acc0 += val[t] * X[(int64_t)col[t] * kp + j];
     }
-    return acc0 + acc1;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) acc[u] = 0;
+    // chunks of kE entries per row: kU*kE index and value loads in flight,
+    // then kU*kE gathers
+    for (int e0 = 0; e0 < maxlen; e0 += kE) {
+        int c[kU][kE];
+        T v[kU][kE];
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+#pragma unroll
+            for (int q = 0; q < kE; ++q) {
+                const int e = e0 + q;
+                const int64_t idx = base[u] + (int64_t)(e < len[u] ? e : 0) * stride;
+                const T vv = val[idx];
+                c[u][q] = col[idx];
+                v[u][q] = e < len[u] ? vv : (T)0;
+            }
+        T xg[kU][kE];
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+#pragma unroll
+            for (int q = 0; q < kE; ++q) xg[u][q] = X[(int64_t)c[u][q] * kp + j];
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+#pragma unroll
+            for (int q = 0; q < kE; ++q) acc[u] += v[u][q] * xg[u][q];
+    }
+}
+
+// Same product for kp >= 2 lanes per row: the kp lanes of a row load kp
+// different entries of it at once (one index and one value load per lane
+// instead of one per entry) and broadcast them with in-group shuffles; the
+// entry loop runs to the wave's longest row (masked entries contribute 0).
+template <typename T, int KP, int kQ = 8>
+__device__ __forceinline__ void rows_dot_coop(const SysDesc &D, const int64_t *row, int j,
+                                              const T *__restrict__ X, T *acc)
+{
+    constexpr int kp = KP;
+    const T *__restrict__ val = (const T *)D.val;
+    const int32_t *__restrict__ col = D.col;
+    int64_t base[kU];
+    int len[kU];
+    int64_t stride;
+    int maxlen = 0;
+    if (D.format == FEM_FORMAT_SELL) {
+        const int sh = D.sell_shift;
+        stride = (int64_t)1 << sh;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const bool ok = row[u] < D.n;
+            base[u] = ok ? D.slice_ptr[row[u] >> sh] + (row[u] & (stride - 1)) : 0;
+            len[u] = ok ? D.rowlen[row[u]] : 0;
+            maxlen = max(maxlen, len[u]);
+        }
+    } else {
+        stride = 1;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const bool ok = row[u] < D.n;
+            base[u] = ok ? D.rowptr[row[u]] : 0;
+            len[u] = ok ? D.rowptr[row[u] + 1] - (int)base[u] : 0;
+            maxlen = max(maxlen, len[u]);
+        }
+    }
+    for (int off = kWave / 2; off >= 1; off >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, off, kWave));
+#pragma unroll
+    for (int u = 0; u < kU; ++u) acc[u] = 0;
+    for (int e0 = 0; e0 < maxlen; e0 += kp) {
+        int mc[kU];
+        T mv[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int e = e0 + j;
+            const bool ok = e < len[u];
+            const int64_t idx = base[u] + (int64_t)(ok ? e : 0) * stride;
+            const T vv = val[idx];
+            mc[u] = col[idx];
+            mv[u] = ok ? vv : (T)0;
+        }
+        const int nq = min(kp, maxlen - e0);
+        // sub-chunks of kQ broadcast entries for kV rows at a time: kV*kQ
+        // gathers in flight
+        for (int q0 = 0; q0 < nq; q0 += kQ) {
+#pragma unroll
+            for (int u0 = 0; u0 < kU; u0 += kV) {
+                int c[kV][kQ];
+                T v[kV][kQ];
+#pragma unroll
+                for (int u = 0; u < kV; ++u)
+#pragma unroll
+                    for (int q = 0; q < kQ; ++q) {
+                        const int src = min(q0 + q, kp - 1);
+                        const int cc = __shfl(mc[u0 + u], src, kp);
+                        const T vv = __shfl(mv[u0 + u], src, kp);
+                        c[u][q] = cc;
+                        v[u][q] = q0 + q < nq ? vv : (T)0;
+                    }
+                T x[kV][kQ];
+#pragma unroll
+                for (int u = 0; u < kV; ++u)
+#pragma unroll
+                    for (int q = 0; q < kQ; ++q) x[u][q] = X[(int64_t)c[u][q] * kp + j];
+#pragma unroll
+                for (int u = 0; u < kV; ++u)
+#pragma unroll
+                    for (int q = 0; q < kQ; ++q) acc[u0 + u] += v[u][q] * x[u][q];
+            }
+        }
+    }
+}
+
+// kQ: broadcast entries per gather sub-chunk (kp lanes per row)
+template <typename T, int KP, int kQ = 8>
+__device__ __forceinline__ void rows_product(const SysDesc &D, const int64_t *row, int j,
+                                             const T *__restrict__ X, T *acc)
+{
+    if constexpr (KP == 1) rows_dot<T>(D, row, X, acc);
+    else rows_dot_coop<T, KP, kQ>(D, row, j, X, acc);
 }
 
 // ---------------------------------------------------------------------------
-// phase 1: q = A p, alpha = rho / p.q
+// phase 1: q = A p, partial p.q
 // ---------------------------------------------------------------------------
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_spmm(const SysTable *__restrict__ tab, int force)
+template <typename T, int KP>
+__global__ __launch_bounds__(kBlock) void k_spmm(const SysTable *__restrict__ tab, int it, int force)
 {
-    __shared__ double tot[kDots * kMaxK];
-    for_each_tile(tab->total_tiles, [&](int64_t t) {
-        const SysDesc D = tab->d[find_sys(tab, t)];
-        if (!force && D.st->n_active == 0) return;
-        const int64_t tl = t - D.tile_base;
-        const int kp = D.kp;
+    __shared__ int s_sys, s_any;
+    if (threadIdx.x == 0) s_sys = -1;
+    __syncthreads();
+    for_each_tile_in(tab->cls_begin[kLog2<KP>], tab->cls_end[kLog2<KP>], [&](int64_t t) {
+        const int s = find_sys(tab, t);
+        const SysDesc D = tab->d[s];
+        constexpr int kp = KP;
         const int j = threadIdx.x & (kp - 1);
+        const int64_t tl = t - D.tile_base;
         const int rps = kBlock / kp;
         const int64_t r0 = tl * D.tile_rows, r1 = min(D.n, r0 + D.tile_rows);
         const T *__restrict__ P = (const T *)D.p;
         T *__restrict__ Q = (T *)D.q;
-        double v[kDots] = {0.0, 0.0, 0.0};
-        for (int64_t row = r0 + threadIdx.x / kp; row < r1; row += rps) {
-            const T acc = row_dot<T>(D, row, j, kp, P);
-            const int64_t idx = row * kp + j;
-            Q[idx] = acc;
-            v[0] += (double)P[idx] * (double)acc;
-        }
-        if (commit_and_reduce(D, tl, 1, v, tot)) {
-            SysState *st = D.st;
-            if (threadIdx.x < D.k) {
-                const int c = threadIdx.x;
-                double a = 0.0;
-                if (st->active[c]) {
-                    const double pq = tot[c];
-                    if (!(pq > 0.0) || !isfinite(pq)) {
-                        st->active[c] = 0;
-                        st->flag[c] = FEMCG_EBREAKDOWN;
-                    } else {
-                        a = st->rho[c] / pq;
-                    }
-                }
-                st->alpha[c] = a;
+        const bool fresh = s != s_sys;
+        // the active-column check of a new system overlaps the first batch
+        const int a_in = (fresh && threadIdx.x < D.k) ? D.st->active[((it + D.par_off) & 1) ^ 1][threadIdx.x] : 0;
+        int64_t rb = r0 + threadIdx.x / kp;
+        int64_t row[kU];
+        T acc[kU];
+        auto batch = [&](int64_t b) {
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                row[u] = b + (int64_t)u * rps;
+                if (row[u] >= r1) row[u] = D.n;  // masked
             }
-            recount_active(st, D.k);
+            rows_product<T, KP>(D, row, j, P, acc);
+        };
+        batch(rb);
+        if (fresh) {
+            const int any = __syncthreads_or(a_in);
+            if (threadIdx.x == 0) {
+                s_sys = s;
+                s_any = any;
+            }
+            __syncthreads();
         }
+        if (!force && !s_any) return;
+        double v[1] = {0.0};
+        for (;;) {
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+                if (row[u] < D.n) {
+                    const int64_t idx = row[u] * kp + j;
+                    Q[idx] = acc[u];
+                    v[0] += (double)P[idx] * (double)acc[u];
+                }
+            rb += (int64_t)kU * rps;
+            if (rb >= r1) break;
+            batch(rb);
+        }
+        write_tile_partials<KP>(D, tl, DOT0, 1, v);
     });
 }
 
 // ---------------------------------------------------------------------------
-// phase 2: x += alpha p, r -= alpha q, r.z and r.r, then beta / Eq. (2)
+// phase 2: alpha, x += alpha p, r -= alpha q, partial r.z and r.r
 // ---------------------------------------------------------------------------
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_update(const SysTable *__restrict__ tab, int force)
+template <typename T, int KP>
+__global__ __launch_bounds__(kBlock) void k_update(const SysTable *__restrict__ tab, int it, int force)
 {
-    __shared__ double tot[kDots * kMaxK];
-    for_each_tile(tab->total_tiles, [&](int64_t t) {
-        const SysDesc D = tab->d[find_sys(tab, t)];
-        if (!force && D.st->n_active == 0) return;
-        const int64_t tl = t - D.tile_base;
-        const int kp = D.kp;
+    __shared__ double s_red[kDots * kMaxK];
+    __shared__ double s_alpha[kMaxK];
+    __shared__ int s_act[kMaxK];
+    __shared__ int s_sys, s_any;
+    if (threadIdx.x == 0) s_sys = -1;
+    __syncthreads();
+    for_each_tile_in(tab->cls_begin[kLog2<KP>], tab->cls_end[kLog2<KP>], [&](int64_t t) {
+        const int s = find_sys(tab, t);
+        const SysDesc D = tab->d[s];
+        constexpr int kp = KP;
         const int j = threadIdx.x & (kp - 1);
+        const int64_t tl = t - D.tile_base;
         const int rps = kBlock / kp;
         const int64_t r0 = tl * D.tile_rows, r1 = min(D.n, r0 + D.tile_rows);
-        const bool act = j < D.k && (force || D.st->active[j]);
-        const double a = act ? D.st->alpha[j] : 0.0;
         T *__restrict__ X = (T *)D.x;
         T *__restrict__ R = (T *)D.r;
         const T *__restrict__ P = (const T *)D.p;
         const T *__restrict__ Q = (const T *)D.q;
         const T *__restrict__ dinv = (const T *)D.dinv;
-        double v[kDots] = {0.0, 0.0, 0.0};
-        if (act) {
-            for (int64_t row = r0 + threadIdx.x / kp; row < r1; row += rps) {
-                const int64_t idx = row * kp + j;
-                X[idx] = (T)((double)X[idx] + a * (double)P[idx]);
-                const T r = (T)((double)R[idx] - a * (double)Q[idx]);
-                R[idx] = r;
-                const double rd = (double)r;
-                v[0] += rd * ((double)dinv[row] * rd);
-                v[1] += rd * rd;
+        T xv[kU], pv[kU], rv[kU], qv[kU], dv[kU];
+        int64_t rb = r0 + threadIdx.x / kp;
+        auto load = [&](int64_t b) {
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int64_t row = b + (int64_t)u * rps;
+                if (row < r1) {
+                    const int64_t idx = row * kp + j;
+                    xv[u] = X[idx];
+                    pv[u] = P[idx];
+                    rv[u] = R[idx];
+                    qv[u] = Q[idx];
+                    dv[u] = dinv[row];
+                }
             }
-        }
-        if (commit_and_reduce(D, tl, 2, v, tot)) {
-            SysState *st = D.st;
-            if (threadIdx.x < D.k) {
+        };
+        load(rb);  // in flight while alpha is reduced
+        if (s != s_sys) {
+            reduce_partials<1, KP>(D, DOT0, s_red);
+            const int prv = ((it + D.par_off) & 1) ^ 1;
+            int a = 0;
+            if (threadIdx.x < kp) {
                 const int c = threadIdx.x;
-                if (st->active[c]) {
-                    st->iters[c] += 1;
-                    const double rz = tot[c], rr = tot[kp + c];
-                    st->rr[c] = rr;
-                    const double thr = st->tol_rel[c] * st->tol_rel[c] * st->bb[c];
-                    if (rr <= thr) {
-                        st->active[c] = 0;
-                    } else if (!(rz > 0.0) || !isfinite(rz) || !isfinite(rr)) {
-                        st->active[c] = 0;
-                        st->flag[c] = FEMCG_EBREAKDOWN;
-                    } else {
-                        st->beta[c] = rz / st->rho[c];
-                        st->rho[c] = rz;
+                double al = 0.0;
+                if (c < D.k && (force || D.st->active[prv][c])) {
+                    const double pq = s_red[c];
+                    if (pq > 0.0 && isfinite(pq)) {
+                        al = D.st->rho[prv][c] / pq;
+                        a = 1;
+                    }
+                }
+                s_alpha[c] = al;
+                s_act[c] = a;
+            }
+            const int any = __syncthreads_or(a);
+            if (threadIdx.x == 0) {
+                s_sys = s;
+                s_any = any;
+            }
+            __syncthreads();
+        }
+        if (!s_any) return;
+        const bool act = s_act[j];
+        const double a = s_alpha[j];
+        double v[2] = {0.0, 0.0};
+        for (;;) {
+            if (act) {
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    const int64_t row = rb + (int64_t)u * rps;
+                    if (row < r1) {
+                        const int64_t idx = row * kp + j;
+                        X[idx] = (T)((double)xv[u] + a * (double)pv[u]);
+                        const T r = (T)((double)rv[u] - a * (double)qv[u]);
+                        R[idx] = r;
+                        const double rd = (double)r;
+                        v[0] += rd * ((double)dv[u] * rd);
+                        v[1] += rd * rd;
                     }
                 }
             }
-            recount_active(st, D.k);
+            rb += (int64_t)kU * rps;
+            if (rb >= r1 || !act) break;
+            load(rb);
         }
+        write_tile_partials<KP>(D, tl, DOT1, 2, v);
     });
 }
 
 // ---------------------------------------------------------------------------
-// phase 3: p = D^-1 r + beta p
+// phase 3: beta and the Eq. (2) test; p = D^-1 r + beta p
 // ---------------------------------------------------------------------------
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pupdate(const SysTable *__restrict__ tab, int force)
+template <typename T, int KP>
+__global__ __launch_bounds__(kBlock) void k_pupdate(const SysTable *__restrict__ tab, int it, int force)
 {
-    for_each_tile(tab->total_tiles, [&](int64_t t) {
-        const SysDesc D = tab->d[find_sys(tab, t)];
-        if (!force && D.st->n_active == 0) return;
-        const int64_t tl = t - D.tile_base;
-        const int kp = D.kp;
+    __shared__ double s_red[kDots * kMaxK];
+    __shared__ double s_beta[kMaxK];
+    __shared__ int s_act[kMaxK];
+    __shared__ int s_bad[kMaxK];
+    __shared__ int s_sys, s_any;
+    if (threadIdx.x == 0) s_sys = -1;
+    __syncthreads();
+    for_each_tile_in(tab->cls_begin[kLog2<KP>], tab->cls_end[kLog2<KP>], [&](int64_t t) {
+        const int s = find_sys(tab, t);
+        const SysDesc D = tab->d[s];
+        constexpr int kp = KP;
         const int j = threadIdx.x & (kp - 1);
+        const int64_t tl = t - D.tile_base;
         const int rps = kBlock / kp;
         const int64_t r0 = tl * D.tile_rows, r1 = min(D.n, r0 + D.tile_rows);
-        const bool act = j < D.k && (force || D.st->active[j]);
-        if (!act) return;
-        const double be = D.st->beta[j];
         const T *__restrict__ R = (const T *)D.r;
         T *__restrict__ P = (T *)D.p;
         const T *__restrict__ dinv = (const T *)D.dinv;
-        for (int64_t row = r0 + threadIdx.x / kp; row < r1; row += rps) {
-            const int64_t idx = row * kp + j;
-            P[idx] = (T)((double)dinv[row] * (double)R[idx] + be * (double)P[idx]);
+        T rv[kU], pv[kU], dv[kU];
+        int64_t rb = r0 + threadIdx.x / kp;
+        auto load = [&](int64_t b) {
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int64_t row = b + (int64_t)u * rps;
+                if (row < r1) {
+                    const int64_t idx = row * kp + j;
+                    rv[u] = R[idx];
+                    pv[u] = P[idx];
+                    dv[u] = dinv[row];
+                }
+            }
+        };
+        load(rb);  // in flight while beta is reduced
+        if (s != s_sys) {
+            reduce_partials<3, KP>(D, DOT0, s_red);
+            const int cur = (it + D.par_off) & 1, prv = cur ^ 1;
+            SysState *st = D.st;
+            int na = 0;
+            if (threadIdx.x < kp) {
+                const int c = threadIdx.x;
+                const bool live = c < D.k && (force || st->active[prv][c]);
+                int fl = c < D.k ? st->flag[c] : 1;
+                double be = 0.0, rho = st->rho[prv][c];
+                const double pq = s_red[c], rz = s_red[kp + c], rr = s_red[2 * kp + c];
+                int inc = 0;
+                if (live) {
+                    if (!(pq > 0.0) || !isfinite(pq)) {
+                        fl = FEMCG_EBREAKDOWN;
+                    } else {
+                        inc = 1;
+                        const double thr = st->tol_rel[c] * st->tol_rel[c] * st->bb[c];
+                        if (rr <= thr) {
+                            // Eq. (2) holds: the column stops here
+                        } else if (!(rz > 0.0) || !isfinite(rz) || !isfinite(rr)) {
+                            fl = FEMCG_EBREAKDOWN;
+                        } else {
+                            na = 1;
+                            be = rz / rho;
+                            rho = rz;
+                        }
+                    }
+                }
+                s_beta[c] = be;
+                s_act[c] = na;
+                s_bad[c] = fl == FEMCG_EBREAKDOWN;
+                if (tl == 0) {  // the designated block publishes the state
+                    st->active[cur][c] = na;
+                    if (c < D.k) {
+                        st->rho[cur][c] = rho;
+                        const int itn = st->iters[prv][c] + inc;
+                        st->iters[cur][c] = itn;
+                        st->h_iters[c] = itn;
+                        st->h_active[c] = na;
+                        st->flag[c] = fl;
+                        if (inc) st->rr[c] = rr;
+                    }
+                }
+            }
+            const int nact = __syncthreads_count(na);
+            if (tl == 0 && threadIdx.x == 0) {
+                st->n_active = nact;
+                int bad = 0;
+                for (int c = 0; c < D.k; ++c) bad |= s_bad[c];
+                if (bad) st->status = FEMCG_EBREAKDOWN;
+            }
+            if (threadIdx.x == 0) {
+                s_sys = s;
+                s_any = nact > 0;
+            }
+            __syncthreads();
+        }
+        if (!s_any && !force) return;
+        const bool act = s_act[j] || (force && j < D.k);
+        if (!act) return;
+        const double be = s_beta[j];
+        for (;;) {
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int64_t row = rb + (int64_t)u * rps;
+                if (row < r1) P[row * kp + j] = (T)((double)dv[u] * (double)rv[u] + be * (double)pv[u]);
+            }
+            rb += (int64_t)kU * rps;
+            if (rb >= r1) break;
+            load(rb);
         }
     });
 }
 
 // ---------------------------------------------------------------------------
 // residual / (re)start: r = b - A x (or r = b, x = 0), p = D^-1 r,
-// b.b, r.r, r.z; columns whose Eq. (2) residual exceeds tol become active.
+// partial b.b, r.r, r.z; then one block per system decides which columns
+// iterate (Eq. (2) residual above tol) and seeds the loop state.
 // ---------------------------------------------------------------------------
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_residual_init(const SysTable *__restrict__ tab)
+template <typename T, int KP>
+__global__ __launch_bounds__(kBlock) void k_residual(const SysTable *__restrict__ tab)
 {
-    __shared__ double tot[kDots * kMaxK];
-    for_each_tile(tab->total_tiles, [&](int64_t t) {
+    for_each_tile_in(tab->cls_begin[kLog2<KP>], tab->cls_end[kLog2<KP>], [&](int64_t t) {
         const SysDesc D = tab->d[find_sys(tab, t)];
         const int64_t tl = t - D.tile_base;
-        const int kp = D.kp;
+        constexpr int kp = KP;
         const int j = threadIdx.x & (kp - 1);
         const int rps = kBlock / kp;
         const int64_t r0 = tl * D.tile_rows, r1 = min(D.n, r0 + D.tile_rows);
@@ -349,12 +612,24 @@ __global__ __launch_bounds__(kBlock) void k_residual_init(const SysTable *__rest
         const T *__restrict__ B = (const T *)D.b;
         const T *__restrict__ dinv = (const T *)D.dinv;
         const int use_x = D.use_x, write_p = D.write_p;
-        double v[kDots] = {0.0, 0.0, 0.0};
-        for (int64_t row = r0 + threadIdx.x / kp; row < r1; row += rps) {
+        double v[3] = {0.0, 0.0, 0.0};
+        for (int64_t rb = r0 + threadIdx.x / kp; rb < r1; rb += kU * rps) {
+            int64_t rows[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                rows[u] = rb + (int64_t)u * rps;
+                if (rows[u] >= r1) rows[u] = D.n;
+            }
+            T axv[kU];
+            if (use_x) rows_product<T, KP, 4>(D, rows, j, X, axv);
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+            const int64_t row = rows[u];
+            if (row >= D.n) continue;
             const int64_t idx = row * kp + j;
             const double b = (double)B[idx];
             double ax = 0.0;
-            if (use_x) ax = (double)row_dot<T>(D, row, j, kp, X);
+            if (use_x) ax = (double)axv[u];
             else X[idx] = (T)0;
             const T r = (T)(b - ax);
             R[idx] = r;
@@ -364,32 +639,60 @@ __global__ __launch_bounds__(kBlock) void k_residual_init(const SysTable *__rest
             v[0] += b * b;
             v[1] += rd * rd;
             v[2] += rd * z;
+            }
         }
-        if (commit_and_reduce(D, tl, 3, v, tot)) {
-            SysState *st = D.st;
-            if (threadIdx.x < D.k) {
-                const int c = threadIdx.x;
-                const double bb = tot[c], rr = tot[kp + c], rz = tot[2 * kp + c];
-                st->bb[c] = bb;
-                st->rr[c] = rr;
-                st->relres[c] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
-                int a = 0;
-                if (st->flag[c] == 0 && bb > 0.0) {
-                    const double thr = st->tol_rel[c] * st->tol_rel[c] * bb;
-                    if (!(rr <= thr)) {
-                        if (!(rz > 0.0) || !isfinite(rz) || !isfinite(rr)) {
-                            st->flag[c] = FEMCG_EBREAKDOWN;
-                        } else {
-                            a = 1;
-                            st->rho[c] = rz;
-                        }
+        write_tile_partials<KP>(D, tl, DOT0, 3, v);
+    });
+}
+
+// one block per system
+__global__ __launch_bounds__(kBlock) void k_residual_final(const SysTable *__restrict__ tab)
+{
+    __shared__ double s_red[kDots * kMaxK];
+    if (blockIdx.x >= tab->nsys) return;
+    const SysDesc D = tab->d[blockIdx.x];
+    switch (D.kp) {
+    case 1: reduce_partials<3, 1>(D, DOT0, s_red); break;
+    case 2: reduce_partials<3, 2>(D, DOT0, s_red); break;
+    case 4: reduce_partials<3, 4>(D, DOT0, s_red); break;
+    case 8: reduce_partials<3, 8>(D, DOT0, s_red); break;
+    case 16: reduce_partials<3, 16>(D, DOT0, s_red); break;
+    case 32: reduce_partials<3, 32>(D, DOT0, s_red); break;
+    default: reduce_partials<3, 64>(D, DOT0, s_red); break;
+    }
+    SysState *st = D.st;
+    const int kp = D.kp;
+    int a = 0, bad = 0;
+    if (threadIdx.x < kp) {
+        const int c = threadIdx.x;
+        if (c < D.k) {
+            const double bb = s_red[c], rr = s_red[kp + c], rz = s_red[2 * kp + c];
+            st->bb[c] = bb;
+            st->rr[c] = rr;
+            st->relres[c] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
+            if (st->flag[c] == 0 && bb > 0.0) {
+                const double thr = st->tol_rel[c] * st->tol_rel[c] * bb;
+                if (!(rr <= thr)) {
+                    if (!(rz > 0.0) || !isfinite(rz) || !isfinite(rr)) {
+                        st->flag[c] = FEMCG_EBREAKDOWN;
+                        bad = 1;
+                    } else {
+                        a = 1;
                     }
                 }
-                st->active[c] = a;
             }
-            recount_active(st, D.k);
+            st->rho[1][c] = rz;
+            st->iters[1][c] = st->h_iters[c];
+            st->h_active[c] = a;
         }
-    });
+        st->active[1][c] = a;
+    }
+    const int nact = __syncthreads_count(a);
+    const int nbad = __syncthreads_count(bad);
+    if (threadIdx.x == 0) {
+        st->n_active = nact;
+        if (nbad) st->status = FEMCG_EBREAKDOWN;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -411,7 +714,7 @@ __global__ __launch_bounds__(kBlock) void k_ir_scale(const SysTable *__restrict_
         const int j = threadIdx.x & (kp - 1);
         const int rps = kBlock / kp;
         const int64_t r0 = tl * D.tile_rows, r1 = min(D.n, r0 + D.tile_rows);
-        const bool act = j < D.k && D.st->active[j];
+        const bool act = j < D.k && D.st->h_active[j];
         const double sc = act ? 1.0 / sqrt(D.st->rr[j]) : 0.0;
         const double *__restrict__ R = (const double *)D.r;
         float *__restrict__ Bi = (float *)E.b;
@@ -422,9 +725,9 @@ __global__ __launch_bounds__(kBlock) void k_ir_scale(const SysTable *__restrict_
         if (tl == 0 && threadIdx.x < D.k) {
             const int c = threadIdx.x;
             SysState *si = E.st;
-            const bool a = D.st->active[c];
+            const bool a = D.st->h_active[c];
             si->flag[c] = a ? 0 : 1;
-            si->iters[c] = 0;
+            si->h_iters[c] = 0;
             const double want = 0.5 * D.st->tol_rel[c] * sqrt(D.st->bb[c] / D.st->rr[c]);
             si->tol_rel[c] = a ? fmax(si->eta, want) : 1.0;
         }
@@ -444,7 +747,7 @@ __global__ __launch_bounds__(kBlock) void k_ir_accum(const SysTable *__restrict_
         const int j = threadIdx.x & (kp - 1);
         const int rps = kBlock / kp;
         const int64_t r0 = tl * D.tile_rows, r1 = min(D.n, r0 + D.tile_rows);
-        const bool act = j < D.k && D.st->active[j];
+        const bool act = j < D.k && D.st->h_active[j];
         if (!act) return;
         const double sc = sqrt(D.st->rr[j]);
         double *__restrict__ X = (double *)D.x;
@@ -501,6 +804,13 @@ __global__ void k_lift(const int32_t *__restrict__ rowptr, const int32_t *__rest
     }
 }
 
+static int flat_grid(int64_t total)
+{
+    int64_t g = (total + kBlock - 1) / kBlock;
+    if (g > 4096) g = 4096;
+    return (int)(g < 1 ? 1 : g);
+}
+
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
@@ -512,34 +822,47 @@ int grid_for(int64_t total_tiles, int max_grid)
     return (int)(g < 1 ? 1 : g);
 }
 
-template <typename T>
-void launch_phase(int phase, const SysTable *tab, int grid, int force, hipStream_t s)
+template <typename T, int KP>
+static void launch_phase_kp(int phase, const SysTable *tab, int grid, int it, int force, hipStream_t s)
 {
     if (phase == PH_SPMM)
-        hipLaunchKernelGGL(k_spmm<T>, dim3(grid), dim3(kBlock), 0, s, tab, force);
+        hipLaunchKernelGGL((k_spmm<T, KP>), dim3(grid), dim3(kBlock), 0, s, tab, it, force);
     else if (phase == PH_UPDATE)
-        hipLaunchKernelGGL(k_update<T>, dim3(grid), dim3(kBlock), 0, s, tab, force);
+        hipLaunchKernelGGL((k_update<T, KP>), dim3(grid), dim3(kBlock), 0, s, tab, it, force);
     else
-        hipLaunchKernelGGL(k_pupdate<T>, dim3(grid), dim3(kBlock), 0, s, tab, force);
+        hipLaunchKernelGGL((k_pupdate<T, KP>), dim3(grid), dim3(kBlock), 0, s, tab, it, force);
 }
 
 template <typename T>
-void launch_residual_init(const SysTable *tab, int grid, hipStream_t s)
+void launch_phase(int phase, const SysTable *tab, int grid, int it, int force, unsigned cls_mask,
+                  hipStream_t s)
 {
-    hipLaunchKernelGGL(k_residual_init<T>, dim3(grid), dim3(kBlock), 0, s, tab);
+    if (cls_mask & 1) launch_phase_kp<T, 1>(phase, tab, grid, it, force, s);
+    if (cls_mask & 2) launch_phase_kp<T, 2>(phase, tab, grid, it, force, s);
+    if (cls_mask & 4) launch_phase_kp<T, 4>(phase, tab, grid, it, force, s);
+    if (cls_mask & 8) launch_phase_kp<T, 8>(phase, tab, grid, it, force, s);
+    if (cls_mask & 16) launch_phase_kp<T, 16>(phase, tab, grid, it, force, s);
+    if (cls_mask & 32) launch_phase_kp<T, 32>(phase, tab, grid, it, force, s);
+    if (cls_mask & 64) launch_phase_kp<T, 64>(phase, tab, grid, it, force, s);
 }
 
-template void launch_phase<double>(int, const SysTable *, int, int, hipStream_t);
-template void launch_phase<float>(int, const SysTable *, int, int, hipStream_t);
-template void launch_residual_init<double>(const SysTable *, int, hipStream_t);
-template void launch_residual_init<float>(const SysTable *, int, hipStream_t);
-
-static int flat_grid(int64_t total)
+template <typename T>
+void launch_residual_init(const SysTable *tab, int grid, int nsys, unsigned cls_mask, hipStream_t s)
 {
-    int64_t g = (total + kBlock - 1) / kBlock;
-    if (g > 4096) g = 4096;
-    return (int)(g < 1 ? 1 : g);
+    if (cls_mask & 1) hipLaunchKernelGGL((k_residual<T, 1>), dim3(grid), dim3(kBlock), 0, s, tab);
+    if (cls_mask & 2) hipLaunchKernelGGL((k_residual<T, 2>), dim3(grid), dim3(kBlock), 0, s, tab);
+    if (cls_mask & 4) hipLaunchKernelGGL((k_residual<T, 4>), dim3(grid), dim3(kBlock), 0, s, tab);
+    if (cls_mask & 8) hipLaunchKernelGGL((k_residual<T, 8>), dim3(grid), dim3(kBlock), 0, s, tab);
+    if (cls_mask & 16) hipLaunchKernelGGL((k_residual<T, 16>), dim3(grid), dim3(kBlock), 0, s, tab);
+    if (cls_mask & 32) hipLaunchKernelGGL((k_residual<T, 32>), dim3(grid), dim3(kBlock), 0, s, tab);
+    if (cls_mask & 64) hipLaunchKernelGGL((k_residual<T, 64>), dim3(grid), dim3(kBlock), 0, s, tab);
+    hipLaunchKernelGGL(k_residual_final, dim3(nsys), dim3(kBlock), 0, s, tab);
 }
+
+template void launch_phase<double>(int, const SysTable *, int, int, int, unsigned, hipStream_t);
+template void launch_phase<float>(int, const SysTable *, int, int, int, unsigned, hipStream_t);
+template void launch_residual_init<double>(const SysTable *, int, int, unsigned, hipStream_t);
+template void launch_residual_init<float>(const SysTable *, int, int, unsigned, hipStream_t);
 
 void launch_gather(const double *src, int64_t ld_src, const int32_t *perm, int64_t n, int k, int kp,
                    double *dst, hipStream_t s)
