@@ -173,6 +173,15 @@ int fem_tune(fem_matrix *A, int32_t k, int32_t precision, int32_t *C_out, int32_
  * {8,16,32,64}, sorting window sigma >= 1). */
 int fem_set_format(fem_matrix *A, int32_t format, int32_t C, int32_t sigma);
 
+/* Tiling of the iteration kernels.  band = 0: large tiles, every block of a
+ * phase reduces all tile partials of the previous phase at its start (small
+ * systems); band = 1: small tiles swept by each XCD's blocks as one band of
+ * rows, partial sums folded by the blocks that complete each group of tiles
+ * (large systems); band = -1: automatic (band for vectors above 64 MB).
+ * tile: rows per tile target count (band 0) or bytes of one FP64 vector
+ * slice per tile (band 1); 0 = default.  Drops cached workspaces. */
+int fem_set_tiling(fem_matrix *A, int32_t band, int32_t tile);
+
 /* Time one hot kernel of the iteration on the workspace of the last solve
  * (same launch configuration as inside the solve), `reps` launches bracketed
  * by HIP events on `stream`.  kernel: 0 = SpMM + p.q, 1 = fused update,

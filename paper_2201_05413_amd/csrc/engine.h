@@ -24,10 +24,13 @@ struct Arena {
 struct Work {
     int kp = 0, prec = 0;
     int64_t n = 0;
-    int tile_rows = 0, ntiles = 0;
+    int tile_rows = 0, ntiles = 0, ngroups = 0;
+    int band = 0;
     double *B64 = nullptr, *X64 = nullptr, *R64 = nullptr, *P64 = nullptr, *Q64 = nullptr;
     float *B32 = nullptr, *X32 = nullptr, *R32 = nullptr, *P32 = nullptr, *Q32 = nullptr;
     double *part64 = nullptr, *part32 = nullptr;
+    double *gpart64 = nullptr, *gpart32 = nullptr;
+    uint32_t *gtk64 = nullptr, *gtk32 = nullptr;
     char *mem = nullptr;
     size_t bytes = 0;
     ~Work()
@@ -50,6 +53,8 @@ struct fem_matrix {
     int32_t *d_lrow = nullptr, *d_lcol = nullptr;
     double *d_lval = nullptr;
     int tile_target = 0;  // 0 = automatic
+    int band_mode = -1;   // -1 automatic, 0 / 1 forced
+    int band_tile_bytes = 32768;
     int max_grid = 2048;
     std::map<std::pair<int, int>, std::unique_ptr<femcg::Work>> works;
     std::map<std::pair<int, int>, std::unique_ptr<femcg::Engine>> engines;

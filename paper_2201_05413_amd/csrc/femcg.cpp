@@ -127,16 +127,32 @@ int upload_solver_copy(fem_matrix *A)
     return FEMCG_OK;
 }
 
-static void choose_tiles(const fem_matrix *A, int kp, int &tile_rows, int &ntiles)
+// Tiling of one system.  Small systems: large tiles whose partials every
+// block of the next phase reduces at its start.  Large systems (band mode):
+// small tiles that the blocks of each XCD sweep as one band, so rows that
+// share gathered neighbours are processed close in time on the same L2.
+static void choose_tiles(const fem_matrix *A, int kp, int &tile_rows, int &ntiles, int &band)
 {
     const int64_t n = A->dev.n;
     const int rps = kBlock / kp;
     const int unit = std::max(rps, A->dev.format == FEM_FORMAT_SELL ? A->dev.C : 1);
-    // every block reduces all tile partials of its system at the start of a
-    // phase, so keep ntiles * kp bounded (<= 16K partials per dot)
-    int target = A->tile_target > 0 ? A->tile_target : std::max(256, std::min(1024, 16384 / kp));
-    if (const char *ev = std::getenv("FEMCG_TILE_TARGET")) target = std::max(1, atoi(ev));  // tuning override
-    int64_t rows = (n + target - 1) / target;
+    const double vec_bytes = (double)n * kp * 8.0;
+    // band tiles help mid-size right-hand-side counts; at kp >= 32 the tiles
+    // are so thin that the per-tile overhead outweighs the locality gain
+    band = A->band_mode >= 0 ? A->band_mode : (vec_bytes > 64e6 && kp < 32 ? 1 : 0);
+    if (const char *ev = std::getenv("FEMCG_BAND")) band = atoi(ev);  // tuning override
+    int64_t rows;
+    if (band) {
+        int tb = A->band_tile_bytes;
+        if (const char *ev = std::getenv("FEMCG_BAND_TILE_BYTES")) tb = std::max(1024, atoi(ev));
+        rows = std::max<int64_t>(1, tb / (kp * 8));
+    } else {
+        // every block reduces all tile partials at the start of a phase, so
+        // keep ntiles * kp bounded (<= 16K partials per dot)
+        int target = A->tile_target > 0 ? A->tile_target : std::max(256, std::min(1024, 16384 / kp));
+        if (const char *ev = std::getenv("FEMCG_TILE_TARGET")) target = std::max(1, atoi(ev));  // tuning override
+        rows = (n + target - 1) / target;
+    }
     rows = ((rows + unit - 1) / unit) * unit;
     if (rows < unit) rows = unit;
     if (rows > (1 << 30)) rows = 1 << 30;
@@ -156,9 +172,10 @@ int get_work(fem_matrix *A, int kp, int prec, Work **out)
     w->kp = kp;
     w->prec = prec;
     w->n = A->dev.n;
-    choose_tiles(A, kp, w->tile_rows, w->ntiles);
+    choose_tiles(A, kp, w->tile_rows, w->ntiles, w->band);
+    w->ngroups = (w->ntiles + kGroup - 1) / kGroup;
     const size_t nv = (size_t)std::max<int64_t>(w->n, 1) * kp;
-    const size_t np = (size_t)w->ntiles * kDots * kp;
+    const size_t np = (size_t)w->ntiles * kDots * kp, ngp = (size_t)w->ngroups * kDots * kp;
     Arena ar;
     for (int pass = 0; pass < 2; ++pass) {
         ar.used = 0;
@@ -175,8 +192,12 @@ int get_work(fem_matrix *A, int kp, int prec, Work **out)
             w->P32 = (float *)ar.take(nv * 4);
             w->Q32 = (float *)ar.take(nv * 4);
             w->part32 = (double *)ar.take(np * 8);
+            w->gpart32 = (double *)ar.take(ngp * 8);
+            w->gtk32 = (uint32_t *)ar.take((size_t)w->ngroups * 4);
         }
         w->part64 = (double *)ar.take(np * 8);
+        w->gpart64 = (double *)ar.take(ngp * 8);
+        w->gtk64 = (uint32_t *)ar.take((size_t)w->ngroups * 4);
         if (pass == 0) {
             ar.size = ar.used;
             if (hipMalloc((void **)&ar.base, ar.size) != hipSuccess)
@@ -194,7 +215,7 @@ int get_work(fem_matrix *A, int kp, int prec, Work **out)
 size_t work_bytes_estimate(int64_t n, int kp, int prec, int ntiles)
 {
     const size_t nv = (size_t)std::max<int64_t>(n, 1) * kp;
-    const size_t parts = (size_t)ntiles * kDots * kp * 8;
+    const size_t parts = (size_t)ntiles * kDots * kp * 8 * 2;
     const size_t vec = prec == PCG_FP64 ? nv * 8 * 5 : nv * (8 * 3 + 4 * 5);
     return vec + parts * (prec == PCG_FP64 ? 1 : 2) + 16 * 256;
 }
@@ -206,8 +227,21 @@ size_t matrix_bytes_estimate(const SolverCopy &sc, const HostSystem &hs)
            hs.l_col.size() * 12 + hs.l_rowptr.size() * 4;
 }
 
+static SysDesc make_desc_base(const fem_matrix *A, const Work *w, bool fp32, const void *b, void *x, void *r,
+                              void *p, void *q, double *part, SysState *st, int k);
+
 static SysDesc make_desc(const fem_matrix *A, const Work *w, bool fp32, const void *b, void *x, void *r,
                          void *p, void *q, double *part, SysState *st, int k)
+{
+    SysDesc D = make_desc_base(A, w, fp32, b, x, r, p, q, part, st, k);
+    D.band = w->band;
+    D.gpart = fp32 ? w->gpart32 : w->gpart64;
+    D.gticket = fp32 ? w->gtk32 : w->gtk64;
+    return D;
+}
+
+static SysDesc make_desc_base(const fem_matrix *A, const Work *w, bool fp32, const void *b, void *x, void *r,
+                              void *p, void *q, double *part, SysState *st, int k)
 {
     SysDesc D{};
     const DevSparse &d = A->dev;
@@ -1106,6 +1140,17 @@ int fem_tune(fem_matrix *A, int32_t k, int32_t precision, int32_t *C_out, int32_
     if (C_out) *C_out = bc.C;
     if (sigma_out) *sigma_out = bc.sigma;
     return bc.format;
+}
+
+int fem_set_tiling(fem_matrix *A, int32_t band, int32_t tile)
+{
+    if (!A || band < -1 || band > 1 || tile < 0) return fail(FEMCG_EINVAL, "bad tiling arguments");
+    A->band_mode = band;
+    if (band == 1) A->band_tile_bytes = tile > 0 ? std::max(1024, (int)tile) : 32768;
+    else A->tile_target = tile;
+    A->engines.clear();
+    A->works.clear();
+    return FEMCG_OK;
 }
 
 int pcg_time_kernel(fem_matrix *A, int32_t kernel, int32_t reps, void *stream, double *ms, double *bytes)

@@ -19,6 +19,7 @@ constexpr int kWave = 64;
 constexpr int kMaxK = FEMCG_MAX_K;
 constexpr int kDots = 3;           // dot products a kernel may reduce per column
 constexpr int kNumXcd = 8;         // MI355X: 8 XCDs x 32 CUs, one L2 each
+constexpr int kGroup = 64;         // band mode: tiles per reduction group
 
 // Per-system solver state, resident on the device.
 //
@@ -35,6 +36,9 @@ struct alignas(256) SysState {
     double tol_rel[kMaxK];  // Eq. (2) threshold of each column
     double eta;             // inner systems of iterative refinement: reduction target
     double pad_d;
+    double sums[kDots][kMaxK];  // reduced dots of the last producing phase (band mode)
+    uint32_t ticket;            // band mode: completed reduction groups of the running phase
+    int32_t pad_t;
     int32_t flag[kMaxK];    // 0 normal, 1 disabled (not solved here), FEMCG_EBREAKDOWN
     // host-facing copies
     double rr[kMaxK];       // ||r||^2 of the last residual evaluation
@@ -58,7 +62,9 @@ struct SysDesc {
     int32_t use_x;          // residual phase: 1 = r = b - A x, 0 = r = b and x = 0
     int32_t write_p;        // residual phase: 1 = also start p = D^-1 r
     int32_t par_off;        // iteration parity of this system = (launch index + par_off) & 1
-    int32_t pad_i;
+    int32_t band;           // 0: each block reduces all tile partials at the start of the next
+                            //    phase; 1: small tiles swept as a band per XCD, partials
+                            //    folded by the blocks that complete each group of tiles
     int64_t tile_base;      // first global tile index of this system
     const int32_t *rowptr;  // CSR [n+1]
     const int64_t *slice_ptr; // SELL [n/C+1]: first entry of each slice
@@ -69,6 +75,8 @@ struct SysDesc {
     const void *b;          // T [n][kp] right-hand side (internal order)
     void *x, *r, *p, *q;    // T [n][kp]
     double *part;           // [kDots][ntiles][kp] per-tile partial dots
+    double *gpart;          // band mode: [ngroups][kDots*kp] per-group sums
+    uint32_t *gticket;      // band mode: [ngroups] tiles arrived, zero between phases
     SysState *st;
 };
 

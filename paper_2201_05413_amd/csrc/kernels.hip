@@ -32,6 +32,21 @@
 
 namespace femcg {
 
+// Pointers read from the system table are generic; casting them to the global
+// address space makes the compiler emit global (not flat) memory instructions,
+// whose completion is tracked apart from LDS and scalar memory operations.
+#define GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ GLOBAL T *gptr(T *p)
+{
+    return (GLOBAL T *)p;
+}
+template <typename T>
+__device__ __forceinline__ const GLOBAL T *gptr(const T *p)
+{
+    return (const GLOBAL T *)p;
+}
+
 enum { DOT0 = 0, DOT1 = 1, DOT2 = 2 };
 
 template <int KP>
@@ -100,6 +115,20 @@ __device__ __forceinline__ double wave_reduce_cols(double v)
     return v;
 }
 
+// Agent-coherent accesses (sc1: coherent across the 8 XCD L2s).
+__device__ __forceinline__ void st_agent(GLOBAL double *p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_agent(const GLOBAL double *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void stores_done()
+{
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's memory operations acknowledged
+}
+
 // Sum the per-thread values v[0..nd) of this block per column and store them
 // as tile tl's partials of dots d0..d0+nd-1.
 template <int KP>
@@ -115,7 +144,10 @@ __device__ void write_tile_partials(const SysDesc &D, int64_t tl, int d0, int nd
     __syncthreads();
     if (threadIdx.x < nd * kp) {
         const int i = threadIdx.x, d = d0 + i / kp, j = i % kp;
-        D.part[((int64_t)d * D.ntiles + tl) * kp + j] = ((ws[0][i] + ws[1][i]) + ws[2][i]) + ws[3][i];
+        const double val = ((ws[0][i] + ws[1][i]) + ws[2][i]) + ws[3][i];
+        GLOBAL double *dst = gptr(D.part) + ((int64_t)d * D.ntiles + tl) * kp + j;
+        if (D.band) st_agent(dst, val);
+        else *dst = val;
     }
     __syncthreads();
 }
@@ -135,7 +167,7 @@ __device__ void reduce_partials(const SysDesc &D, int d0, double *out)
     const int j = threadIdx.x & (kp - 1);
     const int t0 = threadIdx.x / kp, ts = kBlock / kp;
     const int64_t stride = (int64_t)D.ntiles * kp;
-    const double *src = D.part + (int64_t)d0 * stride + j;
+    const GLOBAL double *src = gptr(D.part) + (int64_t)d0 * stride + j;
     double s[ND];
 #pragma unroll
     for (int d = 0; d < ND; ++d) s[d] = 0.0;
@@ -158,23 +190,139 @@ __device__ void reduce_partials(const SysDesc &D, int d0, double *out)
 }
 
 // ---------------------------------------------------------------------------
+// band mode: partials folded by the blocks that complete each group of tiles
+//
+// Tile partials are published with agent-coherent stores (sc1: coherent across
+// the XCD L2s), a block waits once for its stores to be acknowledged and then
+// adds its tile counts to the groups it touched; the block whose addition
+// completes a group sums that group's tiles (fixed order) into gpart, and the
+// block completing the last group sums the groups (fixed order) into
+// st->sums.  No block ever waits for another, and per-tile partials keep the
+// result independent of the tile-to-block assignment.
+// ---------------------------------------------------------------------------
+
+constexpr int kMaxRuns = 32;
+
+struct BandLog {
+    int64_t g[kMaxRuns];
+    int cnt[kMaxRuns];
+    int n;
+    int ndone;
+    int64_t done[kMaxRuns];
+    int final_flag;
+};
+
+// dst[i] = sum_{r < rows} src(r, i) for i < W with src(r, i) = base[(i / kp) *
+// dstride + r * rstride + i % kp]; g lanes per sum, fixed order.
+template <int KP>
+__device__ __forceinline__ double band_sum(const GLOBAL double *base, int64_t rows, int64_t rstride,
+                                           int64_t dstride, int W, int i, int sub, int g)
+{
+    double s = 0.0;
+    if (i < W) {
+        const GLOBAL double *src = base + (int64_t)(i / KP) * dstride + (i % KP);
+        for (int64_t r = sub; r < rows; r += g) s += ld_agent(src + r * rstride);
+    }
+    for (int off = g / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, kWave);
+    return s;
+}
+
+// Publish the arrivals logged since the last flush and fold completed groups.
+// Dots d0..d0+ND-1 of system D.  All threads call it.
+template <int ND, int KP>
+__device__ void band_flush(const SysDesc &D, int d0, BandLog &lg)
+{
+    constexpr int W = ND * KP;
+    stores_done();
+    __syncthreads();
+    const int64_t ng = (D.ntiles + kGroup - 1) / kGroup;
+    if (threadIdx.x == 0) {
+        int nd = 0;
+        for (int r = 0; r < lg.n; ++r) {
+            const int64_t g = lg.g[r];
+            const int gcount = (int)min((int64_t)kGroup, (int64_t)D.ntiles - g * kGroup);
+            const unsigned prev = __hip_atomic_fetch_add(&gptr(D.gticket)[g], (unsigned)lg.cnt[r], __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+            if (prev + (unsigned)lg.cnt[r] == (unsigned)gcount) lg.done[nd++] = g;
+        }
+        lg.ndone = nd;
+        lg.n = 0;
+    }
+    __syncthreads();
+    int g_lanes = kWave;
+    while (g_lanes > 1 && g_lanes * W > kBlock) g_lanes >>= 1;
+    const int i = threadIdx.x / g_lanes, sub = threadIdx.x % g_lanes;
+    const int64_t tstride = (int64_t)D.ntiles * KP;  // between dots
+    for (int r = 0; r < lg.ndone; ++r) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const int64_t g = lg.done[r];
+        const int gcount = (int)min((int64_t)kGroup, (int64_t)D.ntiles - g * kGroup);
+        if (threadIdx.x == 0) gptr(D.gticket)[g] = 0u;
+        const double sgrp = band_sum<KP>(gptr(D.part) + (int64_t)d0 * tstride + g * kGroup * KP, gcount, KP, tstride,
+                                         W, i, sub, g_lanes);
+        if (i < W && sub == 0) st_agent(gptr(D.gpart) + g * (kDots * KP) + i, sgrp);
+        stores_done();
+        __syncthreads();
+        if (threadIdx.x == 0)
+            lg.final_flag = (__hip_atomic_fetch_add(&gptr(D.st)->ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
+                             1u) == (unsigned)ng;
+        __syncthreads();
+        if (lg.final_flag) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (threadIdx.x == 0) gptr(D.st)->ticket = 0u;
+            const double tot = band_sum<KP>(gptr(D.gpart), ng, kDots * KP, KP, W, i, sub, g_lanes);
+            if (i < W && sub == 0) gptr(D.st)->sums[d0 + i / KP][i % KP] = tot;
+        }
+        __syncthreads();
+    }
+}
+
+// Log one tile of a band-mode system (after its partials are stored); flushes
+// when the log is full.  All threads call it.
+template <int ND, int KP>
+__device__ __forceinline__ void band_log(const SysDesc &D, int64_t tl, int d0, BandLog &lg)
+{
+    const int64_t g = tl / kGroup;
+    if (threadIdx.x == 0) {
+        if (lg.n > 0 && lg.g[lg.n - 1] == g) {
+            lg.cnt[lg.n - 1]++;
+        } else {
+            lg.g[lg.n] = g;
+            lg.cnt[lg.n] = 1;
+            lg.n++;
+        }
+    }
+    __syncthreads();
+    if (lg.n == kMaxRuns) band_flush<ND, KP>(D, d0, lg);
+}
+
+// ---------------------------------------------------------------------------
 // sparse row products: acc[u] = sum_e A[row_u][e] * X[col_e][j] for kU rows
 // at once.  The rows' entry streams are interleaved so that a thread has kU
 // independent index/value loads (then kU gathers) in flight; entries past a
 // row's end are clamped to a valid index and masked to zero, so every load is
 // in bounds and issued without a branch.
 // ---------------------------------------------------------------------------
-constexpr int kU = 4;  // rows per thread in flight
+#ifndef FEMCG_KU
+#define FEMCG_KU 2
+#endif
+#ifndef FEMCG_KV
+#define FEMCG_KV 2
+#endif
+#ifndef FEMCG_KQ
+#define FEMCG_KQ 4
+#endif
+constexpr int kU = FEMCG_KU;  // rows per thread in flight
 constexpr int kE = 4;  // entries per row per chunk (one lane per row)
-constexpr int kV = 2;  // rows per sub-chunk (kp lanes per row)
+constexpr int kV = FEMCG_KV < FEMCG_KU ? FEMCG_KV : FEMCG_KU;  // rows per sub-chunk (kp lanes per row)
 
 template <typename T>
-__device__ __forceinline__ void rows_dot(const SysDesc &D, const int64_t *row, const T *__restrict__ X, T *acc)
+__device__ __forceinline__ void rows_dot(const SysDesc &D, const int64_t *row, const GLOBAL T *__restrict__ X, T *acc)
 {
     constexpr int kp = 1;
     constexpr int j = 0;
-    const T *__restrict__ val = (const T *)D.val;
-    const int32_t *__restrict__ col = D.col;
+    const GLOBAL GLOBAL T *__restrict__ val = gptr((const T *)D.val);
+    const GLOBAL int32_t *__restrict__ col = gptr(D.col);
     int64_t base[kU];
     int len[kU];
     int64_t stride;
@@ -185,8 +333,8 @@ __device__ __forceinline__ void rows_dot(const SysDesc &D, const int64_t *row, c
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
             const bool ok = row[u] < D.n;
-            base[u] = ok ? D.slice_ptr[row[u] >> sh] + (row[u] & (stride - 1)) : 0;
-            len[u] = ok ? D.rowlen[row[u]] : 0;
+            base[u] = ok ? gptr(D.slice_ptr)[row[u] >> sh] + (row[u] & (stride - 1)) : 0;
+            len[u] = ok ? gptr(D.rowlen)[row[u]] : 0;
             maxlen = max(maxlen, len[u]);
         }
     } else {
@@ -194,8 +342,8 @@ __device__ __forceinline__ void rows_dot(const SysDesc &D, const int64_t *row, c
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
             const bool ok = row[u] < D.n;
-            base[u] = ok ? D.rowptr[row[u]] : 0;
-            len[u] = ok ? D.rowptr[row[u] + 1] - (int)base[u] : 0;
+            base[u] = ok ? gptr(D.rowptr)[row[u]] : 0;
+            len[u] = ok ? gptr(D.rowptr)[row[u] + 1] - (int)base[u] : 0;
             maxlen = max(maxlen, len[u]);
         }
     }
@@ -232,13 +380,13 @@ __device__ __forceinline__ void rows_dot(const SysDesc &D, const int64_t *row, c
 // different entries of it at once (one index and one value load per lane
 // instead of one per entry) and broadcast them with in-group shuffles; the
 // entry loop runs to the wave's longest row (masked entries contribute 0).
-template <typename T, int KP, int kQ = 8>
+template <typename T, int KP, int kQ = FEMCG_KQ>
 __device__ __forceinline__ void rows_dot_coop(const SysDesc &D, const int64_t *row, int j,
-                                              const T *__restrict__ X, T *acc)
+                                              const GLOBAL T *__restrict__ X, T *acc)
 {
     constexpr int kp = KP;
-    const T *__restrict__ val = (const T *)D.val;
-    const int32_t *__restrict__ col = D.col;
+    const GLOBAL GLOBAL T *__restrict__ val = gptr((const T *)D.val);
+    const GLOBAL int32_t *__restrict__ col = gptr(D.col);
     int64_t base[kU];
     int len[kU];
     int64_t stride;
@@ -249,8 +397,8 @@ __device__ __forceinline__ void rows_dot_coop(const SysDesc &D, const int64_t *r
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
             const bool ok = row[u] < D.n;
-            base[u] = ok ? D.slice_ptr[row[u] >> sh] + (row[u] & (stride - 1)) : 0;
-            len[u] = ok ? D.rowlen[row[u]] : 0;
+            base[u] = ok ? gptr(D.slice_ptr)[row[u] >> sh] + (row[u] & (stride - 1)) : 0;
+            len[u] = ok ? gptr(D.rowlen)[row[u]] : 0;
             maxlen = max(maxlen, len[u]);
         }
     } else {
@@ -258,8 +406,8 @@ __device__ __forceinline__ void rows_dot_coop(const SysDesc &D, const int64_t *r
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
             const bool ok = row[u] < D.n;
-            base[u] = ok ? D.rowptr[row[u]] : 0;
-            len[u] = ok ? D.rowptr[row[u] + 1] - (int)base[u] : 0;
+            base[u] = ok ? gptr(D.rowptr)[row[u]] : 0;
+            len[u] = ok ? gptr(D.rowptr)[row[u] + 1] - (int)base[u] : 0;
             maxlen = max(maxlen, len[u]);
         }
     }
@@ -311,9 +459,9 @@ __device__ __forceinline__ void rows_dot_coop(const SysDesc &D, const int64_t *r
 }
 
 // kQ: broadcast entries per gather sub-chunk (kp lanes per row)
-template <typename T, int KP, int kQ = 8>
+template <typename T, int KP, int kQ = FEMCG_KQ>
 __device__ __forceinline__ void rows_product(const SysDesc &D, const int64_t *row, int j,
-                                             const T *__restrict__ X, T *acc)
+                                             const GLOBAL T *__restrict__ X, T *acc)
 {
     if constexpr (KP == 1) rows_dot<T>(D, row, X, acc);
     else rows_dot_coop<T, KP, kQ>(D, row, j, X, acc);
@@ -326,22 +474,35 @@ __device__ __forceinline__ void rows_product(const SysDesc &D, const int64_t *ro
 template <typename T, int KP>
 __global__ __launch_bounds__(kBlock) void k_spmm(const SysTable *__restrict__ tab, int it, int force)
 {
-    __shared__ int s_sys, s_any;
-    if (threadIdx.x == 0) s_sys = -1;
+    __shared__ int s_sys, s_any, s_logsys;
+    __shared__ BandLog lg;
+    if (threadIdx.x == 0) {
+        s_sys = -1;
+        s_logsys = -1;
+        lg.n = 0;
+    }
     __syncthreads();
+    SysDesc Dlog;
     for_each_tile_in(tab->cls_begin[kLog2<KP>], tab->cls_end[kLog2<KP>], [&](int64_t t) {
         const int s = find_sys(tab, t);
         const SysDesc D = tab->d[s];
+        if (s != s_logsys) {
+            if (s_logsys >= 0 && Dlog.band) band_flush<1, KP>(Dlog, DOT0, lg);
+            __syncthreads();
+            if (threadIdx.x == 0) s_logsys = s;
+            __syncthreads();
+            Dlog = D;
+        }
         constexpr int kp = KP;
         const int j = threadIdx.x & (kp - 1);
         const int64_t tl = t - D.tile_base;
         const int rps = kBlock / kp;
         const int64_t r0 = tl * D.tile_rows, r1 = min(D.n, r0 + D.tile_rows);
-        const T *__restrict__ P = (const T *)D.p;
-        T *__restrict__ Q = (T *)D.q;
+        const GLOBAL GLOBAL T *__restrict__ P = gptr((const T *)D.p);
+        GLOBAL T *__restrict__ Q = gptr((T *)D.q);
         const bool fresh = s != s_sys;
         // the active-column check of a new system overlaps the first batch
-        const int a_in = (fresh && threadIdx.x < D.k) ? D.st->active[((it + D.par_off) & 1) ^ 1][threadIdx.x] : 0;
+        const int a_in = (fresh && threadIdx.x < D.k) ? gptr(D.st)->active[((it + D.par_off) & 1) ^ 1][threadIdx.x] : 0;
         int64_t rb = r0 + threadIdx.x / kp;
         int64_t row[kU];
         T acc[kU];
@@ -377,7 +538,9 @@ __global__ __launch_bounds__(kBlock) void k_spmm(const SysTable *__restrict__ ta
             batch(rb);
         }
         write_tile_partials<KP>(D, tl, DOT0, 1, v);
+        if (D.band) band_log<1, KP>(D, tl, DOT0, lg);
     });
+    if (s_logsys >= 0 && Dlog.band) band_flush<1, KP>(Dlog, DOT0, lg);
 }
 
 // ---------------------------------------------------------------------------
@@ -390,22 +553,35 @@ __global__ __launch_bounds__(kBlock) void k_update(const SysTable *__restrict__ 
     __shared__ double s_red[kDots * kMaxK];
     __shared__ double s_alpha[kMaxK];
     __shared__ int s_act[kMaxK];
-    __shared__ int s_sys, s_any;
-    if (threadIdx.x == 0) s_sys = -1;
+    __shared__ int s_sys, s_any, s_logsys;
+    __shared__ BandLog lg;
+    if (threadIdx.x == 0) {
+        s_sys = -1;
+        s_logsys = -1;
+        lg.n = 0;
+    }
     __syncthreads();
+    SysDesc Dlog;
     for_each_tile_in(tab->cls_begin[kLog2<KP>], tab->cls_end[kLog2<KP>], [&](int64_t t) {
         const int s = find_sys(tab, t);
         const SysDesc D = tab->d[s];
+        if (s != s_logsys) {
+            if (s_logsys >= 0 && Dlog.band) band_flush<2, KP>(Dlog, DOT1, lg);
+            __syncthreads();
+            if (threadIdx.x == 0) s_logsys = s;
+            __syncthreads();
+            Dlog = D;
+        }
         constexpr int kp = KP;
         const int j = threadIdx.x & (kp - 1);
         const int64_t tl = t - D.tile_base;
         const int rps = kBlock / kp;
         const int64_t r0 = tl * D.tile_rows, r1 = min(D.n, r0 + D.tile_rows);
-        T *__restrict__ X = (T *)D.x;
-        T *__restrict__ R = (T *)D.r;
-        const T *__restrict__ P = (const T *)D.p;
-        const T *__restrict__ Q = (const T *)D.q;
-        const T *__restrict__ dinv = (const T *)D.dinv;
+        GLOBAL T *__restrict__ X = gptr((T *)D.x);
+        GLOBAL T *__restrict__ R = gptr((T *)D.r);
+        const GLOBAL GLOBAL T *__restrict__ P = gptr((const T *)D.p);
+        const GLOBAL GLOBAL T *__restrict__ Q = gptr((const T *)D.q);
+        const GLOBAL GLOBAL T *__restrict__ dinv = gptr((const T *)D.dinv);
         T xv[kU], pv[kU], rv[kU], qv[kU], dv[kU];
         int64_t rb = r0 + threadIdx.x / kp;
         auto load = [&](int64_t b) {
@@ -424,16 +600,21 @@ __global__ __launch_bounds__(kBlock) void k_update(const SysTable *__restrict__ 
         };
         load(rb);  // in flight while alpha is reduced
         if (s != s_sys) {
-            reduce_partials<1, KP>(D, DOT0, s_red);
+            if (D.band) {
+                if (threadIdx.x < kp) s_red[threadIdx.x] = gptr(D.st)->sums[DOT0][threadIdx.x];
+                __syncthreads();
+            } else {
+                reduce_partials<1, KP>(D, DOT0, s_red);
+            }
             const int prv = ((it + D.par_off) & 1) ^ 1;
             int a = 0;
             if (threadIdx.x < kp) {
                 const int c = threadIdx.x;
                 double al = 0.0;
-                if (c < D.k && (force || D.st->active[prv][c])) {
+                if (c < D.k && (force || gptr(D.st)->active[prv][c])) {
                     const double pq = s_red[c];
                     if (pq > 0.0 && isfinite(pq)) {
-                        al = D.st->rho[prv][c] / pq;
+                        al = gptr(D.st)->rho[prv][c] / pq;
                         a = 1;
                     }
                 }
@@ -472,7 +653,9 @@ __global__ __launch_bounds__(kBlock) void k_update(const SysTable *__restrict__ 
             load(rb);
         }
         write_tile_partials<KP>(D, tl, DOT1, 2, v);
+        if (D.band) band_log<2, KP>(D, tl, DOT1, lg);
     });
+    if (s_logsys >= 0 && Dlog.band) band_flush<2, KP>(Dlog, DOT1, lg);
 }
 
 // ---------------------------------------------------------------------------
@@ -497,9 +680,9 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(const SysTable *__restrict__
         const int64_t tl = t - D.tile_base;
         const int rps = kBlock / kp;
         const int64_t r0 = tl * D.tile_rows, r1 = min(D.n, r0 + D.tile_rows);
-        const T *__restrict__ R = (const T *)D.r;
-        T *__restrict__ P = (T *)D.p;
-        const T *__restrict__ dinv = (const T *)D.dinv;
+        const GLOBAL GLOBAL T *__restrict__ R = gptr((const T *)D.r);
+        GLOBAL T *__restrict__ P = gptr((T *)D.p);
+        const GLOBAL GLOBAL T *__restrict__ dinv = gptr((const T *)D.dinv);
         T rv[kU], pv[kU], dv[kU];
         int64_t rb = r0 + threadIdx.x / kp;
         auto load = [&](int64_t b) {
@@ -516,9 +699,14 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(const SysTable *__restrict__
         };
         load(rb);  // in flight while beta is reduced
         if (s != s_sys) {
-            reduce_partials<3, KP>(D, DOT0, s_red);
+            if (D.band) {
+                if (threadIdx.x < 3 * kp) s_red[threadIdx.x] = gptr(D.st)->sums[threadIdx.x / kp][threadIdx.x % kp];
+                __syncthreads();
+            } else {
+                reduce_partials<3, KP>(D, DOT0, s_red);
+            }
             const int cur = (it + D.par_off) & 1, prv = cur ^ 1;
-            SysState *st = D.st;
+            GLOBAL SysState *st = gptr(D.st);
             int na = 0;
             if (threadIdx.x < kp) {
                 const int c = threadIdx.x;
@@ -599,18 +787,34 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(const SysTable *__restrict__
 template <typename T, int KP>
 __global__ __launch_bounds__(kBlock) void k_residual(const SysTable *__restrict__ tab)
 {
+    __shared__ int s_logsys;
+    __shared__ BandLog lg;
+    if (threadIdx.x == 0) {
+        s_logsys = -1;
+        lg.n = 0;
+    }
+    __syncthreads();
+    SysDesc Dlog;
     for_each_tile_in(tab->cls_begin[kLog2<KP>], tab->cls_end[kLog2<KP>], [&](int64_t t) {
-        const SysDesc D = tab->d[find_sys(tab, t)];
+        const int s = find_sys(tab, t);
+        const SysDesc D = tab->d[s];
+        if (s != s_logsys) {
+            if (s_logsys >= 0 && Dlog.band) band_flush<3, KP>(Dlog, DOT0, lg);
+            __syncthreads();
+            if (threadIdx.x == 0) s_logsys = s;
+            __syncthreads();
+            Dlog = D;
+        }
         const int64_t tl = t - D.tile_base;
         constexpr int kp = KP;
         const int j = threadIdx.x & (kp - 1);
         const int rps = kBlock / kp;
         const int64_t r0 = tl * D.tile_rows, r1 = min(D.n, r0 + D.tile_rows);
-        T *__restrict__ X = (T *)D.x;
-        T *__restrict__ R = (T *)D.r;
-        T *__restrict__ P = (T *)D.p;
-        const T *__restrict__ B = (const T *)D.b;
-        const T *__restrict__ dinv = (const T *)D.dinv;
+        GLOBAL T *__restrict__ X = gptr((T *)D.x);
+        GLOBAL T *__restrict__ R = gptr((T *)D.r);
+        GLOBAL T *__restrict__ P = gptr((T *)D.p);
+        const GLOBAL GLOBAL T *__restrict__ B = gptr((const T *)D.b);
+        const GLOBAL GLOBAL T *__restrict__ dinv = gptr((const T *)D.dinv);
         const int use_x = D.use_x, write_p = D.write_p;
         double v[3] = {0.0, 0.0, 0.0};
         for (int64_t rb = r0 + threadIdx.x / kp; rb < r1; rb += kU * rps) {
@@ -642,7 +846,9 @@ __global__ __launch_bounds__(kBlock) void k_residual(const SysTable *__restrict_
             }
         }
         write_tile_partials<KP>(D, tl, DOT0, 3, v);
+        if (D.band) band_log<3, KP>(D, tl, DOT0, lg);
     });
+    if (s_logsys >= 0 && Dlog.band) band_flush<3, KP>(Dlog, DOT0, lg);
 }
 
 // one block per system
@@ -651,7 +857,10 @@ __global__ __launch_bounds__(kBlock) void k_residual_final(const SysTable *__res
     __shared__ double s_red[kDots * kMaxK];
     if (blockIdx.x >= tab->nsys) return;
     const SysDesc D = tab->d[blockIdx.x];
-    switch (D.kp) {
+    if (D.band) {
+        if (threadIdx.x < 3 * D.kp) s_red[threadIdx.x] = gptr(D.st)->sums[threadIdx.x / D.kp][threadIdx.x % D.kp];
+        __syncthreads();
+    } else switch (D.kp) {
     case 1: reduce_partials<3, 1>(D, DOT0, s_red); break;
     case 2: reduce_partials<3, 2>(D, DOT0, s_red); break;
     case 4: reduce_partials<3, 4>(D, DOT0, s_red); break;
@@ -660,7 +869,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_final(const SysTable *__res
     case 32: reduce_partials<3, 32>(D, DOT0, s_red); break;
     default: reduce_partials<3, 64>(D, DOT0, s_red); break;
     }
-    SysState *st = D.st;
+    GLOBAL SysState *st = gptr(D.st);
     const int kp = D.kp;
     int a = 0, bad = 0;
     if (threadIdx.x < kp) {
@@ -714,21 +923,21 @@ __global__ __launch_bounds__(kBlock) void k_ir_scale(const SysTable *__restrict_
         const int j = threadIdx.x & (kp - 1);
         const int rps = kBlock / kp;
         const int64_t r0 = tl * D.tile_rows, r1 = min(D.n, r0 + D.tile_rows);
-        const bool act = j < D.k && D.st->h_active[j];
-        const double sc = act ? 1.0 / sqrt(D.st->rr[j]) : 0.0;
-        const double *__restrict__ R = (const double *)D.r;
-        float *__restrict__ Bi = (float *)E.b;
+        const bool act = j < D.k && gptr(D.st)->h_active[j];
+        const double sc = act ? 1.0 / sqrt(gptr(D.st)->rr[j]) : 0.0;
+        const GLOBAL GLOBAL double *__restrict__ R = gptr((const double *)D.r);
+        GLOBAL float *__restrict__ Bi = gptr((float *)E.b);
         for (int64_t row = r0 + threadIdx.x / kp; row < r1; row += rps) {
             const int64_t idx = row * kp + j;
             Bi[idx] = act ? (float)(R[idx] * sc) : 0.0f;
         }
         if (tl == 0 && threadIdx.x < D.k) {
             const int c = threadIdx.x;
-            SysState *si = E.st;
-            const bool a = D.st->h_active[c];
+            GLOBAL SysState *si = gptr(E.st);
+            const bool a = gptr(D.st)->h_active[c];
             si->flag[c] = a ? 0 : 1;
             si->h_iters[c] = 0;
-            const double want = 0.5 * D.st->tol_rel[c] * sqrt(D.st->bb[c] / D.st->rr[c]);
+            const double want = 0.5 * gptr(D.st)->tol_rel[c] * sqrt(gptr(D.st)->bb[c] / gptr(D.st)->rr[c]);
             si->tol_rel[c] = a ? fmax(si->eta, want) : 1.0;
         }
     });
@@ -747,11 +956,11 @@ __global__ __launch_bounds__(kBlock) void k_ir_accum(const SysTable *__restrict_
         const int j = threadIdx.x & (kp - 1);
         const int rps = kBlock / kp;
         const int64_t r0 = tl * D.tile_rows, r1 = min(D.n, r0 + D.tile_rows);
-        const bool act = j < D.k && D.st->h_active[j];
+        const bool act = j < D.k && gptr(D.st)->h_active[j];
         if (!act) return;
-        const double sc = sqrt(D.st->rr[j]);
-        double *__restrict__ X = (double *)D.x;
-        const float *__restrict__ Xi = (const float *)E.x;
+        const double sc = sqrt(gptr(D.st)->rr[j]);
+        GLOBAL double *__restrict__ X = gptr((double *)D.x);
+        const GLOBAL float *__restrict__ Xi = gptr((const float *)E.x);
         for (int64_t row = r0 + threadIdx.x / kp; row < r1; row += rps) {
             const int64_t idx = row * kp + j;
             X[idx] += sc * (double)Xi[idx];

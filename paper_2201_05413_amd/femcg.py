@@ -34,7 +34,8 @@ PCG_FP64 = 0
 PCG_MIXED = 1
 
 EXPORTS = ["pcg_default_opts", "fem_assemble", "fem_dofs", "fem_csr", "fem_rhs", "fem_spmv", "pcg_solve",
-           "pcg_solve_batch", "pcg_stats", "fem_tune", "fem_set_format", "pcg_time_kernel", "fem_free",
+           "pcg_solve_batch", "pcg_stats", "fem_tune", "fem_set_format", "fem_set_tiling", "pcg_time_kernel",
+           "fem_free",
            "fem_last_error", "serve_create", "serve_submit", "serve_step", "serve_poll", "serve_clock",
            "serve_destroy"]
 
@@ -104,6 +105,7 @@ def lib():
         "pcg_stats": (C.c_int, [P, C.POINTER(pcg_stats_t)]),
         "fem_tune": (C.c_int, [P, I32, I32, C.POINTER(I32), C.POINTER(I32), P]),
         "fem_set_format": (C.c_int, [P, I32, I32, I32]),
+        "fem_set_tiling": (C.c_int, [P, I32, I32]),
         "pcg_time_kernel": (C.c_int, [P, I32, I32, P, C.POINTER(D), C.POINTER(D)]),
         "fem_free": (None, [P]),
         "fem_last_error": (C.c_char_p, []),
@@ -257,6 +259,10 @@ def pcg_stats(A):
 
 def fem_set_format(A, fmt, Cw=64, sigma=1):
     return _check(lib().fem_set_format(A.h, fmt, Cw, sigma))
+
+
+def fem_set_tiling(A, band=-1, tile=0):
+    return _check(lib().fem_set_tiling(A.h, band, tile))
 
 
 def fem_tune(A, k, precision=PCG_FP64, stream=None):

@@ -198,3 +198,44 @@ def test_format_and_tuner_agree():
     rc3, X3, _ = c.solve(1e-12)
     assert rc == rc2 == rc3 == 0
     assert oracle.x_err(X1, X2) <= 1e-9 and oracle.x_err(X1, X3) <= 1e-9
+
+
+@pytest.mark.parametrize("dim,m,jit,order,k", [(2, 200, 0.3, 1, 1), (3, 30, 0.2, 1, 8), (2, 60, 0.25, 2, 32),
+                                               (3, 12, 0.3, 2, 3)])
+@pytest.mark.parametrize("prec", [femcg.PCG_FP64, femcg.PCG_MIXED])
+def test_band_mode_matches_oracle(dim, m, jit, order, k, prec):
+    # band mode with tiny tiles: 145..343 tiles, i.e. several reduction groups
+    # of 64 tiles and a ragged last group, folded across blocks in each launch
+    c = Case(dim, m, jit, order, k, seed=41, noise=0.01)
+    femcg.fem_set_tiling(c.A, 1, 1024)
+    Xs, _, _, _, st = c.orc.pcg(c.Bo, 1e-14)
+    rc, X, stats = c.solve(1e-12, precision=prec)
+    assert rc == 0, stats
+    assert np.all(c.orc.relres(c.Bo, X) <= 1e-12 * 1.0001)
+    for j in range(c.k):
+        assert oracle.x_err(Xs[:, j], X[:, j]) <= 1e-8
+    # the SpMM alone, band-mode reduction of p.q exercised by fem_spmv
+    rng = np.random.default_rng(5)
+    Xr = rng.standard_normal((c.A.n_free, k))
+    Y = torch.zeros((c.A.n_free, k), dtype=torch.float64, device="cuda")
+    femcg.fem_spmv(c.A, dev(Xr), Y)
+    torch.cuda.synchronize()
+    Yo = c.orc.spmv(Xr)
+    assert np.abs(Y.cpu().numpy() - Yo).max() <= 1e-12 * np.abs(Yo).max()
+
+
+def test_band_and_tile_modes_agree_and_batch_bitwise():
+    cases = [Case(2, 70, 0.3, 1, 2, seed=51), Case(3, 12, 0.2, 1, 4, seed=52)]
+    femcg.fem_set_tiling(cases[0].A, 1, 2048)
+    femcg.fem_set_tiling(cases[1].A, 0, 0)
+    alone = [c.solve(1e-10)[1] for c in cases]
+    Bs = [c.B() for c in cases]
+    Xs = [torch.zeros_like(b) for b in Bs]
+    st = femcg.pcg_solve_batch([c.A for c in cases], Bs, Xs, [1e-10] * 2)
+    torch.cuda.synchronize()
+    assert st == [0, 0]
+    for X, Xa in zip(Xs, alone):
+        assert np.array_equal(X.cpu().numpy(), Xa)
+    femcg.fem_set_tiling(cases[0].A, 0, 0)
+    X0 = cases[0].solve(1e-10)[1]
+    assert oracle.x_err(alone[0], X0) <= 1e-7
