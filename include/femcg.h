@@ -52,6 +52,8 @@ extern "C" {
 #define FEM_FORMAT_CSR 0
 #define FEM_FORMAT_SELL 1        /* SELL-C-sigma, rows sorted by length in windows of sigma */
 #define FEM_FORMAT_AUTO 2        /* chosen by the autotuner (fem_tune) */
+#define FEM_ORDER_SFC 0x10       /* flag for fem_set_format: internal rows in Morton
+                                    (Z-curve) order of the DOF coordinates */
 
 /* Arithmetic of the Krylov iteration. */
 #define PCG_FP64 0               /* FP64 values, vectors and dots */
@@ -164,13 +166,17 @@ int pcg_stats(const fem_matrix *A, pcg_stats_t *out);
 
 /* Autotune the solver copy for k right-hand sides: times SpMM over candidate
  * formats (CSR; SELL with C in {16,32,64}, sigma in {1, 64, 1024}) on the
- * device and keeps the fastest.  Returns the chosen format; C_out and sigma_out
+ * device and keeps the fastest (3D meshes also try the Morton row order).
+ * Returns the chosen format, FEM_ORDER_SFC included; C_out and sigma_out
  * may be NULL. */
 int fem_tune(fem_matrix *A, int32_t k, int32_t precision, int32_t *C_out, int32_t *sigma_out,
              void *stream);
 
 /* Rebuild the solver copy in an explicit format (SELL: slice height C in
- * {8,16,32,64}, sorting window sigma >= 1). */
+ * {8,16,32,64}, sorting window sigma >= 1).  format may carry FEM_ORDER_SFC:
+ * the internal row order then follows a Morton curve through the DOF
+ * coordinates before the sigma sort, so rows processed together share
+ * gathered neighbours (3D grids); the public DOF order is unchanged. */
 int fem_set_format(fem_matrix *A, int32_t format, int32_t C, int32_t sigma);
 
 /* Tiling of the iteration kernels.  band = 0: large tiles, every block of a
@@ -189,6 +195,19 @@ int fem_set_tiling(fem_matrix *A, int32_t band, int32_t tile);
  * one launch. */
 int pcg_time_kernel(fem_matrix *A, int32_t kernel, int32_t reps, void *stream, double *ms,
                     double *bytes);
+
+/* Cold-cache SpMM rate (Sect. 4 SpMV throughput, measured so that no copy is
+ * cache-resident): builds the SpMM launch of each of the nmat matrices for
+ * k right-hand sides in `precision` on its own workspace (p zero-filled),
+ * launches all once, then times `reps` rounds of launching them in turn,
+ * so with copies totalling far more than the 256 MB last-level cache every
+ * launch starts cold.  Host pointers; the matrices stay owned by the caller.
+ * *ms = mean duration of one launch, *bytes = mean algorithmic bytes of one
+ * launch (numerically nonzero entries, values + int32 column indices + row
+ * pointers or slice lengths, p read once and q written once).  Overwrites the
+ * workspace vectors of the matrices (not B or X of any caller). */
+int pcg_time_spmm_cold(int32_t nmat, fem_matrix *const *A, int32_t k, int32_t precision, int32_t reps,
+                       void *stream, double *ms, double *bytes);
 
 void fem_free(fem_matrix *A);
 

@@ -390,13 +390,31 @@ int assemble_host(const fem_mesh *mesh, int order, HostSystem &hs, std::string &
 // Solver copy: drop |a| <= 4 eps max_row|a| (never the diagonal), permute rows
 // symmetrically so that rows sorted by length (within windows of sigma rows)
 // share SELL slices.
+// Morton key of a point: each coordinate quantised to `bits` bits over the
+// bounding box, bits interleaved (x lowest).
+static uint64_t morton_key(const double *x, int dim, const double *lo, const double *inv, int bits)
+{
+    uint64_t q[3] = {0, 0, 0};
+    const uint64_t top = (1ull << bits) - 1;
+    for (int r = 0; r < dim; ++r) {
+        double t = (x[r] - lo[r]) * inv[r];
+        uint64_t v = t <= 0 ? 0 : (uint64_t)(t * (double)top + 0.5);
+        q[r] = v > top ? top : v;
+    }
+    uint64_t key = 0;
+    for (int b = bits - 1; b >= 0; --b)
+        for (int r = dim - 1; r >= 0; --r) key = (key << 1) | ((q[r] >> b) & 1u);
+    return key;
+}
+
 int build_solver_copy(const HostSystem &hs, int format, int C, int sigma, SolverCopy &sc,
-                      std::string &err)
+                      std::string &err, int sfc)
 {
     const int64_t n = hs.nfree;
     sc.n = n;
     sc.format = format;
     sc.C = C;
+    sc.sfc = sfc;
     sc.sigma = std::max(1, sigma);
     // pruned rows in free order
     std::vector<int64_t> rp(n + 1, 0);
@@ -421,9 +439,26 @@ int build_solver_copy(const HostSystem &hs, int format, int C, int sigma, Solver
             err = "non-positive diagonal in A";
             return FEMCG_EMESH;
         }
-    // permutation
+    // permutation: optional Morton order, then the sigma sort
     sc.perm.resize(n);
     for (int64_t i = 0; i < n; ++i) sc.perm[i] = (int32_t)i;
+    if (sfc) {
+        const int dim = hs.dim;
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300}, inv[3];
+        for (int64_t i = 0; i < n; ++i)
+            for (int r = 0; r < dim; ++r) {
+                const double x = hs.dof_coords[hs.free2dof[i] * dim + r];
+                lo[r] = std::min(lo[r], x);
+                hi[r] = std::max(hi[r], x);
+            }
+        for (int r = 0; r < dim; ++r) inv[r] = hi[r] > lo[r] ? 1.0 / (hi[r] - lo[r]) : 0.0;
+        const int bits = dim == 3 ? 21 : 31;
+        std::vector<uint64_t> key(n);
+        parallel_for(n, [&](int64_t i0, int64_t i1) {
+            for (int64_t i = i0; i < i1; ++i) key[i] = morton_key(&hs.dof_coords[hs.free2dof[i] * dim], dim, lo, inv, bits);
+        });
+        std::stable_sort(sc.perm.begin(), sc.perm.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+    }
     if (format == FEM_FORMAT_SELL && sc.sigma > 1) {
         for (int64_t w = 0; w < n; w += sc.sigma) {
             const int64_t e = std::min(n, w + sc.sigma);

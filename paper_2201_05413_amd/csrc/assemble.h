@@ -29,7 +29,7 @@ struct HostSystem {
 
 // Solver copy of A on the host, in internal (permuted) row order.
 struct SolverCopy {
-    int format = FEM_FORMAT_CSR, C = 64, sigma = 1;
+    int format = FEM_FORMAT_CSR, C = 64, sigma = 1, sfc = 0;
     int64_t n = 0, nnz = 0, stored = 0;
     std::vector<int32_t> perm;           // internal row -> free row
     std::vector<double> diag;            // free order
@@ -47,6 +47,6 @@ void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &fn);
 bool element_matrix(int dim, int order, const double *P, double *K);
 int assemble_host(const fem_mesh *mesh, int order, HostSystem &hs, std::string &err);
 int build_solver_copy(const HostSystem &hs, int format, int C, int sigma, SolverCopy &sc,
-                      std::string &err);
+                      std::string &err, int sfc = 0);
 
 }  // namespace femcg

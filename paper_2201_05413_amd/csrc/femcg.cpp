@@ -18,6 +18,7 @@
 #include <cstring>
 #include <cstdlib>
 #include <deque>
+#include <functional>
 #include <mutex>
 
 #include "engine.h"
@@ -137,9 +138,9 @@ static void choose_tiles(const fem_matrix *A, int kp, int &tile_rows, int &ntile
     const int rps = kBlock / kp;
     const int unit = std::max(rps, A->dev.format == FEM_FORMAT_SELL ? A->dev.C : 1);
     const double vec_bytes = (double)n * kp * 8.0;
-    // band tiles help mid-size right-hand-side counts; at kp >= 32 the tiles
-    // are so thin that the per-tile overhead outweighs the locality gain
-    band = A->band_mode >= 0 ? A->band_mode : (vec_bytes > 64e6 && kp < 32 ? 1 : 0);
+    // vectors beyond the last-level cache: thin band tiles keep each XCD's
+    // working window of P compact and let the dispatcher balance tiles
+    band = A->band_mode >= 0 ? A->band_mode : (vec_bytes > 64e6 ? 1 : 0);
     if (const char *ev = std::getenv("FEMCG_BAND")) band = atoi(ev);  // tuning override
     int64_t rows;
     if (band) {
@@ -158,6 +159,15 @@ static void choose_tiles(const fem_matrix *A, int kp, int &tile_rows, int &ntile
     if (rows > (1 << 30)) rows = 1 << 30;
     tile_rows = (int)rows;
     ntiles = (int)((n + rows - 1) / rows);
+}
+
+// Grid cap for a launch over systems of this matrix.  Band tiles carry no
+// per-block reduction prologue, so they run one tile per block at up to four
+// times the resident grid: the hardware dispatcher then balances the uneven
+// gather cost of the tiles, which a static tile split cannot.
+static int grid_cap(const fem_matrix *A, const Work *w)
+{
+    return (w && w->band) ? 4 * A->max_grid : A->max_grid;
 }
 
 int get_work(fem_matrix *A, int kp, int prec, Work **out)
@@ -587,7 +597,9 @@ int engine_tick(Engine *e, int *rc_out)
         } else {
             T = e->h_main->total_tiles;
         }
-        const int grid = e->grid > 0 ? e->grid : grid_for(T, iter_ids.empty() ? 1 : e->slots[iter_ids[0]].A->max_grid);
+        int cap = 1;
+        for (int id : iter_ids) cap = std::max(cap, grid_cap(e->slots[id].A, e->slots[id].w));
+        const int grid = e->grid > 0 ? e->grid : grid_for(T, cap);
         nrun = (int)std::max<int64_t>(1, std::min<int64_t>(budget, e->m));
         if (e->use_graph && nrun == e->m) {
             if ((rc = ensure_graph(e, grid))) {
@@ -774,6 +786,8 @@ int fem_assemble(const fem_mesh *mesh, int32_t order, int32_t format, fem_matrix
     }
     if ((rc = upload_solver_copy(A.get()))) return rc;
     if ((rc = upload_lifting(A.get()))) return rc;
+    if (const char *ev = std::getenv("FEMCG_MAX_GRID"))  // tuning override
+        A->max_grid = std::max(kNumXcd, (atoi(ev) / kNumXcd) * kNumXcd);
     A->setup_s = now_s() - t0;
     A->stats.n = A->hs.nfree;
     A->stats.nnz = (int64_t)A->hs.a_col.size();
@@ -854,7 +868,7 @@ int fem_spmv(fem_matrix *A, const double *X, double *Y, int32_t k, void *stream)
     D.tile_base = 0;
     set_single_table(h, D);
     HIPCHK(hipMemcpyAsync(d, h, table_bytes(1), hipMemcpyHostToDevice, s));
-    launch_phase<double>(PH_SPMM, d, grid_for(D.ntiles, A->max_grid), 0, 1, 1u << class_of(kp), s);
+    launch_phase<double>(PH_SPMM, d, grid_for(D.ntiles, grid_cap(A, w)), 0, 1, 1u << class_of(kp), s);
     launch_scatter(w->Q64, A->d_perm, n, k, kp, nullptr, Y, s);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
@@ -1004,11 +1018,13 @@ int pcg_solve_batch(int32_t nsys, fem_matrix *const *A, const double *const *B, 
     e->stream = s;
     e->grid = A[0]->max_grid;
     int64_t tiles = 0;
+    int cap = 1;
     for (int i = 0; i < nsys; ++i) {
         const int kp = pad_k(k[i]);
         Work *w;
         if ((rc = get_work(A[i], kp, o.precision, &w))) return rc;
         tiles += w->ntiles;
+        cap = std::max(cap, grid_cap(A[i], w));
         Slot &sl = e->slots[i];
         sl = Slot{};
         sl.A = A[i];
@@ -1026,7 +1042,7 @@ int pcg_solve_batch(int32_t nsys, fem_matrix *const *A, const double *const *B, 
         if (sl.use_x0) launch_gather(X[i], k[i], A[i]->d_perm, n, k[i], kp, w->X64, s);
         if ((rc = engine_admit(e.get(), i))) return rc;
     }
-    e->grid = grid_for(tiles, A[0]->max_grid);
+    e->grid = grid_for(tiles, cap);
     int pending = nsys;
     while (pending > 0) {
         pending = engine_tick(e.get(), &rc);
@@ -1054,15 +1070,79 @@ int pcg_stats(const fem_matrix *A, pcg_stats_t *out)
     return FEMCG_OK;
 }
 
-int fem_set_format(fem_matrix *A, int32_t format, int32_t C, int32_t sigma)
+int fem_set_format(fem_matrix *A, int32_t format_flags, int32_t C, int32_t sigma)
 {
     if (!A) return fail(FEMCG_EINVAL, "NULL matrix");
+    const int sfc = (format_flags & FEM_ORDER_SFC) ? 1 : 0;
+    const int format = format_flags & ~FEM_ORDER_SFC;
     if (format != FEM_FORMAT_CSR && format != FEM_FORMAT_SELL) return fail(FEMCG_EUNSUPPORTED, "format %d", format);
     if (format == FEM_FORMAT_SELL && (C < 1 || C > 64 || (C & (C - 1)))) return fail(FEMCG_EINVAL, "C=%d", C);
     std::string err;
-    int rc = build_solver_copy(A->hs, format, format == FEM_FORMAT_SELL ? C : 64, std::max(1, sigma), A->sc, err);
+    int rc = build_solver_copy(A->hs, format, format == FEM_FORMAT_SELL ? C : 64, std::max(1, sigma), A->sc, err, sfc);
     if (rc) return fail(rc, "%s", err.c_str());
     return upload_solver_copy(A);
+}
+
+// One SpMM launch on a matrix's own workspace, p zero-filled (values do not
+// change the memory traffic), every tile forced: the timing probe of the
+// autotuner and of the cold-cache measurement.
+struct SpmmProbe {
+    SysTable *h = nullptr, *d = nullptr;
+    SysState *st = nullptr;
+    int grid = 1;
+    unsigned cm = 0;
+    bool fp32 = false;
+    int init(fem_matrix *A, int k, int precision, hipStream_t s)
+    {
+        const int kp = pad_k(k);
+        Work *w;
+        int rc = get_work(A, kp, precision, &w);
+        if (rc) return rc;
+        fp32 = precision == PCG_MIXED;
+        void *P = fp32 ? (void *)w->P32 : (void *)w->P64;
+        HIPCHK(hipMemsetAsync(P, 0, (size_t)A->dev.n * kp * (fp32 ? 4 : 8), s));
+        HIPCHK(hipHostMalloc((void **)&h, table_bytes(1), hipHostMallocDefault));
+        HIPCHK(hipMalloc((void **)&d, table_bytes(1)));
+        HIPCHK(hipMalloc((void **)&st, sizeof(SysState)));
+        HIPCHK(hipMemsetAsync(st, 0, sizeof(SysState), s));
+        SysDesc D = fp32 ? make_desc(A, w, true, w->B32, w->X32, w->R32, w->P32, w->Q32, w->part32, st, k)
+                         : make_desc(A, w, false, w->B64, w->X64, w->R64, w->P64, w->Q64, w->part64, st, k);
+        D.tile_base = 0;
+        set_single_table(h, D);
+        HIPCHK(hipMemcpyAsync(d, h, table_bytes(1), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+        cm = 1u << class_of(kp);
+        grid = grid_for(D.ntiles, grid_cap(A, w));
+        return FEMCG_OK;
+    }
+    void launch(hipStream_t s) const
+    {
+        if (fp32) launch_phase<float>(PH_SPMM, d, grid, 0, 1, cm, s);
+        else launch_phase<double>(PH_SPMM, d, grid, 0, 1, cm, s);
+    }
+    ~SpmmProbe()
+    {
+        if (h) (void)hipHostFree(h);
+        if (d) (void)hipFree(d);
+        if (st) (void)hipFree(st);
+    }
+};
+
+// Total time of `reps` calls of fn, bracketed by events on stream s.
+static int time_launches(hipStream_t s, int reps, const std::function<void()> &fn, float *ms)
+{
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    HIPCHK(hipEventRecord(a, s));
+    for (int r = 0; r < reps; ++r) fn();
+    HIPCHK(hipEventRecord(b, s));
+    HIPCHK(hipEventSynchronize(b));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventElapsedTime(ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return FEMCG_OK;
 }
 
 // Autotuner: time the SpMM phase for each candidate layout on a synthetic p
@@ -1078,58 +1158,24 @@ int fem_tune(fem_matrix *A, int32_t k, int32_t precision, int32_t *C_out, int32_
     std::vector<Cand> cands = {{FEM_FORMAT_CSR, 64, 1}};
     for (int Cw : {16, 32, 64})
         for (int sg : {1, 64, 1024}) cands.push_back({FEM_FORMAT_SELL, Cw, sg});
+    // 3D: the natural order puts face neighbours a whole plane of rows away;
+    // a Morton order keeps them near in index (and in cache)
+    if (A->hs.dim == 3) {
+        cands.push_back({FEM_FORMAT_CSR | FEM_ORDER_SFC, 64, 1});
+        for (int Cw : {16, 32, 64}) cands.push_back({FEM_FORMAT_SELL | FEM_ORDER_SFC, Cw, 1});
+    }
     const int kp = pad_k(k);
     double best = 1e30;
     Cand bc = cands[0];
     for (const Cand &c : cands) {
         int rc = fem_set_format(A, c.format, c.C, c.sigma);
         if (rc) return rc;
-        Work *w;
-        if ((rc = get_work(A, kp, precision, &w))) return rc;
-        // p = 1 in every used lane (values do not change the memory traffic)
-        std::vector<double> ones64((size_t)A->dev.n * kp, 1.0);
-        std::vector<float> ones32(precision == PCG_MIXED ? ones64.size() : 0, 1.0f);
-        void *P = precision == PCG_FP64 ? (void *)w->P64 : (void *)w->P32;
-        if (precision == PCG_FP64)
-            HIPCHK(hipMemcpy(P, ones64.data(), ones64.size() * 8, hipMemcpyHostToDevice));
-        else
-            HIPCHK(hipMemcpy(P, ones32.data(), ones32.size() * 4, hipMemcpyHostToDevice));
-        SysTable *h = nullptr, *d = nullptr;
-        SysState *st = nullptr;
-        HIPCHK(hipHostMalloc((void **)&h, table_bytes(1), hipHostMallocDefault));
-        HIPCHK(hipMalloc((void **)&d, table_bytes(1)));
-        HIPCHK(hipMalloc((void **)&st, sizeof(SysState)));
-        HIPCHK(hipMemset(st, 0, sizeof(SysState)));
-        const bool fp32 = precision == PCG_MIXED;
-        SysDesc D = fp32 ? make_desc(A, w, true, w->B32, w->X32, w->R32, w->P32, w->Q32, w->part32, st, k)
-                         : make_desc(A, w, false, w->B64, w->X64, w->R64, w->P64, w->Q64, w->part64, st, k);
-        D.tile_base = 0;
-        set_single_table(h, D);
-        HIPCHK(hipMemcpy(d, h, table_bytes(1), hipMemcpyHostToDevice));
-        const unsigned cm = 1u << class_of(kp);
-        const int grid = grid_for(D.ntiles, A->max_grid);
-        hipEvent_t a, b;
-        HIPCHK(hipEventCreate(&a));
-        HIPCHK(hipEventCreate(&b));
-        const int reps = 10;
-        for (int r = 0; r < 2; ++r) {
-            if (fp32) launch_phase<float>(PH_SPMM, d, grid, 0, 1, cm, s);
-            else launch_phase<double>(PH_SPMM, d, grid, 0, 1, cm, s);
-        }
-        HIPCHK(hipEventRecord(a, s));
-        for (int r = 0; r < reps; ++r) {
-            if (fp32) launch_phase<float>(PH_SPMM, d, grid, 0, 1, cm, s);
-            else launch_phase<double>(PH_SPMM, d, grid, 0, 1, cm, s);
-        }
-        HIPCHK(hipEventRecord(b, s));
-        HIPCHK(hipEventSynchronize(b));
+        SpmmProbe pr;
+        if ((rc = pr.init(A, k, precision, s))) return rc;
+        pr.launch(s);
+        pr.launch(s);
         float t = 0;
-        HIPCHK(hipEventElapsedTime(&t, a, b));
-        (void)hipEventDestroy(a);
-        (void)hipEventDestroy(b);
-        (void)hipHostFree(h);
-        (void)hipFree(d);
-        (void)hipFree(st);
+        if ((rc = time_launches(s, 10, [&]() { pr.launch(s); }, &t))) return rc;
         if (t < best) {
             best = t;
             bc = c;
@@ -1176,7 +1222,7 @@ int pcg_time_kernel(fem_matrix *A, int32_t kernel, int32_t reps, void *stream, d
     HIPCHK(hipMemcpyAsync(e->d_main, h, table_bytes(1), hipMemcpyHostToDevice, s));
     e->main_ids.clear();
     e->main_dirty = true;
-    const int grid = grid_for(h->total_tiles, A->max_grid);
+    const int grid = grid_for(h->total_tiles, grid_cap(A, w));
     hipEvent_t a, b;
     HIPCHK(hipEventCreate(&a));
     HIPCHK(hipEventCreate(&b));
@@ -1201,6 +1247,36 @@ int pcg_time_kernel(fem_matrix *A, int32_t kernel, int32_t reps, void *stream, d
         else if (kernel == PH_UPDATE) *bytes = 6.0 * n * k * sv + n * sv;
         else *bytes = 3.0 * n * k * sv + n * sv;
     }
+    return FEMCG_OK;
+}
+
+int pcg_time_spmm_cold(int32_t nmat, fem_matrix *const *A, int32_t k, int32_t precision, int32_t reps,
+                       void *stream, double *ms, double *bytes)
+{
+    if (nmat < 1 || !A || !ms || k < 1 || k > kMaxK || reps < 1) return fail(FEMCG_EINVAL, "bad arguments");
+    if (precision != PCG_FP64 && precision != PCG_MIXED) return fail(FEMCG_EINVAL, "bad precision");
+    for (int i = 0; i < nmat; ++i)
+        if (!A[i]) return fail(FEMCG_EINVAL, "NULL matrix %d", i);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<std::unique_ptr<SpmmProbe>> pr(nmat);
+    int rc;
+    double by = 0.0;
+    const double sv = precision == PCG_MIXED ? 4.0 : 8.0;
+    for (int i = 0; i < nmat; ++i) {
+        pr[i].reset(new SpmmProbe);
+        if ((rc = pr[i]->init(A[i], k, precision, s))) return rc;
+        const double n = (double)A[i]->sc.n, nnz = (double)A[i]->sc.nnz;
+        const double idx = A[i]->sc.format == FEM_FORMAT_SELL ? 4.0 * n : 4.0 * (n + 1);
+        by += nnz * (sv + 4.0) + idx + 2.0 * n * k * sv;
+    }
+    for (int i = 0; i < nmat; ++i) pr[i]->launch(s);  // warm: leaves only the last copies cached
+    float t = 0;
+    if ((rc = time_launches(s, reps, [&]() {
+             for (int i = 0; i < nmat; ++i) pr[i]->launch(s);
+         }, &t)))
+        return rc;
+    *ms = t / ((double)reps * nmat);
+    if (bytes) *bytes = by / nmat;
     return FEMCG_OK;
 }
 

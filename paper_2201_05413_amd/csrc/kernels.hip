@@ -458,12 +458,94 @@ __device__ __forceinline__ void rows_dot_coop(const SysDesc &D, const int64_t *r
     }
 }
 
+// Same product with the broadcast through LDS: the kp lanes of a row store
+// kp entries of it into a per-wave LDS area, then every lane reads entry q of
+// its row with a broadcast LDS read.  The reads do not depend on other lanes'
+// registers, so a whole sub-chunk of reads and gathers issues before any wait.
+#ifndef FEMCG_LDS_BCAST
+#define FEMCG_LDS_BCAST 1
+#endif
+template <typename T, int KP, int kQ>
+__device__ __forceinline__ void rows_dot_lds(const SysDesc &D, const int64_t *row, int j,
+                                             const GLOBAL T *__restrict__ X, T *acc)
+{
+    constexpr int kp = KP;
+    __shared__ int s_c[kBlock / kWave][kU][kWave];
+    __shared__ T s_v[kBlock / kWave][kU][kWave];
+    const GLOBAL T *__restrict__ val = gptr((const T *)D.val);
+    const GLOBAL int32_t *__restrict__ col = gptr(D.col);
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int gb = lane - j;  // first lane of this row's group
+    int64_t base[kU];
+    int len[kU];
+    int64_t stride;
+    int maxlen = 0;
+    if (D.format == FEM_FORMAT_SELL) {
+        const int sh = D.sell_shift;
+        stride = (int64_t)1 << sh;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const bool ok = row[u] < D.n;
+            base[u] = ok ? gptr(D.slice_ptr)[row[u] >> sh] + (row[u] & (stride - 1)) : 0;
+            len[u] = ok ? gptr(D.rowlen)[row[u]] : 0;
+            maxlen = max(maxlen, len[u]);
+        }
+    } else {
+        stride = 1;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const bool ok = row[u] < D.n;
+            base[u] = ok ? gptr(D.rowptr)[row[u]] : 0;
+            len[u] = ok ? gptr(D.rowptr)[row[u] + 1] - (int)base[u] : 0;
+            maxlen = max(maxlen, len[u]);
+        }
+    }
+    for (int off = kWave / 2; off >= 1; off >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, off, kWave));
+#pragma unroll
+    for (int u = 0; u < kU; ++u) acc[u] = 0;
+    for (int e0 = 0; e0 < maxlen; e0 += kp) {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int e = e0 + j;
+            const bool ok = e < len[u];
+            const int64_t idx = base[u] + (int64_t)(ok ? e : 0) * stride;
+            const T vv = val[idx];
+            s_c[wave][u][lane] = col[idx];
+            s_v[wave][u][lane] = ok ? vv : (T)0;
+        }
+        const int nq = min(kp, maxlen - e0);
+        for (int q0 = 0; q0 < nq; q0 += kQ) {
+            int c[kU][kQ];
+            T v[kU][kQ];
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+#pragma unroll
+                for (int q = 0; q < kQ; ++q) {
+                    const int src = gb + min(q0 + q, kp - 1);
+                    c[u][q] = s_c[wave][u][src];
+                    const T vv = s_v[wave][u][src];
+                    v[u][q] = q0 + q < nq ? vv : (T)0;
+                }
+            T x[kU][kQ];
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+#pragma unroll
+                for (int q = 0; q < kQ; ++q) x[u][q] = X[(int64_t)c[u][q] * kp + j];
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+#pragma unroll
+                for (int q = 0; q < kQ; ++q) acc[u] += v[u][q] * x[u][q];
+        }
+    }
+}
+
 // kQ: broadcast entries per gather sub-chunk (kp lanes per row)
 template <typename T, int KP, int kQ = FEMCG_KQ>
 __device__ __forceinline__ void rows_product(const SysDesc &D, const int64_t *row, int j,
                                              const GLOBAL T *__restrict__ X, T *acc)
 {
     if constexpr (KP == 1) rows_dot<T>(D, row, X, acc);
+    else if constexpr (FEMCG_LDS_BCAST) rows_dot_lds<T, KP, kQ>(D, row, j, X, acc);
     else rows_dot_coop<T, KP, kQ>(D, row, j, X, acc);
 }
 

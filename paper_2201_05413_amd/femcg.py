@@ -30,11 +30,12 @@ FEMCG_MAX_K = 64
 FEM_FORMAT_CSR = 0
 FEM_FORMAT_SELL = 1
 FEM_FORMAT_AUTO = 2
+FEM_ORDER_SFC = 0x10
 PCG_FP64 = 0
 PCG_MIXED = 1
 
 EXPORTS = ["pcg_default_opts", "fem_assemble", "fem_dofs", "fem_csr", "fem_rhs", "fem_spmv", "pcg_solve",
-           "pcg_solve_batch", "pcg_stats", "fem_tune", "fem_set_format", "fem_set_tiling", "pcg_time_kernel",
+           "pcg_solve_batch", "pcg_stats", "fem_tune", "fem_set_format", "fem_set_tiling", "pcg_time_kernel", "pcg_time_spmm_cold",
            "fem_free",
            "fem_last_error", "serve_create", "serve_submit", "serve_step", "serve_poll", "serve_clock",
            "serve_destroy"]
@@ -107,6 +108,7 @@ def lib():
         "fem_set_format": (C.c_int, [P, I32, I32, I32]),
         "fem_set_tiling": (C.c_int, [P, I32, I32]),
         "pcg_time_kernel": (C.c_int, [P, I32, I32, P, C.POINTER(D), C.POINTER(D)]),
+        "pcg_time_spmm_cold": (C.c_int, [I32, P, I32, I32, I32, P, C.POINTER(D), C.POINTER(D)]),
         "fem_free": (None, [P]),
         "fem_last_error": (C.c_char_p, []),
         "serve_create": (C.c_int, [D, I32, I32, I32, C.POINTER(P)]),
@@ -182,11 +184,14 @@ class Matrix:
         _check(lib().fem_dofs(h, C.byref(n_all), C.byref(n_free), None, None, None))
         self.n_all, self.n_free = n_all.value, n_free.value
 
-    def __del__(self):
+    def free(self):
         h = getattr(self, "h", None)
         if h and _lib is not None:
             _lib.fem_free(h)
-            self.h = None
+        self.h = None
+
+    def __del__(self):
+        self.free()
 
     def dofs(self):
         coords = np.zeros((self.n_all, self.dim))
@@ -269,6 +274,14 @@ def fem_tune(A, k, precision=PCG_FP64, stream=None):
     cw, sg = C.c_int32(), C.c_int32()
     f = _check(lib().fem_tune(A.h, k, precision, C.byref(cw), C.byref(sg), _stream(stream)))
     return f, cw.value, sg.value
+
+
+def pcg_time_spmm_cold(mats, k, precision=PCG_FP64, reps=5, stream=None):
+    arr = (C.c_void_p * len(mats))(*[m.h for m in mats])
+    ms, by = C.c_double(), C.c_double()
+    _check(lib().pcg_time_spmm_cold(len(mats), arr, k, precision, reps, _stream(stream), C.byref(ms),
+                                    C.byref(by)))
+    return ms.value, by.value
 
 
 def pcg_time_kernel(A, kernel, reps=20, stream=None):

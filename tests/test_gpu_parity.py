@@ -239,3 +239,47 @@ def test_band_and_tile_modes_agree_and_batch_bitwise():
     femcg.fem_set_tiling(cases[0].A, 0, 0)
     X0 = cases[0].solve(1e-10)[1]
     assert oracle.x_err(alone[0], X0) <= 1e-7
+
+
+@pytest.mark.parametrize("dim,m,jit,order,k,fmt,cw", [
+    (3, 21, 0.3, 1, 8, femcg.FEM_FORMAT_CSR, 64), (3, 9, 0.2, 2, 3, femcg.FEM_FORMAT_SELL, 32),
+    (2, 45, 0.25, 1, 1, femcg.FEM_FORMAT_SELL, 16), (3, 17, 0.0, 1, 32, femcg.FEM_FORMAT_SELL, 64)])
+def test_morton_order_matches_oracle(dim, m, jit, order, k, fmt, cw):
+    # internal Morton row order: the permutation stays internal, so SpMM and
+    # the solve in public DOF order match the oracle exactly as before
+    c = Case(dim, m, jit, order, k, seed=61, noise=0.01 if jit else 0.0)
+    femcg.fem_set_format(c.A, fmt | femcg.FEM_ORDER_SFC, cw, 1)
+    rng = np.random.default_rng(6)
+    Xr = rng.standard_normal((c.A.n_free, k))
+    Y = torch.zeros((c.A.n_free, k), dtype=torch.float64, device="cuda")
+    femcg.fem_spmv(c.A, dev(Xr), Y)
+    torch.cuda.synchronize()
+    Yo = c.orc.spmv(Xr)
+    assert np.abs(Y.cpu().numpy() - Yo).max() <= 1e-12 * np.abs(Yo).max()
+    Xs, _, _, _, _ = c.orc.pcg(c.Bo, 1e-14)
+    for prec in (femcg.PCG_FP64, femcg.PCG_MIXED):
+        rc, X, st = c.solve(1e-12, precision=prec)
+        assert rc == 0, st
+        assert np.all(c.orc.relres(c.Bo, X) <= 1e-12 * 1.0001)
+        for j in range(k):
+            assert oracle.x_err(Xs[:, j], X[:, j]) <= 1e-8
+
+
+def test_tuner_on_3d_and_cold_timing():
+    c = Case(3, 19, 0.3, 1, 4, seed=62)
+    f, cw, sg = femcg.fem_tune(c.A, 4)
+    assert (f & ~femcg.FEM_ORDER_SFC) in (femcg.FEM_FORMAT_CSR, femcg.FEM_FORMAT_SELL)
+    rc, X, st = c.solve(1e-10)
+    assert rc == 0 and np.all(c.orc.relres(c.Bo, X) <= 1e-10 * 1.0001)
+    # the cold-cache probe runs on the copies' own workspaces and leaves the
+    # caller's vectors alone
+    mats = [c.A] + [femcg.Matrix(c.mesh, 1) for _ in range(3)]
+    B = c.B()
+    Xt = torch.zeros_like(B)
+    ms, by = femcg.pcg_time_spmm_cold(mats, 4, reps=2)
+    assert ms > 0 and by > 0
+    n, nnz = c.A.n_free, c.A.stats()["nnz_nonzero"]
+    assert by >= nnz * 12 + 2 * n * 4 * 8
+    rc = femcg.pcg_solve(c.A, B, Xt, 1e-10, femcg.default_opts(tol=1e-10))
+    torch.cuda.synchronize()
+    assert rc == 0 and np.all(c.orc.relres(c.Bo, Xt.cpu().numpy()) <= 1e-10 * 1.0001)
