@@ -183,9 +183,13 @@ int fem_set_format(fem_matrix *A, int32_t format, int32_t C, int32_t sigma);
  * phase reduces all tile partials of the previous phase at its start (small
  * systems); band = 1: small tiles swept by each XCD's blocks as one band of
  * rows, partial sums folded by the blocks that complete each group of tiles
- * (large systems); band = -1: automatic (band for vectors above 64 MB).
- * tile: rows per tile target count (band 0) or bytes of one FP64 vector
- * slice per tile (band 1); 0 = default.  Drops cached workspaces. */
+ * (large systems); band = 2: the whole iteration loop of the system in one
+ * 1024-thread workgroup (p in LDS, no launch per phase; needs n * kp <= 4096,
+ * kp = k rounded up to a power of two, else pcg_solve fails with
+ * FEMCG_EINVAL); band = -1: automatic (band 2 when it fits, else band 1 for
+ * vectors above 64 MB, else band 0).  tile: rows per tile target count
+ * (band 0) or bytes of one FP64 vector slice per tile (band 1); 0 = default.
+ * Drops cached workspaces. */
 int fem_set_tiling(fem_matrix *A, int32_t band, int32_t tile);
 
 /* Time one hot kernel of the iteration on the workspace of the last solve

@@ -26,6 +26,7 @@ struct Work {
     int64_t n = 0;
     int tile_rows = 0, ntiles = 0, ngroups = 0;
     int band = 0;
+    int small = 0;  // whole iteration loop in one workgroup (k_solve_small)
     double *B64 = nullptr, *X64 = nullptr, *R64 = nullptr, *P64 = nullptr, *Q64 = nullptr;
     float *B32 = nullptr, *X32 = nullptr, *R32 = nullptr, *P32 = nullptr, *Q32 = nullptr;
     double *part64 = nullptr, *part32 = nullptr;
@@ -53,7 +54,7 @@ struct fem_matrix {
     int32_t *d_lrow = nullptr, *d_lcol = nullptr;
     double *d_lval = nullptr;
     int tile_target = 0;  // 0 = automatic
-    int band_mode = -1;   // -1 automatic, 0 / 1 forced
+    int band_mode = -1;   // -1 automatic; 0 tile, 1 band, 2 single-workgroup loop forced
     int band_tile_bytes = 32768;
     int max_grid = 2048;
     std::map<std::pair<int, int>, std::unique_ptr<femcg::Work>> works;
@@ -111,9 +112,10 @@ struct Engine {
     hipStream_t stream = nullptr;
     // device tables: main (iterating), and the aux tables of one tick
     SysTable *d_main = nullptr, *d_ri64 = nullptr, *d_acc64 = nullptr, *d_acc32 = nullptr,
-             *d_sc64 = nullptr, *d_sc32 = nullptr, *d_ri32 = nullptr;
+             *d_sc64 = nullptr, *d_sc32 = nullptr, *d_ri32 = nullptr, *d_small = nullptr;
     SysTable *h_main = nullptr, *h_ri64 = nullptr, *h_acc64 = nullptr, *h_acc32 = nullptr,
-             *h_sc64 = nullptr, *h_sc32 = nullptr, *h_ri32 = nullptr;  // pinned staging
+             *h_sc64 = nullptr, *h_sc32 = nullptr, *h_ri32 = nullptr, *h_small = nullptr;  // pinned staging
+    int small_count[kNumClass] = {};  // systems per kp class in the small table
     SysState *d_st64 = nullptr, *d_st32 = nullptr;
     SysState *h_st64 = nullptr, *h_st32 = nullptr;  // pinned
     std::vector<Slot> slots;

@@ -140,7 +140,7 @@ static void choose_tiles(const fem_matrix *A, int kp, int &tile_rows, int &ntile
     const double vec_bytes = (double)n * kp * 8.0;
     // vectors beyond the last-level cache: thin band tiles keep each XCD's
     // working window of P compact and let the dispatcher balance tiles
-    band = A->band_mode >= 0 ? A->band_mode : (vec_bytes > 64e6 ? 1 : 0);
+    band = (A->band_mode == 0 || A->band_mode == 1) ? A->band_mode : (vec_bytes > 64e6 ? 1 : 0);
     if (const char *ev = std::getenv("FEMCG_BAND")) band = atoi(ev);  // tuning override
     int64_t rows;
     if (band) {
@@ -183,6 +183,12 @@ int get_work(fem_matrix *A, int kp, int prec, Work **out)
     w->prec = prec;
     w->n = A->dev.n;
     choose_tiles(A, kp, w->tile_rows, w->ntiles, w->band);
+    const bool fits_small = w->n * kp <= kSmallElems;
+    if (A->band_mode == 2 && !fits_small)
+        return fail(FEMCG_EINVAL, "single-workgroup mode needs n * kp <= %d (n = %lld, kp = %d)", kSmallElems,
+                    (long long)w->n, kp);
+    w->small = A->band_mode == 2 || (A->band_mode == -1 && fits_small);
+    if (const char *ev = std::getenv("FEMCG_SMALL")) w->small = w->small && atoi(ev) != 0;  // tuning override
     w->ngroups = (w->ntiles + kGroup - 1) / kGroup;
     const size_t nv = (size_t)std::max<int64_t>(w->n, 1) * kp;
     const size_t np = (size_t)w->ntiles * kDots * kp, ngp = (size_t)w->ngroups * kDots * kp;
@@ -283,10 +289,10 @@ Engine::~Engine()
     for (auto &g : gexec)
         if (g) (void)hipGraphExecDestroy(g);
     if (cap) (void)hipStreamDestroy(cap);
-    SysTable *dt[] = {d_main, d_ri64, d_acc64, d_acc32, d_sc64, d_sc32, d_ri32};
+    SysTable *dt[] = {d_main, d_ri64, d_acc64, d_acc32, d_sc64, d_sc32, d_ri32, d_small};
     for (auto p : dt)
         if (p) (void)hipFree(p);
-    SysTable *ht[] = {h_main, h_ri64, h_acc64, h_acc32, h_sc64, h_sc32, h_ri32};
+    SysTable *ht[] = {h_main, h_ri64, h_acc64, h_acc32, h_sc64, h_sc32, h_ri32, h_small};
     for (auto p : ht)
         if (p) (void)hipHostFree(p);
     if (d_st64) (void)hipFree(d_st64);
@@ -310,8 +316,10 @@ int engine_create(int prec, int max_slots, int m, bool use_graph, std::unique_pt
     e->use_graph = use_graph;
     e->slots.resize(e->max_slots);
     const size_t tb = table_bytes(e->max_slots);
-    SysTable **dts[] = {&e->d_main, &e->d_ri64, &e->d_acc64, &e->d_acc32, &e->d_sc64, &e->d_sc32, &e->d_ri32};
-    SysTable **hts[] = {&e->h_main, &e->h_ri64, &e->h_acc64, &e->h_acc32, &e->h_sc64, &e->h_sc32, &e->h_ri32};
+    SysTable **dts[] = {&e->d_main, &e->d_ri64, &e->d_acc64, &e->d_acc32, &e->d_sc64, &e->d_sc32, &e->d_ri32,
+                        &e->d_small};
+    SysTable **hts[] = {&e->h_main, &e->h_ri64, &e->h_acc64, &e->h_acc32, &e->h_sc64, &e->h_sc32, &e->h_ri32,
+                        &e->h_small};
     for (auto p : dts) {
         HIPCHK(hipMalloc((void **)p, tb));
         HIPCHK(hipMemset(*p, 0, tb));
@@ -388,6 +396,28 @@ static int64_t fill_table(Engine *e, SysTable *h, std::vector<int> &ids, bool fp
     h->total_tiles = base;
     if (mask) *mask = m;
     return base;
+}
+
+// Table of single-workgroup systems: class c owns system indices
+// [cls_begin[c], cls_end[c]) (ids sorted by kp), one workgroup each.
+static void fill_small_table(Engine *e, SysTable *h, const std::vector<int> &ids, bool fp32)
+{
+    for (int c = 0; c < kNumClass; ++c) {
+        h->cls_begin[c] = h->cls_end[c] = 0;
+        e->small_count[c] = 0;
+    }
+    h->nsys = (int)ids.size();
+    h->total_tiles = 0;
+    for (size_t i = 0; i < ids.size(); ++i) {
+        SysDesc D = slot_desc(e, ids[i], fp32);
+        D.tile_base = 0;
+        D.par_off = e->slots[ids[i]].par_off;
+        const int c = class_of(D.kp);
+        if (e->small_count[c] == 0) h->cls_begin[c] = (int64_t)i;
+        e->small_count[c]++;
+        h->cls_end[c] = (int64_t)i + 1;
+        h->d[i] = D;
+    }
 }
 
 static void set_single_table(SysTable *h, const SysDesc &D)
@@ -577,45 +607,68 @@ int engine_tick(Engine *e, int *rc_out)
     std::stable_sort(iter_ids.begin(), iter_ids.end(),
                      [&](int a, int b) { return e->slots[a].kp < e->slots[b].kp; });
     if (iter_ids != e->main_ids) {
-        // a system entering the table starts at parity 0 on the next launch
+        // a system entering the table (first time, or back from a residual
+        // check) starts at parity 0 on the next launch: its state was just
+        // written to slot 1 by the residual kernel
         for (int sid : iter_ids)
             if (std::find(e->main_ids.begin(), e->main_ids.end(), sid) == e->main_ids.end())
                 e->slots[sid].par_off = (int)(e->it_global & 1);
+        e->main_ids = iter_ids;  // also when empty: a later return is an entry
         e->main_dirty = true;
     }
+    // systems whose whole loop fits one workgroup run in k_solve_small; the
+    // rest in the phase kernels of the main table (graph of m iterations)
+    std::vector<int> big_ids, small_ids;
+    for (int sid : iter_ids) (e->slots[sid].w->small ? small_ids : big_ids).push_back(sid);
     int nrun = 0;
     if (!iter_ids.empty()) {
-        int64_t T = 0;
-        if (e->main_dirty) {
-            T = fill_table(e, e->h_main, iter_ids, mixed, 0, 0, &e->main_mask);
-            if ((rc = upload_table(e, e->d_main, e->h_main))) {
+        // small systems alone: the kernel iterates to convergence (or the
+        // budget) in one launch; mixed with large ones, m at a time
+        nrun = (int)std::max<int64_t>(1, std::min<int64_t>(budget, big_ids.empty() ? INT32_MAX : e->m));
+        const bool dirty = e->main_dirty;
+        if (!small_ids.empty()) {
+            if (dirty) {
+                fill_small_table(e, e->h_small, small_ids, mixed);
+                if ((rc = upload_table(e, e->d_small, e->h_small))) {
+                    *rc_out = rc;
+                    return -1;
+                }
+            }
+            if (mixed) launch_small<float>(e->d_small, e->small_count, (int)(e->it_global & 1), nrun, e->stream);
+            else launch_small<double>(e->d_small, e->small_count, (int)(e->it_global & 1), nrun, e->stream);
+            HIPCHK(hipGetLastError());
+        }
+        if (!big_ids.empty()) {
+            int64_t T = 0;
+            if (dirty) {
+                T = fill_table(e, e->h_main, big_ids, mixed, 0, 0, &e->main_mask);
+                if ((rc = upload_table(e, e->d_main, e->h_main))) {
+                    *rc_out = rc;
+                    return -1;
+                }
+            } else {
+                T = e->h_main->total_tiles;
+            }
+            int cap = 1;
+            for (int id : big_ids) cap = std::max(cap, grid_cap(e->slots[id].A, e->slots[id].w));
+            const int grid = e->grid > 0 ? e->grid : grid_for(T, cap);
+            if (e->use_graph && nrun == e->m) {
+                if ((rc = ensure_graph(e, grid))) {
+                    *rc_out = rc;
+                    return -1;
+                }
+                hipError_t le = hipGraphLaunch(e->gexec[e->it_global & 1], e->stream);
+                if (le != hipSuccess) {
+                    *rc_out = fail(FEMCG_EDEVICE, "hipGraphLaunch: %s", hipGetErrorString(le));
+                    return -1;
+                }
+                e->replays++;
+            } else if ((rc = launch_iterations(e, nrun, grid, e->it_global))) {
                 *rc_out = rc;
                 return -1;
             }
-            e->main_ids = iter_ids;
-            e->main_dirty = false;
-        } else {
-            T = e->h_main->total_tiles;
         }
-        int cap = 1;
-        for (int id : iter_ids) cap = std::max(cap, grid_cap(e->slots[id].A, e->slots[id].w));
-        const int grid = e->grid > 0 ? e->grid : grid_for(T, cap);
-        nrun = (int)std::max<int64_t>(1, std::min<int64_t>(budget, e->m));
-        if (e->use_graph && nrun == e->m) {
-            if ((rc = ensure_graph(e, grid))) {
-                *rc_out = rc;
-                return -1;
-            }
-            hipError_t le = hipGraphLaunch(e->gexec[e->it_global & 1], e->stream);
-            if (le != hipSuccess) {
-                *rc_out = fail(FEMCG_EDEVICE, "hipGraphLaunch: %s", hipGetErrorString(le));
-                return -1;
-            }
-            e->replays++;
-        } else if ((rc = launch_iterations(e, nrun, grid, e->it_global))) {
-            *rc_out = rc;
-            return -1;
-        }
+        e->main_dirty = false;
         e->it_global += nrun;
     }
     // 3. poll the states
@@ -1190,7 +1243,7 @@ int fem_tune(fem_matrix *A, int32_t k, int32_t precision, int32_t *C_out, int32_
 
 int fem_set_tiling(fem_matrix *A, int32_t band, int32_t tile)
 {
-    if (!A || band < -1 || band > 1 || tile < 0) return fail(FEMCG_EINVAL, "bad tiling arguments");
+    if (!A || band < -1 || band > 2 || tile < 0) return fail(FEMCG_EINVAL, "bad tiling arguments");
     A->band_mode = band;
     if (band == 1) A->band_tile_bytes = tile > 0 ? std::max(1024, (int)tile) : 32768;
     else A->tile_target = tile;

@@ -20,6 +20,9 @@ constexpr int kMaxK = FEMCG_MAX_K;
 constexpr int kDots = 3;           // dot products a kernel may reduce per column
 constexpr int kNumXcd = 8;         // MI355X: 8 XCDs x 32 CUs, one L2 each
 constexpr int kGroup = 64;         // band mode: tiles per reduction group
+constexpr int kSmallBlock = 1024;  // small systems: one workgroup runs the whole loop
+constexpr int kSmallPass = 4;      // small systems: rows per thread (at kp lanes per row)
+constexpr int kSmallElems = kSmallBlock * kSmallPass;  // small systems: n * kp bound (p in LDS)
 
 // Per-system solver state, resident on the device.
 //
@@ -128,6 +131,10 @@ void launch_phase(int phase, const SysTable *tab, int grid, int it, int force, u
 // per-system finalize (one block per system) that decides which columns iterate
 template <typename T>
 void launch_residual_init(const SysTable *tab, int grid, int nsys, unsigned cls_mask, hipStream_t s);
+// Small systems (n * kp <= kSmallElems): `niter` iterations, one workgroup
+// per system; the table's class ranges index systems, cls_count[c] of them.
+template <typename T>
+void launch_small(const SysTable *tab, const int *cls_count, int it, int niter, hipStream_t s);
 void launch_gather(const double *src, int64_t ld_src, const int32_t *perm, int64_t n, int k,
                    int kp, double *dst, hipStream_t s);
 void launch_scatter(const double *src, const int32_t *perm, int64_t n, int k, int kp,

@@ -861,6 +861,234 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(const SysTable *__restrict__
 }
 
 // ---------------------------------------------------------------------------
+// Small systems: the whole iteration loop in one workgroup.
+//
+// For n * kp <= kSmallElems one 1024-thread workgroup runs up to `niter`
+// iterations of a system with no kernel boundary: p lives in LDS (the SpMM
+// gathers from it), x, r, D^-1 and q of a thread's rows live in registers
+// (written back when the launch ends), and the three reductions of an
+// iteration are a wave xor tree plus a fixed-order sum over the 16 waves
+// (deterministic, identical on every thread).  The per-column arithmetic and
+// the Eq. (2) test are those of k_update / k_pupdate; the loop state is read
+// from the slot of the first launch index and written to both parity slots
+// at the end.  Grid: one workgroup per system of the class.
+// ---------------------------------------------------------------------------
+
+template <int KP, int ND>
+__device__ __forceinline__ void small_reduce(double (*red)[kSmallBlock / kWave][KP], const double *v, double *out)
+{
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int j = threadIdx.x & (KP - 1);
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        const double s = wave_reduce_cols<KP>(v[d]);
+        if (lane < KP) red[d][wave][lane] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < kSmallBlock / kWave; ++w) t += red[d][w][j];
+        out[d] = t;
+    }
+}
+
+template <typename T, int KP>
+__global__ __launch_bounds__(kSmallBlock) void k_solve_small(const SysTable *__restrict__ tab, int it0, int niter)
+{
+    constexpr int kp = KP, rpp = kSmallBlock / kp;
+    __shared__ T s_p[kSmallElems];
+    __shared__ double s_red[3][kSmallBlock / kWave][KP];
+    const int64_t sidx = tab->cls_begin[kLog2<KP>] + blockIdx.x;
+    if (sidx >= tab->cls_end[kLog2<KP>]) return;
+    const SysDesc D = tab->d[sidx];
+    const int n = (int)D.n;
+    const int j = threadIdx.x & (kp - 1);
+    const int rt = threadIdx.x / kp;
+    const int npass = (n + rpp - 1) / rpp;
+    GLOBAL T *__restrict__ X = gptr((T *)D.x);
+    GLOBAL T *__restrict__ Rg = gptr((T *)D.r);
+    GLOBAL T *__restrict__ Pg = gptr((T *)D.p);
+    const GLOBAL T *__restrict__ dinv = gptr((const T *)D.dinv);
+    const GLOBAL T *__restrict__ val = gptr((const T *)D.val);
+    const GLOBAL int32_t *__restrict__ col = gptr(D.col);
+    const bool sell = D.format == FEM_FORMAT_SELL;
+    const int sh = D.sell_shift;
+    GLOBAL SysState *st = gptr(D.st);
+
+    for (int i = threadIdx.x; i < n * kp; i += kSmallBlock) s_p[i] = Pg[i];
+    T xv[kSmallPass], rv[kSmallPass], dv[kSmallPass], qv[kSmallPass];
+    int base[kSmallPass], len[kSmallPass];  // n * kp <= kSmallElems: 32-bit offsets
+#pragma unroll
+    for (int i = 0; i < kSmallPass; ++i) {
+        const int row = rt + i * rpp;
+        xv[i] = rv[i] = dv[i] = qv[i] = (T)0;
+        base[i] = 0;
+        len[i] = 0;
+        if (i < npass && row < n) {
+            xv[i] = X[(int64_t)row * kp + j];
+            rv[i] = Rg[(int64_t)row * kp + j];
+            dv[i] = dinv[row];
+            if (sell) {
+                base[i] = (int)gptr(D.slice_ptr)[row >> sh] + (row & ((1 << sh) - 1));
+                len[i] = gptr(D.rowlen)[row];
+            } else {
+                base[i] = gptr(D.rowptr)[row];
+                len[i] = gptr(D.rowptr)[row + 1] - base[i];
+            }
+        }
+    }
+    const int estride = sell ? (1 << sh) : 1;
+    const int prv0 = ((it0 + D.par_off) & 1) ^ 1;
+    const bool real = j < D.k;
+    double rho = st->rho[prv0][j];
+    int act = real ? st->active[prv0][j] : 0;
+    int iters = st->iters[prv0][j];
+    int fl = real ? st->flag[j] : 1;
+    double rr_last = st->rr[j];
+    const double thr = st->tol_rel[j] * st->tol_rel[j] * st->bb[j];
+    int nact = __syncthreads_count(threadIdx.x < kp && act);
+
+    for (int it = 0; it < niter && nact > 0; ++it) {
+        // q = A p and p.q
+        double v[2];
+        v[0] = 0.0;
+#pragma unroll
+        for (int i = 0; i < kSmallPass; ++i) {
+            if (i < npass) {
+                T acc = (T)0;
+                for (int e0 = 0; e0 < len[i]; e0 += 4) {
+                    int c[4];
+                    T a[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int e = e0 + q;
+                        const int idx = base[i] + (e < len[i] ? e : 0) * estride;
+                        const T vv = val[idx];
+                        c[q] = col[idx];
+                        a[q] = e < len[i] ? vv : (T)0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc += a[q] * s_p[c[q] * kp + j];
+                }
+                qv[i] = acc;
+                const int row = rt + i * rpp;
+                if (row < n) v[0] += (double)s_p[row * kp + j] * (double)acc;
+            }
+        }
+        double pq;
+        small_reduce<KP, 1>(&s_red[0], v, &pq);
+        // alpha; x += alpha p, r -= alpha q; r.z and r.r
+        const bool live = act != 0;
+        const bool okpq = pq > 0.0 && isfinite(pq);
+        const double al = (live && okpq) ? rho / pq : 0.0;
+        v[0] = 0.0;
+        v[1] = 0.0;
+        if (live && okpq) {
+#pragma unroll
+            for (int i = 0; i < kSmallPass; ++i) {
+                const int row = rt + i * rpp;
+                if (i < npass && row < n) {
+                    xv[i] = (T)((double)xv[i] + al * (double)s_p[row * kp + j]);
+                    const T r = (T)((double)rv[i] - al * (double)qv[i]);
+                    rv[i] = r;
+                    const double rd = (double)r;
+                    v[0] += rd * ((double)dv[i] * rd);
+                    v[1] += rd * rd;
+                }
+            }
+        }
+        double sums[2];
+        small_reduce<KP, 2>(&s_red[1], v, sums);
+        const double rz = sums[0], rr = sums[1];
+        // beta and the Eq. (2) test; p = D^-1 r + beta p
+        int na = 0, inc = 0;
+        double be = 0.0;
+        if (live) {
+            if (!okpq) {
+                fl = FEMCG_EBREAKDOWN;
+            } else {
+                inc = 1;
+                if (rr <= thr) {
+                    // Eq. (2) holds: the column stops here
+                } else if (!(rz > 0.0) || !isfinite(rz) || !isfinite(rr)) {
+                    fl = FEMCG_EBREAKDOWN;
+                } else {
+                    na = 1;
+                    be = rz / rho;
+                    rho = rz;
+                }
+            }
+            iters += inc;
+            if (inc) rr_last = rr;
+        }
+        if (na) {
+#pragma unroll
+            for (int i = 0; i < kSmallPass; ++i) {
+                const int row = rt + i * rpp;
+                if (i < npass && row < n) {
+                    const int li = row * kp + j;
+                    s_p[li] = (T)((double)dv[i] * (double)rv[i] + be * (double)s_p[li]);
+                }
+            }
+        }
+        act = na;
+        nact = __syncthreads_count(threadIdx.x < kp && na);
+    }
+    // write back p, x and r; publish the state in both parity slots
+    for (int i = threadIdx.x; i < n * kp; i += kSmallBlock) Pg[i] = s_p[i];
+#pragma unroll
+    for (int i = 0; i < kSmallPass; ++i) {
+        const int row = rt + i * rpp;
+        if (i < npass && row < n) {
+            X[(int64_t)row * kp + j] = xv[i];
+            Rg[(int64_t)row * kp + j] = rv[i];
+        }
+    }
+    const int bad = __syncthreads_count(threadIdx.x < kp && fl == FEMCG_EBREAKDOWN);
+    if (threadIdx.x < kp) {
+        const int c = threadIdx.x;
+        st->active[0][c] = act;
+        st->active[1][c] = act;
+        if (real) {
+            st->rho[0][c] = rho;
+            st->rho[1][c] = rho;
+            st->iters[0][c] = iters;
+            st->iters[1][c] = iters;
+            st->h_iters[c] = iters;
+            st->h_active[c] = act;
+            st->flag[c] = fl;
+            st->rr[c] = rr_last;
+        }
+    }
+    if (threadIdx.x == 0) {
+        st->n_active = nact;
+        if (bad) st->status = FEMCG_EBREAKDOWN;
+    }
+}
+
+template <typename T, int KP>
+static void launch_small_kp(const SysTable *tab, int nsys_cls, int it, int niter, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_solve_small<T, KP>), dim3(nsys_cls), dim3(kSmallBlock), 0, s, tab, it, niter);
+}
+
+template <typename T>
+void launch_small(const SysTable *tab, const int *cls_count, int it, int niter, hipStream_t s)
+{
+    if (cls_count[0]) launch_small_kp<T, 1>(tab, cls_count[0], it, niter, s);
+    if (cls_count[1]) launch_small_kp<T, 2>(tab, cls_count[1], it, niter, s);
+    if (cls_count[2]) launch_small_kp<T, 4>(tab, cls_count[2], it, niter, s);
+    if (cls_count[3]) launch_small_kp<T, 8>(tab, cls_count[3], it, niter, s);
+    if (cls_count[4]) launch_small_kp<T, 16>(tab, cls_count[4], it, niter, s);
+    if (cls_count[5]) launch_small_kp<T, 32>(tab, cls_count[5], it, niter, s);
+    if (cls_count[6]) launch_small_kp<T, 64>(tab, cls_count[6], it, niter, s);
+}
+template void launch_small<double>(const SysTable *, const int *, int, int, hipStream_t);
+template void launch_small<float>(const SysTable *, const int *, int, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
 // residual / (re)start: r = b - A x (or r = b, x = 0), p = D^-1 r,
 // partial b.b, r.r, r.z; then one block per system decides which columns
 // iterate (Eq. (2) residual above tol) and seeds the loop state.

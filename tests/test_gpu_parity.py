@@ -283,3 +283,63 @@ def test_tuner_on_3d_and_cold_timing():
     rc = femcg.pcg_solve(c.A, B, Xt, 1e-10, femcg.default_opts(tol=1e-10))
     torch.cuda.synchronize()
     assert rc == 0 and np.all(c.orc.relres(c.Bo, Xt.cpu().numpy()) <= 1e-10 * 1.0001)
+
+
+SMALL_CASES = [(2, 37, 0.3, 1, 1), (2, 23, 0.25, 2, 2), (3, 11, 0.3, 1, 4), (3, 9, 0.3, 2, 1), (2, 64, 0.0, 1, 1),
+               (2, 20, 0.3, 1, 8), (2, 10, 0.3, 1, 32), (2, 8, 0.2, 1, 64)]
+
+
+@pytest.mark.parametrize("dim,m,jit,order,k", SMALL_CASES)
+@pytest.mark.parametrize("prec", [femcg.PCG_FP64, femcg.PCG_MIXED])
+def test_single_workgroup_loop_matches_oracle(dim, m, jit, order, k, prec):
+    # n * kp <= 4096: the whole loop in one workgroup (mode 2) against the
+    # phase kernels (mode 0) and the oracle, (R) at 1e-8 and (S) at 1e-12
+    c = Case(dim, m, jit, order, k, seed=71, noise=0.01 if jit else 0.0)
+    Xs, _, _, _, st = c.orc.pcg(c.Bo, 1e-14)
+    assert st == 0
+    _, its_t, _, _, _ = c.orc.pcg(c.Bo, 1e-8)
+    res = {}
+    for mode in (2, 0):
+        femcg.fem_set_tiling(c.A, mode, 0)
+        for tol in (1e-8, 1e-12):
+            rc, X, stats = c.solve(tol, precision=prec)
+            assert rc == 0, (mode, stats)
+            assert np.all(c.orc.relres(c.Bo, X) <= tol * 1.0001)
+            if tol == 1e-12:
+                for j in range(k):
+                    assert oracle.x_err(Xs[:, j], X[:, j]) <= 1e-8
+                res[mode] = X
+            elif prec == femcg.PCG_FP64:
+                for j in range(k):
+                    assert abs(stats["iters"][j] - its_t[j]) <= 0.02 * its_t[j] + 2, (mode, stats["iters"], its_t)
+    for j in range(k):
+        assert oracle.x_err(res[0][:, j], res[2][:, j]) <= 1e-9
+
+
+def test_single_workgroup_mode_limits():
+    c = Case(2, 40, 0.3, 1, 4, seed=72)  # n = 1444, kp = 4: above n * kp = 4096
+    femcg.fem_set_tiling(c.A, 2, 0)
+    with pytest.raises(femcg.FemcgError) as ei:
+        c.solve(1e-8)
+    assert ei.value.code == femcg.FEMCG_EINVAL
+    femcg.fem_set_tiling(c.A, -1, 0)
+    rc, X, st = c.solve(1e-10)
+    assert rc == 0 and np.all(c.orc.relres(c.Bo, X) <= 1e-10 * 1.0001)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_reentry_after_odd_launch_counts(mode):
+    # mixed precision leaves and re-enters the iteration table at every
+    # refinement step; with an odd number of iterations per tick the launch
+    # index parity changes between entries, and a re-entering system must
+    # start from the state slot its residual kernel wrote
+    c = Case(2, 30, 0.3, 1, 2, seed=73, noise=0.01)
+    femcg.fem_set_tiling(c.A, mode, 0 if mode != 1 else 1024)
+    Xs, _, _, _, _ = c.orc.pcg(c.Bo, 1e-14)
+    for prec in (femcg.PCG_MIXED, femcg.PCG_FP64):
+        for ce in (7, 5, 3):
+            rc, X, st = c.solve(1e-12, precision=prec, check_every=ce)
+            assert rc == 0, (prec, ce, st)
+            assert np.all(c.orc.relres(c.Bo, X) <= 1e-12 * 1.0001)
+            for j in range(c.k):
+                assert oracle.x_err(Xs[:, j], X[:, j]) <= 1e-8
