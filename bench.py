@@ -203,10 +203,11 @@ def run_single(args):
     torch.cuda.synchronize()
     achieved = by_spmm / (ms_spmm * 1e-3) / 1e9
     cold = None
-    if args.cold_mb > 0:
+    # (a system whose SpMM moves under 16 MB is latency-bound: no cold rate)
+    if args.cold_mb > 0 and by_spmm >= 16e6:
         # the same SpMM on rotating copies whose total far exceeds the 256 MB
         # last-level cache: no launch finds its operands cache-resident
-        ncopy = max(4, int(math.ceil(args.cold_mb * 1e6 / by_spmm)))
+        ncopy = min(128, max(4, int(math.ceil(args.cold_mb * 1e6 / by_spmm))))
         t0 = time.time()
         mats = [A]
         for _ in range(ncopy - 1):

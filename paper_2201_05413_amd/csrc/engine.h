@@ -27,6 +27,11 @@ struct Work {
     int tile_rows = 0, ntiles = 0, ngroups = 0;
     int band = 0;
     int small = 0;  // whole iteration loop in one workgroup (k_solve_small)
+    // small systems: the matrix padded per workgroup thread, [pass][ell_len][1024/kp]
+    int ell_len = 0;
+    int32_t *ell_col = nullptr;
+    double *ell_v64 = nullptr;
+    float *ell_v32 = nullptr;
     double *B64 = nullptr, *X64 = nullptr, *R64 = nullptr, *P64 = nullptr, *Q64 = nullptr;
     float *B32 = nullptr, *X32 = nullptr, *R32 = nullptr, *P32 = nullptr, *Q32 = nullptr;
     double *part64 = nullptr, *part32 = nullptr;

@@ -192,6 +192,15 @@ int get_work(fem_matrix *A, int kp, int prec, Work **out)
     w->ngroups = (w->ntiles + kGroup - 1) / kGroup;
     const size_t nv = (size_t)std::max<int64_t>(w->n, 1) * kp;
     const size_t np = (size_t)w->ntiles * kDots * kp, ngp = (size_t)w->ngroups * kDots * kp;
+    // small systems: ELL layout of the solver copy per workgroup thread group
+    const int rpp = kSmallBlock / kp;
+    const int npass = w->small ? (int)((w->n + rpp - 1) / rpp) : 0;
+    if (w->small) {
+        int64_t L = 1;
+        for (int64_t i = 0; i < w->n; ++i) L = std::max<int64_t>(L, A->sc.rowptr[i + 1] - A->sc.rowptr[i]);
+        w->ell_len = (int)((L + 1) / 2 * 2);
+    }
+    const size_t ne = (size_t)npass * w->ell_len * rpp;
     Arena ar;
     for (int pass = 0; pass < 2; ++pass) {
         ar.used = 0;
@@ -214,6 +223,11 @@ int get_work(fem_matrix *A, int kp, int prec, Work **out)
         w->part64 = (double *)ar.take(np * 8);
         w->gpart64 = (double *)ar.take(ngp * 8);
         w->gtk64 = (uint32_t *)ar.take((size_t)w->ngroups * 4);
+        if (ne) {
+            w->ell_col = (int32_t *)ar.take(ne * 4);
+            w->ell_v64 = (double *)ar.take(ne * 8);
+            w->ell_v32 = (float *)ar.take(ne * 4);
+        }
         if (pass == 0) {
             ar.size = ar.used;
             if (hipMalloc((void **)&ar.base, ar.size) != hipSuccess)
@@ -223,6 +237,26 @@ int get_work(fem_matrix *A, int kp, int prec, Work **out)
     }
     w->mem = ar.base;
     w->bytes = ar.size;
+    if (ne) {
+        std::vector<int32_t> ec(ne);
+        std::vector<double> ev(ne);
+        std::vector<float> ef(ne);
+        for (int i = 0; i < npass; ++i)
+            for (int t = 0; t < rpp; ++t) {
+                const int64_t row = (int64_t)i * rpp + t;
+                const int64_t b = row < w->n ? A->sc.rowptr[row] : 0;
+                const int64_t len = row < w->n ? A->sc.rowptr[row + 1] - b : 0;
+                for (int e = 0; e < w->ell_len; ++e) {
+                    const size_t o = ((size_t)i * w->ell_len + e) * rpp + t;
+                    ec[o] = e < len ? A->sc.col[b + e] : (row < w->n ? (int32_t)row : 0);
+                    ev[o] = e < len ? A->sc.val[b + e] : 0.0;
+                    ef[o] = (float)ev[o];
+                }
+            }
+        HIPCHK(hipMemcpy(w->ell_col, ec.data(), ne * 4, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(w->ell_v64, ev.data(), ne * 8, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(w->ell_v32, ef.data(), ne * 4, hipMemcpyHostToDevice));
+    }
     *out = w.get();
     A->works[key] = std::move(w);
     return FEMCG_OK;
@@ -251,6 +285,9 @@ static SysDesc make_desc(const fem_matrix *A, const Work *w, bool fp32, const vo
 {
     SysDesc D = make_desc_base(A, w, fp32, b, x, r, p, q, part, st, k);
     D.band = w->band;
+    D.ell_col = w->ell_col;
+    D.ell_val = fp32 ? (const void *)w->ell_v32 : (const void *)w->ell_v64;
+    D.ell_len = w->ell_len;
     D.gpart = fp32 ? w->gpart32 : w->gpart64;
     D.gticket = fp32 ? w->gtk32 : w->gtk64;
     return D;

@@ -81,6 +81,13 @@ struct SysDesc {
     double *gpart;          // band mode: [ngroups][kDots*kp] per-group sums
     uint32_t *gticket;      // band mode: [ngroups] tiles arrived, zero between phases
     SysState *st;
+    // single-workgroup systems: entry e of the row served by thread group t
+    // in pass i at [(i * ell_len + e) * (kSmallBlock / kp) + t]; rows padded
+    // to ell_len (even) with (own row, 0)
+    const int32_t *ell_col;
+    const void *ell_val;    // T
+    int32_t ell_len;
+    int32_t pad_e;
 };
 
 constexpr int kMaxSys = 256;

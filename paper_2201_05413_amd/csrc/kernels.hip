@@ -864,9 +864,11 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(const SysTable *__restrict__
 // Small systems: the whole iteration loop in one workgroup.
 //
 // For n * kp <= kSmallElems one 1024-thread workgroup runs up to `niter`
-// iterations of a system with no kernel boundary: p lives in LDS (the SpMM
-// gathers from it), x, r, D^-1 and q of a thread's rows live in registers
-// (written back when the launch ends), and the three reductions of an
+// iterations of a system with no kernel boundary: p, x and D^-1 live in LDS
+// (the SpMM gathers from p there), r and q of a thread's rows in registers
+// (all written back when the launch ends); the matrix streams from the L2 in
+// a padded per-thread layout (ell_*), kC entries of every row of a thread per
+// load round, and the reductions of an
 // iteration are a wave xor tree plus a fixed-order sum over the 16 waves
 // (deterministic, identical on every thread).  The per-column arithmetic and
 // the Eq. (2) test are those of k_update / k_pupdate; the loop state is read
@@ -898,7 +900,10 @@ template <typename T, int KP>
 __global__ __launch_bounds__(kSmallBlock) void k_solve_small(const SysTable *__restrict__ tab, int it0, int niter)
 {
     constexpr int kp = KP, rpp = kSmallBlock / kp;
+    constexpr int kC = 2;  // entries per row per load round (ell_len is even)
     __shared__ T s_p[kSmallElems];
+    __shared__ T s_x[kSmallElems];
+    __shared__ T s_d[kSmallElems];
     __shared__ double s_red[3][kSmallBlock / kWave][KP];
     const int64_t sidx = tab->cls_begin[kLog2<KP>] + blockIdx.x;
     if (sidx >= tab->cls_end[kLog2<KP>]) return;
@@ -911,35 +916,23 @@ __global__ __launch_bounds__(kSmallBlock) void k_solve_small(const SysTable *__r
     GLOBAL T *__restrict__ Rg = gptr((T *)D.r);
     GLOBAL T *__restrict__ Pg = gptr((T *)D.p);
     const GLOBAL T *__restrict__ dinv = gptr((const T *)D.dinv);
-    const GLOBAL T *__restrict__ val = gptr((const T *)D.val);
-    const GLOBAL int32_t *__restrict__ col = gptr(D.col);
-    const bool sell = D.format == FEM_FORMAT_SELL;
-    const int sh = D.sell_shift;
+    const GLOBAL int32_t *__restrict__ ecol = gptr(D.ell_col);
+    const GLOBAL T *__restrict__ eval = gptr((const T *)D.ell_val);
+    const int L = D.ell_len;
     GLOBAL SysState *st = gptr(D.st);
 
-    for (int i = threadIdx.x; i < n * kp; i += kSmallBlock) s_p[i] = Pg[i];
-    T xv[kSmallPass], rv[kSmallPass], dv[kSmallPass], qv[kSmallPass];
-    int base[kSmallPass], len[kSmallPass];  // n * kp <= kSmallElems: 32-bit offsets
+    for (int i = threadIdx.x; i < n * kp; i += kSmallBlock) {
+        s_p[i] = Pg[i];
+        s_x[i] = X[i];
+    }
+    for (int i = threadIdx.x; i < n; i += kSmallBlock) s_d[i] = dinv[i];
+    T rv[kSmallPass], qv[kSmallPass];
 #pragma unroll
     for (int i = 0; i < kSmallPass; ++i) {
         const int row = rt + i * rpp;
-        xv[i] = rv[i] = dv[i] = qv[i] = (T)0;
-        base[i] = 0;
-        len[i] = 0;
-        if (i < npass && row < n) {
-            xv[i] = X[(int64_t)row * kp + j];
-            rv[i] = Rg[(int64_t)row * kp + j];
-            dv[i] = dinv[row];
-            if (sell) {
-                base[i] = (int)gptr(D.slice_ptr)[row >> sh] + (row & ((1 << sh) - 1));
-                len[i] = gptr(D.rowlen)[row];
-            } else {
-                base[i] = gptr(D.rowptr)[row];
-                len[i] = gptr(D.rowptr)[row + 1] - base[i];
-            }
-        }
+        rv[i] = qv[i] = (T)0;
+        if (i < npass && row < n) rv[i] = Rg[(int64_t)row * kp + j];
     }
-    const int estride = sell ? (1 << sh) : 1;
     const int prv0 = ((it0 + D.par_off) & 1) ^ 1;
     const bool real = j < D.k;
     double rho = st->rho[prv0][j];
@@ -951,31 +944,39 @@ __global__ __launch_bounds__(kSmallBlock) void k_solve_small(const SysTable *__r
     int nact = __syncthreads_count(threadIdx.x < kp && act);
 
     for (int it = 0; it < niter && nact > 0; ++it) {
-        // q = A p and p.q
+        // q = A p: one round of loads brings kC entries of every row of the
+        // thread (all passes; uniform offsets, no masking: rows are padded),
+        // then the gathers come from LDS
+        T acc[kSmallPass];
+#pragma unroll
+        for (int i = 0; i < kSmallPass; ++i) acc[i] = (T)0;
+        for (int e0 = 0; e0 < L; e0 += kC) {
+            int c[kSmallPass][kC];
+            T a[kSmallPass][kC];
+#pragma unroll
+            for (int i = 0; i < kSmallPass; ++i)
+                if (i < npass) {
+#pragma unroll
+                    for (int q = 0; q < kC; ++q) {
+                        const unsigned o = (unsigned)((i * L + e0 + q) * rpp + rt);
+                        c[i][q] = ecol[o];
+                        a[i][q] = eval[o];
+                    }
+                }
+#pragma unroll
+            for (int i = 0; i < kSmallPass; ++i)
+                if (i < npass) {
+#pragma unroll
+                    for (int q = 0; q < kC; ++q) acc[i] += a[i][q] * s_p[c[i][q] * kp + j];
+                }
+        }
         double v[2];
         v[0] = 0.0;
 #pragma unroll
         for (int i = 0; i < kSmallPass; ++i) {
-            if (i < npass) {
-                T acc = (T)0;
-                for (int e0 = 0; e0 < len[i]; e0 += 4) {
-                    int c[4];
-                    T a[4];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int e = e0 + q;
-                        const int idx = base[i] + (e < len[i] ? e : 0) * estride;
-                        const T vv = val[idx];
-                        c[q] = col[idx];
-                        a[q] = e < len[i] ? vv : (T)0;
-                    }
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) acc += a[q] * s_p[c[q] * kp + j];
-                }
-                qv[i] = acc;
-                const int row = rt + i * rpp;
-                if (row < n) v[0] += (double)s_p[row * kp + j] * (double)acc;
-            }
+            qv[i] = acc[i];
+            const int row = rt + i * rpp;
+            if (i < npass && row < n) v[0] += (double)s_p[row * kp + j] * (double)acc[i];
         }
         double pq;
         small_reduce<KP, 1>(&s_red[0], v, &pq);
@@ -990,11 +991,12 @@ __global__ __launch_bounds__(kSmallBlock) void k_solve_small(const SysTable *__r
             for (int i = 0; i < kSmallPass; ++i) {
                 const int row = rt + i * rpp;
                 if (i < npass && row < n) {
-                    xv[i] = (T)((double)xv[i] + al * (double)s_p[row * kp + j]);
+                    const int li = row * kp + j;
+                    s_x[li] = (T)((double)s_x[li] + al * (double)s_p[li]);
                     const T r = (T)((double)rv[i] - al * (double)qv[i]);
                     rv[i] = r;
                     const double rd = (double)r;
-                    v[0] += rd * ((double)dv[i] * rd);
+                    v[0] += rd * ((double)s_d[row] * rd);
                     v[1] += rd * rd;
                 }
             }
@@ -1029,7 +1031,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_solve_small(const SysTable *__r
                 const int row = rt + i * rpp;
                 if (i < npass && row < n) {
                     const int li = row * kp + j;
-                    s_p[li] = (T)((double)dv[i] * (double)rv[i] + be * (double)s_p[li]);
+                    s_p[li] = (T)((double)s_d[row] * (double)rv[i] + be * (double)s_p[li]);
                 }
             }
         }
@@ -1037,14 +1039,14 @@ __global__ __launch_bounds__(kSmallBlock) void k_solve_small(const SysTable *__r
         nact = __syncthreads_count(threadIdx.x < kp && na);
     }
     // write back p, x and r; publish the state in both parity slots
-    for (int i = threadIdx.x; i < n * kp; i += kSmallBlock) Pg[i] = s_p[i];
+    for (int i = threadIdx.x; i < n * kp; i += kSmallBlock) {
+        Pg[i] = s_p[i];
+        X[i] = s_x[i];
+    }
 #pragma unroll
     for (int i = 0; i < kSmallPass; ++i) {
         const int row = rt + i * rpp;
-        if (i < npass && row < n) {
-            X[(int64_t)row * kp + j] = xv[i];
-            Rg[(int64_t)row * kp + j] = rv[i];
-        }
+        if (i < npass && row < n) Rg[(int64_t)row * kp + j] = rv[i];
     }
     const int bad = __syncthreads_count(threadIdx.x < kp && fl == FEMCG_EBREAKDOWN);
     if (threadIdx.x < kp) {
