@@ -152,6 +152,32 @@ __device__ void write_tile_partials(const SysDesc &D, int64_t tl, int d0, int nd
     __syncthreads();
 }
 
+// Same for one dot when each lane holds V adjacent columns: lane l serves
+// columns V*(l % (KP/V)) .. +V-1 of its row; v[t] is column V*(l % (KP/V)) + t.
+template <int KP, int V>
+__device__ void write_tile_partials_vec(const SysDesc &D, int64_t tl, int d0, const double *v)
+{
+    __shared__ double ws[kBlock / kWave][kMaxK];
+    constexpr int kp = KP, lpr = KP / V;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+#pragma unroll
+    for (int t = 0; t < V; ++t) {
+        double s = v[t];
+#pragma unroll
+        for (int off = kWave / 2; off >= lpr; off >>= 1) s += __shfl_xor(s, off, kWave);
+        if (lane < lpr) ws[wave][V * lane + t] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < kp) {
+        const int j = threadIdx.x;
+        const double val = ((ws[0][j] + ws[1][j]) + ws[2][j]) + ws[3][j];
+        GLOBAL double *dst = gptr(D.part) + ((int64_t)d0 * D.ntiles + tl) * kp + j;
+        if (D.band) st_agent(dst, val);
+        else *dst = val;
+    }
+    __syncthreads();
+}
+
 // out[(d-d0)*kp + j] = sum over the system's tiles of partial dot d, column j.
 // Thread (t0 = tid / kp, j = tid % kp) sums tiles t0, t0 + 256/kp, ... (the
 // loads of a wave are contiguous; the loads of all ND dots are issued together,
@@ -311,6 +337,9 @@ __device__ __forceinline__ void band_log(const SysDesc &D, int64_t tl, int d0, B
 #endif
 #ifndef FEMCG_KQ
 #define FEMCG_KQ 4
+#endif
+#ifndef FEMCG_KQV
+#define FEMCG_KQV 4
 #endif
 constexpr int kU = FEMCG_KU;  // rows per thread in flight
 constexpr int kE = 4;  // entries per row per chunk (one lane per row)
@@ -539,6 +568,90 @@ __device__ __forceinline__ void rows_dot_lds(const SysDesc &D, const int64_t *ro
     }
 }
 
+// Vector-wide variant of rows_dot_lds: kp / V lanes per row, lane j gathers
+// columns V*j .. V*j+V-1 of a row of X with one V-wide load.  The wider
+// loads halve (FP64) or quarter (FP32) the gather instructions per byte,
+// which bound the SpMM at kp >= 8.
+template <typename T, int V>
+using vec_t = T __attribute__((ext_vector_type(V)));
+template <typename T>
+constexpr int kVecW = sizeof(T) == 8 ? 2 : 4;
+
+template <typename T, int KP, int V, int kQ>
+__device__ __forceinline__ void rows_dot_lds_vec(const SysDesc &D, const int64_t *row, int j,
+                                                 const GLOBAL T *__restrict__ X, vec_t<T, V> *acc)
+{
+    constexpr int kp = KP, lpr = KP / V;
+    __shared__ int s_c[kBlock / kWave][kU][kWave];
+    __shared__ T s_v[kBlock / kWave][kU][kWave];
+    const GLOBAL T *__restrict__ val = gptr((const T *)D.val);
+    const GLOBAL int32_t *__restrict__ col = gptr(D.col);
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int gb = lane - j;  // first lane of this row's group
+    int64_t base[kU];
+    int len[kU];
+    int64_t stride;
+    int maxlen = 0;
+    if (D.format == FEM_FORMAT_SELL) {
+        const int sh = D.sell_shift;
+        stride = (int64_t)1 << sh;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const bool ok = row[u] < D.n;
+            base[u] = ok ? gptr(D.slice_ptr)[row[u] >> sh] + (row[u] & (stride - 1)) : 0;
+            len[u] = ok ? gptr(D.rowlen)[row[u]] : 0;
+            maxlen = max(maxlen, len[u]);
+        }
+    } else {
+        stride = 1;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const bool ok = row[u] < D.n;
+            base[u] = ok ? gptr(D.rowptr)[row[u]] : 0;
+            len[u] = ok ? gptr(D.rowptr)[row[u] + 1] - (int)base[u] : 0;
+            maxlen = max(maxlen, len[u]);
+        }
+    }
+    for (int off = kWave / 2; off >= 1; off >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, off, kWave));
+#pragma unroll
+    for (int u = 0; u < kU; ++u) acc[u] = (vec_t<T, V>)(T)0;
+    for (int e0 = 0; e0 < maxlen; e0 += lpr) {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int e = e0 + j;
+            const bool ok = e < len[u];
+            const int64_t idx = base[u] + (int64_t)(ok ? e : 0) * stride;
+            const T vv = val[idx];
+            s_c[wave][u][lane] = col[idx];
+            s_v[wave][u][lane] = ok ? vv : (T)0;
+        }
+        const int nq = min(lpr, maxlen - e0);
+        for (int q0 = 0; q0 < nq; q0 += kQ) {
+            int c[kU][kQ];
+            T v[kU][kQ];
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+#pragma unroll
+                for (int q = 0; q < kQ; ++q) {
+                    const int src = gb + min(q0 + q, lpr - 1);
+                    c[u][q] = s_c[wave][u][src];
+                    const T vv = s_v[wave][u][src];
+                    v[u][q] = q0 + q < nq ? vv : (T)0;
+                }
+            vec_t<T, V> x[kU][kQ];
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+#pragma unroll
+                for (int q = 0; q < kQ; ++q)
+                    x[u][q] = *(const GLOBAL vec_t<T, V> *)(X + (int64_t)c[u][q] * kp + V * j);
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+#pragma unroll
+                for (int q = 0; q < kQ; ++q) acc[u] += v[u][q] * x[u][q];
+        }
+    }
+}
+
 // kQ: broadcast entries per gather sub-chunk (kp lanes per row)
 template <typename T, int KP, int kQ = FEMCG_KQ>
 __device__ __forceinline__ void rows_product(const SysDesc &D, const int64_t *row, int j,
@@ -576,13 +689,60 @@ __global__ __launch_bounds__(kBlock) void k_spmm(const SysTable *__restrict__ ta
             Dlog = D;
         }
         constexpr int kp = KP;
-        const int j = threadIdx.x & (kp - 1);
         const int64_t tl = t - D.tile_base;
-        const int rps = kBlock / kp;
         const int64_t r0 = tl * D.tile_rows, r1 = min(D.n, r0 + D.tile_rows);
         const GLOBAL GLOBAL T *__restrict__ P = gptr((const T *)D.p);
         GLOBAL T *__restrict__ Q = gptr((T *)D.q);
         const bool fresh = s != s_sys;
+        if constexpr (KP / kVecW<T> >= 4) {
+            // V-wide lanes: kp / V lanes per row
+            constexpr int V = kVecW<T>, lpr = KP / V, rpsv = kBlock / lpr;
+            const int jv = threadIdx.x & (lpr - 1);
+            const int a_in = (fresh && threadIdx.x < D.k) ? gptr(D.st)->active[((it + D.par_off) & 1) ^ 1][threadIdx.x] : 0;
+            int64_t rb = r0 + threadIdx.x / lpr;
+            int64_t row[kU];
+            vec_t<T, V> acc[kU];
+            auto batch = [&](int64_t b) {
+#pragma unroll
+                for (int u = 0; u < kU; ++u) {
+                    row[u] = b + (int64_t)u * rpsv;
+                    if (row[u] >= r1) row[u] = D.n;  // masked
+                }
+                rows_dot_lds_vec<T, KP, V, FEMCG_KQV>(D, row, jv, P, acc);
+            };
+            batch(rb);
+            if (fresh) {
+                const int any = __syncthreads_or(a_in);
+                if (threadIdx.x == 0) {
+                    s_sys = s;
+                    s_any = any;
+                }
+                __syncthreads();
+            }
+            if (!force && !s_any) return;
+            double v[V];
+#pragma unroll
+            for (int t2 = 0; t2 < V; ++t2) v[t2] = 0.0;
+            for (;;) {
+#pragma unroll
+                for (int u = 0; u < kU; ++u)
+                    if (row[u] < D.n) {
+                        const int64_t idx = row[u] * kp + V * jv;
+                        *(GLOBAL vec_t<T, V> *)(Q + idx) = acc[u];
+                        const vec_t<T, V> pv = *(const GLOBAL vec_t<T, V> *)(P + idx);
+#pragma unroll
+                        for (int t2 = 0; t2 < V; ++t2) v[t2] += (double)pv[t2] * (double)acc[u][t2];
+                    }
+                rb += (int64_t)kU * rpsv;
+                if (rb >= r1) break;
+                batch(rb);
+            }
+            write_tile_partials_vec<KP, V>(D, tl, DOT0, v);
+            if (D.band) band_log<1, KP>(D, tl, DOT0, lg);
+            return;
+        }
+        const int j = threadIdx.x & (kp - 1);
+        const int rps = kBlock / kp;
         // the active-column check of a new system overlaps the first batch
         const int a_in = (fresh && threadIdx.x < D.k) ? gptr(D.st)->active[((it + D.par_off) & 1) ^ 1][threadIdx.x] : 0;
         int64_t rb = r0 + threadIdx.x / kp;
