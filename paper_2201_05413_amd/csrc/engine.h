@@ -27,6 +27,7 @@ struct Work {
     int tile_rows = 0, ntiles = 0, ngroups = 0;
     int band = 0;
     int small = 0;  // whole iteration loop in one workgroup (k_solve_small)
+    int nt = 0;     // iteration working set beyond the last-level cache: streaming hints
     // small systems: the matrix padded per workgroup thread, [pass][ell_len][1024/kp]
     int ell_len = 0;
     int32_t *ell_col = nullptr;

@@ -188,6 +188,15 @@ int get_work(fem_matrix *A, int kp, int prec, Work **out)
         return fail(FEMCG_EINVAL, "single-workgroup mode needs n * kp <= %d (n = %lld, kp = %d)", kSmallElems,
                     (long long)w->n, kp);
     w->small = A->band_mode == 2 || (A->band_mode == -1 && fits_small);
+    {
+        // one iteration touches the matrix, x, r, p, q and D^-1; the MI355X
+        // last-level (Infinity) cache holds 256 MB
+        const double sv = prec == PCG_FP64 ? 8.0 : 4.0;
+        const double vb = (double)w->n * kp * sv;
+        const double mb = (double)A->sc.stored * (sv + 4.0);
+        w->nt = (mb + 4.0 * vb + (double)w->n * sv) > 256e6 ? 1 : 0;
+        if (const char *ev = std::getenv("FEMCG_NT")) w->nt = atoi(ev);  // tuning override
+    }
     if (const char *ev = std::getenv("FEMCG_SMALL")) w->small = w->small && atoi(ev) != 0;  // tuning override
     w->ngroups = (w->ntiles + kGroup - 1) / kGroup;
     const size_t nv = (size_t)std::max<int64_t>(w->n, 1) * kp;
@@ -288,6 +297,7 @@ static SysDesc make_desc(const fem_matrix *A, const Work *w, bool fp32, const vo
     D.ell_col = w->ell_col;
     D.ell_val = fp32 ? (const void *)w->ell_v32 : (const void *)w->ell_v64;
     D.ell_len = w->ell_len;
+    D.nt = w->nt;
     D.gpart = fp32 ? w->gpart32 : w->gpart64;
     D.gticket = fp32 ? w->gtk32 : w->gtk64;
     return D;
@@ -1313,23 +1323,37 @@ int pcg_time_kernel(fem_matrix *A, int32_t kernel, int32_t reps, void *stream, d
     e->main_ids.clear();
     e->main_dirty = true;
     const int grid = grid_for(h->total_tiles, grid_cap(A, w));
-    hipEvent_t a, b;
-    HIPCHK(hipEventCreate(&a));
-    HIPCHK(hipEventCreate(&b));
-    auto launch = [&]() {
-        if (fp32) launch_phase<float>(kernel, e->d_main, grid, 0, 1, cm, s);
-        else launch_phase<double>(kernel, e->d_main, grid, 0, 1, cm, s);
+    auto launch = [&](int ph) {
+        if (fp32) launch_phase<float>(ph, e->d_main, grid, 0, 1, cm, s);
+        else launch_phase<double>(ph, e->d_main, grid, 0, 1, cm, s);
     };
-    launch();  // warm
-    HIPCHK(hipEventRecord(a, s));
-    for (int r = 0; r < reps; ++r) launch();
-    HIPCHK(hipEventRecord(b, s));
-    HIPCHK(hipEventSynchronize(b));
-    float t = 0;
-    HIPCHK(hipEventElapsedTime(&t, a, b));
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
-    *ms = t / reps;
+    std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
+    int rc = FEMCG_OK;
+    for (auto &x : ev)
+        if (hipEventCreate(&x) != hipSuccess) rc = fail(FEMCG_EDEVICE, "hipEventCreate failed");
+    double tot = 0.0;
+    if (rc == FEMCG_OK) {
+        for (int ph = 0; ph < 3; ++ph) launch(ph);  // one untimed iteration
+        for (int r = 0; r < reps; ++r)
+            for (int ph = 0; ph < 3; ++ph) {
+                if (ph == kernel) (void)hipEventRecord(ev[2 * r], s);
+                launch(ph);
+                if (ph == kernel) (void)hipEventRecord(ev[2 * r + 1], s);
+            }
+        hipError_t ce = hipEventSynchronize(ev[2 * reps - 1]);
+        if (ce == hipSuccess) ce = hipGetLastError();
+        if (ce != hipSuccess) rc = fail(FEMCG_EDEVICE, "kernel timing: %s", hipGetErrorString(ce));
+        for (int r = 0; r < reps && rc == FEMCG_OK; ++r) {
+            float t = 0;
+            if (hipEventElapsedTime(&t, ev[2 * r], ev[2 * r + 1]) != hipSuccess)
+                rc = fail(FEMCG_EDEVICE, "hipEventElapsedTime failed");
+            tot += t;
+        }
+    }
+    for (auto &x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (rc) return rc;
+    *ms = tot / reps;
     if (bytes) {
         const double n = (double)A->sc.n, nnz = (double)A->sc.nnz, k = A->stats.k, sv = fp32 ? 4.0 : 8.0;
         const double idx = A->sc.format == FEM_FORMAT_SELL ? 4.0 * n : 4.0 * (n + 1);

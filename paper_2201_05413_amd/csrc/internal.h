@@ -87,7 +87,7 @@ struct SysDesc {
     const int32_t *ell_col;
     const void *ell_val;    // T
     int32_t ell_len;
-    int32_t pad_e;
+    int32_t nt;             // 1: x, r, q accessed non-temporally (working set beyond the LLC)
 };
 
 constexpr int kMaxSys = 256;
