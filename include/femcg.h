@@ -194,9 +194,10 @@ int fem_set_tiling(fem_matrix *A, int32_t band, int32_t tile);
 
 /* Time one hot kernel of the iteration on the workspace of the last solve
  * (same launch configuration as inside the solve): `reps` full iterations
- * (SpMM, update, p-update, every column forced active) run on `stream`, and
- * HIP events bracket each launch of the chosen kernel only, so the caches
- * hold what they hold inside a solve.  kernel: 0 = SpMM + p.q, 1 = fused
+ * (SpMM, update, p-update, every column forced active) run on `stream`, so
+ * the caches hold what they hold inside a solve; each launch of the chosen
+ * kernel records its start and end into HIP events from its dispatch packet
+ * (hipExtLaunchKernel), the times a kernel trace reports.  kernel: 0 = SpMM + p.q, 1 = fused
  * update, 2 = p-update.  Writes the mean duration in ms and the algorithmic
  * bytes of one launch.  Overwrites the workspace vectors (not B or X). */
 int pcg_time_kernel(fem_matrix *A, int32_t kernel, int32_t reps, void *stream, double *ms,

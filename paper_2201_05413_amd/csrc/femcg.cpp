@@ -1333,12 +1333,13 @@ int pcg_time_kernel(fem_matrix *A, int32_t kernel, int32_t reps, void *stream, d
         if (hipEventCreate(&x) != hipSuccess) rc = fail(FEMCG_EDEVICE, "hipEventCreate failed");
     double tot = 0.0;
     if (rc == FEMCG_OK) {
+        const int cls = class_of(kp);
         for (int ph = 0; ph < 3; ++ph) launch(ph);  // one untimed iteration
         for (int r = 0; r < reps; ++r)
             for (int ph = 0; ph < 3; ++ph) {
-                if (ph == kernel) (void)hipEventRecord(ev[2 * r], s);
-                launch(ph);
-                if (ph == kernel) (void)hipEventRecord(ev[2 * r + 1], s);
+                if (ph != kernel) launch(ph);
+                else if (fp32) launch_phase_timed<float>(ph, e->d_main, grid, 0, 1, cls, s, ev[2 * r], ev[2 * r + 1]);
+                else launch_phase_timed<double>(ph, e->d_main, grid, 0, 1, cls, s, ev[2 * r], ev[2 * r + 1]);
             }
         hipError_t ce = hipEventSynchronize(ev[2 * reps - 1]);
         if (ce == hipSuccess) ce = hipGetLastError();

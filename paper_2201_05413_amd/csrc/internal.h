@@ -138,6 +138,11 @@ void launch_phase(int phase, const SysTable *tab, int grid, int it, int force, u
 // per-system finalize (one block per system) that decides which columns iterate
 template <typename T>
 void launch_residual_init(const SysTable *tab, int grid, int nsys, unsigned cls_mask, hipStream_t s);
+// One phase of a single-class table (class cls: kp = 1 << cls), with the
+// kernel's start and end recorded into ev0 / ev1 by its dispatch packet.
+template <typename T>
+void launch_phase_timed(int phase, const SysTable *tab, int grid, int it, int force, int cls, hipStream_t s,
+                        hipEvent_t ev0, hipEvent_t ev1);
 // Small systems (n * kp <= kSmallElems): `niter` iterations, one workgroup
 // per system; the table's class ranges index systems, cls_count[c] of them.
 template <typename T>

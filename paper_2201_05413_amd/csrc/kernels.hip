@@ -30,6 +30,8 @@
 // point; the roofline is HBM bandwidth.
 #include "internal.h"
 
+#include <hip/hip_ext.h>
+
 #include <type_traits>
 
 namespace femcg {
@@ -367,7 +369,10 @@ __device__ __forceinline__ void band_log(const SysDesc &D, int64_t tl, int d0, B
 #define FEMCG_KQV 4
 #endif
 constexpr int kU = FEMCG_KU;  // rows per thread in flight
-constexpr int kE = 4;  // entries per row per chunk (one lane per row)
+#ifndef FEMCG_KE
+#define FEMCG_KE 4
+#endif
+constexpr int kE = FEMCG_KE;  // entries per row per chunk (one lane per row)
 constexpr int kV = FEMCG_KV < FEMCG_KU ? FEMCG_KV : FEMCG_KU;  // rows per sub-chunk (kp lanes per row)
 
 template <typename T>
@@ -1561,6 +1566,39 @@ void launch_phase(int phase, const SysTable *tab, int grid, int it, int force, u
     if (cls_mask & 32) launch_phase_kp<T, 32>(phase, tab, grid, it, force, s);
     if (cls_mask & 64) launch_phase_kp<T, 64>(phase, tab, grid, it, force, s);
 }
+
+// One phase kernel of a single kp class with the dispatch packet's own start
+// and end times recorded into ev0 / ev1 (the times a kernel trace reports).
+template <typename T, int KP>
+static void launch_phase_kp_timed(int phase, const SysTable *tab, int grid, int it, int force, hipStream_t s,
+                                  hipEvent_t ev0, hipEvent_t ev1)
+{
+    if (phase == PH_SPMM)
+        hipExtLaunchKernelGGL((k_spmm<T, KP>), dim3(grid), dim3(kBlock), 0, s, ev0, ev1, 0, tab, it, force);
+    else if (phase == PH_UPDATE)
+        hipExtLaunchKernelGGL((k_update<T, KP>), dim3(grid), dim3(kBlock), 0, s, ev0, ev1, 0, tab, it, force);
+    else
+        hipExtLaunchKernelGGL((k_pupdate<T, KP>), dim3(grid), dim3(kBlock), 0, s, ev0, ev1, 0, tab, it, force);
+}
+
+template <typename T>
+void launch_phase_timed(int phase, const SysTable *tab, int grid, int it, int force, int cls, hipStream_t s,
+                        hipEvent_t ev0, hipEvent_t ev1)
+{
+    switch (cls) {
+    case 0: launch_phase_kp_timed<T, 1>(phase, tab, grid, it, force, s, ev0, ev1); break;
+    case 1: launch_phase_kp_timed<T, 2>(phase, tab, grid, it, force, s, ev0, ev1); break;
+    case 2: launch_phase_kp_timed<T, 4>(phase, tab, grid, it, force, s, ev0, ev1); break;
+    case 3: launch_phase_kp_timed<T, 8>(phase, tab, grid, it, force, s, ev0, ev1); break;
+    case 4: launch_phase_kp_timed<T, 16>(phase, tab, grid, it, force, s, ev0, ev1); break;
+    case 5: launch_phase_kp_timed<T, 32>(phase, tab, grid, it, force, s, ev0, ev1); break;
+    default: launch_phase_kp_timed<T, 64>(phase, tab, grid, it, force, s, ev0, ev1); break;
+    }
+}
+template void launch_phase_timed<double>(int, const SysTable *, int, int, int, int, hipStream_t, hipEvent_t,
+                                         hipEvent_t);
+template void launch_phase_timed<float>(int, const SysTable *, int, int, int, int, hipStream_t, hipEvent_t,
+                                        hipEvent_t);
 
 template <typename T>
 void launch_residual_init(const SysTable *tab, int grid, int nsys, unsigned cls_mask, hipStream_t s)
