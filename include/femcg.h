@@ -188,7 +188,8 @@ int fem_set_format(fem_matrix *A, int32_t format, int32_t C, int32_t sigma);
  * kp = k rounded up to a power of two, else pcg_solve fails with
  * FEMCG_EINVAL); band = -1: automatic (band 2 when it fits, else band 1 for
  * vectors above 64 MB, else band 0).  tile: rows per tile target count
- * (band 0) or bytes of one FP64 vector slice per tile (band 1); 0 = default.
+ * (band 0) or bytes of one FP64 vector slice per tile (band 1); 0 = default
+ * (band 1: 16..64 KB, sized for about 4096 tiles).
  * Drops cached workspaces. */
 int fem_set_tiling(fem_matrix *A, int32_t band, int32_t tile);
 

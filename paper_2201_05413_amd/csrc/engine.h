@@ -61,7 +61,7 @@ struct fem_matrix {
     double *d_lval = nullptr;
     int tile_target = 0;  // 0 = automatic
     int band_mode = -1;   // -1 automatic; 0 tile, 1 band, 2 single-workgroup loop forced
-    int band_tile_bytes = 32768;
+    int band_tile_bytes = 0;  // 0 = automatic
     int max_grid = 2048;
     std::map<std::pair<int, int>, std::unique_ptr<femcg::Work>> works;
     std::map<std::pair<int, int>, std::unique_ptr<femcg::Engine>> engines;

@@ -144,7 +144,13 @@ static void choose_tiles(const fem_matrix *A, int kp, int &tile_rows, int &ntile
     if (const char *ev = std::getenv("FEMCG_BAND")) band = atoi(ev);  // tuning override
     int64_t rows;
     if (band) {
+        // automatic: about 4096 tiles (enough blocks to fill the chip with one
+        // tile each), 16..64 KB of one vector per tile
         int tb = A->band_tile_bytes;
+        if (tb <= 0) {
+            tb = 16384;
+            while (tb < 65536 && vec_bytes / (2.0 * tb) >= 4096.0) tb *= 2;
+        }
         if (const char *ev = std::getenv("FEMCG_BAND_TILE_BYTES")) tb = std::max(1024, atoi(ev));
         rows = std::max<int64_t>(1, tb / (kp * 8));
     } else {
@@ -1292,7 +1298,7 @@ int fem_set_tiling(fem_matrix *A, int32_t band, int32_t tile)
 {
     if (!A || band < -1 || band > 2 || tile < 0) return fail(FEMCG_EINVAL, "bad tiling arguments");
     A->band_mode = band;
-    if (band == 1) A->band_tile_bytes = tile > 0 ? std::max(1024, (int)tile) : 32768;
+    if (band == 1) A->band_tile_bytes = tile > 0 ? std::max(1024, (int)tile) : 0;
     else A->tile_target = tile;
     A->engines.clear();
     A->works.clear();
