@@ -277,18 +277,21 @@ def run_single(args):
 
 def run_serve(args):
     """Serving stream: Poisson arrivals of mixed 2D/3D, P1/P2, structured/jittered
-    requests with 1..16 random harmonic right-hand sides, tol 1e-8.  The server
-    (continuous batching, admission by device footprint) is compared with
-    one-at-a-time FP64 PCG replaying the same arrival trace."""
+    requests with 1..16 random harmonic right-hand sides, tol 1e-8.  First the
+    server's capacity (every request submitted at once), then the same requests
+    replayed as Poisson arrivals at fractions of that capacity; one-at-a-time
+    FP64 PCG replays the trace at 0.7x capacity for comparison."""
+    import ctypes as C
+
     import numpy as np
     import torch
 
     import meshgen
-    import oracle
     from paper_2201_05413_amd import femcg
 
     torch.cuda.set_device(0)
-    reqs = meshgen.request_stream(args.n_requests, args.rate, seed=6, max2d=args.max2d, max3d=args.max3d)
+    # arrival times at rate 1; a trace at rate r divides them by r
+    reqs = meshgen.request_stream(args.n_requests, 1.0, seed=6, max2d=args.max2d, max3d=args.max3d)
     t0 = time.time()
     wls = [meshgen.build_request(r) for r in reqs]
     log("generated %d requests in %.1f s" % (len(wls), time.time() - t0))
@@ -309,52 +312,64 @@ def run_serve(args):
             e = np.unique(np.concatenate(pairs))
             mid = 0.5 * (coords[e >> 32] + coords[e & 0xFFFFFFFF])
             coords = np.concatenate([coords, mid])
-        gs.append(w.dirichlet(coords))
-    budget = args.budget_gb * 1e9
+        gs.append(np.ascontiguousarray(w.dirichlet(coords)))
     prec = femcg.PCG_MIXED if args.serve_mixed else femcg.PCG_FP64
     L = femcg.lib()
-    import ctypes as C
-    srv = C.c_void_p()
-    femcg._check(L.serve_create(budget, args.slots, prec, args.check_every, C.byref(srv)))
-    keep = []
-    ids = {}
-    done = {}
-    t_start = L.serve_clock(srv)
-    nxt = 0
-    while len(done) < len(reqs):
-        now = L.serve_clock(srv) - t_start
-        while nxt < len(reqs) and reqs[nxt]["t_arrival"] <= now:
-            w = wls[nxt]
-            m, hold = femcg.make_mesh_struct(w.mesh)
-            g = np.ascontiguousarray(gs[nxt])
-            keep.append((hold, g))
-            rid = L.serve_submit(srv, C.byref(m), w.order, femcg._np_ptr(g), w.k, w.tol)
-            femcg._check(rid)
-            ids[rid] = nxt
-            nxt += 1
-        open_ = L.serve_step(srv)
-        femcg._check(open_)
-        for rid in list(ids):
-            info = femcg.fem_request_info()
-            r = L.serve_poll(srv, rid, None, C.byref(info))
-            if r == 1:
-                i = ids.pop(rid)
-                done[i] = dict(status=info.status, t_arr=reqs[i]["t_arrival"], t_submit=info.t_submit - t_start,
-                               t_ready=info.t_ready - t_start, t_admit=info.t_admit - t_start,
-                               t_done=info.t_done - t_start, iters=info.iters_max, relres=info.relres_max,
-                               n=info.n, k=info.k)
-        if open_ == 0 and nxt < len(reqs):
-            time.sleep(max(0.0, min(0.01, reqs[nxt]["t_arrival"] - (L.serve_clock(srv) - t_start))))
-    T_srv = max(d["t_done"] for d in done.values())
-    L.serve_destroy(srv)
-    lat = [d["t_done"] - d["t_arr"] for d in done.values()]
-    lat_solve = [d["t_done"] - d["t_ready"] for d in done.values()]
-    bad = [i for i, d in done.items() if d["status"] != 0 or d["relres"] > reqs[i].get("tol", 1e-8) * 1.0001]
+    meshes = [femcg.make_mesh_struct(w.mesh) for w in wls]
+
+    def serve(t_arr):
+        """Replay arrival times t_arr (seconds) through a fresh server."""
+        srv = C.c_void_p()
+        femcg._check(L.serve_create(args.budget_gb * 1e9, args.slots, prec, args.check_every, C.byref(srv)))
+        ids, done = {}, {}
+        t_start = L.serve_clock(srv)
+        nxt = 0
+        while len(done) < len(wls):
+            now = L.serve_clock(srv) - t_start
+            while nxt < len(wls) and t_arr[nxt] <= now:
+                m, _ = meshes[nxt]
+                rid = L.serve_submit(srv, C.byref(m), wls[nxt].order, femcg._np_ptr(gs[nxt]), wls[nxt].k,
+                                     wls[nxt].tol)
+                femcg._check(rid)
+                ids[rid] = nxt
+                nxt += 1
+            open_ = L.serve_step(srv)
+            femcg._check(open_)
+            for rid in list(ids):
+                info = femcg.fem_request_info()
+                if L.serve_poll(srv, rid, None, C.byref(info)) == 1:
+                    i = ids.pop(rid)
+                    done[i] = dict(status=info.status, t_arr=t_arr[i], t_ready=info.t_ready - t_start,
+                                   t_done=info.t_done - t_start, relres=info.relres_max)
+            if open_ == 0 and nxt < len(wls):
+                time.sleep(max(0.0, min(0.01, t_arr[nxt] - (L.serve_clock(srv) - t_start))))
+        L.serve_destroy(srv)
+        T = max(d["t_done"] for d in done.values())
+        lat = [d["t_done"] - d["t_arr"] for d in done.values()]
+        lat_s = [d["t_done"] - max(d["t_ready"], d["t_arr"]) for d in done.values()]
+        bad = [i for i, d in done.items() if d["status"] != 0 or d["relres"] > wls[i].tol * 1.0001]
+        return dict(solves_per_s=round(len(wls) / T, 3), wall_s=round(T, 3),
+                    p50_ms=round(1e3 * percentile(lat, 50), 2), p99_ms=round(1e3 * percentile(lat, 99), 2),
+                    p50_excl_assembly_ms=round(1e3 * percentile(lat_s, 50), 2),
+                    p99_excl_assembly_ms=round(1e3 * percentile(lat_s, 99), 2), failed_or_above_tol=bad)
+
+    base = np.array([r["t_arrival"] for r in reqs])
+    cap = serve(np.zeros(len(wls)))
+    capacity = cap["solves_per_s"]
+    log("capacity (all submitted at t=0): %.3f solves/s in %.2f s" % (capacity, cap["wall_s"]))
+    sweep = []
+    for f in args.serve_fractions:
+        rate = f * capacity
+        r = serve(base / rate)
+        r.update(fraction=f, rate_per_s=round(rate, 3))
+        sweep.append(r)
+        log("rate %.2f/s (%.1fx capacity): %.3f solves/s, p50 %.0f ms, p99 %.0f ms"
+            % (rate, f, r["solves_per_s"], r["p50_ms"], r["p99_ms"]))
+    ref = min(args.serve_fractions, key=lambda f: abs(f - 0.7))
+    t_ref = base / (ref * capacity)
     # one-at-a-time FP64 PCG on the same trace
-    t_free = 0.0
-    lat1 = []
+    t_free, lat1 = 0.0, []
     for i, w in enumerate(wls):
-        t_arr = reqs[i]["t_arrival"]
         ta = time.perf_counter()
         A = femcg.Matrix(w.mesh, w.order)
         B = torch.empty((A.n_free, w.k), dtype=torch.float64, device="cuda")
@@ -363,26 +378,27 @@ def run_serve(args):
         femcg.pcg_solve(A, B, X, w.tol, femcg.default_opts(tol=w.tol, check_every=args.check_every))
         torch.cuda.synchronize()
         dur = time.perf_counter() - ta
-        start = max(t_arr, t_free)
+        start = max(t_ref[i], t_free)
         t_free = start + dur
-        lat1.append(t_free - t_arr)
-        del A
-    T_one = t_free
+        lat1.append(t_free - t_ref[i])
+        del A, B, X
+    main = [r for r in sweep if r["fraction"] == ref][0]
     line = {
-        "metric": METRIC, "value": round(len(reqs) / T_srv, 3), "unit": "solves/s", "n_gpus": 1,
-        "steps": len(reqs), "warmup": 0, "ms_per_step": round(1e3 * T_srv / len(reqs), 3),
+        "metric": METRIC, "value": capacity, "unit": "solves/s", "n_gpus": 1,
+        "steps": len(wls), "warmup": 0, "ms_per_step": round(1e3 / capacity, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32-inner/f64-refined" if args.serve_mixed else "f64", "data": "synthetic",
         "config": {"workload": "c5_serving_stream", "recipe": " ".join((run_serve.__doc__ or "").split()),
-                   "n_requests": len(reqs), "rate_per_s": args.rate, "slots": args.slots,
-                   "budget_gb": args.budget_gb, "max2d": args.max2d, "max3d": args.max3d},
-        "latency_ms": {"p50": round(1e3 * percentile(lat, 50), 2), "p99": round(1e3 * percentile(lat, 99), 2),
-                       "p50_excl_assembly": round(1e3 * percentile(lat_solve, 50), 2),
-                       "p99_excl_assembly": round(1e3 * percentile(lat_solve, 99), 2)},
-        "one_at_a_time_fp64": {"solves_per_s": round(len(reqs) / T_one, 3),
+                   "n_requests": len(wls), "slots": args.slots, "budget_gb": args.budget_gb,
+                   "max2d": args.max2d, "max3d": args.max3d, "check_every": args.check_every},
+        "capacity_run": cap,
+        "latency_ms": {"rate_per_s": main["rate_per_s"], "fraction_of_capacity": ref, "p50": main["p50_ms"],
+                       "p99": main["p99_ms"], "p50_excl_assembly": main["p50_excl_assembly_ms"],
+                       "p99_excl_assembly": main["p99_excl_assembly_ms"]},
+        "sweep": sweep,
+        "one_at_a_time_fp64": {"rate_per_s": main["rate_per_s"], "solves_per_s": round(len(wls) / t_free, 3),
                                "p50_ms": round(1e3 * percentile(lat1, 50), 2),
                                "p99_ms": round(1e3 * percentile(lat1, 99), 2)},
-        "failed_or_above_tol": bad,
     }
     print(json.dumps(line), flush=True)
 
@@ -415,7 +431,8 @@ def main():
                     help="counter runs: FP64 solve capped at this many iterations, kernels timed, no JSON line")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--n-requests", type=int, default=40)
-    ap.add_argument("--rate", type=float, default=20.0)
+    ap.add_argument("--serve-fractions", type=float, nargs="+", default=[0.3, 0.7, 1.0],
+                    help="serving: arrival rates as fractions of the measured capacity")
     ap.add_argument("--slots", type=int, default=32)
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--max2d", type=int, default=1024)

@@ -1391,7 +1391,11 @@ __global__ __launch_bounds__(kBlock) void k_residual_final(const SysTable *__res
             st->bb[c] = bb;
             st->rr[c] = rr;
             st->relres[c] = bb > 0.0 ? sqrt(rr / bb) : 0.0;
-            if (st->flag[c] == 0 && bb > 0.0) {
+            if (st->flag[c] == 0 && !isfinite(bb)) {
+                // non-finite right-hand side: a non-finite scalar (breakdown)
+                st->flag[c] = FEMCG_EBREAKDOWN;
+                bad = 1;
+            } else if (st->flag[c] == 0 && bb > 0.0) {
                 const double thr = st->tol_rel[c] * st->tol_rel[c] * bb;
                 if (!(rr <= thr)) {
                     if (!(rz > 0.0) || !isfinite(rz) || !isfinite(rr)) {

@@ -1,0 +1,58 @@
+"""Parity at the full benchmark sizes, in the launch configuration bench.py
+times (autotuned format, check_every 64, FP64 and mixed): the oracle's own
+Eq. (2) residual of every column (R), and the closed forms where the exact
+discrete solution is known (C3: nodal harmonic cubics on the structured
+Kuhn mesh; C4 column 0: the P2 interpolant of x^2 - y^2), within the bound a
+1e-8 residual allows."""
+import numpy as np
+import pytest
+
+import meshgen
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+from paper_2201_05413_amd import femcg  # noqa: E402
+
+
+def _run(w):
+    A = femcg.Matrix(w.mesh, w.order)
+    coords, _, f2d = A.dofs()
+    g = w.dirichlet(coords)
+    B = torch.empty((A.n_free, w.k), dtype=torch.float64, device="cuda")
+    femcg.fem_rhs(A, g, B)
+    femcg.fem_tune(A, w.k, femcg.PCG_FP64)
+    out = {}
+    for prec in (femcg.PCG_FP64, femcg.PCG_MIXED):
+        X = torch.zeros_like(B)
+        rc = femcg.pcg_solve(A, B, X, w.tol, femcg.default_opts(tol=w.tol, precision=prec, check_every=64))
+        torch.cuda.synchronize()
+        assert rc == 0, (w.name, prec, A.stats())
+        out[prec] = X.cpu().numpy()
+    del B, A
+    orc = oracle.System(w.mesh, w.order)
+    Bo = orc.rhs(g)
+    for prec, X in out.items():
+        rel = orc.relres(Bo, X)
+        assert np.all(rel <= w.tol * 1.0001), (w.name, prec, rel.max())
+    return g, f2d, out
+
+
+def test_c2_full_size():
+    _run(meshgen.c2())
+
+
+def test_c3_full_size_and_cubics():
+    w = meshgen.c3()
+    g, f2d, out = _run(w)
+    for X in out.values():
+        for j in range(w.k):
+            assert oracle.x_err(g[f2d, j], X[:, j]) <= 1e-5
+
+
+def test_c4_full_size_and_column0_closed_form():
+    w = meshgen.c4()
+    g, f2d, out = _run(w)
+    for X in out.values():
+        assert oracle.x_err(g[f2d, 0], X[:, 0]) <= 1e-5
