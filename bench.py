@@ -72,7 +72,16 @@ def cpu_baseline(w, budget_s=15.0):
     el = time.time() - t0
     n, nnz = s.nfree, s.nnz_A
     rate = iter_bytes(n, nnz, 1, 8) * int(it[0]) / el / 1e9
-    return dict(value=round(rate, 3), unit="GB/s", cores=1, kind="oracle",
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return dict(value=round(rate, 3), unit="GB/s", cores=1, kind="oracle", cpu_model=model,
+                host_threads=os.cpu_count(),
                 sample="oracle FP64 Jacobi-PCG, column 0 of %s, first %d iterations (%.1f s; %.2f ms/iteration; "
                        "assembly %.1f s), algorithmic bytes as the GPU line (structural nnz %d)"
                        % (w.name, int(it[0]), el, 1e3 * el / int(it[0]), t_asm, nnz),
