@@ -412,6 +412,66 @@ def run_serve(args):
     print(json.dumps(line), flush=True)
 
 
+def run_assembly(args):
+    """Assembly of A = K_II and K_ID (Sect. 2.2 systems) on the host, on the
+    device (FEM_ASSEMBLE_DEVICE) and by the oracle, for the C2-C4 meshes and
+    3D P2 meshes of growing size; the device result is compared with the
+    host result entry by entry (identical pattern, values to rounding)."""
+    import numpy as np
+    import torch
+
+    import meshgen
+    import oracle
+    from paper_2201_05413_amd import femcg
+
+    torch.cuda.set_device(0)
+    cases = [("c2_2d_p1_jit_1024", meshgen.c2().mesh, 1), ("c3_3d_p1_128", meshgen.c3().mesh, 1),
+             ("c4_2d_p2_jit_513", meshgen.c4().mesh, 2)]
+    for m in args.asm_p2_sides:
+        cases.append(("3d_p2_jit_%d" % m, meshgen.make_mesh(3, m, 0.3, 7), 2))
+    rows = []
+    for name, mesh, order in cases:
+        # warm the device path once (first-use costs), then time both
+        femcg.Matrix(meshgen.make_mesh(mesh["coords"].shape[1], 8, 0.0, 1), order,
+                     femcg.FEM_FORMAT_SELL | femcg.FEM_ASSEMBLE_DEVICE).free()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Ad = femcg.Matrix(mesh, order, femcg.FEM_FORMAT_SELL | femcg.FEM_ASSEMBLE_DEVICE)
+        t_dev = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        Ah = femcg.Matrix(mesh, order, femcg.FEM_FORMAT_SELL)
+        t_host = time.perf_counter() - t0
+        rph, colh, valh = Ah.csr()
+        rpd, cold, vald = Ad.csr()
+        same = bool(np.array_equal(rph, rpd) and np.array_equal(colh, cold))
+        rowmax = np.maximum.reduceat(np.abs(valh), rph[:-1])
+        dmax = np.maximum.reduceat(np.abs(vald - valh), rph[:-1])
+        rel = float((dmax / rowmax).max())
+        row = dict(mesh=name, order=order, n_free=Ah.n_free, nnz=int(colh.size), host_s=round(t_host, 3),
+                   device_s=round(t_dev, 3), speedup=round(t_host / t_dev, 2), pattern_identical=same,
+                   max_row_rel_diff=rel)
+        Ah.free()
+        Ad.free()
+        if Ah.n_free <= args.asm_oracle_max_n:
+            t0 = time.perf_counter()
+            oracle.System(mesh, order)
+            row["oracle_s"] = round(time.perf_counter() - t0, 3)
+        rows.append(row)
+        log("assembly %s: n %d nnz %d host %.2f s device %.3f s (x%.1f), identical pattern %s, max row diff %.1e%s"
+            % (name, row["n_free"], row["nnz"], t_host, t_dev, t_host / t_dev, same, rel,
+               (", oracle %.2f s" % row["oracle_s"]) if "oracle_s" in row else ""))
+    big = rows[-1]
+    line = {
+        "metric": "FEM assembly wall time, host vs device", "value": big["device_s"], "unit": "s",
+        "n_gpus": 1, "steps": len(rows), "warmup": 1, "ms_per_step": None, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "assembly", "recipe": " ".join((run_assembly.__doc__ or "").split()),
+                   "largest": big["mesh"]},
+        "assembly": rows,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def meshgen_doc(name):
     import meshgen
     f = {"c1": meshgen.c1, "c2": meshgen.c2, "c3": meshgen.c3, "c4": meshgen.c4}[name]
@@ -423,7 +483,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "asm"])
     ap.add_argument("--check-every", type=int, default=64)
     ap.add_argument("--format", default="auto", help="auto (tuner) | csr | sell:C:sigma")
     ap.add_argument("--order", default="natural", choices=["natural", "sfc"])
@@ -440,6 +500,10 @@ def main():
                     help="counter runs: FP64 solve capped at this many iterations, kernels timed, no JSON line")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--n-requests", type=int, default=40)
+    ap.add_argument("--asm-p2-sides", type=int, nargs="*", default=[48, 96],
+                    help="assembly timing: sides of the extra 3D P2 meshes")
+    ap.add_argument("--asm-oracle-max-n", type=int, default=3000000,
+                    help="assembly timing: time the oracle's assembly up to this many free DOFs")
     ap.add_argument("--serve-fractions", type=float, nargs="+", default=[0.3, 0.7, 1.0],
                     help="serving: arrival rates as fractions of the measured capacity")
     ap.add_argument("--slots", type=int, default=32)
@@ -457,6 +521,8 @@ def main():
         sys.exit(2)
     if args.workload == "c5":
         run_serve(args)
+    elif args.workload == "asm":
+        run_assembly(args)
     else:
         run_single(args)
 

@@ -54,6 +54,7 @@ extern "C" {
 #define FEM_FORMAT_AUTO 2        /* chosen by the autotuner (fem_tune) */
 #define FEM_ORDER_SFC 0x10       /* flag for fem_set_format: internal rows in Morton
                                     (Z-curve) order of the DOF coordinates */
+#define FEM_ASSEMBLE_DEVICE 0x100 /* flag for fem_assemble: assemble on the device */
 
 /* Arithmetic of the Krylov iteration. */
 #define PCG_FP64 0               /* FP64 values, vectors and dots */
@@ -118,6 +119,12 @@ void pcg_default_opts(pcg_opts *opts);
  * (entries with |a| <= 4 eps64 max_row|a| dropped, FP64 and FP32 values,
  * inverse diagonal) in `format` and uploads it to the current device.
  * Mesh arrays are copied; *out is owned by the caller until fem_free.
+ * With FEM_ASSEMBLE_DEVICE in `format`, the DOF numbering, the Dirichlet
+ * marking, the element matrices and the summation of the element entries
+ * (in the same element order) run on the current device, on the null
+ * stream, with temporary device memory of about 32 bytes per element entry
+ * (cells * nloc^2); meshes beyond its index ranges (3D P2 with 2^21 or more
+ * vertices, 2^31 or more element entries) are assembled on the host.
  * Errors: FEMCG_EINVAL, FEMCG_EMESH (non-positive element), FEMCG_ENOMEM,
  * FEMCG_EUNSUPPORTED, FEMCG_EDEVICE. */
 int fem_assemble(const fem_mesh *mesh, int32_t order, int32_t format, fem_matrix **out);

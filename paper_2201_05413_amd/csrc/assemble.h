@@ -1,6 +1,8 @@
 // assemble.h -- host assembly of the library (not part of the public ABI).
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 #include <functional>
 #include <string>
@@ -44,8 +46,13 @@ struct SolverCopy {
 };
 
 void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &fn);
-bool element_matrix(int dim, int order, const double *P, double *K);
 int assemble_host(const fem_mesh *mesh, int order, HostSystem &hs, std::string &err);
+// Same result computed on the device (stream s): edges, boundary facets,
+// element matrices, and the (row, col) sort and run sums of the element
+// entries; the host system is filled from the device results.  Returns
+// FEMCG_EUNSUPPORTED for meshes beyond its index ranges (callers then use
+// assemble_host).
+int assemble_device(const fem_mesh *mesh, int order, HostSystem &hs, std::string &err, hipStream_t s);
 int build_solver_copy(const HostSystem &hs, int format, int C, int sigma, SolverCopy &sc,
                       std::string &err, int sfc = 0);
 

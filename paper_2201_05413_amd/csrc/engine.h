@@ -63,6 +63,7 @@ struct fem_matrix {
     int band_mode = -1;   // -1 automatic; 0 tile, 1 band, 2 single-workgroup loop forced
     int band_tile_bytes = 0;  // 0 = automatic
     int max_grid = 2048;
+    bool device_assembled = false;
     std::map<std::pair<int, int>, std::unique_ptr<femcg::Work>> works;
     std::map<std::pair<int, int>, std::unique_ptr<femcg::Engine>> engines;
     pcg_stats_t stats{};

@@ -101,7 +101,9 @@ int upload_solver_copy(fem_matrix *A)
     int rc;
     const std::vector<double> &v64 = sc.format == FEM_FORMAT_SELL ? sc.sell_val : sc.val;
     std::vector<float> v32(v64.size()), di32(sc.dinv.size());
-    for (size_t i = 0; i < v64.size(); ++i) v32[i] = (float)v64[i];
+    parallel_for((int64_t)v64.size(), [&](int64_t a, int64_t b) {
+        for (int64_t i = a; i < b; ++i) v32[i] = (float)v64[i];
+    });
     for (size_t i = 0; i < sc.dinv.size(); ++i) di32[i] = (float)sc.dinv[i];
     if (sc.format == FEM_FORMAT_SELL) {
         if ((rc = upload(&d.slice_ptr, sc.slice_ptr))) return rc;
@@ -880,10 +882,19 @@ int fem_assemble(const fem_mesh *mesh, int32_t order, int32_t format, fem_matrix
     std::string err;
     int rc;
     try {
-        rc = assemble_host(mesh, order, A->hs, err);
+        rc = FEMCG_EUNSUPPORTED;
+        if (format & FEM_ASSEMBLE_DEVICE) {
+            rc = assemble_device(mesh, order, A->hs, err, nullptr);
+            A->device_assembled = rc == FEMCG_OK;
+        }
+        if (rc == FEMCG_EUNSUPPORTED) {  // host assembly (also beyond the device path's ranges)
+            A->hs = HostSystem{};
+            err.clear();
+            rc = assemble_host(mesh, order, A->hs, err);
+        }
         if (rc) return fail(rc, "%s", err.c_str());
         if (A->hs.nfree == 0) return fail(FEMCG_EINVAL, "mesh has no free DOFs");
-        const int fmt = format == FEM_FORMAT_CSR ? FEM_FORMAT_CSR : FEM_FORMAT_SELL;
+        const int fmt = (format & 0xf) == FEM_FORMAT_CSR ? FEM_FORMAT_CSR : FEM_FORMAT_SELL;
         const int sigma = (A->hs.order == 2) ? 1024 : 1;
         rc = build_solver_copy(A->hs, fmt, 64, sigma, A->sc, err);
         if (rc) return fail(rc, "%s", err.c_str());

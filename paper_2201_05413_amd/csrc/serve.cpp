@@ -48,12 +48,14 @@ struct fem_server {
     double budget = 0, used = 0;
     int prec = PCG_FP64, max_slots = 1;
     hipStream_t stream = nullptr;
+    hipStream_t asm_stream = nullptr;  // device assembly of queued requests
     std::mutex mu;
     std::condition_variable cv;
     std::deque<Request *> to_assemble;
     std::deque<int64_t> ready;
     std::map<int64_t, std::unique_ptr<Request>> reqs;
     std::vector<std::thread> workers;
+    std::mutex dev_asm;  // one device assembly at a time (bounded temporaries)
     bool stop = false;
     int64_t next_id = 0;
     double t0 = 0;
@@ -74,7 +76,20 @@ static void assemble_worker(fem_server *s)
         std::string err;
         int rc = FEMCG_OK;
         try {
-            rc = assemble_host(&r->mesh, r->order, A->hs, err);
+            // large requests assemble on the device (falls back to the host
+            // beyond its index ranges); small ones stay on the host
+            const int nvl = r->mesh.dim + 1;
+            const int64_t nl = r->order == 1 ? nvl : nvl + nvl * (nvl - 1) / 2;
+            rc = FEMCG_EUNSUPPORTED;
+            if (r->mesh.ncells * nl * nl >= ((int64_t)1 << 20)) {
+                std::lock_guard<std::mutex> g(s->dev_asm);
+                rc = assemble_device(&r->mesh, r->order, A->hs, err, s->asm_stream);
+            }
+            if (rc == FEMCG_EUNSUPPORTED) {
+                A->hs = HostSystem{};
+                err.clear();
+                rc = assemble_host(&r->mesh, r->order, A->hs, err);
+            }
             if (!rc && A->hs.nfree == 0) {
                 rc = FEMCG_EINVAL;
                 err = "no free DOFs";
@@ -191,6 +206,8 @@ int serve_create(double budget_bytes, int32_t max_slots, int32_t precision, int3
     int rc = engine_create(precision, max_slots, check_every > 0 ? check_every : 16, true, s->eng);
     if (rc) return rc;
     if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
+        return fail(FEMCG_EDEVICE, "stream");
+    if (hipStreamCreateWithFlags(&s->asm_stream, hipStreamNonBlocking) != hipSuccess)
         return fail(FEMCG_EDEVICE, "stream");
     s->eng->stream = s->stream;
     s->eng->grid = 2048;
@@ -359,6 +376,7 @@ void serve_destroy(fem_server *s)
     s->eng.reset();
     s->reqs.clear();
     if (s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->asm_stream) (void)hipStreamDestroy(s->asm_stream);
     delete s;
 }
 

@@ -31,6 +31,7 @@ FEM_FORMAT_CSR = 0
 FEM_FORMAT_SELL = 1
 FEM_FORMAT_AUTO = 2
 FEM_ORDER_SFC = 0x10
+FEM_ASSEMBLE_DEVICE = 0x100
 PCG_FP64 = 0
 PCG_MIXED = 1
 

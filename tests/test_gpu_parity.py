@@ -60,8 +60,9 @@ CASES = [
 
 
 @pytest.mark.parametrize("dim,m,jit,order", CASES)
-def test_assembly_matches_oracle(dim, m, jit, order):
-    c = Case(dim, m, jit, order, 2)
+@pytest.mark.parametrize("where", [0, femcg.FEM_ASSEMBLE_DEVICE], ids=["host", "device"])
+def test_assembly_matches_oracle(dim, m, jit, order, where):
+    c = Case(dim, m, jit, order, 2, fmt=femcg.FEM_FORMAT_SELL | where)
     coords_l, dir_l, f2d_l = c.A.dofs()
     coords_o, dir_o, f2d_o = c.orc.dofs()
     assert np.array_equal(coords_l, coords_o)
@@ -343,3 +344,41 @@ def test_reentry_after_odd_launch_counts(mode):
             assert np.all(c.orc.relres(c.Bo, X) <= 1e-12 * 1.0001)
             for j in range(c.k):
                 assert oracle.x_err(Xs[:, j], X[:, j]) <= 1e-8
+
+
+@pytest.mark.parametrize("dim,m,jit,order", CASES + [(3, 15, 0.3, 2), (2, 70, 0.3, 2)])
+def test_device_assembly_equals_host(dim, m, jit, order):
+    # same DOFs, same pattern, values to rounding (same summation order; the
+    # element arithmetic may contract differently on the two sides)
+    mesh = meshgen.make_mesh(dim, m, jit, 17)
+    Ah = femcg.Matrix(mesh, order, femcg.FEM_FORMAT_SELL)
+    Ad = femcg.Matrix(mesh, order, femcg.FEM_FORMAT_SELL | femcg.FEM_ASSEMBLE_DEVICE)
+    for u, v in zip(Ah.dofs(), Ad.dofs()):
+        assert np.array_equal(u, v)
+    rph, colh, valh = Ah.csr()
+    rpd, cold, vald = Ad.csr()
+    assert np.array_equal(rph, rpd) and np.array_equal(colh, cold)
+    rowmax = np.maximum.reduceat(np.abs(valh), rph[:-1])
+    dmax = np.maximum.reduceat(np.abs(vald - valh), rph[:-1])
+    assert (dmax / rowmax).max() <= 1e-14
+    coords, _, _ = Ah.dofs()
+    g = meshgen.harmonic_eval(meshgen.random_coeffs(dim, 3, 4), coords)
+    Bh = torch.empty((Ah.n_free, 3), dtype=torch.float64, device="cuda")
+    Bd = torch.empty_like(Bh)
+    femcg.fem_rhs(Ah, g, Bh)
+    femcg.fem_rhs(Ad, g, Bd)
+    torch.cuda.synchronize()
+    bh, bd = Bh.cpu().numpy(), Bd.cpu().numpy()
+    for j in range(3):
+        assert np.linalg.norm(bh[:, j] - bd[:, j]) <= 1e-13 * np.linalg.norm(bh[:, j])
+
+
+def test_device_assembled_solve_matches_oracle():
+    c = Case(3, 10, 0.25, 2, 4, seed=19, fmt=femcg.FEM_FORMAT_SELL | femcg.FEM_ASSEMBLE_DEVICE, noise=0.01)
+    Xs, _, _, _, _ = c.orc.pcg(c.Bo, 1e-14)
+    for prec in (femcg.PCG_FP64, femcg.PCG_MIXED):
+        rc, X, st = c.solve(1e-12, precision=prec)
+        assert rc == 0
+        assert np.all(c.orc.relres(c.Bo, X) <= 1e-12 * 1.0001)
+        for j in range(c.k):
+            assert oracle.x_err(Xs[:, j], X[:, j]) <= 1e-8
