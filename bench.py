@@ -44,7 +44,7 @@ def percentile(xs, p):
 
 def iter_bytes(n, nnz, k, sv):
     """Algorithmic HBM bytes of one fused PCG iteration."""
-    return nnz * (sv + 4) + 4 * (n + 1) + 11 * n * k * sv + 2 * n * sv
+    return nnz * (sv + 4) + 4 * (n + 1) + 10 * n * k * sv + 2 * n * sv
 
 
 def spmm_bytes(n, nnz, k, sv):

@@ -1016,7 +1016,7 @@ static void fill_stats(fem_matrix *A, const Slot &sl, int prec, double solve_s, 
     st.solve_s = solve_s;
     // algorithmic bytes per iteration: nnz*(s_v+4) + index array + 11 n k s_x + 2 n s_v
     const double n = (double)st.n, nnz = (double)st.nnz_nonzero, k = sl.k;
-    auto it_bytes = [&](double sv) { return nnz * (sv + 4) + 4.0 * (n + 1) + 11.0 * n * k * sv + 2.0 * n * sv; };
+    auto it_bytes = [&](double sv) { return nnz * (sv + 4) + 4.0 * (n + 1) + 10.0 * n * k * sv + 2.0 * n * sv; };
     auto it_flops = [&]() { return 2.0 * nnz * k + 12.0 * n * k; };
     double bytes = 0, flops = 0;
     if (prec == PCG_FP64) {
@@ -1376,8 +1376,8 @@ int pcg_time_kernel(fem_matrix *A, int32_t kernel, int32_t reps, void *stream, d
         const double n = (double)A->sc.n, nnz = (double)A->sc.nnz, k = A->stats.k, sv = fp32 ? 4.0 : 8.0;
         const double idx = A->sc.format == FEM_FORMAT_SELL ? 4.0 * n : 4.0 * (n + 1);
         if (kernel == PH_SPMM) *bytes = nnz * (sv + 4.0) + idx + 2.0 * n * k * sv;
-        else if (kernel == PH_UPDATE) *bytes = 6.0 * n * k * sv + n * sv;
-        else *bytes = 3.0 * n * k * sv + n * sv;
+        else if (kernel == PH_UPDATE) *bytes = 3.0 * n * k * sv + n * sv;
+        else *bytes = 5.0 * n * k * sv + n * sv;
     }
     return FEMCG_OK;
 }
