@@ -173,7 +173,7 @@ int pcg_stats(const fem_matrix *A, pcg_stats_t *out);
 
 /* Autotune the solver copy for k right-hand sides: times SpMM over candidate
  * formats (CSR; SELL with C in {16,32,64}, sigma in {1, 64, 1024}) on the
- * device and keeps the fastest (3D meshes also try the Morton row order).
+ * device and keeps the fastest (3D and P2 meshes also try the Morton row order).
  * Returns the chosen format, FEM_ORDER_SFC included; C_out and sigma_out
  * may be NULL. */
 int fem_tune(fem_matrix *A, int32_t k, int32_t precision, int32_t *C_out, int32_t *sigma_out,

@@ -1276,8 +1276,9 @@ int fem_tune(fem_matrix *A, int32_t k, int32_t precision, int32_t *C_out, int32_
     for (int Cw : {16, 32, 64})
         for (int sg : {1, 64, 1024}) cands.push_back({FEM_FORMAT_SELL, Cw, sg});
     // 3D: the natural order puts face neighbours a whole plane of rows away;
-    // a Morton order keeps them near in index (and in cache)
-    if (A->hs.dim == 3) {
+    // P2: edge DOFs are numbered after all vertices, far from their
+    // vertices' rows.  A Morton order keeps both near in index (and in cache)
+    if (A->hs.dim == 3 || A->hs.order == 2) {
         cands.push_back({FEM_FORMAT_CSR | FEM_ORDER_SFC, 64, 1});
         for (int Cw : {16, 32, 64}) cands.push_back({FEM_FORMAT_SELL | FEM_ORDER_SFC, Cw, 1});
     }
