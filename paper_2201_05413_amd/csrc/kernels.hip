@@ -373,6 +373,10 @@ __device__ __forceinline__ void band_log(const SysDesc &D, int64_t tl, int d0, B
 #define FEMCG_KQV 4
 #endif
 constexpr int kU = FEMCG_KU;  // rows per thread in flight
+#ifndef FEMCG_KUV
+#define FEMCG_KUV 2
+#endif
+constexpr int kUv = FEMCG_KUV;  // rows per thread in flight, update and p-update
 #ifndef FEMCG_KE
 #define FEMCG_KE 4
 #endif
@@ -858,11 +862,11 @@ __global__ __launch_bounds__(kBlock) void k_update(const SysTable *__restrict__ 
         const GLOBAL GLOBAL T *__restrict__ dinv = gptr((const T *)D.dinv);
         auto body = [&](auto ntc) {
             constexpr bool NT = decltype(ntc)::value;
-            T rv[kU], qv[kU], dv[kU];
+            T rv[kUv], qv[kUv], dv[kUv];
             int64_t rb = r0 + threadIdx.x / kp;
             auto load = [&](int64_t b) {
 #pragma unroll
-                for (int u = 0; u < kU; ++u) {
+                for (int u = 0; u < kUv; ++u) {
                     const int64_t row = b + (int64_t)u * rps;
                     if (row < r1) {
                         const int64_t idx = row * kp + j;
@@ -909,7 +913,7 @@ __global__ __launch_bounds__(kBlock) void k_update(const SysTable *__restrict__ 
             for (;;) {
                 if (act) {
 #pragma unroll
-                    for (int u = 0; u < kU; ++u) {
+                    for (int u = 0; u < kUv; ++u) {
                         const int64_t row = rb + (int64_t)u * rps;
                         if (row < r1) {
                             const int64_t idx = row * kp + j;
@@ -921,7 +925,7 @@ __global__ __launch_bounds__(kBlock) void k_update(const SysTable *__restrict__ 
                         }
                     }
                 }
-                rb += (int64_t)kU * rps;
+                rb += (int64_t)kUv * rps;
                 if (rb >= r1 || !act) break;
                 load(rb);
             }
@@ -964,11 +968,11 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(const SysTable *__restrict__
         const GLOBAL GLOBAL T *__restrict__ dinv = gptr((const T *)D.dinv);
         auto body = [&](auto ntc) {
             constexpr bool NT = decltype(ntc)::value;
-            T xv[kU], rv[kU], pv[kU], dv[kU];
+            T xv[kUv], rv[kUv], pv[kUv], dv[kUv];
             int64_t rb = r0 + threadIdx.x / kp;
             auto load = [&](int64_t b) {
 #pragma unroll
-                for (int u = 0; u < kU; ++u) {
+                for (int u = 0; u < kUv; ++u) {
                     const int64_t row = b + (int64_t)u * rps;
                     if (row < r1) {
                         const int64_t idx = row * kp + j;
@@ -1058,7 +1062,7 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(const SysTable *__restrict__
             const double be = s_beta[j];
             for (;;) {
 #pragma unroll
-                for (int u = 0; u < kU; ++u) {
+                for (int u = 0; u < kUv; ++u) {
                     const int64_t row = rb + (int64_t)u * rps;
                     if (row < r1) {
                         const int64_t idx = row * kp + j;
@@ -1066,7 +1070,7 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(const SysTable *__restrict__
                         if (actp) P[idx] = (T)((double)dv[u] * (double)rv[u] + be * (double)pv[u]);
                     }
                 }
-                rb += (int64_t)kU * rps;
+                rb += (int64_t)kUv * rps;
                 if (rb >= r1) break;
                 load(rb);
             }
