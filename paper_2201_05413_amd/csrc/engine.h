@@ -28,8 +28,9 @@ struct Work {
     int band = 0;
     int small = 0;  // whole iteration loop in one workgroup (k_solve_small)
     int nt = 0;     // iteration working set beyond the last-level cache: streaming hints
-    // small systems: the matrix padded per workgroup thread, [pass][ell_len][1024/kp]
-    int ell_len = 0;
+    // small systems: the matrix padded per workgroup thread,
+    // [pass][ell_len][ell_threads/kp]
+    int ell_len = 0, ell_threads = 0;
     int32_t *ell_col = nullptr;
     double *ell_v64 = nullptr;
     float *ell_v32 = nullptr;
@@ -123,6 +124,7 @@ struct Engine {
     SysTable *h_main = nullptr, *h_ri64 = nullptr, *h_acc64 = nullptr, *h_acc32 = nullptr,
              *h_sc64 = nullptr, *h_sc32 = nullptr, *h_ri32 = nullptr, *h_small = nullptr;  // pinned staging
     int small_count[kNumClass] = {};  // systems per kp class in the small table
+    int small_res[kNumClass] = {};    // of which with the matrix resident
     SysState *d_st64 = nullptr, *d_st32 = nullptr;
     SysState *h_st64 = nullptr, *h_st32 = nullptr;  // pinned
     std::vector<Slot> slots;

@@ -209,14 +209,19 @@ int get_work(fem_matrix *A, int kp, int prec, Work **out)
     w->ngroups = (w->ntiles + kGroup - 1) / kGroup;
     const size_t nv = (size_t)std::max<int64_t>(w->n, 1) * kp;
     const size_t np = (size_t)w->ntiles * kDots * kp, ngp = (size_t)w->ngroups * kDots * kp;
-    // small systems: ELL layout of the solver copy per workgroup thread group
-    const int rpp = kSmallBlock / kp;
-    const int npass = w->small ? (int)((w->n + rpp - 1) / rpp) : 0;
+    // small systems: ELL layout of the solver copy per workgroup thread group;
+    // rows of at most kResL entries keep the matrix resident (512 threads)
     if (w->small) {
         int64_t L = 1;
         for (int64_t i = 0; i < w->n; ++i) L = std::max<int64_t>(L, A->sc.rowptr[i + 1] - A->sc.rowptr[i]);
         w->ell_len = (int)((L + 1) / 2 * 2);
+        w->ell_threads = w->ell_len <= kResL ? kResBlock : kSmallBlock;
+        if (const char *ev = std::getenv("FEMCG_SMALL_RES")) {  // tuning override
+            if (atoi(ev) == 0) w->ell_threads = kSmallBlock;
+        }
     }
+    const int rpp = w->small ? w->ell_threads / kp : 1;
+    const int npass = w->small ? (int)((w->n + rpp - 1) / rpp) : 0;
     const size_t ne = (size_t)npass * w->ell_len * rpp;
     Arena ar;
     for (int pass = 0; pass < 2; ++pass) {
@@ -305,6 +310,7 @@ static SysDesc make_desc(const fem_matrix *A, const Work *w, bool fp32, const vo
     D.ell_col = w->ell_col;
     D.ell_val = fp32 ? (const void *)w->ell_v32 : (const void *)w->ell_v64;
     D.ell_len = w->ell_len;
+    D.ell_threads = w->ell_threads;
     D.nt = w->nt;
     D.gpart = fp32 ? w->gpart32 : w->gpart64;
     D.gticket = fp32 ? w->gtk32 : w->gtk64;
@@ -460,6 +466,7 @@ static void fill_small_table(Engine *e, SysTable *h, const std::vector<int> &ids
     for (int c = 0; c < kNumClass; ++c) {
         h->cls_begin[c] = h->cls_end[c] = 0;
         e->small_count[c] = 0;
+        e->small_res[c] = 0;
     }
     h->nsys = (int)ids.size();
     h->total_tiles = 0;
@@ -470,6 +477,7 @@ static void fill_small_table(Engine *e, SysTable *h, const std::vector<int> &ids
         const int c = class_of(D.kp);
         if (e->small_count[c] == 0) h->cls_begin[c] = (int64_t)i;
         e->small_count[c]++;
+        e->small_res[c] += D.ell_threads == kResBlock;
         h->cls_end[c] = (int64_t)i + 1;
         h->d[i] = D;
     }
@@ -689,8 +697,12 @@ int engine_tick(Engine *e, int *rc_out)
                     return -1;
                 }
             }
-            if (mixed) launch_small<float>(e->d_small, e->small_count, (int)(e->it_global & 1), nrun, e->stream);
-            else launch_small<double>(e->d_small, e->small_count, (int)(e->it_global & 1), nrun, e->stream);
+            if (mixed)
+                launch_small<float>(e->d_small, e->small_count, e->small_res, (int)(e->it_global & 1), nrun,
+                                    e->stream);
+            else
+                launch_small<double>(e->d_small, e->small_count, e->small_res, (int)(e->it_global & 1), nrun,
+                                     e->stream);
             HIPCHK(hipGetLastError());
         }
         if (!big_ids.empty()) {

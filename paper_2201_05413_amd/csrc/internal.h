@@ -23,6 +23,9 @@ constexpr int kGroup = 64;         // band mode: tiles per reduction group
 constexpr int kSmallBlock = 1024;  // small systems: one workgroup runs the whole loop
 constexpr int kSmallPass = 4;      // small systems: rows per thread (at kp lanes per row)
 constexpr int kSmallElems = kSmallBlock * kSmallPass;  // small systems: n * kp bound (p in LDS)
+constexpr int kResBlock = 512;     // small systems with the matrix resident on chip
+constexpr int kResPass = kSmallElems / kResBlock;  // rows per thread (at kp lanes per row)
+constexpr int kResL = 8;           // entries per row held in registers
 
 // Per-system solver state, resident on the device.
 //
@@ -82,12 +85,14 @@ struct SysDesc {
     uint32_t *gticket;      // band mode: [ngroups] tiles arrived, zero between phases
     SysState *st;
     // single-workgroup systems: entry e of the row served by thread group t
-    // in pass i at [(i * ell_len + e) * (kSmallBlock / kp) + t]; rows padded
+    // in pass i at [(i * ell_len + e) * (ell_threads / kp) + t]; rows padded
     // to ell_len (even) with (own row, 0)
     const int32_t *ell_col;
     const void *ell_val;    // T
     int32_t ell_len;
     int32_t nt;             // 1: x, r, q accessed non-temporally (working set beyond the LLC)
+    int32_t ell_threads;    // kSmallBlock (matrix streamed from L2) or kResBlock (resident)
+    int32_t pad_r;
 };
 
 constexpr int kMaxSys = 256;
@@ -145,8 +150,10 @@ void launch_phase_timed(int phase, const SysTable *tab, int grid, int it, int fo
                         hipEvent_t ev0, hipEvent_t ev1);
 // Small systems (n * kp <= kSmallElems): `niter` iterations, one workgroup
 // per system; the table's class ranges index systems, cls_count[c] of them.
+// cls_res[c] of the cls_count[c] systems of class c use the resident-matrix
+// kernel (ell_threads == kResBlock).
 template <typename T>
-void launch_small(const SysTable *tab, const int *cls_count, int it, int niter, hipStream_t s);
+void launch_small(const SysTable *tab, const int *cls_count, const int *cls_res, int it, int niter, hipStream_t s);
 void launch_gather(const double *src, int64_t ld_src, const int32_t *perm, int64_t n, int k,
                    int kp, double *dst, hipStream_t s);
 void launch_scatter(const double *src, const int32_t *perm, int64_t n, int k, int kp,

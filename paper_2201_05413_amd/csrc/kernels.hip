@@ -1096,8 +1096,8 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(const SysTable *__restrict__
 // at the end.  Grid: one workgroup per system of the class.
 // ---------------------------------------------------------------------------
 
-template <int KP, int ND>
-__device__ __forceinline__ void small_reduce(double (*red)[kSmallBlock / kWave][KP], const double *v, double *out)
+template <int KP, int ND, int NW = kSmallBlock / kWave>
+__device__ __forceinline__ void small_reduce(double (*red)[NW][KP], const double *v, double *out)
 {
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int j = threadIdx.x & (KP - 1);
@@ -1111,7 +1111,7 @@ __device__ __forceinline__ void small_reduce(double (*red)[kSmallBlock / kWave][
     for (int d = 0; d < ND; ++d) {
         double t = 0.0;
 #pragma unroll
-        for (int w = 0; w < kSmallBlock / kWave; ++w) t += red[d][w][j];
+        for (int w = 0; w < NW; ++w) t += red[d][w][j];
         out[d] = t;
     }
 }
@@ -1128,6 +1128,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_solve_small(const SysTable *__r
     const int64_t sidx = tab->cls_begin[kLog2<KP>] + blockIdx.x;
     if (sidx >= tab->cls_end[kLog2<KP>]) return;
     const SysDesc D = tab->d[sidx];
+    if (D.ell_threads != kSmallBlock) return;  // resident-matrix systems: k_solve_small_res
     const int n = (int)D.n;
     const int j = threadIdx.x & (kp - 1);
     const int rt = threadIdx.x / kp;
@@ -1290,25 +1291,193 @@ __global__ __launch_bounds__(kSmallBlock) void k_solve_small(const SysTable *__r
     }
 }
 
+// Resident variant (rows of at most kResL entries): 512 threads, so a wave
+// may hold up to 256 VGPRs; each thread keeps its rows' matrix values and x,
+// r, q, D^-1 in registers and the column indices (16-bit) with p in LDS.
+// An iteration then touches no memory beyond the CU: the SpMM is kResL LDS
+// gathers and FMAs per row.  Arithmetic, reductions (over 8 waves) and state
+// handling are those of k_solve_small.
 template <typename T, int KP>
-static void launch_small_kp(const SysTable *tab, int nsys_cls, int it, int niter, hipStream_t s)
+__global__ __launch_bounds__(kResBlock) void k_solve_small_res(const SysTable *__restrict__ tab, int it0, int niter)
 {
-    hipLaunchKernelGGL((k_solve_small<T, KP>), dim3(nsys_cls), dim3(kSmallBlock), 0, s, tab, it, niter);
+    constexpr int kp = KP, rpp = kResBlock / kp, nw = kResBlock / kWave;
+    __shared__ T s_p[kSmallElems];
+    __shared__ uint16_t s_col[kResPass][kResL][kResBlock];
+    __shared__ double s_red[3][nw][KP];
+    const int64_t sidx = tab->cls_begin[kLog2<KP>] + blockIdx.x;
+    if (sidx >= tab->cls_end[kLog2<KP>]) return;
+    const SysDesc D = tab->d[sidx];
+    if (D.ell_threads != kResBlock) return;  // streaming systems: k_solve_small
+    const int n = (int)D.n;
+    const int j = threadIdx.x & (kp - 1);
+    const int rt = threadIdx.x / kp;
+    const int npass = (n + rpp - 1) / rpp;
+    const int L = D.ell_len;
+    GLOBAL T *__restrict__ X = gptr((T *)D.x);
+    GLOBAL T *__restrict__ Rg = gptr((T *)D.r);
+    GLOBAL T *__restrict__ Pg = gptr((T *)D.p);
+    const GLOBAL T *__restrict__ dinv = gptr((const T *)D.dinv);
+    const GLOBAL int32_t *__restrict__ ecol = gptr(D.ell_col);
+    const GLOBAL T *__restrict__ eval = gptr((const T *)D.ell_val);
+    GLOBAL SysState *st = gptr(D.st);
+
+    for (int i = threadIdx.x; i < n * kp; i += kResBlock) s_p[i] = Pg[i];
+    T av[kResPass][kResL];
+    T xv[kResPass], rv[kResPass], dv[kResPass], qv[kResPass];
+#pragma unroll
+    for (int i = 0; i < kResPass; ++i) {
+        const int row = rt + i * rpp;
+        xv[i] = rv[i] = dv[i] = qv[i] = (T)0;
+        const bool live = i < npass && row < n;
+        if (live) {
+            xv[i] = X[(int64_t)row * kp + j];
+            rv[i] = Rg[(int64_t)row * kp + j];
+            dv[i] = dinv[row];
+        }
+#pragma unroll
+        for (int e = 0; e < kResL; ++e) {
+            // rows beyond the tile and entries beyond ell_len: (own row, 0)
+            const bool ok = i < npass && e < L;
+            const int o = (i * L + e) * rpp + rt;
+            av[i][e] = ok ? eval[o] : (T)0;
+            if (j == 0) s_col[i][e][rt] = (uint16_t)(ok ? ecol[o] : (row < n ? row : 0));
+        }
+    }
+    const int prv0 = ((it0 + D.par_off) & 1) ^ 1;
+    const bool real = j < D.k;
+    double rho = st->rho[prv0][j];
+    int act = real ? st->active[prv0][j] : 0;
+    int iters = st->iters[prv0][j];
+    int fl = real ? st->flag[j] : 1;
+    double rr_last = st->rr[j];
+    const double thr = st->tol_rel[j] * st->tol_rel[j] * st->bb[j];
+    int nact = __syncthreads_count(threadIdx.x < kp && act);
+
+    for (int it = 0; it < niter && nact > 0; ++it) {
+        double v[2];
+        v[0] = 0.0;
+#pragma unroll
+        for (int i = 0; i < kResPass; ++i) {
+            if (i < npass) {
+                T acc = (T)0;
+#pragma unroll
+                for (int e = 0; e < kResL; ++e) acc += av[i][e] * s_p[(int)s_col[i][e][rt] * kp + j];
+                qv[i] = acc;
+                const int row = rt + i * rpp;
+                if (row < n) v[0] += (double)s_p[row * kp + j] * (double)acc;
+            }
+        }
+        double pq;
+        small_reduce<KP, 1, nw>(&s_red[0], v, &pq);
+        const bool live = act != 0;
+        const bool okpq = pq > 0.0 && isfinite(pq);
+        const double al = (live && okpq) ? rho / pq : 0.0;
+        v[0] = 0.0;
+        v[1] = 0.0;
+        if (live && okpq) {
+#pragma unroll
+            for (int i = 0; i < kResPass; ++i) {
+                const int row = rt + i * rpp;
+                if (i < npass && row < n) {
+                    xv[i] = (T)((double)xv[i] + al * (double)s_p[row * kp + j]);
+                    const T r = (T)((double)rv[i] - al * (double)qv[i]);
+                    rv[i] = r;
+                    const double rd = (double)r;
+                    v[0] += rd * ((double)dv[i] * rd);
+                    v[1] += rd * rd;
+                }
+            }
+        }
+        double sums[2];
+        small_reduce<KP, 2, nw>(&s_red[1], v, sums);
+        const double rz = sums[0], rr = sums[1];
+        int na = 0, inc = 0;
+        double be = 0.0;
+        if (live) {
+            if (!okpq) {
+                fl = FEMCG_EBREAKDOWN;
+            } else {
+                inc = 1;
+                if (rr <= thr) {
+                    // Eq. (2) holds: the column stops here
+                } else if (!(rz > 0.0) || !isfinite(rz) || !isfinite(rr)) {
+                    fl = FEMCG_EBREAKDOWN;
+                } else {
+                    na = 1;
+                    be = rz / rho;
+                    rho = rz;
+                }
+            }
+            iters += inc;
+            if (inc) rr_last = rr;
+        }
+        if (na) {
+#pragma unroll
+            for (int i = 0; i < kResPass; ++i) {
+                const int row = rt + i * rpp;
+                if (i < npass && row < n) {
+                    const int li = row * kp + j;
+                    s_p[li] = (T)((double)dv[i] * (double)rv[i] + be * (double)s_p[li]);
+                }
+            }
+        }
+        act = na;
+        nact = __syncthreads_count(threadIdx.x < kp && na);
+    }
+    for (int i = threadIdx.x; i < n * kp; i += kResBlock) Pg[i] = s_p[i];
+#pragma unroll
+    for (int i = 0; i < kResPass; ++i) {
+        const int row = rt + i * rpp;
+        if (i < npass && row < n) {
+            X[(int64_t)row * kp + j] = xv[i];
+            Rg[(int64_t)row * kp + j] = rv[i];
+        }
+    }
+    const int bad = __syncthreads_count(threadIdx.x < kp && fl == FEMCG_EBREAKDOWN);
+    if (threadIdx.x < kp) {
+        const int c = threadIdx.x;
+        st->active[0][c] = act;
+        st->active[1][c] = act;
+        if (real) {
+            st->rho[0][c] = rho;
+            st->rho[1][c] = rho;
+            st->iters[0][c] = iters;
+            st->iters[1][c] = iters;
+            st->h_iters[c] = iters;
+            st->h_active[c] = act;
+            st->flag[c] = fl;
+            st->rr[c] = rr_last;
+        }
+    }
+    if (threadIdx.x == 0) {
+        st->n_active = nact;
+        if (bad) st->status = FEMCG_EBREAKDOWN;
+    }
+}
+
+template <typename T, int KP>
+static void launch_small_kp(const SysTable *tab, int nsys_cls, int nres, int it, int niter, hipStream_t s)
+{
+    if (nres)
+        hipLaunchKernelGGL((k_solve_small_res<T, KP>), dim3(nsys_cls), dim3(kResBlock), 0, s, tab, it, niter);
+    if (nres < nsys_cls)
+        hipLaunchKernelGGL((k_solve_small<T, KP>), dim3(nsys_cls), dim3(kSmallBlock), 0, s, tab, it, niter);
 }
 
 template <typename T>
-void launch_small(const SysTable *tab, const int *cls_count, int it, int niter, hipStream_t s)
+void launch_small(const SysTable *tab, const int *cls_count, const int *cls_res, int it, int niter, hipStream_t s)
 {
-    if (cls_count[0]) launch_small_kp<T, 1>(tab, cls_count[0], it, niter, s);
-    if (cls_count[1]) launch_small_kp<T, 2>(tab, cls_count[1], it, niter, s);
-    if (cls_count[2]) launch_small_kp<T, 4>(tab, cls_count[2], it, niter, s);
-    if (cls_count[3]) launch_small_kp<T, 8>(tab, cls_count[3], it, niter, s);
-    if (cls_count[4]) launch_small_kp<T, 16>(tab, cls_count[4], it, niter, s);
-    if (cls_count[5]) launch_small_kp<T, 32>(tab, cls_count[5], it, niter, s);
-    if (cls_count[6]) launch_small_kp<T, 64>(tab, cls_count[6], it, niter, s);
+    if (cls_count[0]) launch_small_kp<T, 1>(tab, cls_count[0], cls_res[0], it, niter, s);
+    if (cls_count[1]) launch_small_kp<T, 2>(tab, cls_count[1], cls_res[1], it, niter, s);
+    if (cls_count[2]) launch_small_kp<T, 4>(tab, cls_count[2], cls_res[2], it, niter, s);
+    if (cls_count[3]) launch_small_kp<T, 8>(tab, cls_count[3], cls_res[3], it, niter, s);
+    if (cls_count[4]) launch_small_kp<T, 16>(tab, cls_count[4], cls_res[4], it, niter, s);
+    if (cls_count[5]) launch_small_kp<T, 32>(tab, cls_count[5], cls_res[5], it, niter, s);
+    if (cls_count[6]) launch_small_kp<T, 64>(tab, cls_count[6], cls_res[6], it, niter, s);
 }
-template void launch_small<double>(const SysTable *, const int *, int, int, hipStream_t);
-template void launch_small<float>(const SysTable *, const int *, int, int, hipStream_t);
+template void launch_small<double>(const SysTable *, const int *, const int *, int, int, hipStream_t);
+template void launch_small<float>(const SysTable *, const int *, const int *, int, int, hipStream_t);
+
 
 // ---------------------------------------------------------------------------
 // residual / (re)start: r = b - A x (or r = b, x = 0), p = D^-1 r,
