@@ -18,6 +18,8 @@
 #include <cstring>
 #include <cstdlib>
 #include <deque>
+#include <exception>
+#include <new>
 #include <functional>
 #include <mutex>
 
@@ -930,7 +932,7 @@ int fem_assemble(const fem_mesh *mesh, int32_t order, int32_t format, fem_matrix
 
 void fem_free(fem_matrix *A) { delete A; }
 
-int fem_dofs(const fem_matrix *A, int64_t *n_all, int64_t *n_free, double *dof_coords, uint8_t *dirichlet,
+static int fem_dofs_impl(const fem_matrix *A, int64_t *n_all, int64_t *n_free, double *dof_coords, uint8_t *dirichlet,
              int64_t *free2dof)
 {
     if (!A) return fail(FEMCG_EINVAL, "NULL matrix");
@@ -943,7 +945,7 @@ int fem_dofs(const fem_matrix *A, int64_t *n_all, int64_t *n_free, double *dof_c
     return FEMCG_OK;
 }
 
-int fem_csr(const fem_matrix *A, int64_t *nnz, int64_t *rowptr, int32_t *col, double *val)
+static int fem_csr_impl(const fem_matrix *A, int64_t *nnz, int64_t *rowptr, int32_t *col, double *val)
 {
     if (!A) return fail(FEMCG_EINVAL, "NULL matrix");
     const HostSystem &hs = A->hs;
@@ -954,7 +956,7 @@ int fem_csr(const fem_matrix *A, int64_t *nnz, int64_t *rowptr, int32_t *col, do
     return FEMCG_OK;
 }
 
-int fem_rhs(const fem_matrix *A, const double *g_all, int32_t k, double *B, void *stream)
+static int fem_rhs_impl(const fem_matrix *A, const double *g_all, int32_t k, double *B, void *stream)
 {
     if (!A || !g_all || !B) return fail(FEMCG_EINVAL, "NULL argument");
     if (k < 1 || k > kMaxK) return fail(FEMCG_EUNSUPPORTED, "k=%d outside 1..%d", k, kMaxK);
@@ -973,7 +975,7 @@ int fem_rhs(const fem_matrix *A, const double *g_all, int32_t k, double *B, void
     return FEMCG_OK;
 }
 
-int fem_spmv(fem_matrix *A, const double *X, double *Y, int32_t k, void *stream)
+static int fem_spmv_impl(fem_matrix *A, const double *X, double *Y, int32_t k, void *stream)
 {
     if (!A || !X || !Y) return fail(FEMCG_EINVAL, "NULL argument");
     if (k < 1 || k > kMaxK) return fail(FEMCG_EUNSUPPORTED, "k=%d outside 1..%d", k, kMaxK);
@@ -1066,7 +1068,7 @@ static int get_engine(fem_matrix *A, int kp, int prec, int m, bool graph, Engine
     return FEMCG_OK;
 }
 
-int pcg_solve(fem_matrix *A, const double *B, double *X, int32_t k, double tol, const pcg_opts *opts_in,
+static int pcg_solve_impl(fem_matrix *A, const double *B, double *X, int32_t k, double tol, const pcg_opts *opts_in,
               void *stream)
 {
     g_err.clear();
@@ -1123,7 +1125,7 @@ int pcg_solve(fem_matrix *A, const double *B, double *X, int32_t k, double tol, 
     return sl.status;
 }
 
-int pcg_solve_batch(int32_t nsys, fem_matrix *const *A, const double *const *B, double *const *X,
+static int pcg_solve_batch_impl(int32_t nsys, fem_matrix *const *A, const double *const *B, double *const *X,
                     const int32_t *k, const double *tol, const pcg_opts *opts_in, int32_t *status, void *stream)
 {
     g_err.clear();
@@ -1192,14 +1194,14 @@ int pcg_solve_batch(int32_t nsys, fem_matrix *const *A, const double *const *B, 
     return worst;
 }
 
-int pcg_stats(const fem_matrix *A, pcg_stats_t *out)
+static int pcg_stats_impl(const fem_matrix *A, pcg_stats_t *out)
 {
     if (!A || !out) return fail(FEMCG_EINVAL, "NULL argument");
     *out = A->stats;
     return FEMCG_OK;
 }
 
-int fem_set_format(fem_matrix *A, int32_t format_flags, int32_t C, int32_t sigma)
+static int fem_set_format_impl(fem_matrix *A, int32_t format_flags, int32_t C, int32_t sigma)
 {
     if (!A) return fail(FEMCG_EINVAL, "NULL matrix");
     const int sfc = (format_flags & FEM_ORDER_SFC) ? 1 : 0;
@@ -1276,7 +1278,7 @@ static int time_launches(hipStream_t s, int reps, const std::function<void()> &f
 
 // Autotuner: time the SpMM phase for each candidate layout on a synthetic p
 // (the current solve data is irrelevant to its speed) and keep the fastest.
-int fem_tune(fem_matrix *A, int32_t k, int32_t precision, int32_t *C_out, int32_t *sigma_out, void *stream)
+static int fem_tune_impl(fem_matrix *A, int32_t k, int32_t precision, int32_t *C_out, int32_t *sigma_out, void *stream)
 {
     if (!A || k < 1 || k > kMaxK) return fail(FEMCG_EINVAL, "bad arguments");
     if (precision != PCG_FP64 && precision != PCG_MIXED) return fail(FEMCG_EINVAL, "bad precision");
@@ -1318,7 +1320,7 @@ int fem_tune(fem_matrix *A, int32_t k, int32_t precision, int32_t *C_out, int32_
     return bc.format;
 }
 
-int fem_set_tiling(fem_matrix *A, int32_t band, int32_t tile)
+static int fem_set_tiling_impl(fem_matrix *A, int32_t band, int32_t tile)
 {
     if (!A || band < -1 || band > 2 || tile < 0) return fail(FEMCG_EINVAL, "bad tiling arguments");
     A->band_mode = band;
@@ -1329,7 +1331,7 @@ int fem_set_tiling(fem_matrix *A, int32_t band, int32_t tile)
     return FEMCG_OK;
 }
 
-int pcg_time_kernel(fem_matrix *A, int32_t kernel, int32_t reps, void *stream, double *ms, double *bytes)
+static int pcg_time_kernel_impl(fem_matrix *A, int32_t kernel, int32_t reps, void *stream, double *ms, double *bytes)
 {
     if (!A || !ms || kernel < 0 || kernel > 2 || reps < 1) return fail(FEMCG_EINVAL, "bad arguments");
     if (!A->last_kp) return fail(FEMCG_EINVAL, "no solve on this matrix yet");
@@ -1395,7 +1397,7 @@ int pcg_time_kernel(fem_matrix *A, int32_t kernel, int32_t reps, void *stream, d
     return FEMCG_OK;
 }
 
-int pcg_time_spmm_cold(int32_t nmat, fem_matrix *const *A, int32_t k, int32_t precision, int32_t reps,
+static int pcg_time_spmm_cold_impl(int32_t nmat, fem_matrix *const *A, int32_t k, int32_t precision, int32_t reps,
                        void *stream, double *ms, double *bytes)
 {
     if (nmat < 1 || !A || !ms || k < 1 || k > kMaxK || reps < 1) return fail(FEMCG_EINVAL, "bad arguments");
@@ -1423,6 +1425,142 @@ int pcg_time_spmm_cold(int32_t nmat, fem_matrix *const *A, int32_t k, int32_t pr
     *ms = t / ((double)reps * nmat);
     if (bytes) *bytes = by / nmat;
     return FEMCG_OK;
+}
+
+
+// Entry points: no C++ exception crosses the C ABI (a failed host allocation
+// becomes FEMCG_ENOMEM, anything else FEMCG_EDEVICE with its message).
+
+int fem_dofs(const fem_matrix *A, int64_t *n_all, int64_t *n_free, double *dof_coords, uint8_t *dirichlet, int64_t *free2dof)
+{
+    try {
+        return fem_dofs_impl(A, n_all, n_free, dof_coords, dirichlet, free2dof);
+    } catch (const std::bad_alloc &) {
+        return fail(FEMCG_ENOMEM, "fem_dofs: host allocation failed");
+    } catch (const std::exception &ex) {
+        return fail(FEMCG_EDEVICE, "fem_dofs: %s", ex.what());
+    }
+}
+
+int fem_csr(const fem_matrix *A, int64_t *nnz, int64_t *rowptr, int32_t *col, double *val)
+{
+    try {
+        return fem_csr_impl(A, nnz, rowptr, col, val);
+    } catch (const std::bad_alloc &) {
+        return fail(FEMCG_ENOMEM, "fem_csr: host allocation failed");
+    } catch (const std::exception &ex) {
+        return fail(FEMCG_EDEVICE, "fem_csr: %s", ex.what());
+    }
+}
+
+int fem_rhs(const fem_matrix *A, const double *g_all, int32_t k, double *B, void *stream)
+{
+    try {
+        return fem_rhs_impl(A, g_all, k, B, stream);
+    } catch (const std::bad_alloc &) {
+        return fail(FEMCG_ENOMEM, "fem_rhs: host allocation failed");
+    } catch (const std::exception &ex) {
+        return fail(FEMCG_EDEVICE, "fem_rhs: %s", ex.what());
+    }
+}
+
+int fem_spmv(fem_matrix *A, const double *X, double *Y, int32_t k, void *stream)
+{
+    try {
+        return fem_spmv_impl(A, X, Y, k, stream);
+    } catch (const std::bad_alloc &) {
+        return fail(FEMCG_ENOMEM, "fem_spmv: host allocation failed");
+    } catch (const std::exception &ex) {
+        return fail(FEMCG_EDEVICE, "fem_spmv: %s", ex.what());
+    }
+}
+
+int pcg_solve(fem_matrix *A, const double *B, double *X, int32_t k, double tol, const pcg_opts *opts, void *stream)
+{
+    try {
+        return pcg_solve_impl(A, B, X, k, tol, opts, stream);
+    } catch (const std::bad_alloc &) {
+        return fail(FEMCG_ENOMEM, "pcg_solve: host allocation failed");
+    } catch (const std::exception &ex) {
+        return fail(FEMCG_EDEVICE, "pcg_solve: %s", ex.what());
+    }
+}
+
+int pcg_solve_batch(int32_t nsys, fem_matrix *const *A, const double *const *B, double *const *X, const int32_t *k, const double *tol, const pcg_opts *opts, int32_t *status, void *stream)
+{
+    try {
+        return pcg_solve_batch_impl(nsys, A, B, X, k, tol, opts, status, stream);
+    } catch (const std::bad_alloc &) {
+        return fail(FEMCG_ENOMEM, "pcg_solve_batch: host allocation failed");
+    } catch (const std::exception &ex) {
+        return fail(FEMCG_EDEVICE, "pcg_solve_batch: %s", ex.what());
+    }
+}
+
+int pcg_stats(const fem_matrix *A, pcg_stats_t *out)
+{
+    try {
+        return pcg_stats_impl(A, out);
+    } catch (const std::bad_alloc &) {
+        return fail(FEMCG_ENOMEM, "pcg_stats: host allocation failed");
+    } catch (const std::exception &ex) {
+        return fail(FEMCG_EDEVICE, "pcg_stats: %s", ex.what());
+    }
+}
+
+int fem_tune(fem_matrix *A, int32_t k, int32_t precision, int32_t *C_out, int32_t *sigma_out, void *stream)
+{
+    try {
+        return fem_tune_impl(A, k, precision, C_out, sigma_out, stream);
+    } catch (const std::bad_alloc &) {
+        return fail(FEMCG_ENOMEM, "fem_tune: host allocation failed");
+    } catch (const std::exception &ex) {
+        return fail(FEMCG_EDEVICE, "fem_tune: %s", ex.what());
+    }
+}
+
+int fem_set_format(fem_matrix *A, int32_t format, int32_t C, int32_t sigma)
+{
+    try {
+        return fem_set_format_impl(A, format, C, sigma);
+    } catch (const std::bad_alloc &) {
+        return fail(FEMCG_ENOMEM, "fem_set_format: host allocation failed");
+    } catch (const std::exception &ex) {
+        return fail(FEMCG_EDEVICE, "fem_set_format: %s", ex.what());
+    }
+}
+
+int fem_set_tiling(fem_matrix *A, int32_t band, int32_t tile)
+{
+    try {
+        return fem_set_tiling_impl(A, band, tile);
+    } catch (const std::bad_alloc &) {
+        return fail(FEMCG_ENOMEM, "fem_set_tiling: host allocation failed");
+    } catch (const std::exception &ex) {
+        return fail(FEMCG_EDEVICE, "fem_set_tiling: %s", ex.what());
+    }
+}
+
+int pcg_time_kernel(fem_matrix *A, int32_t kernel, int32_t reps, void *stream, double *ms, double *bytes)
+{
+    try {
+        return pcg_time_kernel_impl(A, kernel, reps, stream, ms, bytes);
+    } catch (const std::bad_alloc &) {
+        return fail(FEMCG_ENOMEM, "pcg_time_kernel: host allocation failed");
+    } catch (const std::exception &ex) {
+        return fail(FEMCG_EDEVICE, "pcg_time_kernel: %s", ex.what());
+    }
+}
+
+int pcg_time_spmm_cold(int32_t nmat, fem_matrix *const *A, int32_t k, int32_t precision, int32_t reps, void *stream, double *ms, double *bytes)
+{
+    try {
+        return pcg_time_spmm_cold_impl(nmat, A, k, precision, reps, stream, ms, bytes);
+    } catch (const std::bad_alloc &) {
+        return fail(FEMCG_ENOMEM, "pcg_time_spmm_cold: host allocation failed");
+    } catch (const std::exception &ex) {
+        return fail(FEMCG_EDEVICE, "pcg_time_spmm_cold: %s", ex.what());
+    }
 }
 
 }  // extern "C"

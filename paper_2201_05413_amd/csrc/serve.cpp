@@ -12,6 +12,8 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <exception>
+#include <new>
 #include <thread>
 
 #include "engine.h"
@@ -195,7 +197,7 @@ static int retire_slot(fem_server *s, int slot)
 
 extern "C" {
 
-int serve_create(double budget_bytes, int32_t max_slots, int32_t precision, int32_t check_every, fem_server **out)
+static int serve_create_impl(double budget_bytes, int32_t max_slots, int32_t precision, int32_t check_every, fem_server **out)
 {
     if (!out || budget_bytes <= 0 || max_slots < 1 || max_slots > kMaxSys) return fail(FEMCG_EINVAL, "bad arguments");
     if (precision != PCG_FP64 && precision != PCG_MIXED) return fail(FEMCG_EINVAL, "bad precision");
@@ -220,7 +222,7 @@ int serve_create(double budget_bytes, int32_t max_slots, int32_t precision, int3
     return FEMCG_OK;
 }
 
-int64_t serve_submit(fem_server *s, const fem_mesh *mesh, int32_t order, const double *g_all, int32_t k, double tol)
+static int64_t serve_submit_impl(fem_server *s, const fem_mesh *mesh, int32_t order, const double *g_all, int32_t k, double tol)
 {
     if (!s || !mesh || !g_all || k < 1 || k > kMaxK || !(tol > 0)) return fail(FEMCG_EINVAL, "bad arguments");
     if ((mesh->dim != 2 && mesh->dim != 3) || (order != 1 && order != 2)) return fail(FEMCG_EUNSUPPORTED, "dim/order");
@@ -268,7 +270,7 @@ int64_t serve_submit(fem_server *s, const fem_mesh *mesh, int32_t order, const d
     return raw->id;
 }
 
-int serve_step(fem_server *s)
+static int serve_step_impl(fem_server *s)
 {
     if (!s) return fail(FEMCG_EINVAL, "NULL server");
     Engine *e = s->eng.get();
@@ -336,7 +338,7 @@ int serve_step(fem_server *s)
     return open;
 }
 
-int serve_poll(fem_server *s, int64_t id, double *X, fem_request_info *info)
+static int serve_poll_impl(fem_server *s, int64_t id, double *X, fem_request_info *info)
 {
     if (!s) return fail(FEMCG_EINVAL, "NULL server");
     std::lock_guard<std::mutex> lk(s->mu);
@@ -378,6 +380,54 @@ void serve_destroy(fem_server *s)
     if (s->stream) (void)hipStreamDestroy(s->stream);
     if (s->asm_stream) (void)hipStreamDestroy(s->asm_stream);
     delete s;
+}
+
+
+// Entry points: no C++ exception crosses the C ABI (a failed host allocation
+// becomes FEMCG_ENOMEM, anything else FEMCG_EDEVICE with its message).
+
+int serve_create(double budget_bytes, int32_t max_slots, int32_t precision, int32_t check_every, fem_server **out)
+{
+    try {
+        return serve_create_impl(budget_bytes, max_slots, precision, check_every, out);
+    } catch (const std::bad_alloc &) {
+        return fail(FEMCG_ENOMEM, "serve_create: host allocation failed");
+    } catch (const std::exception &ex) {
+        return fail(FEMCG_EDEVICE, "serve_create: %s", ex.what());
+    }
+}
+
+int64_t serve_submit(fem_server *s, const fem_mesh *mesh, int32_t order, const double *g_all, int32_t k, double tol)
+{
+    try {
+        return serve_submit_impl(s, mesh, order, g_all, k, tol);
+    } catch (const std::bad_alloc &) {
+        return fail(FEMCG_ENOMEM, "serve_submit: host allocation failed");
+    } catch (const std::exception &ex) {
+        return fail(FEMCG_EDEVICE, "serve_submit: %s", ex.what());
+    }
+}
+
+int serve_step(fem_server *s)
+{
+    try {
+        return serve_step_impl(s);
+    } catch (const std::bad_alloc &) {
+        return fail(FEMCG_ENOMEM, "serve_step: host allocation failed");
+    } catch (const std::exception &ex) {
+        return fail(FEMCG_EDEVICE, "serve_step: %s", ex.what());
+    }
+}
+
+int serve_poll(fem_server *s, int64_t id, double *X, fem_request_info *info)
+{
+    try {
+        return serve_poll_impl(s, id, X, info);
+    } catch (const std::bad_alloc &) {
+        return fail(FEMCG_ENOMEM, "serve_poll: host allocation failed");
+    } catch (const std::exception &ex) {
+        return fail(FEMCG_EDEVICE, "serve_poll: %s", ex.what());
+    }
 }
 
 }  // extern "C"
