@@ -10,6 +10,8 @@ Each wrapper names the passage of the paper the C function follows:
 * ``p1_element`` / ``p1_element_cot`` -- the Laplacian weights of Sect. 2.2
   (gradient form and the paper's cotangent form, K_ij = -w(i,j));
 * ``p2_element`` -- Table 7's higher-degree basis (degree 2), exact quadrature;
+* ``pk_element`` -- Table 7's degrees 3 and 4 on triangles: nodal basis from
+  the inverse Vandermonde matrix, collapsed Gauss-Legendre quadrature;
 * ``System`` -- assembly, Dirichlet lifting (Sect. 2.2: u = f on the boundary,
   b encodes the boundary condition), Jacobi-PCG (Sect. 2.1, M = diag(A)) with
   the exit test of Eq. (2), and the error metric of Eq. (1).
@@ -54,6 +56,7 @@ def _load():
     lib.orc_p1_element.argtypes = [C.c_int, P, P]
     lib.orc_p1_element_cot.argtypes = [C.c_int, P, P]
     lib.orc_p2_element.argtypes = [C.c_int, P, P]
+    lib.orc_pk_element.argtypes = [C.c_int, P, P]
     lib.orc_build.argtypes = [C.c_int, C.c_int64, P, C.c_int64, P, P, C.c_int, C.POINTER(C.c_int)]
     lib.orc_build.restype = P
     lib.orc_free.argtypes = [P]
@@ -105,6 +108,17 @@ def p2_element(X: np.ndarray) -> np.ndarray:
     """P2 element stiffness; local order: vertices, then edges (a,b), a<b, lexicographic."""
     dim = X.shape[1]
     return _element(_load().orc_p2_element, dim, X, 6 if dim == 2 else 10)
+
+
+def pk_element(X: np.ndarray, k: int) -> np.ndarray:
+    """P3/P4 triangle stiffness (Table 7's degrees 3 and 4); local order:
+    lattice points (i/k, j/k) of the reference triangle, i outer, j inner."""
+    return _element(lambda d, x, K: _load().orc_pk_element(k, x, K), 2, X, (k + 1) * (k + 2) // 2)
+
+
+def pk_local_points(k: int) -> np.ndarray:
+    """Barycentric indices (k-i-j, i, j) of the local numbering of pk_element."""
+    return np.array([(k - i - j, i, j) for i in range(k + 1) for j in range(k - i + 1)], dtype=np.int64)
 
 
 def fd7_identity_nnz(m: int) -> int:

@@ -9,16 +9,25 @@
  *
  *  1. DOF numbering.  P1: the mesh vertices.  P2: the vertices, then one DOF
  *     per mesh edge, edges ordered by their (min, max) vertex pair.  The
- *     paper's Table 7 (Sect. 4.2, "polynomial basis") varies the FEM degree;
- *     a DOF on a boundary facet whose vertices are all flagged is a Dirichlet
- *     DOF (Sect. 2.2: u = f on the boundary).
+ *     paper's Table 7 (Sect. 4.2, "polynomial basis") varies the FEM degree
+ *     from 1 to 4 on a triangle mesh; P3 and P4 (triangles only) number the
+ *     vertices, then k-1 DOFs per edge (edges in (min, max) order, the DOF t
+ *     of an edge at ((k-t) x_min + t x_max) / k), then (k-1)(k-2)/2 DOFs per
+ *     cell (cells in order; inside a cell, interior lattice points in
+ *     decreasing lexicographic order of their barycentric index).  A DOF on
+ *     a boundary facet whose vertices are all flagged is a Dirichlet DOF
+ *     (Sect. 2.2: u = f on the boundary).
  *  2. Element matrices K^e_ij = integral over T of grad(phi_i).grad(phi_j).
  *     P1 is written in gradient form, |T| grad(l_i).grad(l_j), and separately
  *     in the paper's cotangent form (Sect. 2.2: w(i,j) = (1/6) sum l_k cot a_k
  *     for tetrahedra, (cot a + cot b)/2 for triangles), where K_ij = -w(i,j)
  *     and K_ii = sum_j w(i,j).  The sign is flipped with respect to the
  *     paper's A(i,j) so that K is positive semi-definite.  P2 is integrated
- *     with a quadrature rule exact for the quadratic integrand.
+ *     with a quadrature rule exact for the quadratic integrand.  P3/P4: the
+ *     nodal basis of the degree-k polynomials at the lattice points, from the
+ *     inverse of their monomial Vandermonde matrix, integrated with a
+ *     collapsed (Duffy) Gauss-Legendre product rule that is exact for the
+ *     degree 2k-2 integrand.
  *  3. Assembly: coordinate triplets, stable counting sort by column and then
  *     by row, duplicates summed in element order.  The structural pattern
  *     (every DOF pair sharing an element) is kept, zeros included.
@@ -248,6 +257,143 @@ int orc_p2_element(int dim, const double *X, double *K)
 }
 
 /* ------------------------------------------------------------------------- */
+/* P3 / P4 triangles                                                          */
+/* ------------------------------------------------------------------------- */
+
+/* Local Pk numbering of the oracle: lattice points (i/k, j/k) of the
+ * reference triangle (0,0), (1,0), (0,1), i outer (0..k), j inner (0..k-i);
+ * barycentric index (k-i-j, i, j). */
+static int pk_local_points(int k, int A[15][3])
+{
+    int c = 0;
+    for (int i = 0; i <= k; i++)
+        for (int j = 0; j <= k - i; j++) {
+            A[c][0] = k - i - j;
+            A[c][1] = i;
+            A[c][2] = j;
+            c++;
+        }
+    return c;
+}
+
+/* Gauss-Legendre rule with n points on [0,1]: Newton's method on the
+ * Legendre polynomial P_n (three-term recurrence) from the starting guesses
+ * cos(pi (i + 3/4) / (n + 1/2)); weight 1 / ((1 - z^2) P_n'(z)^2). */
+static void gauss_legendre01(int n, double *x, double *w)
+{
+    for (int i = 0; i < n; i++) {
+        double z = cos(acos(-1.0) * (i + 0.75) / (n + 0.5)), p0 = 1.0, p1 = z, dp = 1.0;
+        for (int it = 0; it < 100; it++) {
+            p0 = 1.0;
+            p1 = z;
+            for (int j = 2; j <= n; j++) {
+                double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        p0 = 1.0;
+        p1 = z;
+        for (int j = 2; j <= n; j++) {
+            double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+            p0 = p1;
+            p1 = p2;
+        }
+        dp = n * (z * p1 - p0) / (z * z - 1.0);
+        x[i] = 0.5 * (1.0 + z);
+        w[i] = 1.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+/* inverse of the n x n matrix M (row-major) by Gauss-Jordan elimination
+ * with partial pivoting; returns 0 or ORC_EINVAL when singular */
+static int invert(int n, const double *M, double *out)
+{
+    double a[15][30];
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < 2 * n; j++) a[i][j] = j < n ? M[i * n + j] : (j - n == i ? 1.0 : 0.0);
+    for (int c = 0; c < n; c++) {
+        int p = c;
+        for (int r = c + 1; r < n; r++)
+            if (fabs(a[r][c]) > fabs(a[p][c])) p = r;
+        if (a[p][c] == 0.0) return ORC_EINVAL;
+        for (int j = 0; j < 2 * n; j++) { double t = a[c][j]; a[c][j] = a[p][j]; a[p][j] = t; }
+        double d = a[c][c];
+        for (int j = 0; j < 2 * n; j++) a[c][j] /= d;
+        for (int r = 0; r < n; r++)
+            if (r != c && a[r][c] != 0.0) {
+                double f = a[r][c];
+                for (int j = 0; j < 2 * n; j++) a[r][j] -= f * a[c][j];
+            }
+    }
+    for (int i = 0; i < n; i++)
+        for (int j = 0; j < n; j++) out[i * n + j] = a[i][n + j];
+    return 0;
+}
+
+/* P3/P4 triangle stiffness K_ij = integral of grad(phi_i).grad(phi_j) in the
+ * local numbering of pk_local_points.  phi_j = sum_m C[m][j] xi^p eta^q over
+ * the monomials p + q <= k, C the inverse Vandermonde matrix at the lattice
+ * points.  Reference gradients map to the cell by grad_x = J^-T grad_xi.
+ * Quadrature: xi = u (1 - v), eta = v over the unit square with n = k + 1
+ * Gauss points per direction (weight w_u w_v (1 - v)), exact for
+ * polynomials of degree 2n - 2 >= 2k - 2. */
+int orc_pk_element(int k, const double *X, double *K)
+{
+    if (k < 3 || k > 4) return ORC_EINVAL;
+    double G[12];
+    double det = bary_gradients(2, X, G);
+    if (!(det > 0.0)) return ORC_EMESH;
+    int A[15][3], mono[15][2];
+    int nl = pk_local_points(k, A), nm = 0;
+    for (int d = 0; d <= k; d++)
+        for (int q = 0; q <= d; q++) {
+            mono[nm][0] = d - q;
+            mono[nm][1] = q;
+            nm++;
+        }
+    double V[225], Cm[225];
+    for (int i = 0; i < nl; i++) {
+        double xi = (double)A[i][1] / k, eta = (double)A[i][2] / k;
+        for (int m = 0; m < nm; m++) V[i * nm + m] = pow(xi, mono[m][0]) * pow(eta, mono[m][1]);
+    }
+    int rc = invert(nl, V, Cm);
+    if (rc) return rc;
+    int n = k + 1;
+    double gx[8], gw[8];
+    gauss_legendre01(n, gx, gw);
+    for (int i = 0; i < nl * nl; i++) K[i] = 0.0;
+    for (int a = 0; a < n; a++)
+        for (int b = 0; b < n; b++) {
+            double xi = gx[a] * (1.0 - gx[b]), eta = gx[b];
+            double wq = gw[a] * gw[b] * (1.0 - gx[b]) * det;
+            double dm[15][2], grad[15][2];
+            for (int m = 0; m < nm; m++) {
+                int p = mono[m][0], q = mono[m][1];
+                dm[m][0] = p ? p * pow(xi, p - 1) * pow(eta, q) : 0.0;
+                dm[m][1] = q ? q * pow(xi, p) * pow(eta, q - 1) : 0.0;
+            }
+            for (int j = 0; j < nl; j++) {
+                double dxi = 0.0, deta = 0.0;
+                for (int m = 0; m < nm; m++) {
+                    dxi += Cm[m * nl + j] * dm[m][0];
+                    deta += Cm[m * nl + j] * dm[m][1];
+                }
+                /* grad lambda_1 = grad xi, grad lambda_2 = grad eta */
+                for (int r = 0; r < 2; r++) grad[j][r] = dxi * G[1 * 2 + r] + deta * G[2 * 2 + r];
+            }
+            for (int i = 0; i < nl; i++)
+                for (int j = 0; j < nl; j++)
+                    K[i * nl + j] += wq * (grad[i][0] * grad[j][0] + grad[i][1] * grad[j][1]);
+        }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
 /* the assembled system                                                       */
 /* ------------------------------------------------------------------------- */
 
@@ -333,7 +479,8 @@ orc_system *orc_build(int dim, int64_t nverts, const double *coords, int64_t nce
                       const int32_t *cells, const uint8_t *on_boundary, int order, int *err)
 {
     *err = 0;
-    if ((dim != 2 && dim != 3) || (order != 1 && order != 2) || nverts <= 0 || ncells <= 0) {
+    if ((dim != 2 && dim != 3) || order < 1 || order > 4 || (order > 2 && dim != 2) || nverts <= 0 ||
+        ncells <= 0) {
         *err = ORC_EINVAL;
         return NULL;
     }
@@ -345,13 +492,15 @@ orc_system *orc_build(int dim, int64_t nverts, const double *coords, int64_t nce
     s->ncells = ncells;
     int nv = dim + 1;
     int ne_loc = dim == 2 ? 3 : 6;
-    s->nloc = order == 1 ? nv : nv + ne_loc;
+    s->nloc = order == 1 ? nv : (order == 2 ? nv + ne_loc : (order + 1) * (order + 2) / 2);
     int nloc = s->nloc;
+    int ke = order - 1;                          /* DOFs per edge */
+    int ci = (order - 1) * (order - 2) / 2;      /* DOFs inside a cell */
 
     /* ---- DOFs ---- */
     int64_t *ekeys = NULL, *uniq = NULL;
     int64_t nek = 0, nuniq = 0;
-    if (order == 2) {
+    if (order >= 2) {
         int E[6][2];
         p2_local_edges(dim, E);
         nek = ncells * ne_loc;
@@ -371,7 +520,7 @@ orc_system *orc_build(int dim, int64_t nverts, const double *coords, int64_t nce
             if (i == 0 || uniq[i] != uniq[i - 1]) uniq[nuniq++] = uniq[i];
         s->nedges = nuniq;
     }
-    s->ndofs = nverts + s->nedges;
+    s->ndofs = nverts + ke * s->nedges + ci * ncells;
     s->dof_coords = malloc(sizeof(double) * s->ndofs * dim);
     s->dirichlet = calloc(s->ndofs, 1);
     s->cell_dofs = malloc(sizeof(int32_t) * ncells * nloc);
@@ -380,20 +529,76 @@ orc_system *orc_build(int dim, int64_t nverts, const double *coords, int64_t nce
     for (int64_t v = 0; v < nverts; v++) s->dirichlet[v] = on_boundary[v] ? 1 : 0;
     for (int64_t e = 0; e < s->nedges; e++) {
         int64_t a = uniq[e] / nverts, b = uniq[e] % nverts;
-        for (int r = 0; r < dim; r++)
-            s->dof_coords[(nverts + e) * dim + r] = 0.5 * (coords[a * dim + r] + coords[b * dim + r]);
-    }
-    for (int64_t c = 0; c < ncells; c++) {
-        for (int i = 0; i < nv; i++) s->cell_dofs[c * nloc + i] = cells[c * nv + i];
-        if (order == 2)
-            for (int e = 0; e < ne_loc; e++) {
-                int64_t idx = find_key(uniq, nuniq, ekeys[c * ne_loc + e]);
-                s->cell_dofs[c * nloc + nv + e] = (int32_t)(nverts + idx);
+        for (int r = 0; r < dim; r++) {
+            if (order == 2) {
+                s->dof_coords[(nverts + e) * dim + r] = 0.5 * (coords[a * dim + r] + coords[b * dim + r]);
+            } else {
+                for (int t = 1; t <= ke; t++)
+                    s->dof_coords[(nverts + ke * e + t - 1) * dim + r] =
+                        ((order - t) * coords[a * dim + r] + t * coords[b * dim + r]) / order;
             }
+        }
+    }
+    if (order <= 2) {
+        for (int64_t c = 0; c < ncells; c++) {
+            for (int i = 0; i < nv; i++) s->cell_dofs[c * nloc + i] = cells[c * nv + i];
+            if (order == 2)
+                for (int e = 0; e < ne_loc; e++) {
+                    int64_t idx = find_key(uniq, nuniq, ekeys[c * ne_loc + e]);
+                    s->cell_dofs[c * nloc + nv + e] = (int32_t)(nverts + idx);
+                }
+        }
+    } else {
+        /* P3/P4 triangles: classify each local lattice point */
+        int A[15][3];
+        pk_local_points(order, A);
+        int inter[3][3], ninter = 0; /* interior indices, decreasing lexicographic order */
+        for (int a0 = order; a0 >= 0; a0--)
+            for (int a1 = order - a0; a1 >= 0; a1--) {
+                int a2 = order - a0 - a1;
+                if (a0 > 0 && a1 > 0 && a2 > 0) {
+                    inter[ninter][0] = a0;
+                    inter[ninter][1] = a1;
+                    inter[ninter][2] = a2;
+                    ninter++;
+                }
+            }
+        int64_t ibase = nverts + ke * s->nedges;
+        for (int64_t c = 0; c < ncells; c++) {
+            const int32_t *cv = cells + c * 3;
+            for (int i = 0; i < nloc; i++) {
+                int nz = 0, m0 = -1;
+                for (int m = 0; m < 3; m++)
+                    if (A[i][m] == 0) nz++;
+                    else if (m0 < 0) m0 = m;
+                int64_t g;
+                if (nz == 2) {
+                    g = cv[m0];  /* vertex m0 */
+                } else if (nz == 1) {
+                    int p = -1, q = -1;
+                    for (int m = 0; m < 3; m++)
+                        if (A[i][m] > 0) { if (p < 0) p = m; else q = m; }
+                    int64_t gp = cv[p], gq = cv[q];
+                    int64_t lo = gp < gq ? gp : gq, hi = gp < gq ? gq : gp;
+                    int t = gp > gq ? A[i][p] : A[i][q];  /* weight of the larger vertex */
+                    int64_t idx = find_key(uniq, nuniq, lo * nverts + hi);
+                    g = nverts + ke * idx + (t - 1);
+                } else {
+                    int r = 0;
+                    while (!(inter[r][0] == A[i][0] && inter[r][1] == A[i][1] && inter[r][2] == A[i][2])) r++;
+                    g = ibase + ci * c + r;
+                    for (int d = 0; d < dim; d++)
+                        s->dof_coords[g * dim + d] = ((double)A[i][0] * coords[(int64_t)cv[0] * dim + d] +
+                                                      (double)A[i][1] * coords[(int64_t)cv[1] * dim + d] +
+                                                      (double)A[i][2] * coords[(int64_t)cv[2] * dim + d]) / order;
+                }
+                s->cell_dofs[c * nloc + i] = (int32_t)g;
+            }
+        }
     }
     /* Dirichlet edges: edges of boundary facets (facets in exactly one cell)
-     * whose two vertices are flagged */
-    if (order == 2) {
+     * whose two vertices are flagged (all k-1 DOFs of such an edge) */
+    if (order >= 2) {
         if (dim == 2) {
             /* facets are edges: count occurrences in the sorted key list */
             int64_t *cnt = calloc(nuniq, sizeof(int64_t));
@@ -401,7 +606,8 @@ orc_system *orc_build(int dim, int64_t nverts, const double *coords, int64_t nce
             for (int64_t i = 0; i < nek; i++) cnt[find_key(uniq, nuniq, ekeys[i])]++;
             for (int64_t e = 0; e < nuniq; e++) {
                 int64_t a = uniq[e] / nverts, b = uniq[e] % nverts;
-                if (cnt[e] == 1 && on_boundary[a] && on_boundary[b]) s->dirichlet[nverts + e] = 1;
+                if (cnt[e] == 1 && on_boundary[a] && on_boundary[b])
+                    for (int t = 0; t < ke; t++) s->dirichlet[nverts + ke * e + t] = 1;
             }
             free(cnt);
         } else {
@@ -447,11 +653,12 @@ orc_system *orc_build(int dim, int64_t nverts, const double *coords, int64_t nce
         int32_t *ci = malloc(sizeof(int32_t) * ncoo);
         double *vv = malloc(sizeof(double) * ncoo);
         if (!ri || !ci || !vv) { free(ri); free(ci); free(vv); goto nomem; }
-        double Ke[100], X[4 * 3];
+        double Ke[225], X[4 * 3];
         for (int64_t c = 0; c < ncells; c++) {
             for (int i = 0; i < nv; i++)
                 for (int r = 0; r < dim; r++) X[i * dim + r] = coords[(int64_t)cells[c * nv + i] * dim + r];
-            int rc = order == 1 ? orc_p1_element(dim, X, Ke) : orc_p2_element(dim, X, Ke);
+            int rc = order == 1 ? orc_p1_element(dim, X, Ke)
+                   : (order == 2 ? orc_p2_element(dim, X, Ke) : orc_pk_element(order, X, Ke));
             if (rc) { s->n_bad_cells++; continue; }
             for (int i = 0; i < nloc; i++)
                 for (int j = 0; j < nloc; j++) {
