@@ -20,9 +20,15 @@
  *    The library never frees caller memory.
  *  - Dense blocks B and X are row-major [n][k] with the k right-hand sides of
  *    a row contiguous ("interleaved"), in the public DOF order below.
- *  - Public DOF order: mesh vertices in mesh order, then (order 2) one DOF per
- *    mesh edge in lexicographic order of its (min, max) vertex pair.  Solver
- *    vectors hold the free (non-Dirichlet) DOFs in increasing DOF index.
+ *  - Public DOF order: mesh vertices in mesh order, then (order k >= 2) k-1
+ *    DOFs per mesh edge, edges in lexicographic order of their (min, max)
+ *    vertex pair and the DOF t = 1..k-1 of an edge at ((k-t) x_min +
+ *    t x_max) / k (P2: the midpoint, (x_min + x_max) / 2), then (order 3, 4)
+ *    (k-1)(k-2)/2 DOFs per cell, cells in mesh order; inside a cell with
+ *    vertices (v0, v1, v2) the lattice points (a0 x_v0 + a1 x_v1 + a2 x_v2) / k,
+ *    a0 + a1 + a2 = k, all a > 0, in decreasing lexicographic order of
+ *    (a0, a1, a2).  Solver vectors hold the free (non-Dirichlet) DOFs in
+ *    increasing DOF index.
  *    Internal row permutations of the sparse formats are never visible.
  *  - "stream" is a hipStream_t (NULL = the null stream).  Device work is
  *    enqueued on it; calls that must inspect device state synchronise it.
@@ -112,7 +118,9 @@ typedef struct {
 void pcg_default_opts(pcg_opts *opts);
 
 /* Assemble the stiffness matrix K_ij = integral grad(phi_i).grad(phi_j) of
- * the P1 (order 1) or P2 (order 2) Lagrange basis on the mesh -- the sign-
+ * the P1 (order 1) or P2 (order 2) Lagrange basis on triangles or tetrahedra,
+ * or of the P3 / P4 basis on triangles (Table 7's degrees 3 and 4; order 3 or
+ * 4 on a tetrahedral mesh is FEMCG_EUNSUPPORTED) -- the sign-
  * flipped, symmetric counterpart of the paper's Laplacian matrix (Sect. 2.2:
  * cotangent weights w(i,j), diagonal -sum w) -- and eliminate the Dirichlet
  * DOFs (zero source): A = K_II, b = -K_ID g_D.  Builds the solver copy
@@ -124,7 +132,8 @@ void pcg_default_opts(pcg_opts *opts);
  * (in the same element order) run on the current device, on the null
  * stream, with temporary device memory of about 32 bytes per element entry
  * (cells * nloc^2); meshes beyond its index ranges (3D P2 with 2^21 or more
- * vertices, 2^31 or more element entries) are assembled on the host.
+ * vertices, 2^31 or more element entries) and P3 / P4 meshes are assembled
+ * on the host.
  * Errors: FEMCG_EINVAL, FEMCG_EMESH (non-positive element), FEMCG_ENOMEM,
  * FEMCG_EUNSUPPORTED, FEMCG_EDEVICE. */
 int fem_assemble(const fem_mesh *mesh, int32_t order, int32_t format, fem_matrix **out);

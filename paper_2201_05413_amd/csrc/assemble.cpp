@@ -13,6 +13,16 @@
 // 4 l_a l_b at edges, whose gradients are (4 l_a - 1) g_a and
 // 4 (l_a g_b + l_b g_a); products of these integrate with the moments above.
 //
+// P3 and P4 triangles (Table 7's degrees 3 and 4) use the product form of
+// the Lagrange basis on the equispaced lattice (Silvester): for a lattice
+// point with barycentric index (a_0, a_1, a_2), a_0 + a_1 + a_2 = k,
+//   phi = prod_m R_{a_m}(l_m),   R_a(t) = prod_{s<a} (k t - s) / (s + 1),
+// so grad phi = sum_m (d phi / d l_m) g_m and
+//   K = |T| sum_{m,n} (g_m . g_n) M^{mn},
+//   M^{mn}_{ij} = (1/|T|) integral (d phi_i / d l_m)(d phi_j / d l_n),
+// a geometry-free table built once per degree from the 2D moments
+//   integral l_0^a l_1^b l_2^c = 2 |T| a! b! c! / (a + b + c + 2)!.
+//
 // Dirichlet lifting with zero source (Sect. 2.2, u = f on the boundary;
 // b encodes the boundary condition): A = K_II, b = -K_ID g_D.
 #include <algorithm>
@@ -20,6 +30,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <thread>
 
 #include "assemble.h"
@@ -45,6 +56,124 @@ void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &fn)
     for (auto &x : th) x.join();
 }
 
+// ---- P3 / P4 triangles ----------------------------------------------------
+
+// Local numbering of a degree-k triangle: the three vertices, then the k-1
+// points of each edge (0,1), (0,2), (1,2) from its first vertex on, then the
+// interior points in decreasing lexicographic order of their index.
+static int pk_local_index(int k, int idx[15][3])
+{
+    int c = 0;
+    for (int v = 0; v < 3; ++v) {
+        idx[c][0] = idx[c][1] = idx[c][2] = 0;
+        idx[c++][v] = k;
+    }
+    const int ed[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    for (auto &e : ed)
+        for (int s = 1; s < k; ++s) {
+            idx[c][0] = idx[c][1] = idx[c][2] = 0;
+            idx[c][e[0]] = k - s;
+            idx[c++][e[1]] = s;
+        }
+    for (int a0 = k - 2; a0 >= 1; --a0)
+        for (int a1 = k - 1 - a0; a1 >= 1; --a1) {
+            idx[c][0] = a0;
+            idx[c][1] = a1;
+            idx[c++][2] = k - a0 - a1;
+        }
+    return c;
+}
+
+namespace {
+struct PkTable {
+    int k = 0, nl = 0;
+    std::vector<double> M;  // [3][3][nl][nl]
+};
+}  // namespace
+
+static const PkTable &pk_table(int k)
+{
+    static PkTable tab[5];
+    static std::once_flag once[5];
+    std::call_once(once[k], [k] {
+        PkTable &T = tab[k];
+        int idx[15][3];
+        T.k = k;
+        T.nl = pk_local_index(k, idx);
+        const int nl = T.nl, D = k + 1;
+        // R_a and R_a' as coefficient vectors in t (degree <= k)
+        std::vector<std::vector<double>> R(k + 1, std::vector<double>(D, 0.0)), dR = R;
+        for (int a = 0; a <= k; ++a) {
+            std::vector<double> p(D, 0.0);
+            p[0] = 1.0;
+            for (int s0 = 0; s0 < a; ++s0) {  // p *= (k t - s0) / (s0 + 1)
+                std::vector<double> q(D, 0.0);
+                for (int e = 0; e < D; ++e) {
+                    if (p[e] == 0.0) continue;
+                    q[e] += -s0 * p[e] / (s0 + 1);
+                    if (e + 1 < D) q[e + 1] += k * p[e] / (s0 + 1);
+                }
+                p = q;
+            }
+            R[a] = p;
+            for (int e = 1; e < D; ++e) dR[a][e - 1] = e * p[e];
+        }
+        // d phi_i / d l_m as a dense coefficient cube over (e0, e1, e2)
+        const int D3 = D * D * D;
+        std::vector<double> dphi((size_t)nl * 3 * D3, 0.0);
+        for (int i = 0; i < nl; ++i)
+            for (int m = 0; m < 3; ++m) {
+                double *c = &dphi[((size_t)i * 3 + m) * D3];
+                const std::vector<double> *f[3];
+                for (int r = 0; r < 3; ++r) f[r] = r == m ? &dR[idx[i][r]] : &R[idx[i][r]];
+                for (int e0 = 0; e0 < D; ++e0)
+                    for (int e1 = 0; e1 < D; ++e1)
+                        for (int e2 = 0; e2 < D; ++e2)
+                            c[(e0 * D + e1) * D + e2] = (*f[0])[e0] * (*f[1])[e1] * (*f[2])[e2];
+            }
+        double fact[2 * 5 + 3];
+        fact[0] = 1.0;
+        for (int i = 1; i < 13; ++i) fact[i] = fact[i - 1] * i;
+        auto moment = [&](int a, int b, int c) { return 2.0 * fact[a] * fact[b] * fact[c] / fact[a + b + c + 2]; };
+        T.M.assign((size_t)9 * nl * nl, 0.0);
+        std::vector<int> nz;
+        for (int i = 0; i < nl; ++i)
+            for (int m = 0; m < 3; ++m)
+                for (int j = 0; j < nl; ++j)
+                    for (int n = 0; n < 3; ++n) {
+                        const double *a = &dphi[((size_t)i * 3 + m) * D3], *b = &dphi[((size_t)j * 3 + n) * D3];
+                        double sum = 0.0;
+                        for (int x = 0; x < D3; ++x) {
+                            if (a[x] == 0.0) continue;
+                            const int x0 = x / (D * D), x1 = (x / D) % D, x2 = x % D;
+                            for (int y = 0; y < D3; ++y) {
+                                if (b[y] == 0.0) continue;
+                                sum += a[x] * b[y] * moment(x0 + y / (D * D), x1 + (y / D) % D, x2 + y % D);
+                            }
+                        }
+                        T.M[((size_t)(m * 3 + n) * nl + i) * nl + j] = sum;
+                    }
+    });
+    return tab[k];
+}
+
+// K (nl x nl, local order of pk_local_index) of a degree-k triangle P[3][2].
+static bool pk_element_matrix(int k, const double *P, double *K)
+{
+    double g[4][3] = {}, area;
+    if (!simplex_grads(2, P, g, &area)) return false;
+    const PkTable &T = pk_table(k);
+    const int nl = T.nl;
+    for (int i = 0; i < nl * nl; ++i) K[i] = 0.0;
+    for (int m = 0; m < 3; ++m)
+        for (int n = 0; n < 3; ++n) {
+            const double G = area * (g[m][0] * g[n][0] + g[m][1] * g[n][1]);
+            const double *Mmn = &T.M[(size_t)(m * 3 + n) * nl * nl];
+            for (int i = 0; i < nl * nl; ++i) K[i] += G * Mmn[i];
+        }
+    return true;
+}
+
 struct Face {
     int32_t v[3];
     bool operator<(const Face &o) const
@@ -57,8 +186,8 @@ struct Face {
 int assemble_host(const fem_mesh *mesh, int order, HostSystem &hs, std::string &err)
 {
     const int dim = mesh->dim;
-    if ((dim != 2 && dim != 3) || (order != 1 && order != 2)) {
-        err = "unsupported dimension or order";
+    if ((dim != 2 && dim != 3) || order < 1 || order > 4 || (order > 2 && dim != 2)) {
+        err = "unsupported dimension or order (P1/P2 on triangles and tetrahedra, P3/P4 on triangles)";
         return FEMCG_EUNSUPPORTED;
     }
     if (mesh->nverts <= 0 || mesh->ncells <= 0 || !mesh->coords || !mesh->cells || !mesh->on_boundary) {
@@ -82,13 +211,15 @@ int assemble_host(const fem_mesh *mesh, int order, HostSystem &hs, std::string &
     hs.ncells = nc;
     int E[6][2];
     const int nel = local_edges(dim, E);
-    const int nl = order == 1 ? nvl : nvl + nel;
+    const int nl = order <= 2 ? (order == 1 ? nvl : nvl + nel) : (order + 1) * (order + 2) / 2;
+    const int ke = order - 1, ci = (order - 1) * (order - 2) / 2;  // DOFs per edge, per cell interior
     hs.nloc = nl;
 
-    // ---- DOFs: vertices, then edges in (min, max) order ----
+    // ---- DOFs: vertices, then k-1 per edge (edges in (min, max) order), then
+    //      the cell interiors in cell order ----
     std::vector<uint64_t> ekey;
     std::vector<uint64_t> edges;
-    if (order == 2) {
+    if (order >= 2) {
         ekey.resize(nc * nel);
         for (int64_t c = 0; c < nc; ++c)
             for (int e = 0; e < nel; ++e) {
@@ -102,34 +233,65 @@ int assemble_host(const fem_mesh *mesh, int order, HostSystem &hs, std::string &
         edges.erase(std::unique(edges.begin(), edges.end()), edges.end());
     }
     hs.nedges = (int64_t)edges.size();
-    hs.ndofs = nv + hs.nedges;
+    hs.ndofs = nv + ke * hs.nedges + (int64_t)ci * nc;
     if (hs.ndofs >= (int64_t)1 << 31) {
         err = "too many DOFs for int32 indices";
         return FEMCG_EUNSUPPORTED;
     }
     hs.dof_coords.resize(hs.ndofs * dim);
     std::memcpy(hs.dof_coords.data(), mesh->coords, sizeof(double) * nv * dim);
+    // edge DOF t (1..k-1) of edge (a, b), a < b: ((k - t) x_a + t x_b) / k
     for (int64_t e = 0; e < hs.nedges; ++e) {
         const int64_t a = (int64_t)(edges[e] >> 32), b = (int64_t)(edges[e] & 0xffffffffu);
-        for (int r = 0; r < dim; ++r)
-            hs.dof_coords[(nv + e) * dim + r] = 0.5 * (mesh->coords[a * dim + r] + mesh->coords[b * dim + r]);
+        for (int r = 0; r < dim; ++r) {
+            const double xa = mesh->coords[a * dim + r], xb = mesh->coords[b * dim + r];
+            if (order == 2)
+                hs.dof_coords[(nv + e) * dim + r] = 0.5 * (xa + xb);
+            else
+                for (int t = 1; t <= ke; ++t)
+                    hs.dof_coords[(nv + ke * e + t - 1) * dim + r] = ((double)(order - t) * xa + (double)t * xb) / order;
+        }
     }
     hs.cell_dofs.resize(nc * nl);
+    int pidx[15][3];
+    if (order >= 3) pk_local_index(order, pidx);
+    const int64_t ibase = nv + ke * hs.nedges;
     parallel_for(nc, [&](int64_t c0, int64_t c1) {
         for (int64_t c = c0; c < c1; ++c) {
-            for (int i = 0; i < nvl; ++i) hs.cell_dofs[c * nl + i] = mesh->cells[c * nvl + i];
+            const int32_t *cv = mesh->cells + c * nvl;
+            for (int i = 0; i < nvl; ++i) hs.cell_dofs[c * nl + i] = cv[i];
             if (order == 2)
                 for (int e = 0; e < nel; ++e) {
                     auto it = std::lower_bound(edges.begin(), edges.end(), ekey[c * nel + e]);
                     hs.cell_dofs[c * nl + nvl + e] = (int32_t)(nv + (it - edges.begin()));
                 }
+            if (order >= 3) {
+                for (int e = 0; e < 3; ++e) {
+                    const int la = E[e][0], lb = E[e][1];
+                    const int64_t idx = std::lower_bound(edges.begin(), edges.end(), ekey[c * nel + e]) - edges.begin();
+                    for (int s = 1; s < order; ++s) {
+                        // lattice weight of the larger global vertex
+                        const int t = cv[la] > cv[lb] ? order - s : s;
+                        hs.cell_dofs[c * nl + 3 + e * ke + (s - 1)] = (int32_t)(nv + ke * idx + t - 1);
+                    }
+                }
+                for (int r = 0; r < ci; ++r) {
+                    const int *a = pidx[3 + 3 * ke + r];
+                    const int64_t d = ibase + (int64_t)ci * c + r;
+                    hs.cell_dofs[c * nl + 3 + 3 * ke + r] = (int32_t)d;
+                    for (int q = 0; q < dim; ++q)
+                        hs.dof_coords[d * dim + q] = ((double)a[0] * mesh->coords[(int64_t)cv[0] * dim + q] +
+                                                      (double)a[1] * mesh->coords[(int64_t)cv[1] * dim + q] +
+                                                      (double)a[2] * mesh->coords[(int64_t)cv[2] * dim + q]) / order;
+                }
+            }
         }
     });
 
     // ---- Dirichlet DOFs ----
     hs.dirichlet.assign(hs.ndofs, 0);
     for (int64_t v = 0; v < nv; ++v) hs.dirichlet[v] = mesh->on_boundary[v] ? 1 : 0;
-    if (order == 2) {
+    if (order >= 2) {
         auto bnd = [&](uint64_t key) {
             return mesh->on_boundary[key >> 32] && mesh->on_boundary[key & 0xffffffffu];
         };
@@ -142,7 +304,7 @@ int assemble_host(const fem_mesh *mesh, int order, HostSystem &hs, std::string &
                 while (j < all.size() && all[j] == all[i]) ++j;
                 if (j - i == 1 && bnd(all[i])) {
                     const int64_t idx = std::lower_bound(edges.begin(), edges.end(), all[i]) - edges.begin();
-                    hs.dirichlet[nv + idx] = 1;
+                    for (int t = 0; t < ke; ++t) hs.dirichlet[nv + ke * idx + t] = 1;
                 }
                 i = j;
             }
@@ -200,7 +362,9 @@ int assemble_host(const fem_mesh *mesh, int order, HostSystem &hs, std::string &
         for (int64_t c = c0; c < c1; ++c) {
             for (int i = 0; i < nvl; ++i)
                 for (int r = 0; r < dim; ++r) P[i * dim + r] = mesh->coords[(int64_t)mesh->cells[c * nvl + i] * dim + r];
-            if (!element_matrix(dim, order, P, &Ke[(size_t)c * nl * nl])) bad.fetch_add(1);
+            const bool ok = order <= 2 ? element_matrix(dim, order, P, &Ke[(size_t)c * nl * nl])
+                                       : pk_element_matrix(order, P, &Ke[(size_t)c * nl * nl]);
+            if (!ok) bad.fetch_add(1);
         }
     });
     if (bad.load()) {

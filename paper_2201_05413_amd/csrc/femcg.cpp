@@ -909,7 +909,7 @@ int fem_assemble(const fem_mesh *mesh, int32_t order, int32_t format, fem_matrix
         if (rc) return fail(rc, "%s", err.c_str());
         if (A->hs.nfree == 0) return fail(FEMCG_EINVAL, "mesh has no free DOFs");
         const int fmt = (format & 0xf) == FEM_FORMAT_CSR ? FEM_FORMAT_CSR : FEM_FORMAT_SELL;
-        const int sigma = (A->hs.order == 2) ? 1024 : 1;
+        const int sigma = (A->hs.order >= 2) ? 1024 : 1;
         rc = build_solver_copy(A->hs, fmt, 64, sigma, A->sc, err);
         if (rc) return fail(rc, "%s", err.c_str());
     } catch (const std::bad_alloc &) {
@@ -1292,7 +1292,7 @@ static int fem_tune_impl(fem_matrix *A, int32_t k, int32_t precision, int32_t *C
     // 3D: the natural order puts face neighbours a whole plane of rows away;
     // P2: edge DOFs are numbered after all vertices, far from their
     // vertices' rows.  A Morton order keeps both near in index (and in cache)
-    if (A->hs.dim == 3 || A->hs.order == 2) {
+    if (A->hs.dim == 3 || A->hs.order >= 2) {
         cands.push_back({FEM_FORMAT_CSR | FEM_ORDER_SFC, 64, 1});
         for (int Cw : {16, 32, 64}) cands.push_back({FEM_FORMAT_SELL | FEM_ORDER_SFC, Cw, 1});
     }

@@ -81,7 +81,7 @@ static void assemble_worker(fem_server *s)
             // large requests assemble on the device (falls back to the host
             // beyond its index ranges); small ones stay on the host
             const int nvl = r->mesh.dim + 1;
-            const int64_t nl = r->order == 1 ? nvl : nvl + nvl * (nvl - 1) / 2;
+            const int64_t nl = r->order == 1 ? nvl : (r->order == 2 ? nvl + nvl * (nvl - 1) / 2 : (r->order + 1) * (r->order + 2) / 2);
             rc = FEMCG_EUNSUPPORTED;
             if (r->mesh.ncells * nl * nl >= ((int64_t)1 << 20)) {
                 std::lock_guard<std::mutex> g(s->dev_asm);
@@ -96,7 +96,7 @@ static void assemble_worker(fem_server *s)
                 rc = FEMCG_EINVAL;
                 err = "no free DOFs";
             }
-            if (!rc) rc = build_solver_copy(A->hs, FEM_FORMAT_SELL, 64, r->order == 2 ? 1024 : 1, A->sc, err);
+            if (!rc) rc = build_solver_copy(A->hs, FEM_FORMAT_SELL, 64, r->order >= 2 ? 1024 : 1, A->sc, err);
         } catch (const std::bad_alloc &) {
             rc = FEMCG_ENOMEM;
             err = "host allocation failed";
@@ -225,7 +225,8 @@ static int serve_create_impl(double budget_bytes, int32_t max_slots, int32_t pre
 static int64_t serve_submit_impl(fem_server *s, const fem_mesh *mesh, int32_t order, const double *g_all, int32_t k, double tol)
 {
     if (!s || !mesh || !g_all || k < 1 || k > kMaxK || !(tol > 0)) return fail(FEMCG_EINVAL, "bad arguments");
-    if ((mesh->dim != 2 && mesh->dim != 3) || (order != 1 && order != 2)) return fail(FEMCG_EUNSUPPORTED, "dim/order");
+    if ((mesh->dim != 2 && mesh->dim != 3) || order < 1 || order > 4 || (order > 2 && mesh->dim != 2))
+        return fail(FEMCG_EUNSUPPORTED, "dim/order");
     auto r = std::make_unique<Request>();
     r->t_submit = now_s() - s->t0;
     r->order = order;

@@ -31,6 +31,13 @@ def test_inverted_cell_is_rejected(dim):
     assert ei.value.code == femcg.FEMCG_EMESH
 
 
+@pytest.mark.parametrize("dim,order", [(3, 3), (3, 4), (2, 5), (2, 0)])
+def test_unsupported_order_is_rejected(dim, order):
+    with pytest.raises(femcg.FemcgError) as ei:
+        femcg.Matrix(meshgen.make_mesh(dim, 5, 0.0, 1), order)
+    assert ei.value.code == femcg.FEMCG_EUNSUPPORTED
+
+
 def test_argument_errors():
     mesh = meshgen.make_mesh(2, 12, 0.2, 1)
     A = femcg.Matrix(mesh, 1)

@@ -1,7 +1,8 @@
 """GPU parity of the HIP path against the oracle, through the C ABI.
 
 Bars (see the oracle's pins for what fixes the oracle itself):
-* assembly: identical structural pattern, max_row |dA| / max_row |A| <= 1e-12;
+* assembly: identical structural pattern, max_row |dA| / max_row |A| <= 1e-12
+  (P1..P4; the device assembly covers P1/P2 and hands P3/P4 to the host);
   B = -K_ID g_D within 1e-12 norm-wise per column; DOF coordinates bit-equal;
 * SpMM: |y - y_oracle| <= 1e-13 (|A| |x|) row-wise (FP64; the solver copy
   drops entries below 4 eps64 max_row|a|);
@@ -56,6 +57,9 @@ class Case:
 
 CASES = [
     (2, 37, 0.3, 1), (2, 23, 0.25, 2), (3, 11, 0.3, 1), (3, 7, 0.2, 2), (2, 64, 0.0, 1), (3, 17, 0.0, 1),
+    # P3 / P4 triangles (Table 7's degrees 3 and 4): rows of up to 49 / 81
+    # entries; the last one fits the single-workgroup loop
+    (2, 17, 0.3, 3), (2, 13, 0.25, 4), (2, 6, 0.2, 4),
 ]
 
 
@@ -287,7 +291,7 @@ def test_tuner_on_3d_and_cold_timing():
 
 
 SMALL_CASES = [(2, 37, 0.3, 1, 1), (2, 23, 0.25, 2, 2), (3, 11, 0.3, 1, 4), (3, 9, 0.3, 2, 1), (2, 64, 0.0, 1, 1),
-               (2, 20, 0.3, 1, 8), (2, 10, 0.3, 1, 32), (2, 8, 0.2, 1, 64)]
+               (2, 20, 0.3, 1, 8), (2, 10, 0.3, 1, 32), (2, 8, 0.2, 1, 64), (2, 7, 0.3, 3, 2), (2, 6, 0.2, 4, 3)]
 
 
 @pytest.mark.parametrize("dim,m,jit,order,k", SMALL_CASES)
