@@ -12,7 +12,8 @@ CPU as a bounded-sample baseline.
 
 Default workload: 2D P1 on a 1024x1024 vertex grid jittered by 0.3h
 (1,044,484 unknowns), g = x^2 - y^2 + N(0, 0.01^2) noise, tol 1e-8.
-Other workloads: --workload c1|c3|c4 (single solves), c5 (serving stream).
+Other workloads: --workload c1|c3|c4 (single solves), c5 (serving stream),
+asm (host vs device assembly), deg (P1..P4 on one mesh, as in Table 7).
 """
 from __future__ import annotations
 
@@ -472,6 +473,94 @@ def run_assembly(args):
     print(json.dumps(line), flush=True)
 
 
+def run_degrees(args):
+    """Polynomial degree study in the manner of Table 7 (Sect. 4.2): one 2D
+    mesh of 294 x 294 vertices jittered by 0.3h (86,436 vertices; Table 7's
+    mesh has 86,425), P1 to P4, Dirichlet data g = exp(x) cos(y) (harmonic,
+    so u = g is the exact solution), tol 1e-12 (Table 7's epsilon).  Per
+    degree: DOFs, structural nonzeros, assembly and tuner time, FP64 and
+    mixed time-to-tol (median of the timed solves), iterations, the SpMM
+    kernel's rate against the HBM roofline, the max nodal error against u,
+    and the oracle's own residual of the FP64 solution."""
+    import numpy as np
+    import torch
+
+    import meshgen
+    import oracle
+    from paper_2201_05413_amd import femcg
+
+    torch.cuda.set_device(0)
+    mesh = meshgen.mesh2d(294, 0.3, 11)
+    tol = 1e-12
+    rows = []
+    for order in args.degrees:
+        t0 = time.perf_counter()
+        A = femcg.Matrix(mesh, order, femcg.FEM_FORMAT_SELL | femcg.FEM_ASSEMBLE_DEVICE)
+        t_asm = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        fmt, cw, sg = femcg.fem_tune(A, 1, femcg.PCG_FP64)
+        t_tune = time.perf_counter() - t0
+        coords, _, f2d = A.dofs()
+        g = (np.exp(coords[:, 0]) * np.cos(coords[:, 1]))[:, None]
+        n = A.n_free
+        B = torch.empty((n, 1), dtype=torch.float64, device="cuda")
+        femcg.fem_rhs(A, g, B)
+        res = {}
+        for prec, key in ((femcg.PCG_FP64, "fp64"), (femcg.PCG_MIXED, "mixed")):
+            o = femcg.default_opts(tol=tol, precision=prec, check_every=args.check_every, inner_eta=args.eta)
+            X = torch.zeros_like(B)
+            femcg.pcg_solve(A, B, X, tol, o)  # warm-up (graph capture)
+            ts = []
+            for _ in range(max(1, args.steps)):
+                X.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rc = femcg.pcg_solve(A, B, X, tol, o)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+                if rc != 0:
+                    raise RuntimeError("P%d %s solve status %d" % (order, key, rc))
+            st = A.stats()
+            res[key] = dict(ms=round(1e3 * percentile(ts, 50), 3), iters=int(st["iters"][0]),
+                            outer=int(st.get("outer", 0)), x=X.cpu().numpy())
+        x = res["fp64"]["x"]
+        err = float(np.abs(x[:, 0] - g[f2d, 0]).max())
+        st = A.stats()
+        nnz, nnz_nz = int(st["nnz"]), int(st["nnz_nonzero"])
+        femcg.pcg_solve(A, B, torch.zeros_like(B), tol, femcg.default_opts(tol=tol))
+        ms_k, by_k = femcg.pcg_time_kernel(A, 0, reps=args.kernel_reps)
+        gbs = by_k / (ms_k * 1e-3) / 1e9
+        row = dict(degree=order, dofs=int(len(coords)), n_free=n, nnz_structural=nnz, nnz_kept=nnz_nz,
+                   assembly_s=round(t_asm, 3), device_assembled=bool(order <= 2), tune_s=round(t_tune, 3),
+                   format=dict(sell=bool(fmt & femcg.FEM_FORMAT_SELL), C=cw, sigma=sg,
+                               morton=bool(fmt & femcg.FEM_ORDER_SFC)),
+                   fp64_ms=res["fp64"]["ms"], fp64_iters=res["fp64"]["iters"],
+                   mixed_ms=res["mixed"]["ms"], mixed_inner_iters=res["mixed"]["iters"],
+                   max_nodal_error=err, spmm_ms=round(ms_k, 5), spmm_gbs=round(gbs, 1),
+                   spmm_frac=round(gbs / HBM_PEAK_GBS, 4))
+        if not args.no_check:
+            t0 = time.perf_counter()
+            orc = oracle.System(mesh, order)
+            row["oracle_relres_fp64"] = float(orc.relres(orc.rhs(g), x).max())
+            row["oracle_check_s"] = round(time.perf_counter() - t0, 2)
+            del orc
+        rows.append(row)
+        log("P%d: dofs %d nnz %d | asm %.2f s tune %.2f s | fp64 %.2f ms (%d its) mixed %.2f ms | err %.2e | "
+            "SpMM %.1f GB/s%s" % (order, row["dofs"], nnz, t_asm, t_tune, row["fp64_ms"], row["fp64_iters"],
+                                  row["mixed_ms"], err, gbs,
+                                  (" | oracle relres %.2e" % row["oracle_relres_fp64"]) if not args.no_check else ""))
+        A.free()
+    line = {
+        "metric": "time-to-1e-12 residual per FEM degree (Table 7 analog)", "value": rows[-1]["fp64_ms"],
+        "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": None,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 (FP64 PCG) + f32-inner/f64-refined (mixed PCG)", "data": "synthetic",
+        "config": {"workload": "degrees_2d_294_jit", "recipe": " ".join((run_degrees.__doc__ or "").split())},
+        "degrees": rows,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def meshgen_doc(name):
     import meshgen
     f = {"c1": meshgen.c1, "c2": meshgen.c2, "c3": meshgen.c3, "c4": meshgen.c4}[name]
@@ -483,7 +572,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "asm"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "asm", "deg"])
     ap.add_argument("--check-every", type=int, default=64)
     ap.add_argument("--format", default="auto", help="auto (tuner) | csr | sell:C:sigma")
     ap.add_argument("--order", default="natural", choices=["natural", "sfc"])
@@ -504,6 +593,7 @@ def main():
                     help="assembly timing: sides of the extra 3D P2 meshes")
     ap.add_argument("--asm-oracle-max-n", type=int, default=3000000,
                     help="assembly timing: time the oracle's assembly up to this many free DOFs")
+    ap.add_argument("--degrees", type=int, nargs="+", default=[1, 2, 3, 4], help="deg workload: FEM degrees")
     ap.add_argument("--serve-fractions", type=float, nargs="+", default=[0.3, 0.7, 1.0],
                     help="serving: arrival rates as fractions of the measured capacity")
     ap.add_argument("--slots", type=int, default=32)
@@ -523,6 +613,8 @@ def main():
         run_serve(args)
     elif args.workload == "asm":
         run_assembly(args)
+    elif args.workload == "deg":
+        run_degrees(args)
     else:
         run_single(args)
 

@@ -28,6 +28,7 @@ struct Work {
     int band = 0;
     int small = 0;  // whole iteration loop in one workgroup (k_solve_small)
     int nt = 0;     // iteration working set beyond the last-level cache: streaming hints
+    int lpr = 1;    // SpMM lanes per row at kp = 1 (long rows: 2, 4 or 8)
     // small systems: the matrix padded per workgroup thread,
     // [pass][ell_len][ell_threads/kp]
     int ell_len = 0, ell_threads = 0;

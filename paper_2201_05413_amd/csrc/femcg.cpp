@@ -136,7 +136,21 @@ int upload_solver_copy(fem_matrix *A)
 // block of the next phase reduces at its start.  Large systems (band mode):
 // small tiles that the blocks of each XCD sweep as one band, so rows that
 // share gathered neighbours are processed close in time on the same L2.
-static void choose_tiles(const fem_matrix *A, int kp, int &tile_rows, int &ntiles, int &band)
+// SpMM lanes per row at kp = 1, from the mean kept row length: long rows
+// (P2-P4) are split over 2, 4 or 8 lanes, so each lane's chain of dependent
+// index, value and gather loads shortens (measured on a 2D mesh of 86k
+// vertices: P2 -4%, P3 -19%, P4 -32% time-to-tol; P1 rows, 7 entries on
+// average, stay on one lane).
+static int choose_lpr(const fem_matrix *A, int kp)
+{
+    if (kp != 1) return 1;
+    const double mean = A->sc.n ? (double)A->sc.nnz / (double)A->sc.n : 0.0;
+    int lpr = mean >= 32.0 ? 8 : (mean >= 14.0 ? 4 : (mean >= 8.0 ? 2 : 1));
+    if (const char *ev = std::getenv("FEMCG_LPR")) lpr = atoi(ev);  // tuning override
+    return (lpr == 2 || lpr == 4 || lpr == 8) ? lpr : 1;
+}
+
+static void choose_tiles(const fem_matrix *A, int kp, int lpr, int &tile_rows, int &ntiles, int &band)
 {
     const int64_t n = A->dev.n;
     const int rps = kBlock / kp;
@@ -159,8 +173,11 @@ static void choose_tiles(const fem_matrix *A, int kp, int &tile_rows, int &ntile
         rows = std::max<int64_t>(1, tb / (kp * 8));
     } else {
         // every block reduces all tile partials at the start of a phase, so
-        // keep ntiles * kp bounded (<= 16K partials per dot)
-        int target = A->tile_target > 0 ? A->tile_target : std::max(256, std::min(1024, 16384 / kp));
+        // keep ntiles * kp bounded (<= 16K partials per dot); split rows
+        // (lpr > 1 lanes per row) take 4096 tiles, so that a block's serial
+        // batches stay few
+        int target = A->tile_target > 0 ? A->tile_target
+                                        : (lpr > 1 ? 4096 : std::max(256, std::min(1024, 16384 / kp)));
         if (const char *ev = std::getenv("FEMCG_TILE_TARGET")) target = std::max(1, atoi(ev));  // tuning override
         rows = (n + target - 1) / target;
     }
@@ -192,7 +209,8 @@ int get_work(fem_matrix *A, int kp, int prec, Work **out)
     w->kp = kp;
     w->prec = prec;
     w->n = A->dev.n;
-    choose_tiles(A, kp, w->tile_rows, w->ntiles, w->band);
+    w->lpr = choose_lpr(A, kp);
+    choose_tiles(A, kp, w->lpr, w->tile_rows, w->ntiles, w->band);
     const bool fits_small = w->n * kp <= kSmallElems;
     if (A->band_mode == 2 && !fits_small)
         return fail(FEMCG_EINVAL, "single-workgroup mode needs n * kp <= %d (n = %lld, kp = %d)", kSmallElems,
@@ -208,6 +226,7 @@ int get_work(fem_matrix *A, int kp, int prec, Work **out)
         if (const char *ev = std::getenv("FEMCG_NT")) w->nt = atoi(ev);  // tuning override
     }
     if (const char *ev = std::getenv("FEMCG_SMALL")) w->small = w->small && atoi(ev) != 0;  // tuning override
+
     w->ngroups = (w->ntiles + kGroup - 1) / kGroup;
     const size_t nv = (size_t)std::max<int64_t>(w->n, 1) * kp;
     const size_t np = (size_t)w->ntiles * kDots * kp, ngp = (size_t)w->ngroups * kDots * kp;
@@ -314,6 +333,7 @@ static SysDesc make_desc(const fem_matrix *A, const Work *w, bool fp32, const vo
     D.ell_len = w->ell_len;
     D.ell_threads = w->ell_threads;
     D.nt = w->nt;
+    D.lpr = w->lpr;
     D.gpart = fp32 ? w->gpart32 : w->gpart64;
     D.gticket = fp32 ? w->gtk32 : w->gtk64;
     return D;

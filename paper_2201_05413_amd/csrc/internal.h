@@ -92,7 +92,7 @@ struct SysDesc {
     int32_t ell_len;
     int32_t nt;             // 1: x, r, q accessed non-temporally (working set beyond the LLC)
     int32_t ell_threads;    // kSmallBlock (matrix streamed from L2) or kResBlock (resident)
-    int32_t pad_r;
+    int32_t lpr;            // SpMM at kp = 1: lanes per row (1, 2, 4 or 8)
 };
 
 constexpr int kMaxSys = 256;

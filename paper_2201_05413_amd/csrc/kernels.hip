@@ -443,6 +443,72 @@ __device__ __forceinline__ void rows_dot(const SysDesc &D, const int64_t *row, c
     }
 }
 
+// Same product (k = 1) with LPR lanes per row for long rows: lane j of a row
+// takes its entries j, j + LPR, j + 2 LPR, ...; the lanes' sums are combined
+// with xor shuffles, which leave the same (commutative) sum in every lane of
+// the row.  More lanes per row shorten each lane's chain of dependent
+// index, value and gather loads.
+template <typename T, int LPR>
+__device__ __forceinline__ void rows_dot_split(const SysDesc &D, const int64_t *row, int j,
+                                               const GLOBAL T *__restrict__ X, T *acc)
+{
+    const GLOBAL GLOBAL T *__restrict__ val = gptr((const T *)D.val);
+    const GLOBAL int32_t *__restrict__ col = gptr(D.col);
+    int64_t base[kU];
+    int len[kU];
+    int64_t stride;
+    int maxlen = 0;
+    if (D.format == FEM_FORMAT_SELL) {
+        const int sh = D.sell_shift;
+        stride = (int64_t)1 << sh;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const bool ok = row[u] < D.n;
+            base[u] = ok ? gptr(D.slice_ptr)[row[u] >> sh] + (row[u] & (stride - 1)) : 0;
+            len[u] = ok ? gptr(D.rowlen)[row[u]] : 0;
+            maxlen = max(maxlen, len[u]);
+        }
+    } else {
+        stride = 1;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const bool ok = row[u] < D.n;
+            base[u] = ok ? gptr(D.rowptr)[row[u]] : 0;
+            len[u] = ok ? gptr(D.rowptr)[row[u] + 1] - (int)base[u] : 0;
+            maxlen = max(maxlen, len[u]);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) acc[u] = 0;
+    for (int e0 = j; e0 < maxlen; e0 += LPR * kE) {
+        int c[kU][kE];
+        T v[kU][kE];
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+#pragma unroll
+            for (int q = 0; q < kE; ++q) {
+                const int e = e0 + q * LPR;
+                const int64_t idx = base[u] + (int64_t)(e < len[u] ? e : 0) * stride;
+                const T vv = val[idx];
+                c[u][q] = col[idx];
+                v[u][q] = e < len[u] ? vv : (T)0;
+            }
+        T xg[kU][kE];
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+#pragma unroll
+            for (int q = 0; q < kE; ++q) xg[u][q] = X[c[u][q]];
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+#pragma unroll
+            for (int q = 0; q < kE; ++q) acc[u] += v[u][q] * xg[u][q];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+#pragma unroll
+        for (int off = LPR / 2; off >= 1; off >>= 1) acc[u] += __shfl_xor(acc[u], off, kWave);
+}
+
 // Same product for kp >= 2 lanes per row: the kp lanes of a row load kp
 // different entries of it at once (one index and one value load per lane
 // instead of one per entry) and broadcast them with in-group shuffles; the
@@ -779,46 +845,60 @@ __global__ __launch_bounds__(kBlock) void k_spmm(const SysTable *__restrict__ ta
             if (D.band) band_log<1, KP>(D, tl, DOT0, lg);
             return;
         }
-        const int j = threadIdx.x & (kp - 1);
-        const int rps = kBlock / kp;
-        // the active-column check of a new system overlaps the first batch
-        const int a_in = (fresh && threadIdx.x < D.k) ? gptr(D.st)->active[((it + D.par_off) & 1) ^ 1][threadIdx.x] : 0;
-        int64_t rb = r0 + threadIdx.x / kp;
-        int64_t row[kU];
-        T acc[kU];
-        auto batch = [&](int64_t b) {
+        // LPR lanes per row: the kp columns (kp >= 2), or, at k = 1, LPR lanes
+        // splitting the entries of long rows (D.lpr)
+        auto rows_body = [&](auto lpr_tag) {
+            constexpr int LPR = decltype(lpr_tag)::value;
+            const int j = threadIdx.x & (LPR - 1);
+            const int rps = kBlock / LPR;
+            // the active-column check of a new system overlaps the first batch
+            const int a_in = (fresh && threadIdx.x < D.k) ? gptr(D.st)->active[((it + D.par_off) & 1) ^ 1][threadIdx.x] : 0;
+            int64_t rb = r0 + threadIdx.x / LPR;
+            int64_t row[kU];
+            T acc[kU];
+            auto batch = [&](int64_t b) {
 #pragma unroll
-            for (int u = 0; u < kU; ++u) {
-                row[u] = b + (int64_t)u * rps;
-                if (row[u] >= r1) row[u] = D.n;  // masked
-            }
-            rows_product<T, KP>(D, row, j, P, acc);
-        };
-        batch(rb);
-        if (fresh) {
-            const int any = __syncthreads_or(a_in);
-            if (threadIdx.x == 0) {
-                s_sys = s;
-                s_any = any;
-            }
-            __syncthreads();
-        }
-        if (!force && !s_any) return;
-        double v[1] = {0.0};
-        for (;;) {
-#pragma unroll
-            for (int u = 0; u < kU; ++u)
-                if (row[u] < D.n) {
-                    const int64_t idx = row[u] * kp + j;
-                    Q[idx] = acc[u];
-                    v[0] += (double)P[idx] * (double)acc[u];
+                for (int u = 0; u < kU; ++u) {
+                    row[u] = b + (int64_t)u * rps;
+                    if (row[u] >= r1) row[u] = D.n;  // masked
                 }
-            rb += (int64_t)kU * rps;
-            if (rb >= r1) break;
+                if constexpr (KP == 1 && LPR > 1) rows_dot_split<T, LPR>(D, row, j, P, acc);
+                else rows_product<T, KP>(D, row, j, P, acc);
+            };
             batch(rb);
+            if (fresh) {
+                const int any = __syncthreads_or(a_in);
+                if (threadIdx.x == 0) {
+                    s_sys = s;
+                    s_any = any;
+                }
+                __syncthreads();
+            }
+            if (!force && !s_any) return;
+            double v[1] = {0.0};
+            for (;;) {
+#pragma unroll
+                for (int u = 0; u < kU; ++u)
+                    if (row[u] < D.n && (KP > 1 || j == 0)) {
+                        const int64_t idx = KP > 1 ? row[u] * kp + j : row[u];
+                        Q[idx] = acc[u];
+                        v[0] += (double)P[idx] * (double)acc[u];
+                    }
+                rb += (int64_t)kU * rps;
+                if (rb >= r1) break;
+                batch(rb);
+            }
+            write_tile_partials<KP>(D, tl, DOT0, 1, v);
+            if (D.band) band_log<1, KP>(D, tl, DOT0, lg);
+        };
+        if constexpr (KP == 1) {
+            if (D.lpr == 8) rows_body(std::integral_constant<int, 8>{});
+            else if (D.lpr == 4) rows_body(std::integral_constant<int, 4>{});
+            else if (D.lpr == 2) rows_body(std::integral_constant<int, 2>{});
+            else rows_body(std::integral_constant<int, 1>{});
+        } else {
+            rows_body(std::integral_constant<int, KP>{});
         }
-        write_tile_partials<KP>(D, tl, DOT0, 1, v);
-        if (D.band) band_log<1, KP>(D, tl, DOT0, lg);
     });
     if (s_logsys >= 0 && Dlog.band) band_flush<1, KP>(Dlog, DOT0, lg);
 }

@@ -99,6 +99,30 @@ def test_spmm_matches_oracle(fmt, k):
     assert np.all(np.abs(Y.cpu().numpy() - Yo) <= 1e-13 * absAx)
 
 
+@pytest.mark.parametrize("lpr", [None, 1, 2, 4, 8])
+@pytest.mark.parametrize("order,m", [(3, 19), (4, 15)])
+def test_k1_split_rows_match_oracle(order, m, lpr, monkeypatch):
+    # k = 1 SpMM with the long P3/P4 rows split over 1, 2, 4 or 8 lanes
+    # (None: the automatic choice), through fem_spmv and the phase kernels
+    if lpr is not None:
+        monkeypatch.setenv("FEMCG_LPR", str(lpr))
+    c = Case(2, m, 0.3, order, 1, seed=5, noise=0.01)
+    X = np.random.default_rng(order).standard_normal((c.A.n_free, 1))
+    Y = torch.zeros((c.A.n_free, 1), dtype=torch.float64, device="cuda")
+    femcg.fem_spmv(c.A, dev(X), Y)
+    torch.cuda.synchronize()
+    rp, col, val = c.orc.A()
+    absAx = np.array([np.abs(val[rp[i]:rp[i + 1]]) @ np.abs(X[col[rp[i]:rp[i + 1]], 0])
+                      for i in range(c.orc.nfree)])
+    assert np.all(np.abs(Y.cpu().numpy()[:, 0] - c.orc.spmv(X)[:, 0]) <= 1e-13 * absAx)
+    femcg.fem_set_tiling(c.A, 0, 0)
+    _, its_t, _, _, _ = c.orc.pcg(c.Bo, 1e-10)
+    rc, Xs, st = c.solve(1e-10)
+    assert rc == 0, st
+    assert np.all(c.orc.relres(c.Bo, Xs) <= 1e-10 * 1.0001)
+    assert abs(st["iters"][0] - its_t[0]) <= 0.02 * its_t[0] + 2, (st["iters"], its_t)
+
+
 @pytest.mark.parametrize("dim,m,jit,order", CASES)
 @pytest.mark.parametrize("prec", [femcg.PCG_FP64, femcg.PCG_MIXED])
 def test_solve_matches_oracle(dim, m, jit, order, prec):
