@@ -89,6 +89,21 @@ def cpu_baseline(w, budget_s=15.0):
                 ms_per_iter=1e3 * el / int(it[0]))
 
 
+def calibration_copy(args):
+    """One plain device copy of --calibrate-copy-mb (HBM counter calibration)."""
+    import torch
+
+    if args.calibrate_copy_mb > 0:
+        nel = int(args.calibrate_copy_mb * 1e6 / 8)
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d doubles (%.1f MB read, %.1f MB written)" % (nel, nel * 8e-6, nel * 8e-6))
+        del src, dst
+
+
 def make_workload(name):
     import meshgen
     return {"c1": meshgen.c1, "c2": meshgen.c2, "c3": meshgen.c3, "c4": meshgen.c4}[name]()
@@ -102,15 +117,7 @@ def run_single(args):
     from paper_2201_05413_amd import femcg
 
     torch.cuda.set_device(0)
-    if args.calibrate_copy_mb > 0:
-        nel = int(args.calibrate_copy_mb * 1e6 / 8)
-        src = torch.ones(nel, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log("calibration copy: %d doubles (%.1f MB read, %.1f MB written)" % (nel, nel * 8e-6, nel * 8e-6))
-        del src, dst
+    calibration_copy(args)
     t0 = time.time()
     w = make_workload(args.workload)
     log("workload %s: mesh %.1f s" % (w.name, time.time() - t0))
@@ -490,8 +497,12 @@ def run_degrees(args):
     from paper_2201_05413_amd import femcg
 
     torch.cuda.set_device(0)
+    calibration_copy(args)
     mesh = meshgen.mesh2d(294, 0.3, 11)
     tol = 1e-12
+    traffic = {}
+    if args.traffic_json and os.path.exists(args.traffic_json):
+        traffic = json.load(open(args.traffic_json))
     rows = []
     for order in args.degrees:
         t0 = time.perf_counter()
@@ -505,8 +516,10 @@ def run_degrees(args):
         n = A.n_free
         B = torch.empty((n, 1), dtype=torch.float64, device="cuda")
         femcg.fem_rhs(A, g, B)
-        res = {}
-        for prec, key in ((femcg.PCG_FP64, "fp64"), (femcg.PCG_MIXED, "mixed")):
+        res = {"mixed": dict(ms=None, iters=None)}
+        precs = ((femcg.PCG_FP64, "fp64"),) if args.deg_fp64_only else ((femcg.PCG_FP64, "fp64"),
+                                                                          (femcg.PCG_MIXED, "mixed"))
+        for prec, key in precs:
             o = femcg.default_opts(tol=tol, precision=prec, check_every=args.check_every, inner_eta=args.eta)
             X = torch.zeros_like(B)
             femcg.pcg_solve(A, B, X, tol, o)  # warm-up (graph capture)
@@ -537,7 +550,7 @@ def run_degrees(args):
                    fp64_ms=res["fp64"]["ms"], fp64_iters=res["fp64"]["iters"],
                    mixed_ms=res["mixed"]["ms"], mixed_inner_iters=res["mixed"]["iters"],
                    max_nodal_error=err, spmm_ms=round(ms_k, 5), spmm_gbs=round(gbs, 1),
-                   spmm_frac=round(gbs / HBM_PEAK_GBS, 4))
+                   spmm_frac=round(gbs / HBM_PEAK_GBS, 4), spmm_traffic=traffic.get("deg_p%d" % order))
         if not args.no_check:
             t0 = time.perf_counter()
             orc = oracle.System(mesh, order)
@@ -545,9 +558,9 @@ def run_degrees(args):
             row["oracle_check_s"] = round(time.perf_counter() - t0, 2)
             del orc
         rows.append(row)
-        log("P%d: dofs %d nnz %d | asm %.2f s tune %.2f s | fp64 %.2f ms (%d its) mixed %.2f ms | err %.2e | "
+        log("P%d: dofs %d nnz %d | asm %.2f s tune %.2f s | fp64 %.2f ms (%d its) mixed %s ms | err %.2e | "
             "SpMM %.1f GB/s%s" % (order, row["dofs"], nnz, t_asm, t_tune, row["fp64_ms"], row["fp64_iters"],
-                                  row["mixed_ms"], err, gbs,
+                                  row["mixed_ms"] if row["mixed_ms"] is None else "%.2f" % row["mixed_ms"], err, gbs,
                                   (" | oracle relres %.2e" % row["oracle_relres_fp64"]) if not args.no_check else ""))
         A.free()
     line = {
@@ -594,6 +607,7 @@ def main():
     ap.add_argument("--asm-oracle-max-n", type=int, default=3000000,
                     help="assembly timing: time the oracle's assembly up to this many free DOFs")
     ap.add_argument("--degrees", type=int, nargs="+", default=[1, 2, 3, 4], help="deg workload: FEM degrees")
+    ap.add_argument("--deg-fp64-only", action="store_true", help="deg workload: skip the mixed solves (counter runs)")
     ap.add_argument("--serve-fractions", type=float, nargs="+", default=[0.3, 0.7, 1.0],
                     help="serving: arrival rates as fractions of the measured capacity")
     ap.add_argument("--slots", type=int, default=32)

@@ -441,6 +441,12 @@ static int class_of(int kp)
     return c;
 }
 
+// launch-mask bit of one system: its kp class, or the split-row kp = 1 bit
+static unsigned launch_bit(int kp, int lpr)
+{
+    return (kp == 1 && lpr > 1) ? kSplitBit : 1u << class_of(kp);
+}
+
 // Fill a host table from slot ids (sorted by kp class in place, stable, with
 // their per-system flags); returns total tiles and the class mask.
 static int64_t fill_table(Engine *e, SysTable *h, std::vector<int> &ids, bool fp32, int use_x, int write_p,
@@ -460,7 +466,7 @@ static int64_t fill_table(Engine *e, SysTable *h, std::vector<int> &ids, bool fp
     ids = sid;
     if (use_x_per) *use_x_per = sux;
     int64_t base = 0;
-    unsigned m = 0;
+    unsigned m = 0, seen = 0;
     for (int c = 0; c < kNumClass; ++c) h->cls_begin[c] = h->cls_end[c] = 0;
     h->nsys = (int)ids.size();
     for (size_t i = 0; i < ids.size(); ++i) {
@@ -470,8 +476,9 @@ static int64_t fill_table(Engine *e, SysTable *h, std::vector<int> &ids, bool fp
         D.write_p = write_p;
         D.par_off = e->slots[ids[i]].par_off;
         const int c = class_of(D.kp);
-        if (!(m & (1u << c))) h->cls_begin[c] = base;
-        m |= 1u << c;
+        if (!(seen & (1u << c))) h->cls_begin[c] = base;
+        seen |= 1u << c;
+        m |= launch_bit(D.kp, D.lpr);
         base += D.ntiles;
         h->cls_end[c] = base;
         h->d[i] = D;
@@ -1019,7 +1026,7 @@ static int fem_spmv_impl(fem_matrix *A, const double *X, double *Y, int32_t k, v
     D.tile_base = 0;
     set_single_table(h, D);
     HIPCHK(hipMemcpyAsync(d, h, table_bytes(1), hipMemcpyHostToDevice, s));
-    launch_phase<double>(PH_SPMM, d, grid_for(D.ntiles, grid_cap(A, w)), 0, 1, 1u << class_of(kp), s);
+    launch_phase<double>(PH_SPMM, d, grid_for(D.ntiles, grid_cap(A, w)), 0, 1, launch_bit(kp, w->lpr), s);
     launch_scatter(w->Q64, A->d_perm, n, k, kp, nullptr, Y, s);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
@@ -1262,7 +1269,7 @@ struct SpmmProbe {
         set_single_table(h, D);
         HIPCHK(hipMemcpyAsync(d, h, table_bytes(1), hipMemcpyHostToDevice, s));
         HIPCHK(hipStreamSynchronize(s));
-        cm = 1u << class_of(kp);
+        cm = launch_bit(kp, w->lpr);
         grid = grid_for(D.ntiles, grid_cap(A, w));
         return FEMCG_OK;
     }
@@ -1385,7 +1392,7 @@ static int pcg_time_kernel_impl(fem_matrix *A, int32_t kernel, int32_t reps, voi
         if (hipEventCreate(&x) != hipSuccess) rc = fail(FEMCG_EDEVICE, "hipEventCreate failed");
     double tot = 0.0;
     if (rc == FEMCG_OK) {
-        const int cls = class_of(kp);
+        const int cls = (cm & kSplitBit) ? kSplitCls : class_of(kp);
         for (int ph = 0; ph < 3; ++ph) launch(ph);  // one untimed iteration
         for (int r = 0; r < reps; ++r)
             for (int ph = 0; ph < 3; ++ph) {

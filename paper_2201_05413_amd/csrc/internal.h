@@ -97,6 +97,12 @@ struct SysDesc {
 
 constexpr int kMaxSys = 256;
 constexpr int kNumClass = 7;       // lanes-per-row classes kp = 1, 2, 4, ..., 64
+// launch masks: bit c = class c holds systems; kSplitBit = the kp = 1 class
+// holds systems whose SpMM splits rows over several lanes (SysDesc.lpr > 1),
+// which run in their own SpMM kernel instance (bit 0 then means one-lane
+// kp = 1 systems only); kSplitCls names that instance for timed launches
+constexpr unsigned kSplitBit = 1u << 7;
+constexpr int kSplitCls = 7;
 
 // Systems sorted by kp; class c (kp = 1 << c) owns global tiles
 // [cls_begin[c], cls_end[c]).  Each class is processed by its own kernel

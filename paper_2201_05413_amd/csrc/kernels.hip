@@ -770,9 +770,14 @@ __device__ __forceinline__ void rows_product(const SysDesc &D, const int64_t *ro
 // phase 1: q = A p, partial p.q
 // ---------------------------------------------------------------------------
 
-template <typename T, int KP>
+// SPLIT: the kp = 1 systems whose rows are split over several lanes (D.lpr >
+// 1) run in their own instance of the kernel, so that the one-lane instance
+// keeps its smaller register budget (71 against 82 VGPRs: 7 waves per SIMD
+// instead of 5).  Each instance skips the other's systems whole.
+template <typename T, int KP, bool SPLIT = false>
 __global__ __launch_bounds__(kBlock) void k_spmm(const SysTable *__restrict__ tab, int it, int force)
 {
+    static_assert(!SPLIT || KP == 1, "split rows exist at kp = 1 only");
     __shared__ int s_sys, s_any, s_logsys;
     __shared__ BandLog lg;
     if (threadIdx.x == 0) {
@@ -785,6 +790,9 @@ __global__ __launch_bounds__(kBlock) void k_spmm(const SysTable *__restrict__ ta
     for_each_tile_in(tab->cls_begin[kLog2<KP>], tab->cls_end[kLog2<KP>], [&](int64_t t) {
         const int s = find_sys(tab, t);
         const SysDesc D = tab->d[s];
+        if constexpr (KP == 1) {
+            if ((D.lpr > 1) != SPLIT) return;  // the other instance's system
+        }
         if (s != s_logsys) {
             if (s_logsys >= 0 && Dlog.band) band_flush<1, KP>(Dlog, DOT0, lg);
             __syncthreads();
@@ -891,11 +899,12 @@ __global__ __launch_bounds__(kBlock) void k_spmm(const SysTable *__restrict__ ta
             write_tile_partials<KP>(D, tl, DOT0, 1, v);
             if (D.band) band_log<1, KP>(D, tl, DOT0, lg);
         };
-        if constexpr (KP == 1) {
+        if constexpr (SPLIT) {
             if (D.lpr == 8) rows_body(std::integral_constant<int, 8>{});
             else if (D.lpr == 4) rows_body(std::integral_constant<int, 4>{});
-            else if (D.lpr == 2) rows_body(std::integral_constant<int, 2>{});
-            else rows_body(std::integral_constant<int, 1>{});
+            else rows_body(std::integral_constant<int, 2>{});
+        } else if constexpr (KP == 1) {
+            rows_body(std::integral_constant<int, 1>{});
         } else {
             rows_body(std::integral_constant<int, KP>{});
         }
@@ -1817,9 +1826,15 @@ int grid_for(int64_t total_tiles, int max_grid)
 }
 
 template <typename T, int KP>
-static void launch_phase_kp(int phase, const SysTable *tab, int grid, int it, int force, hipStream_t s)
+static void launch_phase_kp(int phase, const SysTable *tab, int grid, int it, int force, hipStream_t s,
+                            unsigned cls_mask = 0)
 {
-    if (phase == PH_SPMM)
+    if (phase == PH_SPMM && KP == 1) {
+        // one-lane and split-row systems of the kp = 1 class
+        if (cls_mask & 1u) hipLaunchKernelGGL((k_spmm<T, 1, false>), dim3(grid), dim3(kBlock), 0, s, tab, it, force);
+        if (cls_mask & kSplitBit)
+            hipLaunchKernelGGL((k_spmm<T, 1, true>), dim3(grid), dim3(kBlock), 0, s, tab, it, force);
+    } else if (phase == PH_SPMM)
         hipLaunchKernelGGL((k_spmm<T, KP>), dim3(grid), dim3(kBlock), 0, s, tab, it, force);
     else if (phase == PH_UPDATE)
         hipLaunchKernelGGL((k_update<T, KP>), dim3(grid), dim3(kBlock), 0, s, tab, it, force);
@@ -1831,7 +1846,7 @@ template <typename T>
 void launch_phase(int phase, const SysTable *tab, int grid, int it, int force, unsigned cls_mask,
                   hipStream_t s)
 {
-    if (cls_mask & 1) launch_phase_kp<T, 1>(phase, tab, grid, it, force, s);
+    if (cls_mask & (1u | kSplitBit)) launch_phase_kp<T, 1>(phase, tab, grid, it, force, s, cls_mask);
     if (cls_mask & 2) launch_phase_kp<T, 2>(phase, tab, grid, it, force, s);
     if (cls_mask & 4) launch_phase_kp<T, 4>(phase, tab, grid, it, force, s);
     if (cls_mask & 8) launch_phase_kp<T, 8>(phase, tab, grid, it, force, s);
@@ -1858,7 +1873,12 @@ template <typename T>
 void launch_phase_timed(int phase, const SysTable *tab, int grid, int it, int force, int cls, hipStream_t s,
                         hipEvent_t ev0, hipEvent_t ev1)
 {
+    if (cls == kSplitCls && phase == PH_SPMM) {
+        hipExtLaunchKernelGGL((k_spmm<T, 1, true>), dim3(grid), dim3(kBlock), 0, s, ev0, ev1, 0, tab, it, force);
+        return;
+    }
     switch (cls) {
+    case kSplitCls:
     case 0: launch_phase_kp_timed<T, 1>(phase, tab, grid, it, force, s, ev0, ev1); break;
     case 1: launch_phase_kp_timed<T, 2>(phase, tab, grid, it, force, s, ev0, ev1); break;
     case 2: launch_phase_kp_timed<T, 4>(phase, tab, grid, it, force, s, ev0, ev1); break;
@@ -1876,7 +1896,7 @@ template void launch_phase_timed<float>(int, const SysTable *, int, int, int, in
 template <typename T>
 void launch_residual_init(const SysTable *tab, int grid, int nsys, unsigned cls_mask, hipStream_t s)
 {
-    if (cls_mask & 1) hipLaunchKernelGGL((k_residual<T, 1>), dim3(grid), dim3(kBlock), 0, s, tab);
+    if (cls_mask & (1u | kSplitBit)) hipLaunchKernelGGL((k_residual<T, 1>), dim3(grid), dim3(kBlock), 0, s, tab);
     if (cls_mask & 2) hipLaunchKernelGGL((k_residual<T, 2>), dim3(grid), dim3(kBlock), 0, s, tab);
     if (cls_mask & 4) hipLaunchKernelGGL((k_residual<T, 4>), dim3(grid), dim3(kBlock), 0, s, tab);
     if (cls_mask & 8) hipLaunchKernelGGL((k_residual<T, 8>), dim3(grid), dim3(kBlock), 0, s, tab);

@@ -218,6 +218,29 @@ def test_batch_equals_alone_bitwise():
         assert np.array_equal(X.cpu().numpy(), Xa)
 
 
+@pytest.mark.parametrize("prec", [femcg.PCG_FP64, femcg.PCG_MIXED])
+def test_batch_mixing_one_lane_and_split_rows_bitwise(prec):
+    # the kp = 1 class holds one-lane (P1) and split-row (P3, P4) systems, so
+    # each SpMM phase launches both kernel instances over the same table
+    cases = [Case(2, 80, 0.3, 1, 1, seed=25), Case(2, 25, 0.3, 3, 1, seed=26), Case(2, 20, 0.25, 4, 1, seed=27),
+             Case(2, 29, 0.0, 2, 3, seed=28)]
+    alone = []
+    for c in cases:
+        assert c.A.n_free * (4 if c.k == 3 else 1) > 4096  # phase kernels, not the single-workgroup loop
+        rc, X, st = c.solve(1e-10, precision=prec)
+        assert rc == 0
+        assert np.all(c.orc.relres(c.Bo, X) <= 1e-10 * 1.0001)
+        alone.append(X)
+    Bs = [c.B() for c in cases]
+    Xs = [torch.zeros_like(b) for b in Bs]
+    st = femcg.pcg_solve_batch([c.A for c in cases], Bs, Xs, [1e-10] * len(cases),
+                               femcg.default_opts(tol=1e-10, precision=prec))
+    torch.cuda.synchronize()
+    assert st == [0] * len(cases)
+    for X, Xa in zip(Xs, alone):
+        assert np.array_equal(X.cpu().numpy(), Xa)
+
+
 def test_format_and_tuner_agree():
     c = Case(2, 33, 0.25, 2, 3, seed=31)
     rc, X1, _ = c.solve(1e-12)
@@ -230,7 +253,7 @@ def test_format_and_tuner_agree():
 
 
 @pytest.mark.parametrize("dim,m,jit,order,k", [(2, 200, 0.3, 1, 1), (3, 30, 0.2, 1, 8), (2, 60, 0.25, 2, 32),
-                                               (3, 12, 0.3, 2, 3)])
+                                               (3, 12, 0.3, 2, 3), (2, 40, 0.3, 4, 1)])
 @pytest.mark.parametrize("prec", [femcg.PCG_FP64, femcg.PCG_MIXED])
 def test_band_mode_matches_oracle(dim, m, jit, order, k, prec):
     # band mode with tiny tiles: 145..343 tiles, i.e. several reduction groups
