@@ -12,6 +12,9 @@ Each wrapper names the passage of the paper the C function follows:
 * ``p2_element`` -- Table 7's higher-degree basis (degree 2), exact quadrature;
 * ``pk_element`` -- Table 7's degrees 3 and 4 on triangles: nodal basis from
   the inverse Vandermonde matrix, collapsed Gauss-Legendre quadrature;
+* ``bicgstab_csr`` / ``bj_apply`` -- the paper's own iterative solver
+  (Sect. 3.2): BiCGStab right preconditioned by Block-Jacobi with exact
+  blocks of bs consecutive rows;
 * ``System`` -- assembly, Dirichlet lifting (Sect. 2.2: u = f on the boundary,
   b encodes the boundary condition), Jacobi-PCG (Sect. 2.1, M = diag(A)) with
   the exit test of Eq. (2), and the error metric of Eq. (1).
@@ -69,6 +72,8 @@ def _load():
     lib.orc_relres.argtypes = [P, P, P, C.c_int, P]
     lib.orc_pcg.argtypes = [P, P, C.c_int, C.c_double, C.c_int64, P, P, P, P]
     lib.orc_pcg_csr.argtypes = [C.c_int64, P, P, P, P, C.c_int, C.c_double, C.c_int64, P, P, P, P]
+    lib.orc_bj_apply.argtypes = [C.c_int64, P, P, P, C.c_int, P, P]
+    lib.orc_bicgstab_csr.argtypes = [C.c_int64, P, P, P, P, C.c_int, C.c_double, C.c_int64, P, P, P, P]
     lib.orc_fd7_identity_nnz.argtypes = [C.c_int64]
     lib.orc_fd7_identity_nnz.restype = C.c_int64
     _lib = lib
@@ -246,6 +251,38 @@ def pcg_csr(rowptr, col, val, B, tol, max_iter=None):
     st = _load().orc_pcg_csr(n, _ptr(rowptr), _ptr(col), _ptr(val), _ptr(B), k, tol, max_iter,
                              _ptr(X), _ptr(its), _ptr(rel), _ptr(rs))
     return X, its, rel, rs, st
+
+
+def bj_apply(rowptr, col, val, bs, r):
+    """z = M^-1 r for the Block-Jacobi preconditioner with exact blocks of bs
+    consecutive rows (Sect. 3.2's preconditioner)."""
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    z = np.zeros_like(r)
+    _check(_load().orc_bj_apply(len(rowptr) - 1, _ptr(rowptr), _ptr(col), _ptr(val), bs, _ptr(r), _ptr(z)))
+    return z
+
+
+def bicgstab_csr(rowptr, col, val, b, bs, tol, max_iter=None):
+    """BiCGStab, right preconditioned by Block-Jacobi (exact blocks of bs
+    consecutive rows), zero initial guess (Sect. 3.2's solver).  Returns
+    x, iterations, true relative residual, restarts, status."""
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    b = np.ascontiguousarray(np.asarray(b, dtype=np.float64).reshape(-1))
+    n = len(rowptr) - 1
+    if max_iter is None:
+        max_iter = default_max_iter(n)
+    x = np.zeros(n)
+    its = np.zeros(1, dtype=np.int64)
+    rel = np.zeros(1)
+    rs = np.zeros(1, dtype=np.int32)
+    st = _load().orc_bicgstab_csr(n, _ptr(rowptr), _ptr(col), _ptr(val), _ptr(b), bs, tol, max_iter, _ptr(x),
+                                  _ptr(its), _ptr(rel), _ptr(rs))
+    return x, int(its[0]), float(rel[0]), int(rs[0]), st
 
 
 def default_max_iter(n: int) -> int:

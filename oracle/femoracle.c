@@ -38,6 +38,9 @@
  *     ||b - A x|| / ||b||; if that exceeds tol the solve restarts from x
  *     (at most 3 times).  Iterations count the products A p.
  *  6. Eq. (1) error and Eq. (2) residual helpers.
+ *  7. The paper's own iterative solver (Sect. 3.2): BiCGStab, right
+ *     preconditioned by Block-Jacobi with exact solves of blocks of bs
+ *     consecutive rows (dense LU with partial pivoting).
  *
  * Every function returns 0 on success and a negative code on failure.
  */
@@ -1000,6 +1003,203 @@ int orc_pcg_csr(int64_t n, const int64_t *rowptr, const int32_t *col, const doub
     int rc = pcg_csr(&A, B, k, tol, max_iter, X, iters, relres, restarts);
     free(diag);
     return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* BiCGStab with a Block-Jacobi preconditioner                                */
+/* ------------------------------------------------------------------------- */
+
+/* The paper's iterative solver is BiCGStab with a Block-Jacobi
+ * preconditioner (Sect. 3.2).  Blocks here: the consecutive rows
+ * [b bs, min(n, (b+1) bs)) of the matrix, the last one possibly shorter; the
+ * block systems are solved exactly, by a dense LU factorisation with partial
+ * pivoting of each diagonal block (taken once per solve), then two
+ * triangular solves per application.  bs = 1 is the Jacobi preconditioner. */
+typedef struct {
+    int64_t n, nb;
+    int bs;
+    double *lu;    /* [nb][bs][bs] row-major LU factors (unit lower implied) */
+    int32_t *piv;  /* [nb][bs] row interchanges */
+} bj_fact;
+
+static void bj_free(bj_fact *F)
+{
+    free(F->lu);
+    free(F->piv);
+}
+
+static int bj_factor(const csr_view *A, int bs, bj_fact *F)
+{
+    int64_t n = A->n;
+    F->n = n;
+    F->bs = bs;
+    F->nb = (n + bs - 1) / bs;
+    F->lu = calloc((size_t)(F->nb ? F->nb : 1) * bs * bs, sizeof(double));
+    F->piv = calloc((size_t)(F->nb ? F->nb : 1) * bs, sizeof(int32_t));
+    if (!F->lu || !F->piv) { bj_free(F); return ORC_ENOMEM; }
+    for (int64_t b = 0; b < F->nb; b++) {
+        int64_t r0 = b * bs;
+        int m = (int)((r0 + bs <= n) ? bs : n - r0);
+        double *M = F->lu + (size_t)b * bs * bs;
+        int32_t *pv = F->piv + (size_t)b * bs;
+        for (int i = 0; i < m; i++)
+            for (int64_t t = A->rowptr[r0 + i]; t < A->rowptr[r0 + i + 1]; t++) {
+                int64_t c = A->col[t];
+                if (c >= r0 && c < r0 + m) M[i * bs + (c - r0)] += A->val[t];
+            }
+        for (int c = 0; c < m; c++) {
+            int p = c;
+            for (int r = c + 1; r < m; r++)
+                if (fabs(M[r * bs + c]) > fabs(M[p * bs + c])) p = r;
+            if (M[p * bs + c] == 0.0) { bj_free(F); return ORC_EBREAK; }
+            pv[c] = p;
+            if (p != c)
+                for (int j = 0; j < m; j++) {
+                    double t = M[c * bs + j]; M[c * bs + j] = M[p * bs + j]; M[p * bs + j] = t;
+                }
+            for (int r = c + 1; r < m; r++) {
+                double l = M[r * bs + c] / M[c * bs + c];
+                M[r * bs + c] = l;
+                for (int j = c + 1; j < m; j++) M[r * bs + j] -= l * M[c * bs + j];
+            }
+        }
+    }
+    return 0;
+}
+
+/* z = M^-1 r, block by block: permute, forward (unit lower), backward */
+static void bj_apply(const bj_fact *F, const double *r, double *z)
+{
+    int bs = F->bs;
+    for (int64_t b = 0; b < F->nb; b++) {
+        int64_t r0 = b * bs;
+        int m = (int)((r0 + bs <= F->n) ? bs : F->n - r0);
+        const double *M = F->lu + (size_t)b * bs * bs;
+        const int32_t *pv = F->piv + (size_t)b * bs;
+        double y[64];
+        for (int i = 0; i < m; i++) y[i] = r[r0 + i];
+        for (int c = 0; c < m; c++)
+            if (pv[c] != c) { double t = y[c]; y[c] = y[pv[c]]; y[pv[c]] = t; }
+        for (int i = 0; i < m; i++)
+            for (int j = 0; j < i; j++) y[i] -= M[i * bs + j] * y[j];
+        for (int i = m - 1; i >= 0; i--) {
+            for (int j = i + 1; j < m; j++) y[i] -= M[i * bs + j] * y[j];
+            y[i] /= M[i * bs + i];
+        }
+        for (int i = 0; i < m; i++) z[r0 + i] = y[i];
+    }
+}
+
+/* z = M^-1 r for a caller-given CSR matrix (bs <= 64) */
+int orc_bj_apply(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val, int bs,
+                 const double *r, double *z)
+{
+    if (bs < 1 || bs > 64) return ORC_EINVAL;
+    csr_view A = {n, rowptr, col, val, NULL};
+    bj_fact F;
+    int rc = bj_factor(&A, bs, &F);
+    if (rc) return rc;
+    bj_apply(&F, r, z);
+    bj_free(&F);
+    return 0;
+}
+
+/* BiCGStab (van der Vorst), right preconditioned by M, zero initial guess,
+ * one right-hand side:
+ *   r = b - A x, rh = r;  rho_old = alpha = omega = 1;  v = p = 0
+ *   repeat:  rho = (rh, r);  beta = (rho / rho_old)(alpha / omega)
+ *            p = r + beta (p - omega v);  ph = M^-1 p;  v = A ph
+ *            alpha = rho / (rh, v);  s = r - alpha v
+ *            if ||s|| <= tol ||b||:  x += alpha ph, r = s, stop
+ *            sh = M^-1 s;  t = A sh;  omega = (t, s) / (t, t)
+ *            x += alpha ph + omega sh;  r = s - omega t;  rho_old = rho
+ * until ||r|| <= tol ||b|| (the Eq. (2) test on the recursive residual),
+ * then the true residual ||b - A x|| / ||b||, restarting from x when it is
+ * above tol (at most 3 times).  One iteration = one pass of the loop (two
+ * products with A, one when it stops at s).  rho = 0, (rh, v) = 0, omega = 0
+ * or a non-finite scalar is a breakdown. */
+int orc_bicgstab_csr(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                     const double *bvec, int bs, double tol, int64_t max_iter, double *xout,
+                     int64_t *iters, double *relres, int32_t *restarts)
+{
+    if (bs < 1 || bs > 64 || n < 0) return ORC_EINVAL;
+    csr_view A = {n, rowptr, col, val, NULL};
+    bj_fact F;
+    int rc = bj_factor(&A, bs, &F);
+    if (rc) return rc;
+    size_t bytes = sizeof(double) * (n ? n : 1);
+    double *x = calloc(n ? n : 1, sizeof(double)), *r = malloc(bytes), *rh = malloc(bytes);
+    double *p = malloc(bytes), *ph = malloc(bytes), *v = malloc(bytes), *sv = malloc(bytes);
+    double *sh = malloc(bytes), *t = malloc(bytes);
+    int status = 0;
+    if (!x || !r || !rh || !p || !ph || !v || !sv || !sh || !t) { status = ORC_ENOMEM; goto done; }
+    double bnorm = sqrt(dot1(n, bvec, bvec));
+    int64_t its = 0;
+    int rs = 0;
+    double rel = 0.0;
+    if (bnorm == 0.0) goto finish;
+    for (;;) {
+        spmv1(&A, x, t);
+        for (int64_t i = 0; i < n; i++) {
+            r[i] = bvec[i] - t[i];
+            rh[i] = r[i];
+            p[i] = v[i] = 0.0;
+        }
+        double rho_old = 1.0, alpha = 1.0, omega = 1.0;
+        double rnorm = sqrt(dot1(n, r, r));
+        while (rnorm > tol * bnorm && its < max_iter) {
+            double rho = dot1(n, rh, r);
+            if (rho == 0.0 || !isfinite(rho)) { status = ORC_EBREAK; break; }
+            double beta = (rho / rho_old) * (alpha / omega);
+            for (int64_t i = 0; i < n; i++) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+            bj_apply(&F, p, ph);
+            spmv1(&A, ph, v);
+            double sig = dot1(n, rh, v);
+            if (sig == 0.0 || !isfinite(sig)) { status = ORC_EBREAK; break; }
+            alpha = rho / sig;
+            for (int64_t i = 0; i < n; i++) sv[i] = r[i] - alpha * v[i];
+            its++;
+            double snorm = sqrt(dot1(n, sv, sv));
+            if (snorm <= tol * bnorm) {
+                for (int64_t i = 0; i < n; i++) {
+                    x[i] += alpha * ph[i];
+                    r[i] = sv[i];
+                }
+                rnorm = snorm;
+                break;
+            }
+            bj_apply(&F, sv, sh);
+            spmv1(&A, sh, t);
+            double tt = dot1(n, t, t), ts = dot1(n, t, sv);
+            omega = ts / tt;
+            if (omega == 0.0 || !isfinite(omega)) { status = ORC_EBREAK; break; }
+            for (int64_t i = 0; i < n; i++) {
+                x[i] += alpha * ph[i] + omega * sh[i];
+                r[i] = sv[i] - omega * t[i];
+            }
+            rho_old = rho;
+            rnorm = sqrt(dot1(n, r, r));
+        }
+        spmv1(&A, x, t);
+        double rr = 0.0;
+        for (int64_t i = 0; i < n; i++) {
+            double d = bvec[i] - t[i];
+            rr += d * d;
+        }
+        rel = sqrt(rr) / bnorm;
+        if (status == ORC_EBREAK || rel <= tol || its >= max_iter || rs >= 3) break;
+        rs++;
+    }
+    if (its >= max_iter && rel > tol && status == 0) status = 1;
+finish:
+    *iters = its;
+    *relres = rel;
+    if (restarts) *restarts = rs;
+    for (int64_t i = 0; i < n; i++) xout[i] = x[i];
+done:
+    free(x); free(r); free(rh); free(p); free(ph); free(v); free(sv); free(sh); free(t);
+    bj_free(&F);
+    return status;
 }
 
 /* Count of the nonzeros of the paper's regular-grid matrix read as a
