@@ -138,6 +138,39 @@ void pcg_default_opts(pcg_opts *opts);
  * FEMCG_EUNSUPPORTED, FEMCG_EDEVICE. */
 int fem_assemble(const fem_mesh *mesh, int32_t order, int32_t format, fem_matrix **out);
 
+/* Statistics of one bicgstab_solve. */
+typedef struct {
+    int64_t iters;         /* BiCGStab iterations (two products with A each; one
+                              for the last if it stops at the half step) */
+    double relres;         /* true FP64 ||b - A x|| / ||b|| (Eq. (2)) */
+    int32_t restarts;      /* restarts from x after the true residual missed tol */
+    int32_t block_size;
+    int64_t nblocks;
+    double setup_s;        /* block inverses and upload (first call per block size) */
+    double solve_s;        /* wall time of the call */
+    double bytes;          /* algorithmic HBM bytes of the iterations */
+} bicgstab_stats_t;
+
+/* The paper's iterative solver (Sect. 3.2: BiCGStab with a Block-Jacobi
+ * preconditioner) on A = K_II: BiCGStab, right preconditioned by Block-Jacobi
+ * with exact blocks of block_size (1..64) consecutive free DOFs in the public
+ * order (the last block may be shorter; block_size 1 is Jacobi).  One
+ * right-hand side, FP64, zero initial guess.  Stops when the recursive
+ * residual satisfies Eq. (2) (||r|| <= tol ||b||), also at the half step
+ * (||s|| <= tol ||b||), then checks the true residual and restarts from x
+ * when it misses tol (at most 3 times).
+ * B, X: device [n_free] FP64, public order (B read, X written).  max_iter:
+ * cap on iterations, 0 = 20 sqrt(n) log2(n) + 100.  The block inverses
+ * (Gauss-Jordan with partial pivoting, on the host) are built at the first
+ * call with a given block size and kept with A until the format or the block
+ * size changes.  Work is enqueued on `stream` and the call synchronises it.
+ * stats may be NULL.
+ * Returns 0, FEMCG_WARN_MAXITER, or FEMCG_EINVAL (arguments), FEMCG_EBREAKDOWN
+ * (a singular block, rho = 0, (rh, v) = 0, omega = 0 or a non-finite
+ * scalar), FEMCG_ENOMEM, FEMCG_EDEVICE. */
+int bicgstab_solve(fem_matrix *A, const double *B, double *X, double tol, int32_t block_size,
+                   int64_t max_iter, void *stream, bicgstab_stats_t *stats);
+
 /* Sizes and DOF data.  Any output pointer may be NULL.
  * dof_coords: host [n_all][dim]; dirichlet: host [n_all]; free2dof: host
  * [n_free] (the DOF index of each solver row). */

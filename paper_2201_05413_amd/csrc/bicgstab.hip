@@ -1,0 +1,628 @@
+// bicgstab.hip -- BiCGStab right-preconditioned by Block-Jacobi with exact
+// blocks, one right-hand side, FP64 (Sect. 3.2: the paper's iterative solver
+// is BiCGStab with a Block-Jacobi preconditioner).
+//
+// Blocks are bs consecutive free DOFs of the public order (the last one may be
+// shorter).  Each block's inverse is formed once on the host (Gauss-Jordan
+// with partial pivoting) and applied on the device as a dense bs x bs product,
+// fused into the kernel that produces the vector it preconditions:
+//   K1  rho = (rh, r), ||r||^2 from K5's partials; Eq. (2) test; beta;
+//       p = r + beta (p - omega v);  ph = M^-1 p
+//   K2  v = A ph;  partial (rh, v)
+//   K3  alpha = rho / (rh, v);  s = r - alpha v;  sh = M^-1 s;  partial (s, s)
+//   K4  unless ||s|| <= tol ||b||:  t = A sh;  partials (t, s), (t, t)
+//   K5  omega = (t, s) / (t, t);  x += alpha ph + omega sh;  r = s - omega t
+//       (x += alpha ph and r = s when ||s|| <= tol ||b||: the solve then
+//       stops);  partials (rh, r), (r, r)
+// Every block of a kernel reduces the partials it needs in one fixed order,
+// so all blocks derive the same scalars; block 0 records alpha, rho and
+// omega in the state for the kernels that follow.  No kernel reads a partial
+// slot it writes, and the state fields a kernel writes are read only by later
+// kernels (a block that sees another block's "done" in the same kernel would
+// have taken the same decision itself).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <memory>
+#include <new>
+#include <vector>
+
+#include "engine.h"
+
+namespace femcg {
+
+namespace {
+
+constexpr int kB = 256;          // threads per block
+constexpr int kGridMax = 1024;   // blocks, i.e. partials per dot
+enum { SL_B = 0, SL_C = 1, SL_D = 2, SL_E = 3, SL_X = 4, kSlots = 5 };
+
+struct BcgState {
+    double rho_old, alpha, omega, bb, tol2;
+    long long iters, max_iter;
+    int done;       // 0 running, 1 converged, 2 iteration cap, -1 breakdown
+    int stop_next;  // K5 stopped at s: K1 ends the solve
+};
+
+struct BcgArgs {
+    int64_t n;
+    int format, sell_shift;
+    const int32_t *rowptr;
+    const int64_t *slice_ptr;
+    const int32_t *rowlen;
+    const int32_t *col;
+    const double *val;
+    int bs;
+    const double *binv;     // [nb][bs][bs]
+    const int32_t *iperm;   // public free row -> internal row
+    double *b, *x, *r, *rh, *p, *ph, *v, *s, *sh, *t;
+    double *part;           // [kSlots][grid][2]
+    BcgState *st;
+};
+
+__device__ __forceinline__ double row_dot(const BcgArgs &a, int64_t row, const double *__restrict__ x)
+{
+    double acc0 = 0.0, acc1 = 0.0;
+    if (a.format == FEM_FORMAT_SELL) {
+        const int64_t C = (int64_t)1 << a.sell_shift;
+        const int64_t base = a.slice_ptr[row >> a.sell_shift] + (row & (C - 1));
+        const int len = a.rowlen[row];
+        int e = 0;
+        for (; e + 1 < len; e += 2) {
+            const int64_t i0 = base + e * C, i1 = i0 + C;
+            acc0 += a.val[i0] * x[a.col[i0]];
+            acc1 += a.val[i1] * x[a.col[i1]];
+        }
+        if (e < len) acc0 += a.val[base + e * C] * x[a.col[base + e * C]];
+    } else {
+        const int32_t e0 = a.rowptr[row], e1 = a.rowptr[row + 1];
+        int32_t e = e0;
+        for (; e + 1 < e1; e += 2) {
+            acc0 += a.val[e] * x[a.col[e]];
+            acc1 += a.val[e + 1] * x[a.col[e + 1]];
+        }
+        if (e < e1) acc0 += a.val[e] * x[a.col[e]];
+    }
+    return acc0 + acc1;
+}
+
+// block sums of v[0..1] in a fixed tree, stored as this block's partials
+__device__ void write_partials(const BcgArgs &a, int slot, double v0, double v1)
+{
+    __shared__ double red[2][kB];
+    red[0][threadIdx.x] = v0;
+    red[1][threadIdx.x] = v1;
+    __syncthreads();
+    for (int off = kB / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + off];
+            red[1][threadIdx.x] += red[1][threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double *dst = a.part + ((int64_t)slot * gridDim.x + blockIdx.x) * 2;
+        dst[0] = red[0][0];
+        dst[1] = red[1][0];
+    }
+}
+
+// the two sums of one partial slot, in the same order in every block
+__device__ void reduce_slot(const BcgArgs &a, int slot, double out[2])
+{
+    __shared__ double red[2][kB];
+    const int G = gridDim.x;
+    const double *src = a.part + (int64_t)slot * G * 2;
+    double s0 = 0.0, s1 = 0.0;
+    for (int g = threadIdx.x; g < G; g += kB) {
+        s0 += src[2 * g];
+        s1 += src[2 * g + 1];
+    }
+    red[0][threadIdx.x] = s0;
+    red[1][threadIdx.x] = s1;
+    __syncthreads();
+    for (int off = kB / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + off];
+            red[1][threadIdx.x] += red[1][threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    out[0] = red[0][0];
+    out[1] = red[1][0];
+    __syncthreads();
+}
+
+// For every public free row i: w = f(internal row) is stored to out1, and
+// out2 = M^-1 w for the row's block.  A pass of a workgroup covers whole
+// blocks (kB / bs of them), staged in LDS.  Returns this thread's sum of w^2.
+template <typename F>
+__device__ double block_apply(const BcgArgs &a, F &&f, double *__restrict__ out1, double *__restrict__ out2)
+{
+    __shared__ double sw[kB];
+    const int bs = a.bs;
+    const int R = (kB / bs) * bs;
+    const int64_t npass = (a.n + R - 1) / R;
+    double w2 = 0.0;
+    for (int64_t c = blockIdx.x; c < npass; c += gridDim.x) {
+        const int lr = threadIdx.x;
+        const int64_t i = c * R + lr;
+        const bool ok = lr < R && i < a.n;
+        const int32_t ii = ok ? a.iperm[i] : 0;
+        double w = 0.0;
+        if (ok) {
+            w = f(ii);
+            out1[ii] = w;
+            w2 += w * w;
+        }
+        sw[lr] = w;
+        __syncthreads();
+        if (ok) {
+            const int q = lr % bs;
+            const int64_t i0 = i - q;
+            const int m = (int)min<int64_t>(bs, a.n - i0);
+            const double *Bi = a.binv + ((i0 / bs) * bs + q) * (int64_t)bs;
+            double z = 0.0;
+            for (int j = 0; j < m; ++j) z += Bi[j] * sw[lr - q + j];
+            out2[ii] = z;
+        }
+        __syncthreads();
+    }
+    return w2;
+}
+
+__device__ __forceinline__ bool lead() { return blockIdx.x == 0 && threadIdx.x == 0; }
+
+// (b, b) into slot X
+__global__ __launch_bounds__(kB) void k_bcg_bb(BcgArgs a)
+{
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kB) acc += a.b[i] * a.b[i];
+    write_partials(a, SL_X, acc, 0.0);
+}
+
+// start (or restart from x): r = b - A x (x = 0: r = b), rh = r, p = v = 0;
+// partials (rh, r), (r, r) into slot E
+__global__ __launch_bounds__(kB) void k_bcg_init(BcgArgs a, int use_x)
+{
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kB) {
+        double r;
+        if (use_x) {
+            r = a.b[i] - row_dot(a, i, a.x);
+        } else {
+            r = a.b[i];
+            a.x[i] = 0.0;
+        }
+        a.r[i] = r;
+        a.rh[i] = r;
+        a.p[i] = 0.0;
+        a.v[i] = 0.0;
+        acc += r * r;
+    }
+    write_partials(a, SL_E, acc, acc);
+}
+
+// K1
+__global__ __launch_bounds__(kB) void k_bcg_p(BcgArgs a)
+{
+    BcgState *st = a.st;
+    if (st->done) return;
+    double e[2];
+    reduce_slot(a, SL_E, e);
+    const double rho = e[0], rr = e[1];
+    if (st->stop_next || rr <= st->tol2 * st->bb) {
+        if (lead()) st->done = 1;
+        return;
+    }
+    if (st->iters >= st->max_iter) {
+        if (lead()) st->done = 2;
+        return;
+    }
+    if (rho == 0.0 || !isfinite(rho)) {
+        if (lead()) st->done = -1;
+        return;
+    }
+    const double beta = (rho / st->rho_old) * (st->alpha / st->omega);
+    const double omega = st->omega;
+    block_apply(
+        a, [&](int32_t ii) { return a.r[ii] + beta * (a.p[ii] - omega * a.v[ii]); }, a.p, a.ph);
+}
+
+// K2
+__global__ __launch_bounds__(kB) void k_bcg_v(BcgArgs a)
+{
+    if (a.st->done) return;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kB) {
+        const double v = row_dot(a, i, a.ph);
+        a.v[i] = v;
+        acc += a.rh[i] * v;
+    }
+    write_partials(a, SL_B, acc, 0.0);
+}
+
+// K3
+__global__ __launch_bounds__(kB) void k_bcg_s(BcgArgs a)
+{
+    BcgState *st = a.st;
+    if (st->done) return;
+    double e[2], bsum[2];
+    reduce_slot(a, SL_E, e);
+    reduce_slot(a, SL_B, bsum);
+    const double rho = e[0], sig = bsum[0];
+    if (sig == 0.0 || !isfinite(sig)) {
+        if (lead()) st->done = -1;
+        return;
+    }
+    const double alpha = rho / sig;
+    const double w2 = block_apply(
+        a, [&](int32_t ii) { return a.r[ii] - alpha * a.v[ii]; }, a.s, a.sh);
+    write_partials(a, SL_C, w2, 0.0);
+    if (lead()) {
+        st->alpha = alpha;
+        st->rho_old = rho;
+        st->iters += 1;
+    }
+}
+
+// K4
+__global__ __launch_bounds__(kB) void k_bcg_t(BcgArgs a)
+{
+    BcgState *st = a.st;
+    if (st->done) return;
+    double c[2];
+    reduce_slot(a, SL_C, c);
+    if (c[0] <= st->tol2 * st->bb) return;  // stops at s: t is not needed
+    double ts = 0.0, tt = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kB) {
+        const double t = row_dot(a, i, a.sh);
+        a.t[i] = t;
+        ts += t * a.s[i];
+        tt += t * t;
+    }
+    write_partials(a, SL_D, ts, tt);
+}
+
+// K5
+__global__ __launch_bounds__(kB) void k_bcg_xr(BcgArgs a)
+{
+    BcgState *st = a.st;
+    if (st->done) return;
+    double c[2];
+    reduce_slot(a, SL_C, c);
+    const double alpha = st->alpha;
+    const bool half = c[0] <= st->tol2 * st->bb;
+    double omega = 0.0;
+    if (!half) {
+        double d[2];
+        reduce_slot(a, SL_D, d);
+        omega = d[0] / d[1];
+        if (omega == 0.0 || !isfinite(omega)) {
+            if (lead()) st->done = -1;
+            return;
+        }
+    }
+    double rhr = 0.0, rr = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kB) {
+        double r;
+        if (half) {
+            a.x[i] += alpha * a.ph[i];
+            r = a.s[i];
+        } else {
+            a.x[i] += alpha * a.ph[i] + omega * a.sh[i];
+            r = a.s[i] - omega * a.t[i];
+        }
+        a.r[i] = r;
+        rhr += a.rh[i] * r;
+        rr += r * r;
+    }
+    write_partials(a, SL_E, rhr, rr);
+    if (lead()) {
+        if (half) st->stop_next = 1;
+        else st->omega = omega;
+    }
+}
+
+// true residual ||b - A x||^2 into slot X
+__global__ __launch_bounds__(kB) void k_bcg_true(BcgArgs a)
+{
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kB) {
+        const double d = a.b[i] - row_dot(a, i, a.x);
+        acc += d * d;
+    }
+    write_partials(a, SL_X, acc, 0.0);
+}
+
+// public <-> internal order
+__global__ void k_bcg_gather(const double *__restrict__ B, const int32_t *__restrict__ iperm, int64_t n,
+                             double *__restrict__ b)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        b[iperm[i]] = B[i];
+}
+__global__ void k_bcg_scatter(const double *__restrict__ x, const int32_t *__restrict__ iperm, int64_t n,
+                              double *__restrict__ X)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        X[i] = x[iperm[i]];
+}
+
+#define BCHK(call)                                                                            \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) return fail(FEMCG_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// Inverse of each diagonal block of A (public order) by Gauss-Jordan
+// elimination with partial pivoting; returns false for a singular block.
+bool block_inverses(const HostSystem &hs, int bs, std::vector<double> &inv)
+{
+    const int64_t n = hs.nfree, nb = (n + bs - 1) / bs;
+    inv.assign((size_t)nb * bs * bs, 0.0);
+    std::atomic<int> nbad{0};
+    parallel_for(nb, [&](int64_t b0, int64_t b1) {
+        std::vector<double> M((size_t)bs * 2 * bs);
+        for (int64_t b = b0; b < b1; ++b) {
+            const int64_t r0 = b * bs;
+            const int m = (int)std::min<int64_t>(bs, n - r0);
+            std::fill(M.begin(), M.end(), 0.0);
+            for (int i = 0; i < m; ++i) {
+                for (int64_t e = hs.a_rowptr[r0 + i]; e < hs.a_rowptr[r0 + i + 1]; ++e) {
+                    const int64_t c = hs.a_col[e];
+                    if (c >= r0 && c < r0 + m) M[(size_t)i * 2 * bs + (c - r0)] += hs.a_val[e];
+                }
+                M[(size_t)i * 2 * bs + bs + i] = 1.0;
+            }
+            bool ok = true;
+            for (int c = 0; c < m && ok; ++c) {
+                int piv = c;
+                for (int r = c + 1; r < m; ++r)
+                    if (std::fabs(M[(size_t)r * 2 * bs + c]) > std::fabs(M[(size_t)piv * 2 * bs + c])) piv = r;
+                if (M[(size_t)piv * 2 * bs + c] == 0.0) {
+                    ok = false;
+                    break;
+                }
+                if (piv != c)
+                    for (int j = 0; j < 2 * bs; ++j) std::swap(M[(size_t)c * 2 * bs + j], M[(size_t)piv * 2 * bs + j]);
+                const double d = M[(size_t)c * 2 * bs + c];
+                for (int j = 0; j < 2 * bs; ++j) M[(size_t)c * 2 * bs + j] /= d;
+                for (int r = 0; r < m; ++r)
+                    if (r != c) {
+                        const double f = M[(size_t)r * 2 * bs + c];
+                        if (f != 0.0)
+                            for (int j = 0; j < 2 * bs; ++j) M[(size_t)r * 2 * bs + j] -= f * M[(size_t)c * 2 * bs + j];
+                    }
+            }
+            if (!ok) {
+                nbad.fetch_add(1);
+                continue;
+            }
+            for (int i = 0; i < m; ++i)
+                for (int j = 0; j < m; ++j) inv[((size_t)b * bs + i) * bs + j] = M[(size_t)i * 2 * bs + bs + j];
+        }
+    });
+    return nbad.load() == 0;
+}
+
+int bcg_prepare(fem_matrix *A, int bs)
+{
+    if (A->bcg && A->bcg->bs == bs) return FEMCG_OK;
+    const double t0 = now_s();
+    A->bcg.reset();
+    auto W = std::make_unique<BcgWork>();
+    const int64_t n = A->sc.n;
+    W->bs = bs;
+    W->n = n;
+    W->nb = (n + bs - 1) / bs;
+    W->grid = (int)std::max<int64_t>(1, std::min<int64_t>(kGridMax, (n + kB - 1) / kB));
+    std::vector<double> inv;
+    if (!block_inverses(A->hs, bs, inv)) return fail(FEMCG_EBREAKDOWN, "singular diagonal block (block size %d)", bs);
+    std::vector<int32_t> iperm(n);
+    for (int64_t i = 0; i < n; ++i) iperm[A->sc.perm[i]] = (int32_t)i;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t vb = al(sizeof(double) * std::max<int64_t>(n, 1));
+    const size_t ib = al(sizeof(double) * inv.size()), pb = al(sizeof(int32_t) * std::max<int64_t>(n, 1));
+    const size_t partb = al(sizeof(double) * kSlots * W->grid * 2), stb = al(sizeof(BcgState));
+    W->bytes = ib + pb + 10 * vb + partb + stb;
+    if (hipMalloc((void **)&W->mem, W->bytes) != hipSuccess) {
+        W->mem = nullptr;
+        return fail(FEMCG_ENOMEM, "BiCGStab workspace (%zu bytes)", W->bytes);
+    }
+    char *q = W->mem;
+    W->binv = (double *)q;
+    q += ib;
+    W->iperm = (int32_t *)q;
+    q += pb;
+    double **vecs[10] = {&W->b, &W->x, &W->r, &W->rh, &W->p, &W->ph, &W->v, &W->s, &W->sh, &W->t};
+    for (auto v : vecs) {
+        *v = (double *)q;
+        q += vb;
+    }
+    W->part = (double *)q;
+    q += partb;
+    W->st = q;
+    if (hipHostMalloc(&W->h_st, sizeof(BcgState), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&W->h_part, sizeof(double) * W->grid * 2, hipHostMallocDefault) != hipSuccess)
+        return fail(FEMCG_ENOMEM, "pinned host buffers");
+    BCHK(hipMemcpy(W->binv, inv.data(), sizeof(double) * inv.size(), hipMemcpyHostToDevice));
+    BCHK(hipMemcpy(W->iperm, iperm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
+    W->setup_s = now_s() - t0;
+    A->bcg = std::move(W);
+    return FEMCG_OK;
+}
+
+BcgArgs bcg_args(const fem_matrix *A)
+{
+    const BcgWork *W = A->bcg.get();
+    const DevSparse &d = A->dev;
+    BcgArgs a{};
+    a.n = W->n;
+    a.format = d.format;
+    int sh = 0;
+    while ((1 << sh) < d.C) ++sh;
+    a.sell_shift = sh;
+    a.rowptr = d.rowptr;
+    a.slice_ptr = d.slice_ptr;
+    a.rowlen = d.rowlen;
+    a.col = d.col;
+    a.val = (const double *)d.val64;
+    a.bs = W->bs;
+    a.binv = W->binv;
+    a.iperm = W->iperm;
+    a.b = W->b;
+    a.x = W->x;
+    a.r = W->r;
+    a.rh = W->rh;
+    a.p = W->p;
+    a.ph = W->ph;
+    a.v = W->v;
+    a.s = W->s;
+    a.sh = W->sh;
+    a.t = W->t;
+    a.part = W->part;
+    a.st = (BcgState *)W->st;
+    return a;
+}
+
+// sum of the first value of the grid's partials of slot X, in block order
+int read_slot_x(BcgWork *W, hipStream_t s, double *out)
+{
+    BCHK(hipMemcpyAsync(W->h_part, W->part + (size_t)SL_X * W->grid * 2, sizeof(double) * W->grid * 2,
+                        hipMemcpyDeviceToHost, s));
+    BCHK(hipStreamSynchronize(s));
+    double acc = 0.0;
+    for (int g = 0; g < W->grid; ++g) acc += W->h_part[2 * g];
+    *out = acc;
+    return FEMCG_OK;
+}
+
+}  // namespace
+
+BcgWork::~BcgWork()
+{
+    if (mem) (void)hipFree(mem);
+    if (h_st) (void)hipHostFree(h_st);
+    if (h_part) (void)hipHostFree(h_part);
+}
+
+}  // namespace femcg
+
+using namespace femcg;
+
+extern "C" {
+
+static int bicgstab_solve_impl(fem_matrix *A, const double *B, double *X, double tol, int32_t block_size,
+                               int64_t max_iter, void *stream, bicgstab_stats_t *stats)
+{
+    if (!A || !B || !X) return fail(FEMCG_EINVAL, "NULL argument");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(FEMCG_EINVAL, "tol must be positive and finite");
+    if (block_size < 1 || block_size > 64) return fail(FEMCG_EINVAL, "block_size must be 1..64");
+    if (max_iter < 0) return fail(FEMCG_EINVAL, "max_iter must be >= 0");
+    const double t_begin = now_s();
+    int rc = bcg_prepare(A, block_size);
+    if (rc) return rc;
+    BcgWork *W = A->bcg.get();
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = W->n;
+    const int G = W->grid;
+    const BcgArgs a = bcg_args(A);
+    const int ge = (int)std::min<int64_t>(4096, (n + 255) / 256 + 1);
+    hipLaunchKernelGGL(k_bcg_gather, dim3(ge), dim3(256), 0, s, B, W->iperm, n, W->b);
+    hipLaunchKernelGGL(k_bcg_bb, dim3(G), dim3(kB), 0, s, a);
+    BCHK(hipGetLastError());
+    double bb = 0.0;
+    if ((rc = read_slot_x(W, s, &bb))) return rc;
+    if (!std::isfinite(bb)) return fail(FEMCG_EBREAKDOWN, "non-finite right-hand side");
+    BcgState *hst = (BcgState *)W->h_st;
+    const int64_t cap = max_iter > 0 ? max_iter : default_max_iter(n);
+    int64_t iters = 0;
+    int restarts = 0, status = FEMCG_OK;
+    double rel = 0.0;
+    if (bb == 0.0) {
+        BCHK(hipMemsetAsync(X, 0, sizeof(double) * n, s));
+        BCHK(hipStreamSynchronize(s));
+    } else {
+        const int m = 32;  // iterations enqueued between polls
+        int use_x = 0;
+        for (;;) {
+            BcgState init{};
+            init.rho_old = init.alpha = init.omega = 1.0;
+            init.bb = bb;
+            init.tol2 = tol * tol;
+            init.iters = iters;
+            init.max_iter = cap;
+            std::memcpy(hst, &init, sizeof(init));
+            BCHK(hipMemcpyAsync(W->st, hst, sizeof(BcgState), hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_bcg_init, dim3(G), dim3(kB), 0, s, a, use_x);
+            for (;;) {
+                for (int i = 0; i < m; ++i) {
+                    hipLaunchKernelGGL(k_bcg_p, dim3(G), dim3(kB), 0, s, a);
+                    hipLaunchKernelGGL(k_bcg_v, dim3(G), dim3(kB), 0, s, a);
+                    hipLaunchKernelGGL(k_bcg_s, dim3(G), dim3(kB), 0, s, a);
+                    hipLaunchKernelGGL(k_bcg_t, dim3(G), dim3(kB), 0, s, a);
+                    hipLaunchKernelGGL(k_bcg_xr, dim3(G), dim3(kB), 0, s, a);
+                }
+                BCHK(hipGetLastError());
+                BCHK(hipMemcpyAsync(hst, W->st, sizeof(BcgState), hipMemcpyDeviceToHost, s));
+                BCHK(hipStreamSynchronize(s));
+                if (hst->done) break;
+            }
+            iters = hst->iters;
+            if (hst->done < 0) {
+                status = fail(FEMCG_EBREAKDOWN, "BiCGStab breakdown after %lld iterations", (long long)iters);
+                break;
+            }
+            hipLaunchKernelGGL(k_bcg_true, dim3(G), dim3(kB), 0, s, a);
+            BCHK(hipGetLastError());
+            double rr = 0.0;
+            if ((rc = read_slot_x(W, s, &rr))) return rc;
+            rel = std::sqrt(rr / bb);
+            if (hst->done == 2) {
+                status = rel <= tol ? FEMCG_OK : FEMCG_WARN_MAXITER;
+                break;
+            }
+            if (rel <= tol || restarts >= 3) break;
+            ++restarts;
+            use_x = 1;
+        }
+        hipLaunchKernelGGL(k_bcg_scatter, dim3(ge), dim3(256), 0, s, W->x, W->iperm, n, X);
+        BCHK(hipGetLastError());
+        BCHK(hipStreamSynchronize(s));
+    }
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->iters = iters;
+        stats->relres = rel;
+        stats->restarts = restarts;
+        stats->block_size = block_size;
+        stats->nblocks = W->nb;
+        stats->setup_s = W->setup_s;
+        stats->solve_s = now_s() - t_begin;
+        // per iteration: two matrix passes, two block-inverse and row-map
+        // passes, and 23 vector passes (K1 5, K2 3, K3 4, K4 3, K5 8)
+        const double nnz = (double)A->sc.stored;
+        const double per = 2.0 * (nnz * 12.0 + 4.0 * (n + 1)) + 2.0 * (8.0 * n * block_size + 4.0 * n) + 23.0 * 8.0 * n;
+        stats->bytes = per * (double)iters;
+    }
+    return status;
+}
+
+int bicgstab_solve(fem_matrix *A, const double *B, double *X, double tol, int32_t block_size, int64_t max_iter,
+                   void *stream, bicgstab_stats_t *stats)
+{
+    try {
+        return bicgstab_solve_impl(A, B, X, tol, block_size, max_iter, stream, stats);
+    } catch (const std::bad_alloc &) {
+        return fail(FEMCG_ENOMEM, "bicgstab_solve: host allocation failed");
+    } catch (const std::exception &ex) {
+        return fail(FEMCG_EDEVICE, "bicgstab_solve: %s", ex.what());
+    }
+}
+
+}  // extern "C"

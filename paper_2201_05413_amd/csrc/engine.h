@@ -50,6 +50,25 @@ struct Work {
 
 struct Engine;
 
+// BiCGStab + Block-Jacobi workspace of a matrix (bicgstab.hip): the block
+// inverses for one block size, the public -> internal row map, the ten
+// solver vectors (internal order), per-block partial dots and the state.
+struct BcgWork {
+    int bs = 0, grid = 0;
+    int64_t n = 0, nb = 0;
+    char *mem = nullptr;
+    double *binv = nullptr;
+    int32_t *iperm = nullptr;
+    double *b = nullptr, *x = nullptr, *r = nullptr, *rh = nullptr, *p = nullptr, *ph = nullptr;
+    double *v = nullptr, *s = nullptr, *sh = nullptr, *t = nullptr, *part = nullptr;
+    void *st = nullptr;         // device state
+    void *h_st = nullptr;       // pinned host copy of the state
+    double *h_part = nullptr;   // pinned copy of one partial slot
+    size_t bytes = 0;
+    double setup_s = 0.0;
+    ~BcgWork();
+};
+
 }  // namespace femcg
 
 // The opaque handle of the C ABI.
@@ -68,6 +87,7 @@ struct fem_matrix {
     bool device_assembled = false;
     std::map<std::pair<int, int>, std::unique_ptr<femcg::Work>> works;
     std::map<std::pair<int, int>, std::unique_ptr<femcg::Engine>> engines;
+    std::unique_ptr<femcg::BcgWork> bcg;
     pcg_stats_t stats{};
     double setup_s = 0.0;
     int last_kp = 0, last_prec = 0;

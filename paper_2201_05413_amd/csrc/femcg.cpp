@@ -92,6 +92,7 @@ int upload_solver_copy(fem_matrix *A)
     free_dev(A);
     A->works.clear();
     A->engines.clear();
+    A->bcg.reset();
     const SolverCopy &sc = A->sc;
     DevSparse &d = A->dev;
     d.format = sc.format;
@@ -884,6 +885,7 @@ fem_matrix::~fem_matrix()
 {
     engines.clear();
     works.clear();
+    bcg.reset();
     free_dev(this);
     if (d_perm) (void)hipFree(d_perm);
     if (d_lrow) (void)hipFree(d_lrow);

@@ -36,7 +36,7 @@ PCG_FP64 = 0
 PCG_MIXED = 1
 
 EXPORTS = ["pcg_default_opts", "fem_assemble", "fem_dofs", "fem_csr", "fem_rhs", "fem_spmv", "pcg_solve",
-           "pcg_solve_batch", "pcg_stats", "fem_tune", "fem_set_format", "fem_set_tiling", "pcg_time_kernel", "pcg_time_spmm_cold",
+           "pcg_solve_batch", "pcg_stats", "fem_tune", "fem_set_format", "fem_set_tiling", "pcg_time_kernel", "pcg_time_spmm_cold", "bicgstab_solve",
            "fem_free",
            "fem_last_error", "serve_create", "serve_submit", "serve_step", "serve_poll", "serve_clock",
            "serve_destroy"]
@@ -76,6 +76,14 @@ class pcg_stats_t(C.Structure):
                     bytes=self.bytes, gbps=self.gbps, gflops=self.gflops, footprint_mb=self.footprint_mb)
 
 
+class bicgstab_stats_t(C.Structure):
+    _fields_ = [("iters", C.c_int64), ("relres", C.c_double), ("restarts", C.c_int32), ("block_size", C.c_int32),
+                ("nblocks", C.c_int64), ("setup_s", C.c_double), ("solve_s", C.c_double), ("bytes", C.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class fem_request_info(C.Structure):
     _fields_ = [("id", C.c_int64), ("status", C.c_int32), ("k", C.c_int32), ("n", C.c_int64),
                 ("iters_max", C.c_int64), ("t_submit", C.c_double), ("t_ready", C.c_double),
@@ -110,6 +118,7 @@ def lib():
         "fem_set_tiling": (C.c_int, [P, I32, I32]),
         "pcg_time_kernel": (C.c_int, [P, I32, I32, P, C.POINTER(D), C.POINTER(D)]),
         "pcg_time_spmm_cold": (C.c_int, [I32, P, I32, I32, I32, P, C.POINTER(D), C.POINTER(D)]),
+        "bicgstab_solve": (C.c_int, [P, P, P, D, I32, I64, P, C.POINTER(bicgstab_stats_t)]),
         "fem_free": (None, [P]),
         "fem_last_error": (C.c_char_p, []),
         "serve_create": (C.c_int, [D, I32, I32, I32, C.POINTER(P)]),
@@ -244,6 +253,17 @@ def pcg_solve(A, B, X, tol, opts=None, stream=None):
     o = opts if opts is not None else default_opts(tol=tol)
     o.tol = tol
     return _check(lib().pcg_solve(A.h, _dev_ptr(B), _dev_ptr(X), k, tol, C.byref(o), _stream(stream)))
+
+
+def bicgstab_solve(A, B, X, tol, block_size=1, max_iter=0, stream=None):
+    """BiCGStab + Block-Jacobi (exact blocks of block_size rows); B, X device
+    [n_free] or [n_free][1] FP64.  Returns (status, stats dict)."""
+    if B.numel() != A.n_free or X.numel() != A.n_free:
+        raise ValueError("B and X must hold n_free values (one right-hand side)")
+    st = bicgstab_stats_t()
+    rc = _check(lib().bicgstab_solve(A.h, _dev_ptr(B), _dev_ptr(X), tol, block_size, max_iter, _stream(stream),
+                                     C.byref(st)))
+    return rc, st.as_dict()
 
 
 def pcg_solve_batch(As, Bs, Xs, tols, opts=None, stream=None):
