@@ -1116,8 +1116,12 @@ int orc_bj_apply(int64_t n, const int64_t *rowptr, const int32_t *col, const dou
  * until ||r|| <= tol ||b|| (the Eq. (2) test on the recursive residual),
  * then the true residual ||b - A x|| / ||b||, restarting from x when it is
  * above tol (at most 3 times).  One iteration = one pass of the loop (two
- * products with A, one when it stops at s).  rho = 0, (rh, v) = 0, omega = 0
- * or a non-finite scalar is a breakdown. */
+ * products with A, one when it stops at s).  A Lanczos near-breakdown,
+ * |rho| <= 1e-14 ||rh|| ||r|| (rho = 0 included), restarts the iteration
+ * from x with rh = r (at most 100 times): with zero source the lifted b,
+ * hence rh, lives on the rows next to the boundary only, and rho then decays
+ * far faster than r.  (rh, v) = 0, omega = 0 or a non-finite scalar is a
+ * breakdown. */
 int orc_bicgstab_csr(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
                      const double *bvec, int bs, double tol, int64_t max_iter, double *xout,
                      int64_t *iters, double *relres, int32_t *restarts)
@@ -1135,7 +1139,7 @@ int orc_bicgstab_csr(int64_t n, const int64_t *rowptr, const int32_t *col, const
     if (!x || !r || !rh || !p || !ph || !v || !sv || !sh || !t) { status = ORC_ENOMEM; goto done; }
     double bnorm = sqrt(dot1(n, bvec, bvec));
     int64_t its = 0;
-    int rs = 0;
+    int rs = 0, soft = 0;
     double rel = 0.0;
     if (bnorm == 0.0) goto finish;
     for (;;) {
@@ -1146,10 +1150,13 @@ int orc_bicgstab_csr(int64_t n, const int64_t *rowptr, const int32_t *col, const
             p[i] = v[i] = 0.0;
         }
         double rho_old = 1.0, alpha = 1.0, omega = 1.0;
+        double rhrh = dot1(n, rh, rh);
         double rnorm = sqrt(dot1(n, r, r));
+        int lanczos = 0;
         while (rnorm > tol * bnorm && its < max_iter) {
             double rho = dot1(n, rh, r);
-            if (rho == 0.0 || !isfinite(rho)) { status = ORC_EBREAK; break; }
+            if (!isfinite(rho)) { status = ORC_EBREAK; break; }
+            if (!(fabs(rho) > 1e-14 * sqrt(rhrh) * rnorm)) { lanczos = 1; break; }
             double beta = (rho / rho_old) * (alpha / omega);
             for (int64_t i = 0; i < n; i++) p[i] = r[i] + beta * (p[i] - omega * v[i]);
             bj_apply(&F, p, ph);
@@ -1187,6 +1194,11 @@ int orc_bicgstab_csr(int64_t n, const int64_t *rowptr, const int32_t *col, const
             rr += d * d;
         }
         rel = sqrt(rr) / bnorm;
+        if (lanczos && status == 0) {
+            if (soft >= 100 || its >= max_iter) { status = ORC_EBREAK; break; }
+            soft++;
+            continue;
+        }
         if (status == ORC_EBREAK || rel <= tol || its >= max_iter || rs >= 3) break;
         rs++;
     }
@@ -1194,7 +1206,7 @@ int orc_bicgstab_csr(int64_t n, const int64_t *rowptr, const int32_t *col, const
 finish:
     *iters = its;
     *relres = rel;
-    if (restarts) *restarts = rs;
+    if (restarts) *restarts = rs + soft;
     for (int64_t i = 0; i < n; i++) xout[i] = x[i];
 done:
     free(x); free(r); free(rh); free(p); free(ph); free(v); free(sv); free(sh); free(t);

@@ -8,6 +8,8 @@
 * the solution equals a sparse direct solve (scipy) on the SPD FEM matrix
   and on the paper's nonsymmetric form B^-1 L (rows scaled by the lumped
   vertex areas), for several block sizes;
+* a Lanczos near-breakdown (lifted b lives next to the boundary) restarts
+  the iteration and it still reaches the direct solution;
 * b = 0 gives x = 0 in 0 iterations; a singular diagonal block is reported.
 """
 import numpy as np
@@ -90,6 +92,21 @@ def test_solution_equals_sparse_direct_solve(bs, form):
     assert st == 0 and rel <= 1e-12
     assert np.linalg.norm(A @ x - b) <= 1.0001e-12 * np.linalg.norm(b)
     assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
+
+
+def test_lanczos_near_breakdown_restarts_and_still_solves():
+    # lifted Dirichlet data: b (the first shadow residual) lives on the rows
+    # next to the boundary, and (rh, r) collapses long before r does
+    s = oracle.System(meshgen.mesh2d(60, 0.3, 1), 1)
+    coords, _, _ = s.dofs()
+    b = s.rhs((coords[:, 0] ** 2 - coords[:, 1] ** 2)[:, None])[:, 0]
+    assert np.count_nonzero(b) < 0.1 * len(b)
+    rp, col, val = s.A()
+    x, its, rel, rs, st = oracle.bicgstab_csr(rp, col, val, b, 4, 1e-10)
+    assert st == 0 and rs >= 1 and rel <= 1e-10
+    A = sp.csr_matrix((val, col, rp), shape=(s.nfree, s.nfree))
+    xs = sla.spsolve(A.tocsc(), b)
+    assert np.linalg.norm(x - xs) <= 1e-7 * np.linalg.norm(xs)
 
 
 def test_zero_rhs_and_singular_block():
