@@ -143,7 +143,8 @@ typedef struct {
     int64_t iters;         /* BiCGStab iterations (two products with A each; one
                               for the last if it stops at the half step) */
     double relres;         /* true FP64 ||b - A x|| / ||b|| (Eq. (2)) */
-    int32_t restarts;      /* restarts from x after the true residual missed tol */
+    int32_t restarts;      /* restarts from x: the true residual missed tol, or a
+                              Lanczos near-breakdown |(rh, r)| <= 1e-14 ||rh|| ||r|| */
     int32_t block_size;
     int64_t nblocks;
     double setup_s;        /* block inverses and upload (first call per block size) */
@@ -158,7 +159,9 @@ typedef struct {
  * right-hand side, FP64, zero initial guess.  Stops when the recursive
  * residual satisfies Eq. (2) (||r|| <= tol ||b||), also at the half step
  * (||s|| <= tol ||b||), then checks the true residual and restarts from x
- * when it misses tol (at most 3 times).
+ * when it misses tol (at most 3 times).  A Lanczos near-breakdown,
+ * |(rh, r)| <= 1e-14 ||rh|| ||r||, restarts it from x with rh = r (at most
+ * 100 times).
  * B, X: device [n_free] FP64, public order (B read, X written).  max_iter:
  * cap on iterations, 0 = 20 sqrt(n) log2(n) + 100.  The block inverses
  * (Gauss-Jordan with partial pivoting, on the host) are built at the first

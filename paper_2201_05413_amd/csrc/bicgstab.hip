@@ -14,6 +14,10 @@
 //   K5  omega = (t, s) / (t, t);  x += alpha ph + omega sh;  r = s - omega t
 //       (x += alpha ph and r = s when ||s|| <= tol ||b||: the solve then
 //       stops);  partials (rh, r), (r, r)
+// A Lanczos near-breakdown, |rho| <= 1e-14 ||rh|| ||r||, restarts the
+// iteration from x with rh = r (at most 100 times): with zero source the
+// lifted b, hence the first rh, lives on the rows next to the boundary only,
+// and rho can decay far faster than r there.
 // Every block of a kernel reduces the partials it needs in one fixed order,
 // so all blocks derive the same scalars; block 0 records alpha, rho and
 // omega in the state for the kernels that follow.  No kernel reads a partial
@@ -25,6 +29,8 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <exception>
 #include <memory>
@@ -43,8 +49,12 @@ enum { SL_B = 0, SL_C = 1, SL_D = 2, SL_E = 3, SL_X = 4, kSlots = 5 };
 
 struct BcgState {
     double rho_old, alpha, omega, bb, tol2;
+    double rr;      // ||r||^2 seen by the last K1
+    double rhrh;    // ||rh||^2 of this start
+    double bad;     // the scalar that broke down
     long long iters, max_iter;
-    int done;       // 0 running, 1 converged, 2 iteration cap, -1 breakdown
+    int done;       // 0 running, 1 converged, 2 iteration cap, 3 Lanczos restart,
+                    // -1 / -2 / -3 breakdown in rho / (rh, v) / omega
     int stop_next;  // K5 stopped at s: K1 ends the solve
 };
 
@@ -215,6 +225,7 @@ __global__ __launch_bounds__(kB) void k_bcg_p(BcgArgs a)
     double e[2];
     reduce_slot(a, SL_E, e);
     const double rho = e[0], rr = e[1];
+    if (lead()) st->rr = rr;
     if (st->stop_next || rr <= st->tol2 * st->bb) {
         if (lead()) st->done = 1;
         return;
@@ -223,8 +234,18 @@ __global__ __launch_bounds__(kB) void k_bcg_p(BcgArgs a)
         if (lead()) st->done = 2;
         return;
     }
-    if (rho == 0.0 || !isfinite(rho)) {
-        if (lead()) st->done = -1;
+    if (!isfinite(rho)) {
+        if (lead()) {
+            st->bad = rho;
+            st->done = -1;
+        }
+        return;
+    }
+    if (!(fabs(rho) > 1e-14 * sqrt(st->rhrh) * sqrt(rr))) {
+        if (lead()) {
+            st->bad = rho;
+            st->done = 3;
+        }
         return;
     }
     const double beta = (rho / st->rho_old) * (st->alpha / st->omega);
@@ -256,7 +277,10 @@ __global__ __launch_bounds__(kB) void k_bcg_s(BcgArgs a)
     reduce_slot(a, SL_B, bsum);
     const double rho = e[0], sig = bsum[0];
     if (sig == 0.0 || !isfinite(sig)) {
-        if (lead()) st->done = -1;
+        if (lead()) {
+            st->bad = sig;
+            st->done = -2;
+        }
         return;
     }
     const double alpha = rho / sig;
@@ -303,7 +327,10 @@ __global__ __launch_bounds__(kB) void k_bcg_xr(BcgArgs a)
         reduce_slot(a, SL_D, d);
         omega = d[0] / d[1];
         if (omega == 0.0 || !isfinite(omega)) {
-            if (lead()) st->done = -1;
+            if (lead()) {
+                st->bad = omega;
+                st->done = -3;
+            }
             return;
         }
     }
@@ -490,14 +517,14 @@ BcgArgs bcg_args(const fem_matrix *A)
     return a;
 }
 
-// sum of the first value of the grid's partials of slot X, in block order
-int read_slot_x(BcgWork *W, hipStream_t s, double *out)
+// sum of value `comp` of the grid's partials of a slot, in block order
+int read_slot(BcgWork *W, hipStream_t s, int slot, int comp, double *out)
 {
-    BCHK(hipMemcpyAsync(W->h_part, W->part + (size_t)SL_X * W->grid * 2, sizeof(double) * W->grid * 2,
+    BCHK(hipMemcpyAsync(W->h_part, W->part + (size_t)slot * W->grid * 2, sizeof(double) * W->grid * 2,
                         hipMemcpyDeviceToHost, s));
     BCHK(hipStreamSynchronize(s));
     double acc = 0.0;
-    for (int g = 0; g < W->grid; ++g) acc += W->h_part[2 * g];
+    for (int g = 0; g < W->grid; ++g) acc += W->h_part[2 * g + comp];
     *out = acc;
     return FEMCG_OK;
 }
@@ -537,12 +564,12 @@ static int bicgstab_solve_impl(fem_matrix *A, const double *B, double *X, double
     hipLaunchKernelGGL(k_bcg_bb, dim3(G), dim3(kB), 0, s, a);
     BCHK(hipGetLastError());
     double bb = 0.0;
-    if ((rc = read_slot_x(W, s, &bb))) return rc;
+    if ((rc = read_slot(W, s, SL_X, 0, &bb))) return rc;
     if (!std::isfinite(bb)) return fail(FEMCG_EBREAKDOWN, "non-finite right-hand side");
     BcgState *hst = (BcgState *)W->h_st;
     const int64_t cap = max_iter > 0 ? max_iter : default_max_iter(n);
     int64_t iters = 0;
-    int restarts = 0, status = FEMCG_OK;
+    int restarts = 0, soft = 0, status = FEMCG_OK;
     double rel = 0.0;
     if (bb == 0.0) {
         BCHK(hipMemsetAsync(X, 0, sizeof(double) * n, s));
@@ -551,15 +578,19 @@ static int bicgstab_solve_impl(fem_matrix *A, const double *B, double *X, double
         const int m = 32;  // iterations enqueued between polls
         int use_x = 0;
         for (;;) {
+            hipLaunchKernelGGL(k_bcg_init, dim3(G), dim3(kB), 0, s, a, use_x);
+            BCHK(hipGetLastError());
+            double rhrh = 0.0;
+            if ((rc = read_slot(W, s, SL_E, 1, &rhrh))) return rc;
             BcgState init{};
             init.rho_old = init.alpha = init.omega = 1.0;
             init.bb = bb;
             init.tol2 = tol * tol;
+            init.rhrh = rhrh;
             init.iters = iters;
             init.max_iter = cap;
             std::memcpy(hst, &init, sizeof(init));
             BCHK(hipMemcpyAsync(W->st, hst, sizeof(BcgState), hipMemcpyHostToDevice, s));
-            hipLaunchKernelGGL(k_bcg_init, dim3(G), dim3(kB), 0, s, a, use_x);
             for (;;) {
                 for (int i = 0; i < m; ++i) {
                     hipLaunchKernelGGL(k_bcg_p, dim3(G), dim3(kB), 0, s, a);
@@ -572,16 +603,34 @@ static int bicgstab_solve_impl(fem_matrix *A, const double *B, double *X, double
                 BCHK(hipMemcpyAsync(hst, W->st, sizeof(BcgState), hipMemcpyDeviceToHost, s));
                 BCHK(hipStreamSynchronize(s));
                 if (hst->done) break;
+                if (std::getenv("FEMCG_BCG_TRACE") && hst->iters % 512 < 32)
+                    fprintf(stderr, "bicgstab: %lld iterations, ||r|| / ||b|| = %.3e\n", (long long)hst->iters,
+                            std::sqrt(hst->rr / bb));
             }
             iters = hst->iters;
-            if (hst->done < 0) {
-                status = fail(FEMCG_EBREAKDOWN, "BiCGStab breakdown after %lld iterations", (long long)iters);
+            if (hst->done == 3) {  // Lanczos near-breakdown: restart from x
+                if (soft < 100 && iters < cap) {
+                    ++soft;
+                    use_x = 1;
+                    continue;
+                }
+                status = fail(FEMCG_EBREAKDOWN, "BiCGStab: %d Lanczos restarts without convergence (%lld iterations)",
+                              soft, (long long)iters);
                 break;
             }
+            if (hst->done < 0) {
+                static const char *what[] = {"rho = (rh, r)", "(rh, v)", "omega"};
+                status = fail(FEMCG_EBREAKDOWN, "BiCGStab breakdown after %lld iterations: %s = %g (||r|| / ||b|| = %g)",
+                              (long long)iters, what[std::min(2, -hst->done - 1)], hst->bad, std::sqrt(hst->rr / bb));
+                break;
+            }
+            if (std::getenv("FEMCG_BCG_TRACE"))
+                fprintf(stderr, "bicgstab: %lld iterations, ||r|| / ||b|| = %.3e\n", (long long)hst->iters,
+                        std::sqrt(hst->rr / bb));
             hipLaunchKernelGGL(k_bcg_true, dim3(G), dim3(kB), 0, s, a);
             BCHK(hipGetLastError());
             double rr = 0.0;
-            if ((rc = read_slot_x(W, s, &rr))) return rc;
+            if ((rc = read_slot(W, s, SL_X, 0, &rr))) return rc;
             rel = std::sqrt(rr / bb);
             if (hst->done == 2) {
                 status = rel <= tol ? FEMCG_OK : FEMCG_WARN_MAXITER;
@@ -599,7 +648,7 @@ static int bicgstab_solve_impl(fem_matrix *A, const double *B, double *X, double
         std::memset(stats, 0, sizeof(*stats));
         stats->iters = iters;
         stats->relres = rel;
-        stats->restarts = restarts;
+        stats->restarts = restarts + soft;
         stats->block_size = block_size;
         stats->nblocks = W->nb;
         stats->setup_s = W->setup_s;
