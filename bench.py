@@ -14,7 +14,8 @@ Default workload: 2D P1 on a 1024x1024 vertex grid jittered by 0.3h
 (1,044,484 unknowns), g = x^2 - y^2 + N(0, 0.01^2) noise, tol 1e-8.
 Other workloads: --workload c1|c3|c4 (single solves), c5 (serving stream),
 asm (host vs device assembly), deg (P1..P4 on one mesh, as in Table 7),
-bcg (the paper's BiCGStab + Block-Jacobi against Jacobi-PCG).
+bcg (the paper's BiCGStab + Block-Jacobi against Jacobi-PCG), rhs (the
+iterative side of Sect. 4.3's multiple right-hand-side model).
 """
 from __future__ import annotations
 
@@ -653,6 +654,87 @@ def run_bicgstab(args):
     print(json.dumps(line), flush=True)
 
 
+def run_rhs(args):
+    """The iterative side of the multiple right-hand-side model of Sect. 4.3,
+    T_IS(t) = T_IS_PC + t T_IS_SOLVE: Jacobi-PCG on C3's 128^3 Kuhn cube (the
+    paper's Cube 1 grid) and on the C2 system, t = 1, 2, 4, ..., 64 random
+    harmonic right-hand sides (seed 3 / 8), tol 1e-8, solved one at a time
+    (t solves of one column) and as one block of t interleaved columns.
+    T_IS_PC is the preconditioner set-up (Jacobi: D^-1, inside the solver
+    copy) plus the tuner; T_IS_SOLVE is the least-squares slope of T_IS(t)
+    in t.  With a direct solver's factorisation and per-column solve times,
+    t_0 = (T_DS_FACT - T_IS_PC) / (T_IS_SOLVE - T_DS_SOLVE)."""
+    import numpy as np
+    import torch
+
+    import meshgen
+    from paper_2201_05413_amd import femcg
+
+    torch.cuda.set_device(0)
+    ts_all = [1, 2, 4, 8, 16, 32, 64]
+    systems = [("c3_3d_p1_128", meshgen.mesh3d(128), 3, 3), ("c2_2d_p1_jit_1024", meshgen.c2().mesh, 2, 8)]
+    out = []
+    for name, mesh, dim, seed in systems:
+        t0 = time.perf_counter()
+        A = femcg.Matrix(mesh, 1, femcg.FEM_FORMAT_SELL)
+        t_asm = time.perf_counter() - t0
+        coords, _, _ = A.dofs()
+        G = meshgen.harmonic_eval(meshgen.random_coeffs(dim, max(ts_all), seed), coords)
+        n = A.n_free
+        rows = []
+
+        def solve(k, reps):
+            B = torch.empty((n, k), dtype=torch.float64, device="cuda")
+            femcg.fem_rhs(A, np.ascontiguousarray(G[:, :k]), B)
+            X = torch.zeros_like(B)
+            o = femcg.default_opts(tol=1e-8, check_every=args.check_every)
+            femcg.pcg_solve(A, B, X, 1e-8, o)  # warm-up (workspace, graph)
+            tt = []
+            for _ in range(reps):
+                X.zero_()
+                torch.cuda.synchronize()
+                ta = time.perf_counter()
+                rc = femcg.pcg_solve(A, B, X, 1e-8, o)
+                torch.cuda.synchronize()
+                tt.append(time.perf_counter() - ta)
+                if rc != 0:
+                    raise RuntimeError("%s k %d status %d" % (name, k, rc))
+            st = A.stats()
+            return percentile(tt, 50), int(max(st["iters"][:k]))
+
+        t0 = time.perf_counter()
+        femcg.fem_tune(A, 1, femcg.PCG_FP64)
+        t_tune1 = time.perf_counter() - t0
+        t1, it1 = solve(1, max(1, args.steps))
+        for t in ts_all:
+            t0 = time.perf_counter()
+            femcg.fem_tune(A, t, femcg.PCG_FP64)
+            t_tune = time.perf_counter() - t0
+            tb, itb = solve(t, max(1, args.steps))
+            rows.append(dict(t=t, block_ms=round(1e3 * tb, 3), block_ms_per_rhs=round(1e3 * tb / t, 3),
+                             block_iters_max=itb, one_at_a_time_ms=round(1e3 * t1 * t, 3), tune_s=round(t_tune, 3)))
+            log("%s t=%d: block %.2f ms (%.2f ms per rhs, %d its), one at a time %.2f ms"
+                % (name, t, 1e3 * tb, 1e3 * tb / t, itb, 1e3 * t1 * t))
+        tv = np.array([r["t"] for r in rows], dtype=float)
+        yv = np.array([r["block_ms"] for r in rows])
+        slope, icept = np.polyfit(tv, yv, 1)
+        out.append(dict(system=name, n=n, setup_s=round(A.stats()["setup_s"], 3), assembly_wall_s=round(t_asm, 3),
+                        tune_s_k1=round(t_tune1, 3), one_at_a_time_ms_per_rhs=round(1e3 * t1, 3), iters_k1=it1,
+                        T_IS_PC_s=round(A.stats()["setup_s"] + t_tune1, 3),
+                        T_IS_SOLVE_block_ms=round(float(slope), 3), block_fit_intercept_ms=round(float(icept), 3),
+                        rows=rows))
+        A.free()
+    line = {
+        "metric": "T_IS(t) = T_IS_PC + t T_IS_SOLVE (Sect. 4.3), Jacobi-PCG, blocks of t right-hand sides",
+        "value": out[0]["T_IS_SOLVE_block_ms"], "unit": "ms per right-hand side", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": None, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "multi_rhs", "recipe": " ".join((run_rhs.__doc__ or "").split())},
+        "systems": out,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def meshgen_doc(name):
     import meshgen
     f = {"c1": meshgen.c1, "c2": meshgen.c2, "c3": meshgen.c3, "c4": meshgen.c4}[name]
@@ -664,7 +746,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "asm", "deg", "bcg"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "asm", "deg", "bcg", "rhs"])
     ap.add_argument("--check-every", type=int, default=64)
     ap.add_argument("--format", default="auto", help="auto (tuner) | csr | sell:C:sigma")
     ap.add_argument("--order", default="natural", choices=["natural", "sfc"])
@@ -710,6 +792,8 @@ def main():
         run_degrees(args)
     elif args.workload == "bcg":
         run_bicgstab(args)
+    elif args.workload == "rhs":
+        run_rhs(args)
     else:
         run_single(args)
 
