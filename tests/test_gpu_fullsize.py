@@ -3,7 +3,7 @@ times (autotuned format, check_every 64, FP64 and mixed): the oracle's own
 Eq. (2) residual of every column (R), and the closed forms where the exact
 discrete solution is known (C3: nodal harmonic cubics on the structured
 Kuhn mesh; C4 column 0: the P2 interpolant of x^2 - y^2), within the bound a
-1e-8 residual allows."""
+1e-8 residual allows.  BiCGStab + Block-Jacobi runs on the full C2 system."""
 import numpy as np
 import pytest
 
@@ -56,3 +56,23 @@ def test_c4_full_size_and_column0_closed_form():
     g, f2d, out = _run(w)
     for X in out.values():
         assert oracle.x_err(g[f2d, 0], X[:, 0]) <= 1e-5
+
+
+@pytest.mark.parametrize("bs", [1, 4])
+def test_c2_full_size_bicgstab(bs):
+    # the paper's solver on the full C2 system; bs = 1 meets the Lanczos
+    # near-breakdown of the lifted right-hand side and restarts
+    w = meshgen.c2()
+    A = femcg.Matrix(w.mesh, w.order)
+    femcg.fem_tune(A, 1, femcg.PCG_FP64)
+    coords, _, _ = A.dofs()
+    g = w.dirichlet(coords)[:, :1].copy()
+    B = torch.empty((A.n_free, 1), dtype=torch.float64, device="cuda")
+    femcg.fem_rhs(A, g, B)
+    X = torch.zeros_like(B)
+    rc, st = femcg.bicgstab_solve(A, B, X, w.tol, bs)
+    torch.cuda.synchronize()
+    assert rc == 0, st
+    orc = oracle.System(w.mesh, w.order)
+    rel = orc.relres(orc.rhs(g), X.cpu().numpy())[0]
+    assert rel <= w.tol * 1.0001, (rel, st)
