@@ -20,16 +20,21 @@
  *    The library never frees caller memory.
  *  - Dense blocks B and X are row-major [n][k] with the k right-hand sides of
  *    a row contiguous ("interleaved"), in the public DOF order below.
- *  - Public DOF order: mesh vertices in mesh order, then (order k >= 2) k-1
- *    DOFs per mesh edge, edges in lexicographic order of their (min, max)
- *    vertex pair and the DOF t = 1..k-1 of an edge at ((k-t) x_min +
- *    t x_max) / k (P2: the midpoint, (x_min + x_max) / 2), then (order 3, 4)
- *    (k-1)(k-2)/2 DOFs per cell, cells in mesh order; inside a cell with
- *    vertices (v0, v1, v2) the lattice points (a0 x_v0 + a1 x_v1 + a2 x_v2) / k,
- *    a0 + a1 + a2 = k, all a > 0, in decreasing lexicographic order of
- *    (a0, a1, a2).  Solver vectors hold the free (non-Dirichlet) DOFs in
- *    increasing DOF index.
+ *  - Public DOF order: mesh vertices in mesh order, then (element order
+ *    p >= 2) p-1 DOFs per mesh edge, edges in lexicographic order of their
+ *    (min, max) vertex pair and the DOF t = 1..p-1 of an edge at
+ *    ((p-t) x_min + t x_max) / p (P2: the midpoint, (x_min + x_max) / 2),
+ *    then (p = 3, 4) (p-1)(p-2)/2 DOFs per cell, cells in mesh order; inside
+ *    a cell with vertices (v0, v1, v2) the lattice points
+ *    (a0 x_v0 + a1 x_v1 + a2 x_v2) / p, a0 + a1 + a2 = p, all a > 0, in
+ *    decreasing lexicographic order of (a0, a1, a2).  Solver vectors hold the
+ *    free (non-Dirichlet) DOFs in increasing DOF index.
  *    Internal row permutations of the sparse formats are never visible.
+ *  - A fem_matrix owns its workspaces: calls that use the same matrix must
+ *    not overlap (from several threads, or on several streams at once).
+ *    Different matrices are independent.  The serve_* calls of one server
+ *    must come from one thread at a time (its assembly worker runs beside
+ *    them on its own).
  *  - "stream" is a hipStream_t (NULL = the null stream).  Device work is
  *    enqueued on it; calls that must inspect device state synchronise it.
  */
