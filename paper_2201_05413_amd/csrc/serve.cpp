@@ -134,6 +134,9 @@ static int admit_request(fem_server *s, Request *r, int slot)
     Work *w;
     if ((rc = get_work(A, kp, s->prec, &w))) return rc;
     const HostSystem &hs = A->hs;
+    if ((int64_t)r->g.size() != hs.ndofs * r->k)
+        return fail(FEMCG_EINVAL, "request data holds %zu values, the system has %lld DOFs x %d columns", r->g.size(),
+                    (long long)hs.ndofs, r->k);
     // B = -K_ID g_D into R64 (public order), then gathered into B64
     std::vector<double> gd((size_t)std::max<int64_t>(hs.ndir, 1) * r->k, 0.0);
     for (int64_t i = 0; i < hs.ndir; ++i)
@@ -236,11 +239,11 @@ static int64_t serve_submit_impl(fem_server *s, const fem_mesh *mesh, int32_t or
     r->coords.assign(mesh->coords, mesh->coords + mesh->nverts * mesh->dim);
     r->cells.assign(mesh->cells, mesh->cells + mesh->ncells * nvl);
     r->bnd.assign(mesh->on_boundary, mesh->on_boundary + mesh->nverts);
-    // number of DOFs is known only after assembly; g covers vertices (+ edges)
-    // -- the caller passes n_all rows, which for P2 needs the edge count:
-    // count edges here the same way the assembler numbers them
+    // number of DOFs is known only after assembly; the caller passes n_all
+    // rows of g: vertices, p-1 per edge, (p-1)(p-2)/2 per cell (P3/P4), so
+    // count the edges here the same way the assembler numbers them
     int64_t n_all = mesh->nverts;
-    if (order == 2) {
+    if (order >= 2) {
         int E[6][2], c = 0;
         for (int a = 0; a < nvl; ++a)
             for (int b = a + 1; b < nvl; ++b) E[c][0] = a, E[c][1] = b, ++c;
@@ -253,7 +256,8 @@ static int64_t serve_submit_impl(fem_server *s, const fem_mesh *mesh, int32_t or
                 keys.push_back((a << 32) | b);
             }
         std::sort(keys.begin(), keys.end());
-        n_all += (int64_t)(std::unique(keys.begin(), keys.end()) - keys.begin());
+        const int64_t nedges = (int64_t)(std::unique(keys.begin(), keys.end()) - keys.begin());
+        n_all += (int64_t)(order - 1) * nedges + (int64_t)(order - 1) * (order - 2) / 2 * mesh->ncells;
     }
     r->g.assign(g_all, g_all + n_all * k);
     r->mesh.dim = mesh->dim;

@@ -15,8 +15,10 @@ pytestmark = pytest.mark.gpu
 from paper_2201_05413_amd import femcg  # noqa: E402
 
 # (dim, m, jitter, order, k): single-workgroup, tile-mode P2 3D (assembled on
-# the device), tile-mode P1, P2 2D with two columns
-REQS = [(2, 30, 0.3, 1, 3), (3, 14, 0.2, 2, 5), (2, 90, 0.3, 1, 1), (2, 50, 0.0, 2, 2)]
+# the device), tile-mode P1, P2 2D with two columns, P3 with two columns, and
+# P4 with one column (split-row SpMM beside the one-lane P1 in one kp class)
+REQS = [(2, 30, 0.3, 1, 3), (3, 14, 0.2, 2, 5), (2, 90, 0.3, 1, 1), (2, 50, 0.0, 2, 2), (2, 25, 0.3, 3, 2),
+        (2, 18, 0.25, 4, 1)]
 
 
 def _request(i, dim, m, jit, order, k):
@@ -65,7 +67,7 @@ def test_server_results_equal_solo_solves(prec):
         # the same system alone, assembled where the server assembles it
         # (on the device from 2^20 element entries on): bit-identical
         nvl = dim + 1
-        nl = nvl if order == 1 else nvl + nvl * (nvl - 1) // 2
+        nl = nvl if order == 1 else (nvl + nvl * (nvl - 1) // 2 if order == 2 else (order + 1) * (order + 2) // 2)
         big = mesh["cells"].shape[0] * nl * nl >= 1 << 20
         A = femcg.Matrix(mesh, order, femcg.FEM_FORMAT_SELL | (femcg.FEM_ASSEMBLE_DEVICE if big else 0))
         B = torch.empty((A.n_free, k), dtype=torch.float64, device="cuda")
