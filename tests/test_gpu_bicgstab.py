@@ -77,6 +77,14 @@ def test_bicgstab_independent_of_the_internal_row_order(fmt, order_flag, C, sigm
     assert abs(st["iters"] - its_o) <= 0.1 * its_o + 3
 
 
+@pytest.mark.parametrize("dim,order", [(2, 2), (3, 2)])
+def test_bicgstab_on_a_device_assembled_matrix(dim, order):
+    c = Sys(dim, 30 if dim == 2 else 9, 0.2, order, seed=9, fmt=femcg.FEM_FORMAT_SELL | femcg.FEM_ASSEMBLE_DEVICE)
+    rc, x, st = c.solve(1e-10, 16)
+    assert rc == 0
+    assert c.orc.relres(c.b[:, None], x[:, None])[0] <= 1e-10 * 1.0001
+
+
 def test_one_block_is_exact_after_one_iteration():
     c = Sys(2, 8, 0.2, 1, seed=6)  # 36 free DOFs: one block of 64
     assert c.A.n_free <= 64

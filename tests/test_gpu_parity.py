@@ -84,8 +84,10 @@ def test_assembly_matches_oracle(dim, m, jit, order, where):
 
 @pytest.mark.parametrize("fmt", [femcg.FEM_FORMAT_CSR, femcg.FEM_FORMAT_SELL])
 @pytest.mark.parametrize("k", [1, 3, 8, 32])
-def test_spmm_matches_oracle(fmt, k):
-    c = Case(2, 45, 0.3, 2, 1, seed=3, fmt=fmt)
+@pytest.mark.parametrize("order,m", [(2, 45), (4, 21)])
+def test_spmm_matches_oracle(fmt, k, order, m):
+    # P4 rows hold up to 81 entries: split rows at k = 1, vector lanes at k >= 8
+    c = Case(2, m, 0.3, order, 1, seed=3, fmt=fmt)
     rng = np.random.default_rng(k)
     X = rng.standard_normal((c.A.n_free, k))
     Y = torch.zeros((c.A.n_free, k), dtype=torch.float64, device="cuda")
