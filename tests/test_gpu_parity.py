@@ -243,6 +243,21 @@ def test_batch_mixing_one_lane_and_split_rows_bitwise(prec):
         assert np.array_equal(X.cpu().numpy(), Xa)
 
 
+@pytest.mark.parametrize("order,m", [(3, 23), (4, 17)])
+def test_split_rows_mixed_precision_after_tuning(order, m):
+    # the tuner's format (CSR or SELL, optional Morton order) with the FP32
+    # split-row SpMM inside the refinement loop
+    c = Case(2, m, 0.3, order, 1, seed=61, noise=0.01)
+    femcg.fem_tune(c.A, 1, femcg.PCG_MIXED)
+    Xs, _, _, _, st = c.orc.pcg(c.Bo, 1e-14)
+    assert st == 0
+    for prec in (femcg.PCG_MIXED, femcg.PCG_FP64):
+        rc, X, stats = c.solve(1e-12, precision=prec)
+        assert rc == 0, stats
+        assert c.orc.relres(c.Bo, X)[0] <= 1e-12 * 1.0001
+        assert oracle.x_err(Xs[:, 0], X[:, 0]) <= 1e-8
+
+
 def test_format_and_tuner_agree():
     c = Case(2, 33, 0.25, 2, 3, seed=31)
     rc, X1, _ = c.solve(1e-12)
