@@ -457,6 +457,36 @@ int assemble_host(const fem_mesh *mesh, int order, HostSystem &hs, std::string &
     return FEMCG_OK;
 }
 
+// Stable sort of v by cmp on up to 16 threads: chunks sorted in parallel,
+// then merged pairwise (stable merges), level by level; the result is the
+// unique stable order, the same as one std::stable_sort.
+template <typename Cmp>
+static void parallel_stable_sort(std::vector<int32_t> &v, Cmp cmp)
+{
+    const int64_t n = (int64_t)v.size();
+    unsigned hw = std::thread::hardware_concurrency();
+    int T = (int)std::min<unsigned>(hw ? hw : 1, 16);
+    if (n < (1 << 16) || T <= 1) {
+        std::stable_sort(v.begin(), v.end(), cmp);
+        return;
+    }
+    std::vector<int64_t> b(T + 1);
+    for (int t = 0; t <= T; ++t) b[t] = n * t / T;
+    auto run = [](int ntask, const std::function<void(int)> &fn) {
+        std::vector<std::thread> th;
+        for (int i = 0; i < ntask; ++i) th.emplace_back(fn, i);
+        for (auto &x : th) x.join();
+    };
+    run(T, [&](int t) { std::stable_sort(v.begin() + b[t], v.begin() + b[t + 1], cmp); });
+    for (int w = 1; w < T; w *= 2) {
+        const int npair = (T + 2 * w - 1) / (2 * w);
+        run(npair, [&](int p) {
+            const int lo = 2 * w * p, mid = std::min(T, lo + w), hi = std::min(T, lo + 2 * w);
+            if (mid < hi) std::inplace_merge(v.begin() + b[lo], v.begin() + b[mid], v.begin() + b[hi], cmp);
+        });
+    }
+}
+
 // Solver copy: drop |a| <= 4 eps max_row|a| (never the diagonal), permute rows
 // symmetrically so that rows sorted by length (within windows of sigma rows)
 // share SELL slices.
@@ -529,14 +559,17 @@ int build_solver_copy(const HostSystem &hs, int format, int C, int sigma, Solver
         parallel_for(n, [&](int64_t i0, int64_t i1) {
             for (int64_t i = i0; i < i1; ++i) key[i] = morton_key(&hs.dof_coords[hs.free2dof[i] * dim], dim, lo, inv, bits);
         });
-        std::stable_sort(sc.perm.begin(), sc.perm.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+        parallel_stable_sort(sc.perm, [&](int32_t a, int32_t b) { return key[a] < key[b]; });
     }
     if (format == FEM_FORMAT_SELL && sc.sigma > 1) {
-        for (int64_t w = 0; w < n; w += sc.sigma) {
-            const int64_t e = std::min(n, w + sc.sigma);
-            std::stable_sort(sc.perm.begin() + w, sc.perm.begin() + e,
-                             [&](int32_t a, int32_t b) { return len[a] > len[b]; });
-        }
+        const int64_t nw = (n + sc.sigma - 1) / sc.sigma;
+        parallel_for(nw, [&](int64_t w0, int64_t w1) {
+            for (int64_t wi = w0; wi < w1; ++wi) {
+                const int64_t w = wi * sc.sigma, e = std::min(n, w + sc.sigma);
+                std::stable_sort(sc.perm.begin() + w, sc.perm.begin() + e,
+                                 [&](int32_t a, int32_t b) { return len[a] > len[b]; });
+            }
+        });
     }
     std::vector<int32_t> iperm(n);
     for (int64_t i = 0; i < n; ++i) iperm[sc.perm[i]] = (int32_t)i;
@@ -549,7 +582,9 @@ int build_solver_copy(const HostSystem &hs, int format, int C, int sigma, Solver
         return FEMCG_EUNSUPPORTED;
     }
     sc.nnz = nnz;
-    sc.col.resize(nnz);
+    sc.col.clear();
+    sc.val.clear();
+    sc.col.resize(nnz);  // every entry is written by the row loop below
     sc.val.resize(nnz);
     parallel_for(n, [&](int64_t i0, int64_t i1) {
         std::vector<std::pair<int32_t, double>> row;
@@ -583,8 +618,10 @@ int build_solver_copy(const HostSystem &hs, int format, int C, int sigma, Solver
             sc.slice_ptr[s + 1] = sc.slice_ptr[s] + (int64_t)mx * C;
         }
         const int64_t stored = sc.slice_ptr[ns];
-        sc.sell_col.assign(stored, 0);
-        sc.sell_val.assign(stored, 0.0);
+        sc.sell_col.clear();
+        sc.sell_val.clear();
+        sc.sell_col.resize(stored);  // every entry, padding included, is written below
+        sc.sell_val.resize(stored);
         parallel_for(ns, [&](int64_t s0, int64_t s1) {
             for (int64_t s = s0; s < s1; ++s) {
                 const int64_t base = sc.slice_ptr[s];

@@ -5,12 +5,44 @@
 
 #include <cstdint>
 #include <functional>
+#include <memory>
+#include <new>
 #include <string>
+#include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "femcg.h"
 
 namespace femcg {
+
+// Allocator that leaves trivially constructible elements uninitialised, so
+// that a large array is first touched (and paged in) by the parallel loop
+// that fills every element, not by one thread zeroing it first.
+template <typename T>
+struct NoInitAlloc : std::allocator<T> {
+    template <typename U>
+    struct rebind {
+        using other = NoInitAlloc<U>;
+    };
+    NoInitAlloc() = default;
+    template <typename U>
+    NoInitAlloc(const NoInitAlloc<U> &) noexcept
+    {
+    }
+    template <typename U>
+    void construct(U *p) noexcept(std::is_nothrow_default_constructible<U>::value)
+    {
+        ::new ((void *)p) U;
+    }
+    template <typename U, typename... Args>
+    void construct(U *p, Args &&...args)
+    {
+        ::new ((void *)p) U(std::forward<Args>(args)...);
+    }
+};
+template <typename T>
+using BigVec = std::vector<T, NoInitAlloc<T>>;
 
 struct HostSystem {
     int dim = 0, order = 0, nloc = 0;
@@ -36,13 +68,13 @@ struct SolverCopy {
     std::vector<int32_t> perm;           // internal row -> free row
     std::vector<double> diag;            // free order
     std::vector<int32_t> rowptr;         // internal CSR
-    std::vector<int32_t> col;
-    std::vector<double> val;
+    BigVec<int32_t> col;
+    BigVec<double> val;
     std::vector<double> dinv;            // internal order
     std::vector<int64_t> slice_ptr;      // SELL
     std::vector<int32_t> rowlen;
-    std::vector<int32_t> sell_col;
-    std::vector<double> sell_val;
+    BigVec<int32_t> sell_col;
+    BigVec<double> sell_val;
 };
 
 void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &fn);

@@ -77,8 +77,8 @@ static void free_dev(fem_matrix *A)
     d = DevSparse{};
 }
 
-template <typename T>
-static int upload(T **dst, const std::vector<T> &src)
+template <typename T, typename Al>
+static int upload(T **dst, const std::vector<T, Al> &src)
 {
     *dst = nullptr;
     if (src.empty()) return FEMCG_OK;
@@ -102,7 +102,7 @@ int upload_solver_copy(fem_matrix *A)
     d.nnz = sc.nnz;
     d.stored = sc.stored;
     int rc;
-    const std::vector<double> &v64 = sc.format == FEM_FORMAT_SELL ? sc.sell_val : sc.val;
+    const BigVec<double> &v64 = sc.format == FEM_FORMAT_SELL ? sc.sell_val : sc.val;
     std::vector<float> v32(v64.size()), di32(sc.dinv.size());
     parallel_for((int64_t)v64.size(), [&](int64_t a, int64_t b) {
         for (int64_t i = a; i < b; ++i) v32[i] = (float)v64[i];
