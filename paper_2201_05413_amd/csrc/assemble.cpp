@@ -174,6 +174,36 @@ static bool pk_element_matrix(int k, const double *P, double *K)
     return true;
 }
 
+// Stable sort of v by cmp on up to 16 threads: chunks sorted in parallel,
+// then merged pairwise (stable merges), level by level; the result is the
+// unique stable order, the same as one std::stable_sort.
+template <typename V, typename Cmp>
+static void parallel_stable_sort(V &v, Cmp cmp)
+{
+    const int64_t n = (int64_t)v.size();
+    unsigned hw = std::thread::hardware_concurrency();
+    int T = (int)std::min<unsigned>(hw ? hw : 1, 16);
+    if (n < (1 << 16) || T <= 1) {
+        std::stable_sort(v.begin(), v.end(), cmp);
+        return;
+    }
+    std::vector<int64_t> b(T + 1);
+    for (int t = 0; t <= T; ++t) b[t] = n * t / T;
+    auto run = [](int ntask, const std::function<void(int)> &fn) {
+        std::vector<std::thread> th;
+        for (int i = 0; i < ntask; ++i) th.emplace_back(fn, i);
+        for (auto &x : th) x.join();
+    };
+    run(T, [&](int t) { std::stable_sort(v.begin() + b[t], v.begin() + b[t + 1], cmp); });
+    for (int w = 1; w < T; w *= 2) {
+        const int npair = (T + 2 * w - 1) / (2 * w);
+        run(npair, [&](int p) {
+            const int lo = 2 * w * p, mid = std::min(T, lo + w), hi = std::min(T, lo + 2 * w);
+            if (mid < hi) std::inplace_merge(v.begin() + b[lo], v.begin() + b[mid], v.begin() + b[hi], cmp);
+        });
+    }
+}
+
 struct Face {
     int32_t v[3];
     bool operator<(const Face &o) const
@@ -229,7 +259,7 @@ int assemble_host(const fem_mesh *mesh, int order, HostSystem &hs, std::string &
                 ekey[c * nel + e] = (a << 32) | b;
             }
         edges = ekey;
-        std::sort(edges.begin(), edges.end());
+        parallel_stable_sort(edges, std::less<uint64_t>());
         edges.erase(std::unique(edges.begin(), edges.end()), edges.end());
     }
     hs.nedges = (int64_t)edges.size();
@@ -298,7 +328,7 @@ int assemble_host(const fem_mesh *mesh, int order, HostSystem &hs, std::string &
         if (dim == 2) {
             // boundary facets are the edges of exactly one triangle
             std::vector<uint64_t> all = ekey;
-            std::sort(all.begin(), all.end());
+            parallel_stable_sort(all, std::less<uint64_t>());
             for (size_t i = 0; i < all.size();) {
                 size_t j = i;
                 while (j < all.size() && all[j] == all[i]) ++j;
@@ -319,7 +349,7 @@ int assemble_host(const fem_mesh *mesh, int order, HostSystem &hs, std::string &
                     std::sort(f.v, f.v + 3);
                     faces[c * 4 + o] = f;
                 }
-            std::sort(faces.begin(), faces.end());
+            parallel_stable_sort(faces, [](const Face &a, const Face &b) { return a < b; });
             for (size_t i = 0; i < faces.size();) {
                 size_t j = i;
                 while (j < faces.size() && faces[j] == faces[i]) ++j;
@@ -355,7 +385,7 @@ int assemble_host(const fem_mesh *mesh, int order, HostSystem &hs, std::string &
     hs.ndir = (int64_t)hs.dir2dof.size();
 
     // ---- element matrices (parallel over cells) ----
-    std::vector<double> Ke((size_t)nc * nl * nl);
+    BigVec<double> Ke((size_t)nc * nl * nl);  // every entry written below (or the mesh is rejected)
     std::atomic<int64_t> bad{0};
     parallel_for(nc, [&](int64_t c0, int64_t c1) {
         double P[12];
@@ -412,10 +442,15 @@ int assemble_host(const fem_mesh *mesh, int order, HostSystem &hs, std::string &
     }
     hs.a_rowptr = a_cnt;
     hs.l_rowptr = l_cnt;
+    // every entry is written by pass 2
+    hs.a_col.clear();
+    hs.a_val.clear();
+    hs.l_col.clear();
+    hs.l_val.clear();
     hs.a_col.resize(a_cnt[nf]);
-    hs.a_val.assign(a_cnt[nf], 0.0);
+    hs.a_val.resize(a_cnt[nf]);
     hs.l_col.resize(l_cnt[nf]);
-    hs.l_val.assign(l_cnt[nf], 0.0);
+    hs.l_val.resize(l_cnt[nf]);
     // pass 2: columns and values
     parallel_for(nf, [&](int64_t f0, int64_t f1) {
         std::vector<int32_t> cols;
@@ -455,36 +490,6 @@ int assemble_host(const fem_mesh *mesh, int order, HostSystem &hs, std::string &
     hs.cell_dofs.clear();
     hs.cell_dofs.shrink_to_fit();
     return FEMCG_OK;
-}
-
-// Stable sort of v by cmp on up to 16 threads: chunks sorted in parallel,
-// then merged pairwise (stable merges), level by level; the result is the
-// unique stable order, the same as one std::stable_sort.
-template <typename Cmp>
-static void parallel_stable_sort(std::vector<int32_t> &v, Cmp cmp)
-{
-    const int64_t n = (int64_t)v.size();
-    unsigned hw = std::thread::hardware_concurrency();
-    int T = (int)std::min<unsigned>(hw ? hw : 1, 16);
-    if (n < (1 << 16) || T <= 1) {
-        std::stable_sort(v.begin(), v.end(), cmp);
-        return;
-    }
-    std::vector<int64_t> b(T + 1);
-    for (int t = 0; t <= T; ++t) b[t] = n * t / T;
-    auto run = [](int ntask, const std::function<void(int)> &fn) {
-        std::vector<std::thread> th;
-        for (int i = 0; i < ntask; ++i) th.emplace_back(fn, i);
-        for (auto &x : th) x.join();
-    };
-    run(T, [&](int t) { std::stable_sort(v.begin() + b[t], v.begin() + b[t + 1], cmp); });
-    for (int w = 1; w < T; w *= 2) {
-        const int npair = (T + 2 * w - 1) / (2 * w);
-        run(npair, [&](int p) {
-            const int lo = 2 * w * p, mid = std::min(T, lo + w), hi = std::min(T, lo + 2 * w);
-            if (mid < hi) std::inplace_merge(v.begin() + b[lo], v.begin() + b[mid], v.begin() + b[hi], cmp);
-        });
-    }
 }
 
 // Solver copy: drop |a| <= 4 eps max_row|a| (never the diagonal), permute rows

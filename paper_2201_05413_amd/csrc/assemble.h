@@ -53,12 +53,12 @@ struct HostSystem {
     std::vector<int32_t> cell_dofs;      // [ncells][nloc] (released after assembly)
     // A = K_II, structural pattern, columns ascending (free numbering)
     std::vector<int64_t> a_rowptr;
-    std::vector<int32_t> a_col;
-    std::vector<double> a_val;
+    BigVec<int32_t> a_col;
+    BigVec<double> a_val;
     // K_ID: free rows x Dirichlet columns (Dirichlet numbering)
     std::vector<int64_t> l_rowptr;
-    std::vector<int32_t> l_col;
-    std::vector<double> l_val;
+    BigVec<int32_t> l_col;
+    BigVec<double> l_val;
 };
 
 // Solver copy of A on the host, in internal (permuted) row order.
