@@ -137,8 +137,7 @@ void pcg_default_opts(pcg_opts *opts);
  * (in the same element order) run on the current device, on the null
  * stream, with temporary device memory of about 32 bytes per element entry
  * (cells * nloc^2); meshes beyond its index ranges (3D P2 with 2^21 or more
- * vertices, 2^31 or more element entries) and P3 / P4 meshes are assembled
- * on the host.
+ * vertices, 2^31 or more element entries) are assembled on the host.
  * Errors: FEMCG_EINVAL, FEMCG_EMESH (non-positive element), FEMCG_ENOMEM,
  * FEMCG_EUNSUPPORTED, FEMCG_EDEVICE. */
 int fem_assemble(const fem_mesh *mesh, int32_t order, int32_t format, fem_matrix **out);

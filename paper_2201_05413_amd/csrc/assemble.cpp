@@ -157,6 +157,14 @@ static const PkTable &pk_table(int k)
     return tab[k];
 }
 
+// The table M^{mn}_{ij} of degree k, [3][3][nl][nl] (for the device assembly).
+const std::vector<double> &pk_moment_table(int k, int *nl)
+{
+    const PkTable &T = pk_table(k);
+    *nl = T.nl;
+    return T.M;
+}
+
 // K (nl x nl, local order of pk_local_index) of a degree-k triangle P[3][2].
 static bool pk_element_matrix(int k, const double *P, double *K)
 {

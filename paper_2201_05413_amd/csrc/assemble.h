@@ -85,6 +85,11 @@ int assemble_host(const fem_mesh *mesh, int order, HostSystem &hs, std::string &
 // FEMCG_EUNSUPPORTED for meshes beyond its index ranges (callers then use
 // assemble_host).
 int assemble_device(const fem_mesh *mesh, int order, HostSystem &hs, std::string &err, hipStream_t s);
+// P3/P4 triangles: the geometry-free table M^{mn}_{ij} = (1/|T|) integral
+// (d phi_i / d l_m)(d phi_j / d l_n), [3][3][nl][nl], local DOFs: vertices,
+// then the p-1 points of edges (0,1), (0,2), (1,2) from their first vertex on,
+// then interior points in decreasing lexicographic order.
+const std::vector<double> &pk_moment_table(int k, int *nl);
 int build_solver_copy(const HostSystem &hs, int format, int C, int sigma, SolverCopy &sc,
                       std::string &err, int sfc = 0);
 

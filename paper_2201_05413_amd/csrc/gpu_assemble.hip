@@ -3,14 +3,17 @@
 //
 // The stiffness matrix is the element-by-element sum of Sect. 2.2's local
 // matrices (closed forms in element.h).  On the device:
-//   1. P2 edges: sort the (min, max) vertex-pair keys of every cell edge,
-//      unique -> the edge DOFs in (min, max) order; each cell's edge DOF by
-//      binary search.
-//   2. Dirichlet DOFs: boundary vertices as flagged; a P2 edge is Dirichlet if
-//      it lies on a boundary facet (a facet of exactly one cell: run-length
-//      encoding of the sorted facet keys) whose vertices are all flagged.
+//   1. Edges (P2-P4): sort the (min, max) vertex-pair keys of every cell
+//      edge, unique -> the edges in (min, max) order; each cell's edge DOFs by
+//      binary search (P3/P4: p-1 per edge, oriented from the smaller vertex,
+//      then the cell's interior DOFs).
+//   2. Dirichlet DOFs: boundary vertices as flagged; an edge's DOFs are
+//      Dirichlet if it lies on a boundary facet (a facet of exactly one cell:
+//      run-length encoding of the sorted facet keys) whose vertices are all
+//      flagged.
 //   3. Free / Dirichlet numbering: exclusive scans of the flags.
-//   4. Element matrices, one thread per cell.
+//   4. Element matrices, one thread per cell (P3/P4: from the host's
+//      geometry-free moment table, K = |T| sum_mn (g_m . g_n) M^mn).
 //   5. Every entry K_e[a][b] of a free row becomes the pair (row, col) -> value;
 //      a stable radix sort by (row, col) keeps equal keys in cell order, and
 //      each run is summed sequentially in that order (the summation order of
@@ -84,14 +87,30 @@ __device__ __forceinline__ int64_t lower_bound_u64(const uint64_t *__restrict__ 
 
 __global__ void k_cell_dofs(const int32_t *__restrict__ cells, const uint64_t *__restrict__ ekeys,
                             const uint64_t *__restrict__ edges, int64_t nedges, int64_t nc, int nvl, int nel,
-                            int nl, int64_t nv, int32_t *__restrict__ cdofs)
+                            int nl, int64_t nv, int order, int64_t ibase, int32_t *__restrict__ cdofs)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nc) return;
     for (int i = 0; i < nvl; ++i) cdofs[c * nl + i] = cells[c * nvl + i];
-    if (nl > nvl)
+    if (order == 2) {
         for (int e = 0; e < nel; ++e)
             cdofs[c * nl + nvl + e] = (int32_t)(nv + lower_bound_u64(edges, nedges, ekeys[c * nel + e]));
+    } else if (order >= 3) {
+        // triangles: edge e = (la, lb) holds its points s = 1..p-1 from la on;
+        // the global DOF t (1..p-1) counts from the edge's smaller vertex
+        const int ke = order - 1, ci = (order - 1) * (order - 2) / 2;
+        int E[6][2];
+        local_edges(2, E);
+        for (int e = 0; e < 3; ++e) {
+            const int64_t idx = lower_bound_u64(edges, nedges, ekeys[c * 3 + e]);
+            const int32_t va = cells[c * 3 + E[e][0]], vb = cells[c * 3 + E[e][1]];
+            for (int s = 1; s < order; ++s) {
+                const int t = va > vb ? order - s : s;
+                cdofs[c * nl + 3 + e * ke + (s - 1)] = (int32_t)(nv + ke * idx + t - 1);
+            }
+        }
+        for (int r = 0; r < ci; ++r) cdofs[c * nl + 3 + 3 * ke + r] = (int32_t)(ibase + ci * c + r);
+    }
 }
 
 __global__ void k_vertex_flags(const uint8_t *__restrict__ bnd, int64_t nv, uint8_t *__restrict__ dir)
@@ -100,15 +119,18 @@ __global__ void k_vertex_flags(const uint8_t *__restrict__ bnd, int64_t nv, uint
     if (v < nv) dir[v] = bnd[v] ? 1 : 0;
 }
 
-// 2D P2: an edge of exactly one triangle with both ends flagged
+// 2D P2-P4: an edge of exactly one triangle with both ends flagged (its ke DOFs)
 __global__ void k_dir_edges_2d(const uint64_t *__restrict__ ukeys, const int32_t *__restrict__ counts, int64_t nrun,
                                const uint8_t *__restrict__ bnd, const uint64_t *__restrict__ edges, int64_t nedges,
-                               int64_t nv, uint8_t *__restrict__ dir)
+                               int64_t nv, int ke, uint8_t *__restrict__ dir)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nrun || counts[i] != 1) return;
     const uint64_t k = ukeys[i];
-    if (bnd[k >> 32] && bnd[k & 0xffffffffu]) dir[nv + lower_bound_u64(edges, nedges, k)] = 1;
+    if (bnd[k >> 32] && bnd[k & 0xffffffffu]) {
+        const int64_t idx = lower_bound_u64(edges, nedges, k);
+        for (int t = 0; t < ke; ++t) dir[nv + ke * idx + t] = 1;
+    }
 }
 
 // 3D: face keys (sorted vertex triple, 21 bits each)
@@ -159,7 +181,8 @@ __global__ void k_flags_to_int(const uint8_t *__restrict__ dir, int64_t n, int32
 __global__ void k_elements(const double *__restrict__ coords, const int32_t *__restrict__ cells,
                            const int32_t *__restrict__ cdofs, const uint8_t *__restrict__ dir,
                            const int32_t *__restrict__ fscan, int64_t nc, int dim, int order, int nl,
-                           uint64_t *__restrict__ keys, double *__restrict__ vals, unsigned *__restrict__ nbad)
+                           const double *__restrict__ pkM, uint64_t *__restrict__ keys, double *__restrict__ vals,
+                           unsigned *__restrict__ nbad)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nc) return;
@@ -167,6 +190,36 @@ __global__ void k_elements(const double *__restrict__ coords, const int32_t *__r
     double P[12];
     for (int i = 0; i < nvl; ++i)
         for (int r = 0; r < dim; ++r) P[i * dim + r] = coords[(int64_t)cells[c * nvl + i] * dim + r];
+    if (order >= 3) {
+        // P3/P4 triangles: entry (a, b) = sum_mn |T| (g_m . g_n) M^mn_ab,
+        // summed over m, n in the host's order
+        double g[4][3] = {}, area;
+        if (!simplex_grads(2, P, g, &area)) {
+            atomicAdd(nbad, 1u);
+            for (int t = 0; t < nl * nl; ++t) {
+                keys[c * nl * nl + t] = ~0ull;
+                vals[c * nl * nl + t] = 0.0;
+            }
+            return;
+        }
+        double G[9];
+        for (int m = 0; m < 3; ++m)
+            for (int n = 0; n < 3; ++n) G[m * 3 + n] = area * (g[m][0] * g[n][0] + g[m][1] * g[n][1]);
+        const int64_t nl2 = (int64_t)nl * nl;
+        for (int a = 0; a < nl; ++a) {
+            const int32_t ra = cdofs[c * nl + a];
+            const bool free_row = dir[ra] == 0;
+            const uint64_t rk = (uint64_t)(uint32_t)fscan[ra] << 32;
+            for (int b = 0; b < nl; ++b) {
+                double v = 0.0;
+                for (int mn = 0; mn < 9; ++mn) v += G[mn] * pkM[mn * nl2 + a * nl + b];
+                const int64_t o = c * nl2 + a * nl + b;
+                keys[o] = free_row ? (rk | (uint32_t)cdofs[c * nl + b]) : ~0ull;
+                vals[o] = v;
+            }
+        }
+        return;
+    }
     double K[100];
     if (!element_matrix(dim, order, P, K)) {
         atomicAdd(nbad, 1u);
@@ -259,7 +312,7 @@ __global__ void k_split(const uint64_t *__restrict__ keys, const int64_t *__rest
 int assemble_device(const fem_mesh *mesh, int order, HostSystem &hs, std::string &err, hipStream_t s)
 {
     const int dim = mesh->dim;
-    if ((dim != 2 && dim != 3) || (order != 1 && order != 2)) {
+    if ((dim != 2 && dim != 3) || order < 1 || order > 4 || (order > 2 && dim != 2)) {
         err = "unsupported dimension or order";
         return FEMCG_EUNSUPPORTED;
     }
@@ -271,7 +324,8 @@ int assemble_device(const fem_mesh *mesh, int order, HostSystem &hs, std::string
     const int nvl = dim + 1;
     int E[6][2];
     const int nel = local_edges(dim, E);
-    const int nl = order == 1 ? nvl : nvl + nel;
+    const int nl = order == 1 ? nvl : (order == 2 ? nvl + nel : (order + 1) * (order + 2) / 2);
+    const int ke = order - 1, ci = (order - 1) * (order - 2) / 2;  // DOFs per edge, per cell interior
     // index ranges of the device path: 21-bit face keys (3D P2), 32-bit DOFs,
     // int item counts of the device-wide sorts and scans
     if ((dim == 3 && order == 2 && nv >= ((int64_t)1 << 21)) || nv >= ((int64_t)1 << 30) ||
@@ -317,8 +371,8 @@ int assemble_device(const fem_mesh *mesh, int order, HostSystem &hs, std::string
     // ---- 1. edges ----
     uint64_t *d_ekey = nullptr, *d_esort = nullptr, *d_edges = nullptr;
     int64_t nedges = 0;
-    const int64_t ne_all = order == 2 ? nc * nel : 0;
-    if (order == 2) {
+    const int64_t ne_all = order >= 2 ? nc * nel : 0;
+    if (order >= 2) {
         DCHK(buf.alloc(&d_ekey, ne_all));
         DCHK(buf.alloc(&d_esort, ne_all));
         DCHK(buf.alloc(&d_edges, ne_all));
@@ -334,7 +388,7 @@ int assemble_device(const fem_mesh *mesh, int order, HostSystem &hs, std::string
         DCHK(hipStreamSynchronize(s));
     }
     hs.nedges = nedges;
-    hs.ndofs = nv + nedges;
+    hs.ndofs = nv + ke * nedges + (int64_t)ci * nc;
     const int64_t nd = hs.ndofs;
     if (nd >= ((int64_t)1 << 31)) {
         err = "too many DOFs for int32 indices";
@@ -343,14 +397,14 @@ int assemble_device(const fem_mesh *mesh, int order, HostSystem &hs, std::string
     int32_t *d_cdofs;
     DCHK(buf.alloc(&d_cdofs, (size_t)nc * nl));
     hipLaunchKernelGGL(k_cell_dofs, dim3(blocks_for(nc)), dim3(kTpb), 0, s, d_cells, d_ekey, d_edges, nedges, nc, nvl,
-                       nel, nl, nv, d_cdofs);
+                       nel, nl, nv, order, (int64_t)(nv + ke * nedges), d_cdofs);
 
     // ---- 2. Dirichlet flags ----
     uint8_t *d_dir;
     DCHK(buf.alloc(&d_dir, (size_t)nd));
     DCHK(hipMemsetAsync(d_dir, 0, nd, s));
     hipLaunchKernelGGL(k_vertex_flags, dim3(blocks_for(nv)), dim3(kTpb), 0, s, d_bnd, nv, d_dir);
-    if (order == 2) {
+    if (order >= 2) {
         const int64_t nf_all = dim == 2 ? ne_all : nc * 4;
         uint64_t *d_fkey = d_esort;  // 2D: the sorted edge keys are the facet keys
         uint64_t *d_uk;
@@ -376,7 +430,7 @@ int assemble_device(const fem_mesh *mesh, int order, HostSystem &hs, std::string
         DCHK(hipStreamSynchronize(s));
         if (dim == 2)
             hipLaunchKernelGGL(k_dir_edges_2d, dim3(blocks_for(nrun)), dim3(kTpb), 0, s, d_uk, d_cnt, nrun, d_bnd,
-                               d_edges, nedges, nv, d_dir);
+                               d_edges, nedges, nv, ke, d_dir);
         else
             hipLaunchKernelGGL(k_dir_edges_3d, dim3(blocks_for(nrun)), dim3(kTpb), 0, s, d_uk, d_cnt, nrun, d_bnd,
                                d_edges, nedges, nv, d_dir);
@@ -433,8 +487,19 @@ int assemble_device(const fem_mesh *mesh, int order, HostSystem &hs, std::string
     DCHK(buf.alloc(&d_v1, nent));
     DCHK(buf.alloc(&d_bad, 1));
     DCHK(hipMemsetAsync(d_bad, 0, sizeof(unsigned), s));
+    double *d_pkM = nullptr;
+    if (order >= 3) {
+        int nlt = 0;
+        const std::vector<double> &M = pk_moment_table(order, &nlt);
+        if (nlt != nl || M.size() != (size_t)9 * nl * nl) {
+            err = "P3/P4 moment table size mismatch";
+            return FEMCG_EDEVICE;
+        }
+        DCHK(buf.alloc(&d_pkM, M.size()));
+        DCHK(hipMemcpyAsync(d_pkM, M.data(), sizeof(double) * M.size(), hipMemcpyHostToDevice, s));
+    }
     hipLaunchKernelGGL(k_elements, dim3(blocks_for(nc)), dim3(kTpb), 0, s, d_coords, d_cells, d_cdofs, d_dir, d_fscan,
-                       nc, dim, order, nl, d_k0, d_v0, d_bad);
+                       nc, dim, order, nl, (const double *)d_pkM, d_k0, d_v0, d_bad);
     unsigned nbad = 0;
     DCHK(hipMemcpyAsync(&nbad, d_bad, sizeof(unsigned), hipMemcpyDeviceToHost, s));
     DCHK(hipStreamSynchronize(s));
@@ -548,13 +613,44 @@ int assemble_device(const fem_mesh *mesh, int order, HostSystem &hs, std::string
     DCHK(hipStreamSynchronize(s));
     hs.a_rowptr[nf] = na;
     hs.l_rowptr[nf] = nlid;
-    // DOF coordinates: vertices, then edge midpoints
+    // DOF coordinates (the public convention, as the host assembly computes
+    // them): vertices; P2 edge midpoints; P3/P4 edge point t at
+    // ((p-t) x_a + t x_b) / p, then the cell interiors
     hs.dof_coords.resize((size_t)nd * dim);
     std::memcpy(hs.dof_coords.data(), mesh->coords, sizeof(double) * nv * dim);
     for (int64_t e = 0; e < nedges; ++e) {
         const int64_t a = (int64_t)(edges[e] >> 32), b = (int64_t)(edges[e] & 0xffffffffu);
-        for (int r = 0; r < dim; ++r)
-            hs.dof_coords[(nv + e) * dim + r] = 0.5 * (mesh->coords[a * dim + r] + mesh->coords[b * dim + r]);
+        for (int r = 0; r < dim; ++r) {
+            const double xa = mesh->coords[a * dim + r], xb = mesh->coords[b * dim + r];
+            if (order == 2)
+                hs.dof_coords[(nv + e) * dim + r] = 0.5 * (xa + xb);
+            else
+                for (int t = 1; t <= ke; ++t)
+                    hs.dof_coords[(nv + ke * e + t - 1) * dim + r] = ((double)(order - t) * xa + (double)t * xb) / order;
+        }
+    }
+    if (order >= 3) {
+        int ia[3][3], ni = 0;  // interior barycentric indices, decreasing lexicographic order
+        for (int a0 = order - 2; a0 >= 1; --a0)
+            for (int a1 = order - 1 - a0; a1 >= 1; --a1) {
+                ia[ni][0] = a0;
+                ia[ni][1] = a1;
+                ia[ni][2] = order - a0 - a1;
+                ++ni;
+            }
+        const int64_t ibase = nv + ke * nedges;
+        parallel_for(nc, [&](int64_t c0, int64_t c1) {
+            for (int64_t c = c0; c < c1; ++c) {
+                const int32_t *cv = mesh->cells + c * 3;
+                for (int r = 0; r < ci; ++r) {
+                    const int64_t d = ibase + (int64_t)ci * c + r;
+                    for (int q = 0; q < dim; ++q)
+                        hs.dof_coords[d * dim + q] = ((double)ia[r][0] * mesh->coords[(int64_t)cv[0] * dim + q] +
+                                                      (double)ia[r][1] * mesh->coords[(int64_t)cv[1] * dim + q] +
+                                                      (double)ia[r][2] * mesh->coords[(int64_t)cv[2] * dim + q]) / order;
+                }
+            }
+        });
     }
     hs.cell_dofs.clear();
     return FEMCG_OK;

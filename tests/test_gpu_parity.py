@@ -2,7 +2,7 @@
 
 Bars (see the oracle's pins for what fixes the oracle itself):
 * assembly: identical structural pattern, max_row |dA| / max_row |A| <= 1e-12
-  (P1..P4; the device assembly covers P1/P2 and hands P3/P4 to the host);
+  (P1..P4, host and device assembly);
   B = -K_ID g_D within 1e-12 norm-wise per column; DOF coordinates bit-equal;
 * SpMM: |y - y_oracle| <= 1e-13 (|A| |x|) row-wise (FP64; the solver copy
   drops entries below 4 eps64 max_row|a|);
