@@ -66,6 +66,10 @@ extern "C" {
 #define FEM_ORDER_SFC 0x10       /* flag for fem_set_format: internal rows in Morton
                                     (Z-curve) order of the DOF coordinates */
 #define FEM_ASSEMBLE_DEVICE 0x100 /* flag for fem_assemble: assemble on the device */
+#define FEM_ASSEMBLE_HOST_ONLY 0x200 /* flag for fem_assemble: host system and solver copy
+                                        only, no device memory (fem_dofs / fem_csr / fem_free
+                                        work without a GPU; calls that need the device
+                                        return FEMCG_EINVAL) */
 
 /* Arithmetic of the Krylov iteration. */
 #define PCG_FP64 0               /* FP64 values, vectors and dots */
@@ -138,6 +142,10 @@ void pcg_default_opts(pcg_opts *opts);
  * stream, with temporary device memory of about 32 bytes per element entry
  * (cells * nloc^2); meshes beyond its index ranges (3D P2 with 2^21 or more
  * vertices, 2^31 or more element entries) are assembled on the host.
+ * With FEM_ASSEMBLE_HOST_ONLY (excludes FEM_ASSEMBLE_DEVICE) nothing is
+ * uploaded and no HIP call is made: fem_dofs, fem_csr, pcg_stats and fem_free
+ * work without a GPU, and every call that needs the device copy returns
+ * FEMCG_EINVAL.
  * Errors: FEMCG_EINVAL, FEMCG_EMESH (non-positive element), FEMCG_ENOMEM,
  * FEMCG_EUNSUPPORTED, FEMCG_EDEVICE. */
 int fem_assemble(const fem_mesh *mesh, int32_t order, int32_t format, fem_matrix **out);

@@ -548,6 +548,7 @@ static int bicgstab_solve_impl(fem_matrix *A, const double *B, double *X, double
                                int64_t max_iter, void *stream, bicgstab_stats_t *stats)
 {
     if (!A || !B || !X) return fail(FEMCG_EINVAL, "NULL argument");
+    if (int rc = require_device(A)) return rc;
     if (!(tol > 0.0) || !std::isfinite(tol)) return fail(FEMCG_EINVAL, "tol must be positive and finite");
     if (block_size < 1 || block_size > 64) return fail(FEMCG_EINVAL, "block_size must be 1..64");
     if (max_iter < 0) return fail(FEMCG_EINVAL, "max_iter must be >= 0");

@@ -85,6 +85,7 @@ struct fem_matrix {
     int band_tile_bytes = 0;  // 0 = automatic
     int max_grid = 2048;
     bool device_assembled = false;
+    bool host_only = false;   // FEM_ASSEMBLE_HOST_ONLY: no device copy
     std::map<std::pair<int, int>, std::unique_ptr<femcg::Work>> works;
     std::map<std::pair<int, int>, std::unique_ptr<femcg::Engine>> engines;
     std::unique_ptr<femcg::BcgWork> bcg;
@@ -173,5 +174,7 @@ int engine_create(int prec, int max_slots, int m, bool use_graph, std::unique_pt
 int engine_admit(Engine *e, int s);
 int engine_tick(Engine *e, int *rc_out);
 int64_t default_max_iter(int64_t n);
+// FEMCG_EINVAL (with the message) for a matrix assembled without a device copy
+int require_device(const fem_matrix *A);
 
 }  // namespace femcg

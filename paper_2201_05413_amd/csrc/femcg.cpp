@@ -200,6 +200,7 @@ static int grid_cap(const fem_matrix *A, const Work *w)
 
 int get_work(fem_matrix *A, int kp, int prec, Work **out)
 {
+    if (int rc = require_device(A)) return rc;
     auto key = std::make_pair(kp, prec);
     auto it = A->works.find(key);
     if (it != A->works.end()) {
@@ -860,6 +861,12 @@ int engine_tick(Engine *e, int *rc_out)
     return pending;
 }
 
+int require_device(const fem_matrix *A)
+{
+    if (A && A->host_only) return fail(FEMCG_EINVAL, "matrix assembled with FEM_ASSEMBLE_HOST_ONLY has no device copy");
+    return FEMCG_OK;
+}
+
 int64_t default_max_iter(int64_t n)
 {
     n = std::max<int64_t>(n, 2);
@@ -920,6 +927,8 @@ int fem_assemble(const fem_mesh *mesh, int32_t order, int32_t format, fem_matrix
     g_err.clear();
     if (!mesh || !out) return fail(FEMCG_EINVAL, "NULL mesh or out");
     *out = nullptr;
+    if ((format & FEM_ASSEMBLE_DEVICE) && (format & FEM_ASSEMBLE_HOST_ONLY))
+        return fail(FEMCG_EINVAL, "FEM_ASSEMBLE_DEVICE and FEM_ASSEMBLE_HOST_ONLY exclude each other");
     const double t0 = now_s();
     auto A = std::make_unique<fem_matrix>();
     std::string err;
@@ -944,8 +953,11 @@ int fem_assemble(const fem_mesh *mesh, int32_t order, int32_t format, fem_matrix
     } catch (const std::bad_alloc &) {
         return fail(FEMCG_ENOMEM, "host allocation failed during assembly");
     }
-    if ((rc = upload_solver_copy(A.get()))) return rc;
-    if ((rc = upload_lifting(A.get()))) return rc;
+    A->host_only = (format & FEM_ASSEMBLE_HOST_ONLY) != 0;
+    if (!A->host_only) {
+        if ((rc = upload_solver_copy(A.get()))) return rc;
+        if ((rc = upload_lifting(A.get()))) return rc;
+    }
     if (const char *ev = std::getenv("FEMCG_MAX_GRID"))  // tuning override
         A->max_grid = std::max(kNumXcd, (atoi(ev) / kNumXcd) * kNumXcd);
     A->setup_s = now_s() - t0;
@@ -988,6 +1000,7 @@ static int fem_csr_impl(const fem_matrix *A, int64_t *nnz, int64_t *rowptr, int3
 static int fem_rhs_impl(const fem_matrix *A, const double *g_all, int32_t k, double *B, void *stream)
 {
     if (!A || !g_all || !B) return fail(FEMCG_EINVAL, "NULL argument");
+    if (int rc = require_device(A)) return rc;
     if (k < 1 || k > kMaxK) return fail(FEMCG_EUNSUPPORTED, "k=%d outside 1..%d", k, kMaxK);
     const HostSystem &hs = A->hs;
     hipStream_t s = (hipStream_t)stream;
@@ -1007,6 +1020,7 @@ static int fem_rhs_impl(const fem_matrix *A, const double *g_all, int32_t k, dou
 static int fem_spmv_impl(fem_matrix *A, const double *X, double *Y, int32_t k, void *stream)
 {
     if (!A || !X || !Y) return fail(FEMCG_EINVAL, "NULL argument");
+    if (int rc = require_device(A)) return rc;
     if (k < 1 || k > kMaxK) return fail(FEMCG_EUNSUPPORTED, "k=%d outside 1..%d", k, kMaxK);
     hipStream_t s = (hipStream_t)stream;
     const int kp = pad_k(k);
@@ -1102,6 +1116,7 @@ static int pcg_solve_impl(fem_matrix *A, const double *B, double *X, int32_t k, 
 {
     g_err.clear();
     if (!A || !B || !X) return fail(FEMCG_EINVAL, "NULL argument");
+    if (int rc = require_device(A)) return rc;
     if (k < 1 || k > kMaxK) return fail(FEMCG_EUNSUPPORTED, "k=%d outside 1..%d", k, kMaxK);
     pcg_opts o;
     pcg_default_opts(&o);
@@ -1167,6 +1182,7 @@ static int pcg_solve_batch_impl(int32_t nsys, fem_matrix *const *A, const double
     const double t0 = now_s();
     for (int i = 0; i < nsys; ++i) {
         if (!A[i] || !B[i] || !X[i]) return fail(FEMCG_EINVAL, "NULL entry %d", i);
+        if (int rc = require_device(A[i])) return rc;
         if (k[i] < 1 || k[i] > kMaxK) return fail(FEMCG_EUNSUPPORTED, "k[%d]=%d", i, k[i]);
         for (int j = 0; j < i; ++j)
             if (A[j] == A[i] && pad_k(k[j]) == pad_k(k[i]))
@@ -1233,6 +1249,7 @@ static int pcg_stats_impl(const fem_matrix *A, pcg_stats_t *out)
 static int fem_set_format_impl(fem_matrix *A, int32_t format_flags, int32_t C, int32_t sigma)
 {
     if (!A) return fail(FEMCG_EINVAL, "NULL matrix");
+    if (int rc = require_device(A)) return rc;
     const int sfc = (format_flags & FEM_ORDER_SFC) ? 1 : 0;
     const int format = format_flags & ~FEM_ORDER_SFC;
     if (format != FEM_FORMAT_CSR && format != FEM_FORMAT_SELL) return fail(FEMCG_EUNSUPPORTED, "format %d", format);
@@ -1310,6 +1327,7 @@ static int time_launches(hipStream_t s, int reps, const std::function<void()> &f
 static int fem_tune_impl(fem_matrix *A, int32_t k, int32_t precision, int32_t *C_out, int32_t *sigma_out, void *stream)
 {
     if (!A || k < 1 || k > kMaxK) return fail(FEMCG_EINVAL, "bad arguments");
+    if (int rc = require_device(A)) return rc;
     if (precision != PCG_FP64 && precision != PCG_MIXED) return fail(FEMCG_EINVAL, "bad precision");
     hipStream_t s = (hipStream_t)stream;
     struct Cand {
@@ -1433,6 +1451,7 @@ static int pcg_time_spmm_cold_impl(int32_t nmat, fem_matrix *const *A, int32_t k
     if (precision != PCG_FP64 && precision != PCG_MIXED) return fail(FEMCG_EINVAL, "bad precision");
     for (int i = 0; i < nmat; ++i)
         if (!A[i]) return fail(FEMCG_EINVAL, "NULL matrix %d", i);
+        else if (int rc = require_device(A[i])) return rc;
     hipStream_t s = (hipStream_t)stream;
     std::vector<std::unique_ptr<SpmmProbe>> pr(nmat);
     int rc;

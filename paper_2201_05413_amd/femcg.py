@@ -32,6 +32,7 @@ FEM_FORMAT_SELL = 1
 FEM_FORMAT_AUTO = 2
 FEM_ORDER_SFC = 0x10
 FEM_ASSEMBLE_DEVICE = 0x100
+FEM_ASSEMBLE_HOST_ONLY = 0x200
 PCG_FP64 = 0
 PCG_MIXED = 1
 
