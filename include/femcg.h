@@ -174,17 +174,25 @@ typedef struct {
  * when it misses tol (at most 3 times).  A Lanczos near-breakdown,
  * |(rh, r)| <= 1e-14 ||rh|| ||r||, restarts it from x with rh = r (at most
  * 100 times).
+ * row_scale: NULL, or host [n_free] FP64 in the public order, every entry
+ * finite and > 0 (copied): the solver then runs on the row-scaled system
+ * D A x = D b with D = diag(row_scale), whose solution is the same.  With
+ * D = B^-1, B the lumped mass (for P1 the area or volume of the cells
+ * around each vertex), this is the paper's nonsymmetric A = B^-1 L
+ * (Sect. 2.2).  The blocks, the residuals, the Eq. (2) test and the
+ * reported relres are those of the scaled system; all ones gives the
+ * unscaled solve bit for bit.
  * B, X: device [n_free] FP64, public order (B read, X written).  max_iter:
  * cap on iterations, 0 = 20 sqrt(n) log2(n) + 100.  The block inverses
  * (Gauss-Jordan with partial pivoting, on the host) are built at the first
- * call with a given block size and kept with A until the format or the block
- * size changes.  Work is enqueued on `stream` and the call synchronises it.
+ * call with a given block size and row scale and kept with A until the
+ * format, the block size or the row scale changes.  Work is enqueued on `stream` and the call synchronises it.
  * stats may be NULL.
  * Returns 0, FEMCG_WARN_MAXITER, or FEMCG_EINVAL (arguments), FEMCG_EBREAKDOWN
  * (a singular block, rho = 0, (rh, v) = 0, omega = 0 or a non-finite
  * scalar), FEMCG_ENOMEM, FEMCG_EDEVICE. */
 int bicgstab_solve(fem_matrix *A, const double *B, double *X, double tol, int32_t block_size,
-                   int64_t max_iter, void *stream, bicgstab_stats_t *stats);
+                   const double *row_scale, int64_t max_iter, void *stream, bicgstab_stats_t *stats);
 
 /* Sizes and DOF data.  Any output pointer may be NULL.
  * dof_coords: host [n_all][dim]; dirichlet: host [n_all]; free2dof: host

@@ -24,6 +24,11 @@
 // slot it writes, and the state fields a kernel writes are read only by later
 // kernels (a block that sees another block's "done" in the same kernel would
 // have taken the same decision itself).
+//
+// An optional row scale D (positive, per row) turns the system into
+// D A x = D b, the form A = B^-1 L of Sect. 2.2 when D is the inverse lumped
+// mass: b is scaled where it is gathered, every product row is scaled as it
+// is produced, and the block inverses are those of the scaled rows.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -69,6 +74,7 @@ struct BcgArgs {
     int bs;
     const double *binv;     // [nb][bs][bs]
     const int32_t *iperm;   // public free row -> internal row
+    const double *dsc;      // row scale, internal order, or nullptr
     double *b, *x, *r, *rh, *p, *ph, *v, *s, *sh, *t;
     double *part;           // [kSlots][grid][2]
     BcgState *st;
@@ -98,6 +104,13 @@ __device__ __forceinline__ double row_dot(const BcgArgs &a, int64_t row, const d
         if (e < e1) acc0 += a.val[e] * x[a.col[e]];
     }
     return acc0 + acc1;
+}
+
+// row of the (possibly row-scaled) operator
+__device__ __forceinline__ double op_row(const BcgArgs &a, int64_t row, const double *__restrict__ x)
+{
+    const double y = row_dot(a, row, x);
+    return a.dsc ? a.dsc[row] * y : y;
 }
 
 // block sums of v[0..1] in a fixed tree, stored as this block's partials
@@ -203,7 +216,7 @@ __global__ __launch_bounds__(kB) void k_bcg_init(BcgArgs a, int use_x)
     for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kB) {
         double r;
         if (use_x) {
-            r = a.b[i] - row_dot(a, i, a.x);
+            r = a.b[i] - op_row(a, i, a.x);
         } else {
             r = a.b[i];
             a.x[i] = 0.0;
@@ -260,7 +273,7 @@ __global__ __launch_bounds__(kB) void k_bcg_v(BcgArgs a)
     if (a.st->done) return;
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kB) {
-        const double v = row_dot(a, i, a.ph);
+        const double v = op_row(a, i, a.ph);
         a.v[i] = v;
         acc += a.rh[i] * v;
     }
@@ -304,7 +317,7 @@ __global__ __launch_bounds__(kB) void k_bcg_t(BcgArgs a)
     if (c[0] <= st->tol2 * st->bb) return;  // stops at s: t is not needed
     double ts = 0.0, tt = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kB) {
-        const double t = row_dot(a, i, a.sh);
+        const double t = op_row(a, i, a.sh);
         a.t[i] = t;
         ts += t * a.s[i];
         tt += t * t;
@@ -360,18 +373,20 @@ __global__ __launch_bounds__(kB) void k_bcg_true(BcgArgs a)
 {
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kB) {
-        const double d = a.b[i] - row_dot(a, i, a.x);
+        const double d = a.b[i] - op_row(a, i, a.x);
         acc += d * d;
     }
     write_partials(a, SL_X, acc, 0.0);
 }
 
-// public <-> internal order
-__global__ void k_bcg_gather(const double *__restrict__ B, const int32_t *__restrict__ iperm, int64_t n,
-                             double *__restrict__ b)
+// public <-> internal order (the right-hand side scaled by the row scale)
+__global__ void k_bcg_gather(const double *__restrict__ B, const int32_t *__restrict__ iperm,
+                             const double *__restrict__ dsc, int64_t n, double *__restrict__ b)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        b[iperm[i]] = B[i];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t ii = iperm[i];
+        b[ii] = dsc ? dsc[ii] * B[i] : B[i];
+    }
 }
 __global__ void k_bcg_scatter(const double *__restrict__ x, const int32_t *__restrict__ iperm, int64_t n,
                               double *__restrict__ X)
@@ -386,9 +401,10 @@ __global__ void k_bcg_scatter(const double *__restrict__ x, const int32_t *__res
         if (e_ != hipSuccess) return fail(FEMCG_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
-// Inverse of each diagonal block of A (public order) by Gauss-Jordan
-// elimination with partial pivoting; returns false for a singular block.
-bool block_inverses(const HostSystem &hs, int bs, std::vector<double> &inv)
+// Inverse of each diagonal block of D A (public order; D = diag(scale), or
+// the identity when scale is empty) by Gauss-Jordan elimination with partial
+// pivoting; returns false for a singular block.
+bool block_inverses(const HostSystem &hs, int bs, const std::vector<double> &scale, std::vector<double> &inv)
 {
     const int64_t n = hs.nfree, nb = (n + bs - 1) / bs;
     inv.assign((size_t)nb * bs * bs, 0.0);
@@ -400,9 +416,10 @@ bool block_inverses(const HostSystem &hs, int bs, std::vector<double> &inv)
             const int m = (int)std::min<int64_t>(bs, n - r0);
             std::fill(M.begin(), M.end(), 0.0);
             for (int i = 0; i < m; ++i) {
+                const double di = scale.empty() ? 1.0 : scale[r0 + i];
                 for (int64_t e = hs.a_rowptr[r0 + i]; e < hs.a_rowptr[r0 + i + 1]; ++e) {
                     const int64_t c = hs.a_col[e];
-                    if (c >= r0 && c < r0 + m) M[(size_t)i * 2 * bs + (c - r0)] += hs.a_val[e];
+                    if (c >= r0 && c < r0 + m) M[(size_t)i * 2 * bs + (c - r0)] += di * hs.a_val[e];
                 }
                 M[(size_t)i * 2 * bs + bs + i] = 1.0;
             }
@@ -437,26 +454,33 @@ bool block_inverses(const HostSystem &hs, int bs, std::vector<double> &inv)
     return nbad.load() == 0;
 }
 
-int bcg_prepare(fem_matrix *A, int bs)
+int bcg_prepare(fem_matrix *A, int bs, const double *row_scale)
 {
-    if (A->bcg && A->bcg->bs == bs) return FEMCG_OK;
+    const int64_t n = A->sc.n;
+    if (A->bcg && A->bcg->bs == bs) {
+        const std::vector<double> &sc = A->bcg->scale;
+        const bool same = row_scale ? (!sc.empty() && std::memcmp(sc.data(), row_scale, sizeof(double) * n) == 0)
+                                    : sc.empty();
+        if (same) return FEMCG_OK;
+    }
     const double t0 = now_s();
     A->bcg.reset();
     auto W = std::make_unique<BcgWork>();
-    const int64_t n = A->sc.n;
+    if (row_scale) W->scale.assign(row_scale, row_scale + n);
     W->bs = bs;
     W->n = n;
     W->nb = (n + bs - 1) / bs;
     W->grid = (int)std::max<int64_t>(1, std::min<int64_t>(kGridMax, (n + kB - 1) / kB));
     std::vector<double> inv;
-    if (!block_inverses(A->hs, bs, inv)) return fail(FEMCG_EBREAKDOWN, "singular diagonal block (block size %d)", bs);
+    if (!block_inverses(A->hs, bs, W->scale, inv)) return fail(FEMCG_EBREAKDOWN, "singular diagonal block (block size %d)", bs);
     std::vector<int32_t> iperm(n);
     for (int64_t i = 0; i < n; ++i) iperm[A->sc.perm[i]] = (int32_t)i;
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t vb = al(sizeof(double) * std::max<int64_t>(n, 1));
     const size_t ib = al(sizeof(double) * inv.size()), pb = al(sizeof(int32_t) * std::max<int64_t>(n, 1));
     const size_t partb = al(sizeof(double) * kSlots * W->grid * 2), stb = al(sizeof(BcgState));
-    W->bytes = ib + pb + 10 * vb + partb + stb;
+    const size_t db = W->scale.empty() ? 0 : vb;
+    W->bytes = ib + pb + db + 10 * vb + partb + stb;
     if (hipMalloc((void **)&W->mem, W->bytes) != hipSuccess) {
         W->mem = nullptr;
         return fail(FEMCG_ENOMEM, "BiCGStab workspace (%zu bytes)", W->bytes);
@@ -466,6 +490,10 @@ int bcg_prepare(fem_matrix *A, int bs)
     q += ib;
     W->iperm = (int32_t *)q;
     q += pb;
+    if (db) {
+        W->dsc = (double *)q;
+        q += db;
+    }
     double **vecs[10] = {&W->b, &W->x, &W->r, &W->rh, &W->p, &W->ph, &W->v, &W->s, &W->sh, &W->t};
     for (auto v : vecs) {
         *v = (double *)q;
@@ -479,6 +507,11 @@ int bcg_prepare(fem_matrix *A, int bs)
         return fail(FEMCG_ENOMEM, "pinned host buffers");
     BCHK(hipMemcpy(W->binv, inv.data(), sizeof(double) * inv.size(), hipMemcpyHostToDevice));
     BCHK(hipMemcpy(W->iperm, iperm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
+    if (db) {
+        std::vector<double> dint(n);
+        for (int64_t i = 0; i < n; ++i) dint[iperm[i]] = W->scale[i];
+        BCHK(hipMemcpy(W->dsc, dint.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+    }
     W->setup_s = now_s() - t0;
     A->bcg = std::move(W);
     return FEMCG_OK;
@@ -502,6 +535,7 @@ BcgArgs bcg_args(const fem_matrix *A)
     a.bs = W->bs;
     a.binv = W->binv;
     a.iperm = W->iperm;
+    a.dsc = W->dsc;
     a.b = W->b;
     a.x = W->x;
     a.r = W->r;
@@ -545,15 +579,20 @@ using namespace femcg;
 extern "C" {
 
 static int bicgstab_solve_impl(fem_matrix *A, const double *B, double *X, double tol, int32_t block_size,
-                               int64_t max_iter, void *stream, bicgstab_stats_t *stats)
+                               const double *row_scale, int64_t max_iter, void *stream, bicgstab_stats_t *stats)
 {
     if (!A || !B || !X) return fail(FEMCG_EINVAL, "NULL argument");
     if (int rc = require_device(A)) return rc;
     if (!(tol > 0.0) || !std::isfinite(tol)) return fail(FEMCG_EINVAL, "tol must be positive and finite");
     if (block_size < 1 || block_size > 64) return fail(FEMCG_EINVAL, "block_size must be 1..64");
     if (max_iter < 0) return fail(FEMCG_EINVAL, "max_iter must be >= 0");
+    if (row_scale)
+        for (int64_t i = 0; i < A->sc.n; ++i)
+            if (!(row_scale[i] > 0.0) || !std::isfinite(row_scale[i]))
+                return fail(FEMCG_EINVAL, "row_scale[%lld] = %g: entries must be finite and > 0", (long long)i,
+                            row_scale[i]);
     const double t_begin = now_s();
-    int rc = bcg_prepare(A, block_size);
+    int rc = bcg_prepare(A, block_size, row_scale);
     if (rc) return rc;
     BcgWork *W = A->bcg.get();
     hipStream_t s = (hipStream_t)stream;
@@ -561,7 +600,7 @@ static int bicgstab_solve_impl(fem_matrix *A, const double *B, double *X, double
     const int G = W->grid;
     const BcgArgs a = bcg_args(A);
     const int ge = (int)std::min<int64_t>(4096, (n + 255) / 256 + 1);
-    hipLaunchKernelGGL(k_bcg_gather, dim3(ge), dim3(256), 0, s, B, W->iperm, n, W->b);
+    hipLaunchKernelGGL(k_bcg_gather, dim3(ge), dim3(256), 0, s, B, W->iperm, (const double *)W->dsc, n, W->b);
     hipLaunchKernelGGL(k_bcg_bb, dim3(G), dim3(kB), 0, s, a);
     BCHK(hipGetLastError());
     double bb = 0.0;
@@ -655,19 +694,21 @@ static int bicgstab_solve_impl(fem_matrix *A, const double *B, double *X, double
         stats->setup_s = W->setup_s;
         stats->solve_s = now_s() - t_begin;
         // per iteration: two matrix passes, two block-inverse and row-map
-        // passes, and 23 vector passes (K1 5, K2 3, K3 4, K4 3, K5 8)
+        // passes, and 23 vector passes (K1 5, K2 3, K3 4, K4 3, K5 8), plus
+        // the row scale read by each matrix pass
         const double nnz = (double)A->sc.stored;
-        const double per = 2.0 * (nnz * 12.0 + 4.0 * (n + 1)) + 2.0 * (8.0 * n * block_size + 4.0 * n) + 23.0 * 8.0 * n;
+        const double per = 2.0 * (nnz * 12.0 + 4.0 * (n + 1)) + 2.0 * (8.0 * n * block_size + 4.0 * n) +
+                           (23.0 + (W->dsc ? 2.0 : 0.0)) * 8.0 * n;
         stats->bytes = per * (double)iters;
     }
     return status;
 }
 
-int bicgstab_solve(fem_matrix *A, const double *B, double *X, double tol, int32_t block_size, int64_t max_iter,
-                   void *stream, bicgstab_stats_t *stats)
+int bicgstab_solve(fem_matrix *A, const double *B, double *X, double tol, int32_t block_size,
+                   const double *row_scale, int64_t max_iter, void *stream, bicgstab_stats_t *stats)
 {
     try {
-        return bicgstab_solve_impl(A, B, X, tol, block_size, max_iter, stream, stats);
+        return bicgstab_solve_impl(A, B, X, tol, block_size, row_scale, max_iter, stream, stats);
     } catch (const std::bad_alloc &) {
         return fail(FEMCG_ENOMEM, "bicgstab_solve: host allocation failed");
     } catch (const std::exception &ex) {

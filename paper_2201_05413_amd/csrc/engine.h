@@ -59,6 +59,8 @@ struct BcgWork {
     char *mem = nullptr;
     double *binv = nullptr;
     int32_t *iperm = nullptr;
+    double *dsc = nullptr;      // row scale, internal order (nullptr: none)
+    std::vector<double> scale;  // the caller's row scale, public order (empty: none)
     double *b = nullptr, *x = nullptr, *r = nullptr, *rh = nullptr, *p = nullptr, *ph = nullptr;
     double *v = nullptr, *s = nullptr, *sh = nullptr, *t = nullptr, *part = nullptr;
     void *st = nullptr;         // device state

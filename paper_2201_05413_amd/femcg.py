@@ -119,7 +119,7 @@ def lib():
         "fem_set_tiling": (C.c_int, [P, I32, I32]),
         "pcg_time_kernel": (C.c_int, [P, I32, I32, P, C.POINTER(D), C.POINTER(D)]),
         "pcg_time_spmm_cold": (C.c_int, [I32, P, I32, I32, I32, P, C.POINTER(D), C.POINTER(D)]),
-        "bicgstab_solve": (C.c_int, [P, P, P, D, I32, I64, P, C.POINTER(bicgstab_stats_t)]),
+        "bicgstab_solve": (C.c_int, [P, P, P, D, I32, P, I64, P, C.POINTER(bicgstab_stats_t)]),
         "fem_free": (None, [P]),
         "fem_last_error": (C.c_char_p, []),
         "serve_create": (C.c_int, [D, I32, I32, I32, C.POINTER(P)]),
@@ -256,14 +256,20 @@ def pcg_solve(A, B, X, tol, opts=None, stream=None):
     return _check(lib().pcg_solve(A.h, _dev_ptr(B), _dev_ptr(X), k, tol, C.byref(o), _stream(stream)))
 
 
-def bicgstab_solve(A, B, X, tol, block_size=1, max_iter=0, stream=None):
+def bicgstab_solve(A, B, X, tol, block_size=1, max_iter=0, stream=None, row_scale=None):
     """BiCGStab + Block-Jacobi (exact blocks of block_size rows); B, X device
-    [n_free] or [n_free][1] FP64.  Returns (status, stats dict)."""
+    [n_free] or [n_free][1] FP64; row_scale: None or host [n_free] positive
+    values D (solves D A x = D b).  Returns (status, stats dict)."""
     if B.numel() != A.n_free or X.numel() != A.n_free:
         raise ValueError("B and X must hold n_free values (one right-hand side)")
+    d = None
+    if row_scale is not None:
+        d = np.ascontiguousarray(row_scale, dtype=np.float64).reshape(-1)
+        if d.size != A.n_free:
+            raise ValueError("row_scale must hold n_free values")
     st = bicgstab_stats_t()
-    rc = _check(lib().bicgstab_solve(A.h, _dev_ptr(B), _dev_ptr(X), tol, block_size, max_iter, _stream(stream),
-                                     C.byref(st)))
+    rc = _check(lib().bicgstab_solve(A.h, _dev_ptr(B), _dev_ptr(X), tol, block_size,
+                                     None if d is None else _np_ptr(d), max_iter, _stream(stream), C.byref(st)))
     return rc, st.as_dict()
 
 

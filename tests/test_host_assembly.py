@@ -67,7 +67,7 @@ def test_device_calls_are_rejected_on_a_host_only_matrix():
              lambda: lib.pcg_solve(A.h, p, p, 1, 1e-8, None, None),
              lambda: lib.fem_set_format(A.h, femcg.FEM_FORMAT_CSR, 64, 1),
              lambda: lib.fem_tune(A.h, 1, femcg.PCG_FP64, None, None, None),
-             lambda: lib.bicgstab_solve(A.h, p, p, 1e-8, 4, 0, None, None)]
+             lambda: lib.bicgstab_solve(A.h, p, p, 1e-8, 4, None, 0, None, None)]
     for call in calls:
         assert call() == femcg.FEMCG_EINVAL
         assert b"FEM_ASSEMBLE_HOST_ONLY" in lib.fem_last_error()
