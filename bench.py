@@ -617,6 +617,9 @@ def run_bicgstab(args):
     for name, w in (("c2_2d_p1_jit_1024", meshgen.c2()), ("c3_3d_p1_128", meshgen.c3())):
         A = femcg.Matrix(w.mesh, w.order, femcg.FEM_FORMAT_SELL)
         fmt, cw, sg = femcg.fem_tune(A, 1, femcg.PCG_FP64)
+        fname = "%s C%d sigma%d%s" % ("CSR" if (fmt & 0xf) == femcg.FEM_FORMAT_CSR else "SELL", cw, sg,
+                                      " morton" if fmt & femcg.FEM_ORDER_SFC else "")
+        log("%s: tuned format %s" % (name, fname))
         coords, _, _ = A.dofs()
         g = w.dirichlet(coords)[:, :1].copy()
         n = A.n_free
@@ -640,7 +643,7 @@ def run_bicgstab(args):
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - t0)
         st = A.stats()
-        rows.append(dict(system=name, n=n, solver="jacobi_pcg", iters=int(st["iters"][0]),
+        rows.append(dict(system=name, n=n, solver="jacobi_pcg", format=fname, iters=int(st["iters"][0]),
                          ms=round(1e3 * percentile(ts, 50), 3), gbs=round(st["bytes"] / percentile(ts, 50) / 1e9, 1),
                          oracle_relres=check(X)))
         log("%s PCG: %d its, %.2f ms" % (name, rows[-1]["iters"], rows[-1]["ms"]))
@@ -656,7 +659,8 @@ def run_bicgstab(args):
                 if rc != 0:
                     raise RuntimeError("%s BiCGStab bs %d status %d" % (name, bs, rc))
             t = percentile(ts, 50)
-            rows.append(dict(system=name, n=n, solver="bicgstab_bj", form="K", block_size=bs, nblocks=int(bst["nblocks"]),
+            rows.append(dict(system=name, n=n, solver="bicgstab_bj", form="K", format=fname, block_size=bs,
+                             nblocks=int(bst["nblocks"]),
                              iters=int(bst["iters"]), restarts=int(bst["restarts"]), ms=round(1e3 * t, 3),
                              ms_per_iter=round(1e3 * t / max(1, bst["iters"]), 4),
                              gbs=round(bst["bytes"] / t / 1e9, 1), setup_s=round(bst["setup_s"], 3),
@@ -689,7 +693,7 @@ def run_bicgstab(args):
             if Ao is not None:
                 x, b0 = X.cpu().numpy()[:, 0], Bo[:, 0]
                 orel = float(np.linalg.norm(dsc * (b0 - Ao @ x)) / np.linalg.norm(dsc * b0))
-            rows.append(dict(system=name, n=n, solver="bicgstab_bj", form="B^-1 L", block_size=bs,
+            rows.append(dict(system=name, n=n, solver="bicgstab_bj", form="B^-1 L", format=fname, block_size=bs,
                              nblocks=int(bst["nblocks"]), iters=int(bst["iters"]), restarts=int(bst["restarts"]),
                              ms=round(1e3 * t, 3), ms_per_iter=round(1e3 * t / max(1, bst["iters"]), 4),
                              gbs=round(bst["bytes"] / t / 1e9, 1), setup_s=round(bst["setup_s"], 3),

@@ -162,12 +162,24 @@ __device__ void reduce_slot(const BcgArgs &a, int slot, double out[2])
 
 // For every public free row i: w = f(internal row) is stored to out1, and
 // out2 = M^-1 w for the row's block.  A pass of a workgroup covers whole
-// blocks (kB / bs of them), staged in LDS.  Returns this thread's sum of w^2.
+// blocks (kB / bs of them), staged in LDS.  Blocks of one row need no
+// staging and no public order: those run over internal rows, with the
+// inverse diagonal kept in internal order.  Returns this thread's sum of w^2.
 template <typename F>
 __device__ double block_apply(const BcgArgs &a, F &&f, double *__restrict__ out1, double *__restrict__ out2)
 {
     __shared__ double sw[kB];
     const int bs = a.bs;
+    if (bs == 1) {
+        double w2 = 0.0;
+        for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kB) {
+            const double w = f((int32_t)i);
+            out1[i] = w;
+            out2[i] = a.binv[i] * w;
+            w2 += w * w;
+        }
+        return w2;
+    }
     const int R = (kB / bs) * bs;
     const int64_t npass = (a.n + R - 1) / R;
     double w2 = 0.0;
@@ -475,6 +487,11 @@ int bcg_prepare(fem_matrix *A, int bs, const double *row_scale)
     if (!block_inverses(A->hs, bs, W->scale, inv)) return fail(FEMCG_EBREAKDOWN, "singular diagonal block (block size %d)", bs);
     std::vector<int32_t> iperm(n);
     for (int64_t i = 0; i < n; ++i) iperm[A->sc.perm[i]] = (int32_t)i;
+    if (bs == 1) {  // one-row blocks are applied in internal order
+        std::vector<double> d(n);
+        for (int64_t i = 0; i < n; ++i) d[iperm[i]] = inv[i];
+        inv.swap(d);
+    }
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t vb = al(sizeof(double) * std::max<int64_t>(n, 1));
     const size_t ib = al(sizeof(double) * inv.size()), pb = al(sizeof(int32_t) * std::max<int64_t>(n, 1));
