@@ -160,50 +160,105 @@ __device__ void reduce_slot(const BcgArgs &a, int slot, double out[2])
     __syncthreads();
 }
 
+// the sums of two partial slots in one pass, each in reduce_slot's order
+// (so the results are those of two reduce_slot calls)
+__device__ void reduce_two_slots(const BcgArgs &a, int s0, int s1, double o0[2], double o1[2])
+{
+    __shared__ double red[4][kB];
+    const int G = gridDim.x;
+    const double *p0 = a.part + (int64_t)s0 * G * 2, *p1 = a.part + (int64_t)s1 * G * 2;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int g = threadIdx.x; g < G; g += kB) {
+        v[0] += p0[2 * g];
+        v[1] += p0[2 * g + 1];
+        v[2] += p1[2 * g];
+        v[3] += p1[2 * g + 1];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) red[c][threadIdx.x] = v[c];
+    __syncthreads();
+    for (int off = kB / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    o0[0] = red[0][0];
+    o0[1] = red[1][0];
+    o1[0] = red[2][0];
+    o1[1] = red[3][0];
+    __syncthreads();
+}
+
 // For every public free row i: w = f(internal row) is stored to out1, and
-// out2 = M^-1 w for the row's block.  A pass of a workgroup covers whole
-// blocks (kB / bs of them), staged in LDS.  Blocks of one row need no
-// staging and no public order: those run over internal rows, with the
-// inverse diagonal kept in internal order.  Returns this thread's sum of w^2.
+// out2 = M^-1 w for the row's block.  A sub-pass of a workgroup covers whole
+// blocks (kB / bs of them), staged in LDS; each thread keeps kU sub-passes in
+// flight, all loads issued before any store (out1 may be one of f's inputs,
+// at the same index only).  Blocks of one row need no staging and no public
+// order: those run over internal rows, with the inverse diagonal kept in
+// internal order.  Returns this thread's sum of w^2.
+constexpr int kU = 4;
+
 template <typename F>
 __device__ double block_apply(const BcgArgs &a, F &&f, double *__restrict__ out1, double *__restrict__ out2)
 {
-    __shared__ double sw[kB];
+    __shared__ double sw[kU][kB];
     const int bs = a.bs;
+    double w2 = 0.0;
     if (bs == 1) {
-        double w2 = 0.0;
-        for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kB) {
-            const double w = f((int32_t)i);
-            out1[i] = w;
-            out2[i] = a.binv[i] * w;
-            w2 += w * w;
+        const int64_t stride = (int64_t)gridDim.x * kB;
+        for (int64_t i0 = (int64_t)blockIdx.x * kB + threadIdx.x; i0 < a.n; i0 += kU * stride) {
+            double w[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int64_t i = i0 + u * stride;
+                w[u] = i < a.n ? f((int32_t)i) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int64_t i = i0 + u * stride;
+                if (i < a.n) {
+                    out1[i] = w[u];
+                    out2[i] = a.binv[i] * w[u];
+                    w2 += w[u] * w[u];
+                }
+            }
         }
         return w2;
     }
     const int R = (kB / bs) * bs;
-    const int64_t npass = (a.n + R - 1) / R;
-    double w2 = 0.0;
+    const int lr = threadIdx.x, q = lr % bs;
+    const int64_t npass = (a.n + (int64_t)kU * R - 1) / ((int64_t)kU * R);
     for (int64_t c = blockIdx.x; c < npass; c += gridDim.x) {
-        const int lr = threadIdx.x;
-        const int64_t i = c * R + lr;
-        const bool ok = lr < R && i < a.n;
-        const int32_t ii = ok ? a.iperm[i] : 0;
-        double w = 0.0;
-        if (ok) {
-            w = f(ii);
-            out1[ii] = w;
-            w2 += w * w;
+        int32_t ii[kU];
+        double w[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int64_t i = (c * kU + u) * R + lr;
+            ii[u] = (lr < R && i < a.n) ? a.iperm[i] : -1;
         }
-        sw[lr] = w;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) w[u] = ii[u] >= 0 ? f(ii[u]) : 0.0;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            if (ii[u] >= 0) {
+                out1[ii[u]] = w[u];
+                w2 += w[u] * w[u];
+            }
+            sw[u][lr] = w[u];
+        }
         __syncthreads();
-        if (ok) {
-            const int q = lr % bs;
-            const int64_t i0 = i - q;
-            const int m = (int)min<int64_t>(bs, a.n - i0);
-            const double *Bi = a.binv + ((i0 / bs) * bs + q) * (int64_t)bs;
-            double z = 0.0;
-            for (int j = 0; j < m; ++j) z += Bi[j] * sw[lr - q + j];
-            out2[ii] = z;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            if (ii[u] >= 0) {
+                const int64_t i0 = (c * kU + u) * R + lr - q;
+                const int m = (int)min<int64_t>(bs, a.n - i0);
+                const double *Bi = a.binv + ((i0 / bs) * bs + q) * (int64_t)bs;
+                double z = 0.0;
+                for (int j = 0; j < m; ++j) z += Bi[j] * sw[u][lr - q + j];
+                out2[ii[u]] = z;
+            }
         }
         __syncthreads();
     }
@@ -298,8 +353,7 @@ __global__ __launch_bounds__(kB) void k_bcg_s(BcgArgs a)
     BcgState *st = a.st;
     if (st->done) return;
     double e[2], bsum[2];
-    reduce_slot(a, SL_E, e);
-    reduce_slot(a, SL_B, bsum);
+    reduce_two_slots(a, SL_E, SL_B, e, bsum);
     const double rho = e[0], sig = bsum[0];
     if (sig == 0.0 || !isfinite(sig)) {
         if (lead()) {
@@ -342,14 +396,12 @@ __global__ __launch_bounds__(kB) void k_bcg_xr(BcgArgs a)
 {
     BcgState *st = a.st;
     if (st->done) return;
-    double c[2];
-    reduce_slot(a, SL_C, c);
+    double c[2], d[2];
+    reduce_two_slots(a, SL_C, SL_D, c, d);  // D is stale (and unused) at a half step
     const double alpha = st->alpha;
     const bool half = c[0] <= st->tol2 * st->bb;
     double omega = 0.0;
     if (!half) {
-        double d[2];
-        reduce_slot(a, SL_D, d);
         omega = d[0] / d[1];
         if (omega == 0.0 || !isfinite(omega)) {
             if (lead()) {
