@@ -106,6 +106,24 @@ __device__ __forceinline__ double row_dot(const BcgArgs &a, int64_t row, const d
     return acc0 + acc1;
 }
 
+// The rows a thread visits in a product kernel.  Blocks are dispatched to the
+// XCDs round-robin (block b on XCD b mod kNumXcd), so each XCD takes one
+// contiguous share of the rows and its blocks walk that share in kB-row
+// chunks: rows that gather the same neighbours meet in one L2.  Grids that are
+// not a multiple of the XCD count use the plain grid stride.
+struct RowWalk {
+    int64_t begin, end, step;
+};
+__device__ __forceinline__ RowWalk row_walk(int64_t n)
+{
+    const int G = gridDim.x;
+    if (G % kNumXcd != 0) return {(int64_t)blockIdx.x * kB + threadIdx.x, n, (int64_t)G * kB};
+    const int x = blockIdx.x % kNumXcd, j = blockIdx.x / kNumXcd;
+    const int64_t share = (n + kNumXcd - 1) / kNumXcd;
+    const int64_t lo = min<int64_t>(n, x * share), hi = min<int64_t>(n, lo + share);
+    return {lo + (int64_t)j * kB + threadIdx.x, hi, (int64_t)(G / kNumXcd) * kB};
+}
+
 // row of the (possibly row-scaled) operator
 __device__ __forceinline__ double op_row(const BcgArgs &a, int64_t row, const double *__restrict__ x)
 {
@@ -339,7 +357,8 @@ __global__ __launch_bounds__(kB) void k_bcg_v(BcgArgs a)
 {
     if (a.st->done) return;
     double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kB) {
+    const RowWalk w = row_walk(a.n);
+    for (int64_t i = w.begin; i < w.end; i += w.step) {
         const double v = op_row(a, i, a.ph);
         a.v[i] = v;
         acc += a.rh[i] * v;
@@ -382,7 +401,8 @@ __global__ __launch_bounds__(kB) void k_bcg_t(BcgArgs a)
     reduce_slot(a, SL_C, c);
     if (c[0] <= st->tol2 * st->bb) return;  // stops at s: t is not needed
     double ts = 0.0, tt = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kB) {
+    const RowWalk w = row_walk(a.n);
+    for (int64_t i = w.begin; i < w.end; i += w.step) {
         const double t = op_row(a, i, a.sh);
         a.t[i] = t;
         ts += t * a.s[i];
