@@ -640,6 +640,48 @@ BcgArgs bcg_args(const fem_matrix *A)
     return a;
 }
 
+// one poll window: m iterations of the five phase kernels
+void enqueue_window(const BcgArgs &a, int G, int m, hipStream_t s)
+{
+    for (int i = 0; i < m; ++i) {
+        hipLaunchKernelGGL(k_bcg_p, dim3(G), dim3(kB), 0, s, a);
+        hipLaunchKernelGGL(k_bcg_v, dim3(G), dim3(kB), 0, s, a);
+        hipLaunchKernelGGL(k_bcg_s, dim3(G), dim3(kB), 0, s, a);
+        hipLaunchKernelGGL(k_bcg_t, dim3(G), dim3(kB), 0, s, a);
+        hipLaunchKernelGGL(k_bcg_xr, dim3(G), dim3(kB), 0, s, a);
+    }
+}
+
+// The window captured once per workspace (its arguments are fixed: the
+// workspace is rebuilt when the format, the block size or the row scale
+// changes) on a private stream, replayed on the caller's stream.
+int ensure_window_graph(BcgWork *W, const BcgArgs &a, int m)
+{
+    if (W->gexec) return FEMCG_OK;
+    if (!W->cap) {
+        hipStream_t cs = nullptr;
+        BCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        W->cap = cs;
+    }
+    hipStream_t cs = (hipStream_t)W->cap;
+    hipGraph_t g = nullptr;
+    BCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    enqueue_window(a, W->grid, m, cs);
+    const hipError_t le = hipGetLastError();
+    const hipError_t ce = hipStreamEndCapture(cs, &g);
+    if (le != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(FEMCG_EDEVICE, "BiCGStab graph capture: %s", hipGetErrorString(le));
+    }
+    if (ce != hipSuccess) return fail(FEMCG_EDEVICE, "BiCGStab graph capture: %s", hipGetErrorString(ce));
+    hipGraphExec_t ge = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return fail(FEMCG_EDEVICE, "BiCGStab graph instantiate: %s", hipGetErrorString(ie));
+    W->gexec = ge;
+    return FEMCG_OK;
+}
+
 // sum of value `comp` of the grid's partials of a slot, in block order
 int read_slot(BcgWork *W, hipStream_t s, int slot, int comp, double *out)
 {
@@ -656,6 +698,8 @@ int read_slot(BcgWork *W, hipStream_t s, int slot, int comp, double *out)
 
 BcgWork::~BcgWork()
 {
+    if (gexec) (void)hipGraphExecDestroy((hipGraphExec_t)gexec);
+    if (cap) (void)hipStreamDestroy((hipStream_t)cap);
     if (mem) (void)hipFree(mem);
     if (h_st) (void)hipHostFree(h_st);
     if (h_part) (void)hipHostFree(h_part);
@@ -705,6 +749,9 @@ static int bicgstab_solve_impl(fem_matrix *A, const double *B, double *X, double
         BCHK(hipStreamSynchronize(s));
     } else {
         const int m = 32;  // iterations enqueued between polls
+        const char *gv = std::getenv("FEMCG_BCG_GRAPH");
+        const bool use_graph = !(gv && gv[0] == '0');
+        if (use_graph && (rc = ensure_window_graph(W, a, m))) return rc;
         int use_x = 0;
         for (;;) {
             hipLaunchKernelGGL(k_bcg_init, dim3(G), dim3(kB), 0, s, a, use_x);
@@ -721,13 +768,8 @@ static int bicgstab_solve_impl(fem_matrix *A, const double *B, double *X, double
             std::memcpy(hst, &init, sizeof(init));
             BCHK(hipMemcpyAsync(W->st, hst, sizeof(BcgState), hipMemcpyHostToDevice, s));
             for (;;) {
-                for (int i = 0; i < m; ++i) {
-                    hipLaunchKernelGGL(k_bcg_p, dim3(G), dim3(kB), 0, s, a);
-                    hipLaunchKernelGGL(k_bcg_v, dim3(G), dim3(kB), 0, s, a);
-                    hipLaunchKernelGGL(k_bcg_s, dim3(G), dim3(kB), 0, s, a);
-                    hipLaunchKernelGGL(k_bcg_t, dim3(G), dim3(kB), 0, s, a);
-                    hipLaunchKernelGGL(k_bcg_xr, dim3(G), dim3(kB), 0, s, a);
-                }
+                if (use_graph) BCHK(hipGraphLaunch((hipGraphExec_t)W->gexec, s));
+                else enqueue_window(a, G, m, s);
                 BCHK(hipGetLastError());
                 BCHK(hipMemcpyAsync(hst, W->st, sizeof(BcgState), hipMemcpyDeviceToHost, s));
                 BCHK(hipStreamSynchronize(s));

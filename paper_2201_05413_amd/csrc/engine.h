@@ -66,6 +66,8 @@ struct BcgWork {
     void *st = nullptr;         // device state
     void *h_st = nullptr;       // pinned host copy of the state
     double *h_part = nullptr;   // pinned copy of one partial slot
+    void *cap = nullptr;        // private capture stream (hipStream_t)
+    void *gexec = nullptr;      // graph of one poll window of iterations (hipGraphExec_t)
     size_t bytes = 0;
     double setup_s = 0.0;
     ~BcgWork();

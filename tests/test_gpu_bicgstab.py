@@ -229,3 +229,17 @@ def test_row_scale_errors():
         femcg.bicgstab_solve(c.A, B, X, 1e-10, 4, row_scale=np.ones(n - 1))
     rc, st = femcg.bicgstab_solve(c.A, B, X, 1e-10, 4, row_scale=np.full(n, 2.0))
     assert rc == 0
+
+
+def test_graph_replay_and_direct_launches_agree_bitwise(monkeypatch):
+    # the poll window runs as a captured graph by default; FEMCG_BCG_GRAPH=0
+    # enqueues the same kernels one by one
+    c = Sys(2, 33, 0.3, 1, seed=8)
+    out = []
+    for env in ("0", "1", "0"):
+        monkeypatch.setenv("FEMCG_BCG_GRAPH", env)
+        rc, x, st = c.solve(1e-10, 4)
+        assert rc == 0
+        out.append((x, st["iters"]))
+    for x, its in out[1:]:
+        assert np.array_equal(x, out[0][0]) and its == out[0][1]
