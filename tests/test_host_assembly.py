@@ -81,3 +81,15 @@ def test_device_and_host_only_flags_exclude_each_other():
     with pytest.raises(femcg.FemcgError) as ei:
         femcg.Matrix(mesh, 1, femcg.FEM_FORMAT_SELL | femcg.FEM_ASSEMBLE_DEVICE | femcg.FEM_ASSEMBLE_HOST_ONLY)
     assert ei.value.code == femcg.FEMCG_EINVAL
+
+
+def test_binding_checks_bicgstab_arguments_before_any_device_call():
+    torch = pytest.importorskip("torch")
+    A = _host_matrix(meshgen.make_mesh(2, 8, 0.2, 3), 1)
+    B = torch.zeros(A.n_free, dtype=torch.float64)
+    with pytest.raises(ValueError):
+        femcg.bicgstab_solve(A, B, B, 1e-8, 4, row_scale=np.ones(A.n_free + 1))
+    with pytest.raises(ValueError):
+        femcg.bicgstab_solve(A, torch.zeros(A.n_free + 1, dtype=torch.float64), B, 1e-8, 4)
+    with pytest.raises(TypeError):  # host tensors: the boundary takes device memory
+        femcg.bicgstab_solve(A, B, B, 1e-8, 4, row_scale=np.ones(A.n_free))
