@@ -60,8 +60,8 @@ def test_c4_full_size_and_column0_closed_form():
 
 @pytest.mark.parametrize("bs", [1, 4])
 def test_c2_full_size_bicgstab(bs):
-    # the paper's solver on the full C2 system; bs = 1 meets the Lanczos
-    # near-breakdown of the lifted right-hand side and restarts
+    # the paper's solver on the full C2 system (its lifted right-hand side
+    # lives next to the boundary: the Lanczos restart path)
     w = meshgen.c2()
     A = femcg.Matrix(w.mesh, w.order)
     femcg.fem_tune(A, 1, femcg.PCG_FP64)
@@ -76,3 +76,36 @@ def test_c2_full_size_bicgstab(bs):
     orc = oracle.System(w.mesh, w.order)
     rel = orc.relres(orc.rhs(g), X.cpu().numpy())[0]
     assert rel <= w.tol * 1.0001, (rel, st)
+
+
+def test_c2_full_size_bicgstab_on_the_paper_form():
+    # A = B^-1 L (Sect. 2.2) on the full C2 system: rows scaled by the inverse
+    # area of the cells around each vertex; the oracle's matrix gives the
+    # scaled residual
+    import scipy.sparse as sp
+    w = meshgen.c2()
+    A = femcg.Matrix(w.mesh, w.order)
+    femcg.fem_tune(A, 1, femcg.PCG_FP64)
+    coords, _, f2d = A.dofs()
+    Xc = np.asarray(w.mesh["coords"], dtype=np.float64)
+    T = np.asarray(w.mesh["cells"], dtype=np.int64)
+    area = 0.5 * np.abs((Xc[T[:, 1], 0] - Xc[T[:, 0], 0]) * (Xc[T[:, 2], 1] - Xc[T[:, 0], 1])
+                        - (Xc[T[:, 2], 0] - Xc[T[:, 0], 0]) * (Xc[T[:, 1], 1] - Xc[T[:, 0], 1]))
+    Bl = np.zeros(len(Xc))
+    for j in range(3):
+        np.add.at(Bl, T[:, j], area)
+    dsc = 1.0 / Bl[f2d]
+    g = w.dirichlet(coords)[:, :1].copy()
+    B = torch.empty((A.n_free, 1), dtype=torch.float64, device="cuda")
+    femcg.fem_rhs(A, g, B)
+    X = torch.zeros_like(B)
+    rc, st = femcg.bicgstab_solve(A, B, X, w.tol, 4, row_scale=dsc)
+    torch.cuda.synchronize()
+    assert rc == 0, st
+    orc = oracle.System(w.mesh, w.order)
+    rp, col, val = orc.A()
+    Ao = sp.csr_matrix((val, col, rp), shape=(A.n_free, A.n_free))
+    b = orc.rhs(g)[:, 0]
+    x = X.cpu().numpy()[:, 0]
+    rel = np.linalg.norm(dsc * (b - Ao @ x)) / np.linalg.norm(dsc * b)
+    assert rel <= w.tol * 1.0001 and abs(st["relres"] - rel) <= 0.05 * rel, (rel, st)
