@@ -1,5 +1,6 @@
-"""The C-ABI library loads and exports every symbol include/femcg.h declares
-(no compute call: this runs without a GPU)."""
+"""The C-ABI library loads and exports every symbol include/femcg.h declares,
+and the binding's argument lists have the header's parameter counts (no
+compute call: this runs without a GPU)."""
 import ctypes
 import os
 import re
@@ -41,3 +42,24 @@ def test_last_error_is_empty_string_without_gpu_work():
     lib = ctypes.CDLL(LIB)
     lib.fem_last_error.restype = ctypes.c_char_p
     assert lib.fem_last_error() is not None
+
+
+def declared_signatures():
+    """name -> number of parameters, from the prototypes in the header."""
+    txt = re.sub(r"/\*.*?\*/", "", open(HDR).read(), flags=re.S)
+    out = {}
+    for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([a-z_][a-z0-9_]*)\s*\(([^;{]*?)\)\s*;",
+                         txt, flags=re.M | re.S):
+        params = " ".join(m.group(2).split())
+        out[m.group(1)] = 0 if params in ("", "void") else params.count(",") + 1
+    return out
+
+
+def test_binding_argument_lists_match_the_header():
+    from paper_2201_05413_amd import femcg
+    L = femcg.lib()
+    sigs = declared_signatures()
+    assert sorted(sigs) == declared_functions()
+    bad = {n: (k, len(getattr(L, n).argtypes or [])) for n, k in sigs.items()
+           if len(getattr(L, n).argtypes or []) != k}
+    assert not bad, bad  # name: (header, binding)
