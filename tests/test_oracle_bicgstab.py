@@ -117,3 +117,12 @@ def test_zero_rhs_and_singular_block():
     val2[rp[0]:rp[1]] = 0.0  # first row empty: its 1x1 block is singular
     *_, st = oracle.bicgstab_csr(rp, col, val2, b, 1, 1e-10)
     assert st == -4  # breakdown
+
+
+def test_unreachable_tol_warns_after_the_last_restart():
+    # tol 1e-17 is below the rounding floor of the true residual: the
+    # recursion converges, the true residual misses Eq. (2) three restarts in
+    # a row, and the result is a warning (1), well before the iteration cap
+    s, rp, col, val, b = _system(m=12)
+    x, its, rel, rs, st = oracle.bicgstab_csr(rp, col, val, b, 4, 1e-17)
+    assert st == 1 and rel > 1e-17 and rs == 3 and its < oracle.default_max_iter(s.nfree)

@@ -109,3 +109,13 @@ def test_breakdown_reported():
     X1, its1, _, _, st1 = oracle.pcg_csr(*s.A(), B, 1e-10)
     X2, its2, _, _, st2 = s.pcg(B, 1e-10)
     assert st1 == st2 == 0 and np.array_equal(X1, X2) and its1[0] == its2[0]
+
+
+def test_unreachable_tol_warns_after_the_last_restart():
+    # below the rounding floor the true residual misses Eq. (2) after every
+    # restart: status 1 (warning) with the residual reached, not success
+    s = oracle.System(meshgen.mesh2d(12, 0.3, 2), 1)
+    coords, _, _ = s.dofs()
+    g = meshgen.harmonic_eval(meshgen.random_coeffs(2, 1, 5), coords)
+    X, its, rel, rs, st = s.pcg(s.rhs(g), 1e-17)
+    assert st == 1 and rs[0] == 3 and rel[0] > 1e-17 and its[0] < oracle.default_max_iter(s.nfree)
