@@ -188,7 +188,9 @@ typedef struct {
  * call with a given block size and row scale and kept with A until the
  * format, the block size or the row scale changes.  Work is enqueued on `stream` and the call synchronises it.
  * stats may be NULL.
- * Returns 0, FEMCG_WARN_MAXITER, or FEMCG_EINVAL (arguments), FEMCG_EBREAKDOWN
+ * Returns 0 (the true residual meets Eq. (2)), FEMCG_WARN_MAXITER (it does
+ * not: the iteration cap was reached, or the third restart still missed tol;
+ * stats hold the residual), or FEMCG_EINVAL (arguments), FEMCG_EBREAKDOWN
  * (a singular block, rho = 0, (rh, v) = 0, omega = 0 or a non-finite
  * scalar), FEMCG_ENOMEM, FEMCG_EDEVICE. */
 int bicgstab_solve(fem_matrix *A, const double *B, double *X, double tol, int32_t block_size,

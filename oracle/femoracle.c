@@ -968,7 +968,9 @@ static int pcg_csr(const csr_view *A, const double *B, int k, double tol, int64_
             if (status == ORC_EBREAK || rel <= tol || its >= max_iter || rs >= 3) break;
             rs++;
         }
-        if (its >= max_iter && rel > tol && status == 0) status = 1;
+        /* Eq. (2) not met, either at the iteration cap or after the last
+         * allowed restart: a warning, not success */
+        if (rel > tol && status == 0) status = 1;
         iters[j] = its;
         relres[j] = rel;
         if (restarts) restarts[j] = rs;
@@ -1202,7 +1204,7 @@ int orc_bicgstab_csr(int64_t n, const int64_t *rowptr, const int32_t *col, const
         if (status == ORC_EBREAK || rel <= tol || its >= max_iter || rs >= 3) break;
         rs++;
     }
-    if (its >= max_iter && rel > tol && status == 0) status = 1;
+    if (rel > tol && status == 0) status = 1;  /* cap or restarts spent: Eq. (2) not met */
 finish:
     *iters = its;
     *relres = rel;

@@ -807,7 +807,11 @@ static int bicgstab_solve_impl(fem_matrix *A, const double *B, double *X, double
                 status = rel <= tol ? FEMCG_OK : FEMCG_WARN_MAXITER;
                 break;
             }
-            if (rel <= tol || restarts >= 3) break;
+            if (rel <= tol) break;
+            if (restarts >= 3) {  // the true residual still misses Eq. (2)
+                status = FEMCG_WARN_MAXITER;
+                break;
+            }
             ++restarts;
             use_x = 1;
         }

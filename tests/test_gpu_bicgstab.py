@@ -113,6 +113,11 @@ def test_bicgstab_edge_cases():
     # iteration cap: warning with the residual reached
     rc, x, st = c.solve(1e-12, 1, max_iter=5)
     assert rc == femcg.FEMCG_WARN_MAXITER and st["iters"] == 5 and st["relres"] > 1e-12
+    # a tolerance below the rounding floor: the third restart still misses
+    # it, which is a warning too, long before the cap
+    rc, x, st = c.solve(1e-17, 4)
+    assert rc == femcg.FEMCG_WARN_MAXITER and st["restarts"] >= 3 and st["relres"] > 1e-17
+    assert st["iters"] < oracle.default_max_iter(n)
     # argument errors leave the matrix usable
     for bs in (0, 65):
         with pytest.raises(femcg.FemcgError) as ei:
