@@ -1,6 +1,6 @@
 /*
  * femcg.h -- C ABI of the MI355X (gfx950) Jacobi-PCG library for the
- * P1/P2 finite-element Laplace systems of "Evaluating Accuracy and
+ * P1-P4 finite-element Laplace systems of "Evaluating Accuracy and
  * Efficiency of HPC Solvers for Sparse Linear Systems with Applications to
  * PDEs" (Galizia, Cammarasana, Clematis, Patane).
  *
@@ -196,9 +196,14 @@ typedef struct {
 int bicgstab_solve(fem_matrix *A, const double *B, double *X, double tol, int32_t block_size,
                    const double *row_scale, int64_t max_iter, void *stream, bicgstab_stats_t *stats);
 
-/* Sizes and DOF data.  Any output pointer may be NULL.
- * dof_coords: host [n_all][dim]; dirichlet: host [n_all]; free2dof: host
- * [n_free] (the DOF index of each solver row). */
+/* Sizes and DOF data of the discretisation (Sect. 2.2: P1 DOFs are the mesh
+ * vertices; Table 7's degrees add p-1 DOFs per edge and (p-1)(p-2)/2 per
+ * cell), in the public DOF order above.  Any output pointer may be NULL.
+ * n_all: every DOF; n_free: the non-Dirichlet DOFs, the solver's unknowns.
+ * dof_coords: host [n_all][dim]; dirichlet: host [n_all] (1 = the DOF lies
+ * on the boundary, where u = f is imposed); free2dof: host [n_free] (the DOF
+ * index of each solver row).  Works on a host-only matrix.  Returns 0 or
+ * FEMCG_EINVAL (A NULL). */
 int fem_dofs(const fem_matrix *A, int64_t *n_all, int64_t *n_free, double *dof_coords,
              uint8_t *dirichlet, int64_t *free2dof);
 
@@ -235,7 +240,12 @@ int pcg_solve_batch(int32_t nsys, fem_matrix *const *A, const double *const *B, 
                     const int32_t *k, const double *tol, const pcg_opts *opts, int32_t *status,
                     void *stream);
 
-/* Statistics of the last solve on this matrix. */
+/* Statistics of the last solve on this matrix (Sect. 2.3's measures:
+ * execution time, FLOPS and memory, beside the iterations and the accuracy
+ * of Eq. (2) per column as relres, the true FP64 ||b - A x|| / ||b||;
+ * Eq. (1) needs a ground-truth solution and is left to the caller).  The fields are described with
+ * pcg_stats_t.  Works on a host-only matrix (sizes only).  Returns 0 or
+ * FEMCG_EINVAL (A or out NULL). */
 int pcg_stats(const fem_matrix *A, pcg_stats_t *out);
 
 /* Autotune the solver copy for k right-hand sides: times SpMM over candidate
@@ -278,8 +288,8 @@ int fem_set_tiling(fem_matrix *A, int32_t band, int32_t tile);
 int pcg_time_kernel(fem_matrix *A, int32_t kernel, int32_t reps, void *stream, double *ms,
                     double *bytes);
 
-/* Cold-cache SpMM rate (Sect. 4 SpMV throughput, measured so that no copy is
- * cache-resident): builds the SpMM launch of each of the nmat matrices for
+/* Cold-cache SpMM rate (the MatMult of Sect. 3.2 as an SpMM, timed so that
+ * no copy is cache-resident): builds the SpMM launch of each of the nmat matrices for
  * k right-hand sides in `precision` on its own workspace (p zero-filled),
  * launches all once, then times `reps` rounds of launching them in turn,
  * so with copies totalling far more than the 256 MB last-level cache every
@@ -316,6 +326,8 @@ typedef struct {
     double t_admit;         /* admitted to the device */
     double t_done;
     double relres_max;
+    double footprint_mb;    /* device memory the request held against the budget
+                               (0 if it never had a footprint: failed assembly) */
 } fem_request_info;
 
 /* budget_bytes: device memory the server may hold for admitted requests.

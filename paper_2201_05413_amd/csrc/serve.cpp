@@ -362,6 +362,7 @@ static int serve_poll_impl(fem_server *s, int64_t id, double *X, fem_request_inf
         info->t_admit = r->t_admit;
         info->t_done = r->t_done;
         info->relres_max = r->relres_max;
+        info->footprint_mb = (double)r->footprint * 1e-6;
     }
     if (X && !r->X.empty()) std::memcpy(X, r->X.data(), r->X.size() * 8);
     s->reqs.erase(it);

@@ -89,7 +89,7 @@ class fem_request_info(C.Structure):
     _fields_ = [("id", C.c_int64), ("status", C.c_int32), ("k", C.c_int32), ("n", C.c_int64),
                 ("iters_max", C.c_int64), ("t_submit", C.c_double), ("t_ready", C.c_double),
                 ("t_admit", C.c_double),
-                ("t_done", C.c_double), ("relres_max", C.c_double)]
+                ("t_done", C.c_double), ("relres_max", C.c_double), ("footprint_mb", C.c_double)]
 
 
 _lib = None

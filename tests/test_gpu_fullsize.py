@@ -3,7 +3,8 @@ times (autotuned format, check_every 64, FP64 and mixed): the oracle's own
 Eq. (2) residual of every column (R), and the closed forms where the exact
 discrete solution is known (C3: nodal harmonic cubics on the structured
 Kuhn mesh; C4 column 0: the P2 interpolant of x^2 - y^2), within the bound a
-1e-8 residual allows.  BiCGStab + Block-Jacobi runs on the full C2 system."""
+1e-8 residual allows.  BiCGStab + Block-Jacobi runs on the full C2 system
+and on the full C3 cube."""
 import numpy as np
 import pytest
 
@@ -76,6 +77,30 @@ def test_c2_full_size_bicgstab(bs):
     orc = oracle.System(w.mesh, w.order)
     rel = orc.relres(orc.rhs(g), X.cpu().numpy())[0]
     assert rel <= w.tol * 1.0001, (rel, st)
+
+
+@pytest.mark.parametrize("bs", [1, 4])
+def test_c3_full_size_bicgstab(bs):
+    # the paper's solver on the full 128^3 Kuhn cube (Cube 1's grid), column
+    # 0 of C3's data: the oracle's residual (R), and the nodal harmonic cubic,
+    # which is the exact discrete solution on this mesh
+    w = meshgen.c3()
+    A = femcg.Matrix(w.mesh, w.order)
+    femcg.fem_tune(A, 1, femcg.PCG_FP64)
+    coords, _, f2d = A.dofs()
+    g = w.dirichlet(coords)[:, :1].copy()
+    B = torch.empty((A.n_free, 1), dtype=torch.float64, device="cuda")
+    femcg.fem_rhs(A, g, B)
+    X = torch.zeros_like(B)
+    rc, st = femcg.bicgstab_solve(A, B, X, w.tol, bs)
+    torch.cuda.synchronize()
+    assert rc == 0, st
+    x = X.cpu().numpy()
+    del B, X, A
+    orc = oracle.System(w.mesh, w.order)
+    rel = orc.relres(orc.rhs(g), x)[0]
+    assert rel <= w.tol * 1.0001, (rel, st)
+    assert oracle.x_err(g[f2d, 0], x[:, 0]) <= 1e-5
 
 
 def test_c2_full_size_bicgstab_on_the_paper_form():

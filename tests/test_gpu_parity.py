@@ -83,7 +83,7 @@ def test_assembly_matches_oracle(dim, m, jit, order, where):
 
 
 @pytest.mark.parametrize("fmt", [femcg.FEM_FORMAT_CSR, femcg.FEM_FORMAT_SELL])
-@pytest.mark.parametrize("k", [1, 3, 8, 32])
+@pytest.mark.parametrize("k", [1, 3, 8, 12, 16, 32, 64])
 @pytest.mark.parametrize("order,m", [(2, 45), (4, 21)])
 def test_spmm_matches_oracle(fmt, k, order, m):
     # P4 rows hold up to 81 entries: split rows at k = 1, vector lanes at k >= 8
@@ -143,6 +143,44 @@ def test_solve_matches_oracle(dim, m, jit, order, prec):
         if prec == femcg.PCG_FP64 and tol == 1e-8:
             _, its_t, _, _, _ = c.orc.pcg(c.Bo, tol)
             for j in range(c.k):
+                assert abs(stats["iters"][j] - its_t[j]) <= 0.02 * its_t[j] + 2, (stats["iters"], its_t)
+
+
+WIDE_K = [(2, 37, 0.3, 1, 12), (3, 11, 0.3, 1, 16), (2, 23, 0.25, 2, 64), (3, 9, 0.2, 2, 12)]
+
+
+@pytest.mark.parametrize("dim,m,jit,order,k", WIDE_K)
+@pytest.mark.parametrize("mode", [0, 1], ids=["tile", "band"])
+@pytest.mark.parametrize("prec", [femcg.PCG_FP64, femcg.PCG_MIXED])
+def test_wide_k_phase_kernels_match_oracle(dim, m, jit, order, k, mode, prec):
+    # kp = 16 (k = 12, 16) and kp = 64 instances of the phase kernels, FP64
+    # and FP32-inner, in tile mode and in band mode (small tiles, several
+    # reduction groups): SpMM element by element, (R) at 1e-8, (S) at 1e-12
+    c = Case(dim, m, jit, order, k, seed=43, noise=0.01)
+    assert c.A.n_free * (16 if k <= 16 else 64) > 4096  # not the single-workgroup loop
+    femcg.fem_set_tiling(c.A, mode, 1024 if mode == 1 else 0)
+    rng = np.random.default_rng(k + mode)
+    Xr = rng.standard_normal((c.A.n_free, k))
+    Y = torch.zeros((c.A.n_free, k), dtype=torch.float64, device="cuda")
+    femcg.fem_spmv(c.A, dev(Xr), Y)
+    torch.cuda.synchronize()
+    rp, col, val = c.orc.A()
+    absAx = np.zeros_like(Xr)
+    for i in range(c.orc.nfree):
+        absAx[i] = np.abs(val[rp[i]:rp[i + 1]]) @ np.abs(Xr[col[rp[i]:rp[i + 1]]])
+    assert np.all(np.abs(Y.cpu().numpy() - c.orc.spmv(Xr)) <= 1e-13 * absAx)
+    Xs, _, _, _, st = c.orc.pcg(c.Bo, 1e-14)
+    assert st == 0
+    _, its_t, _, _, _ = c.orc.pcg(c.Bo, 1e-8)
+    for tol in (1e-8, 1e-12):
+        rc, X, stats = c.solve(tol, precision=prec)
+        assert rc == 0, stats
+        assert np.all(c.orc.relres(c.Bo, X) <= tol * 1.0001)
+        if tol == 1e-12:
+            for j in range(k):
+                assert oracle.x_err(Xs[:, j], X[:, j]) <= 1e-8, j
+        elif prec == femcg.PCG_FP64:
+            for j in range(k):
                 assert abs(stats["iters"][j] - its_t[j]) <= 0.02 * its_t[j] + 2, (stats["iters"], its_t)
 
 

@@ -2,6 +2,7 @@
 is bit-identical to the same system solved alone (batch invariance of the
 phase and single-workgroup kernels) and passes the oracle's Eq. (2) check."""
 import ctypes as C
+import time
 
 import numpy as np
 import pytest
@@ -76,3 +77,109 @@ def test_server_results_equal_solo_solves(prec):
         assert femcg.pcg_solve(A, B, Xs, tol, femcg.default_opts(tol=tol, precision=prec, check_every=ce)) == 0
         torch.cuda.synchronize()
         assert np.array_equal(Xs.cpu().numpy(), X)
+
+
+# requests for the pressure test: k = 12 and k = 16 run the kp = 16 kernels,
+# (2, 300, ...) is larger than the whole budget
+PRESSURE = [(2, 40, 0.3, 1, 12), (3, 12, 0.2, 1, 3), (2, 60, 0.0, 2, 2), (2, 25, 0.3, 1, 16), (2, 30, 0.3, 3, 1)]
+TOO_BIG = (2, 300, 0.3, 1, 16)
+
+
+def _drain(L, srv, ids, out, X_of):
+    """Poll every id in `ids`; store (info, X) of the finished ones in out."""
+    for rid in list(ids):
+        i = ids[rid]
+        X = X_of(i)
+        info = femcg.fem_request_info()
+        if L.serve_poll(srv, rid, femcg._np_ptr(X) if X is not None else None, C.byref(info)) == 1:
+            out[i] = (info, X)
+            del ids[rid]
+
+
+@pytest.mark.parametrize("prec", [femcg.PCG_FP64, femcg.PCG_MIXED])
+def test_server_under_memory_pressure(prec):
+    # Continuous batching under pressure: a budget that holds about two
+    # requests and two slots; requests arrive between ticks while others run,
+    # queue until a retirement frees memory, and one request larger than the
+    # budget is rejected with FEMCG_EADMIT.  Every served result equals the
+    # solo solve bit for bit and passes the oracle's Eq. (2) check.
+    tol, ce = 1e-9, 8
+    L = femcg.lib()
+    reqs = [_request(20 + i, *r) for i, r in enumerate(PRESSURE)]
+    big = _request(40, *TOO_BIG)
+    keep = []
+
+    def submit(srv, mesh, order, g, k):
+        ms, hold = femcg.make_mesh_struct(mesh)
+        keep.append(hold)
+        rid = L.serve_submit(srv, C.byref(ms), order, femcg._np_ptr(g), k, tol)
+        femcg._check(rid)
+        return rid
+
+    # footprints as the server counts them, from a roomy probe server
+    srv = C.c_void_p()
+    femcg._check(L.serve_create(8e9, 8, prec, ce, C.byref(srv)))
+    try:
+        ids = {submit(srv, mesh, r[3], g, r[4]): i for i, (r, (mesh, _, g)) in enumerate(zip(PRESSURE, reqs))}
+        while L.serve_step(srv) > 0:
+            pass
+        probe = {}
+        _drain(L, srv, ids, probe, lambda i: None)
+    finally:
+        L.serve_destroy(srv)
+    fp = sorted(probe[i][0].footprint_mb * 1e6 for i in range(len(PRESSURE)))
+    assert fp[0] > 0
+    # any two requests fit the budget and no three do: memory, not the slot
+    # count, is what makes later arrivals wait
+    budget = 1.01 * (fp[-1] + fp[-2])
+    assert fp[0] + fp[1] + fp[2] > budget
+    srv = C.c_void_p()
+    femcg._check(L.serve_create(budget, 4, prec, ce, C.byref(srv)))
+    got = {}
+    try:
+        ids = {}
+        nxt = 0
+        big_id = None
+        # tick -> submissions before it; the first two need more than two
+        # ticks of check_every iterations, so the third arrives while they run
+        schedule = {0: 2, 2: 1, 3: "big", 5: 2}
+        for tick in range(100000):
+            sub = schedule.get(tick, 0)
+            if sub == "big":
+                big_id = submit(srv, big[0], TOO_BIG[3], big[2], TOO_BIG[4])
+            else:
+                for _ in range(sub):
+                    r = PRESSURE[nxt]
+                    ids[submit(srv, reqs[nxt][0], r[3], reqs[nxt][2], r[4])] = nxt
+                    nxt += 1
+            if sub:
+                time.sleep(0.5)  # host assembly runs on the server's own thread
+            left = L.serve_step(srv)
+            femcg._check(left)
+            _drain(L, srv, ids, got, lambda i: np.zeros((reqs[i][1].nfree, PRESSURE[i][4])))
+            if left == 0 and tick > max(schedule):
+                break
+        assert nxt == len(PRESSURE) and not ids
+        info = femcg.fem_request_info()
+        assert L.serve_poll(srv, big_id, None, C.byref(info)) == 1
+        assert info.status == femcg.FEMCG_EADMIT and info.footprint_mb * 1e6 > budget
+    finally:
+        L.serve_destroy(srv)
+    infos = [got[i][0] for i in range(len(PRESSURE))]
+    for i, inf in enumerate(infos):
+        assert inf.status == 0, (i, inf.status)
+        assert inf.footprint_mb == probe[i][0].footprint_mb
+    # queueing happened: some request was admitted only after another retired
+    assert any(a.t_admit >= b.t_done for a in infos for b in infos if a is not b)
+    # and requests overlapped on the device
+    assert any(a.t_admit < b.t_done and b.t_admit < a.t_done for a in infos for b in infos if a is not b)
+    for i, ((dim, m, jit, order, k), (mesh, orc, g)) in enumerate(zip(PRESSURE, reqs)):
+        X = got[i][1]
+        assert np.all(orc.relres(orc.rhs(g), X) <= tol * 1.0001), i
+        A = femcg.Matrix(mesh, order, femcg.FEM_FORMAT_SELL)
+        B = torch.empty((A.n_free, k), dtype=torch.float64, device="cuda")
+        femcg.fem_rhs(A, g, B)
+        Xs = torch.zeros_like(B)
+        assert femcg.pcg_solve(A, B, Xs, tol, femcg.default_opts(tol=tol, precision=prec, check_every=ce)) == 0
+        torch.cuda.synchronize()
+        assert np.array_equal(Xs.cpu().numpy(), X), i
