@@ -33,28 +33,35 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "femoracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_OMP_PATH = os.path.join(_HERE, "liboracle_omp.so")
 _lib = None
+_omp = None
 
 ERRORS = {-1: "invalid argument", -2: "out of memory", -3: "invalid mesh (non-positive cell)",
           -4: "breakdown (p.Ap <= 0)"}
 
 
 def build(force: bool = True) -> str:
-    """Compile femoracle.c with gcc into liboracle.so (plain -O2, one thread)."""
-    if force or not os.path.exists(_LIB_PATH):
-        tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB_PATH)
+    """Compile femoracle.c with gcc into liboracle.so (plain -O2, one thread),
+    and the same source with -fopenmp into liboracle_omp.so, the all-core
+    timing build of the CPU baseline (independent columns on separate
+    threads; per-column arithmetic unchanged)."""
+    for path, extra in ((_LIB_PATH, []), (_OMP_PATH, ["-fopenmp"])):
+        if force or not os.path.exists(path):
+            tmp = path + ".tmp"
+            subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared"] + extra + ["-o", tmp, _SRC, "-lm"])
+            os.replace(tmp, path)
     return _LIB_PATH
 
 
-def _load():
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+def _load(omp: bool = False):
+    global _lib, _omp
+    if (_omp if omp else _lib) is not None:
+        return _omp if omp else _lib
+    path = _OMP_PATH if omp else _LIB_PATH
+    if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
         build(force=True)
-    lib = C.CDLL(_LIB_PATH)
+    lib = C.CDLL(path)
     P = C.c_void_p
     lib.orc_p1_element.argtypes = [C.c_int, P, P]
     lib.orc_p1_element_cot.argtypes = [C.c_int, P, P]
@@ -76,7 +83,11 @@ def _load():
     lib.orc_bicgstab_csr.argtypes = [C.c_int64, P, P, P, P, C.c_int, C.c_double, C.c_int64, P, P, P, P]
     lib.orc_fd7_identity_nnz.argtypes = [C.c_int64]
     lib.orc_fd7_identity_nnz.restype = C.c_int64
-    _lib = lib
+    lib.orc_threads.argtypes = [C.c_int]
+    if omp:
+        _omp = lib
+    else:
+        _lib = lib
     return lib
 
 
@@ -233,8 +244,12 @@ class System:
         return u
 
 
-def pcg_csr(rowptr, col, val, B, tol, max_iter=None):
-    """The oracle's Jacobi-PCG on a caller-given CSR matrix (for planted-defect tests)."""
+def pcg_csr(rowptr, col, val, B, tol, max_iter=None, threads=0):
+    """The oracle's Jacobi-PCG on a caller-given CSR matrix (planted-defect
+    tests).  threads > 0 runs the all-core build (the CPU baseline's timing
+    build): the k columns on that many threads, each with the same
+    arithmetic, so the results are identical.  Returns X, iterations,
+    relres, restarts, status."""
     rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
     col = np.ascontiguousarray(col, dtype=np.int32)
     val = np.ascontiguousarray(val, dtype=np.float64)
@@ -248,9 +263,17 @@ def pcg_csr(rowptr, col, val, B, tol, max_iter=None):
     its = np.zeros(k, dtype=np.int64)
     rel = np.zeros(k)
     rs = np.zeros(k, dtype=np.int32)
-    st = _load().orc_pcg_csr(n, _ptr(rowptr), _ptr(col), _ptr(val), _ptr(B), k, tol, max_iter,
-                             _ptr(X), _ptr(its), _ptr(rel), _ptr(rs))
+    lib = _load(omp=threads > 0)
+    if threads > 0:
+        lib.orc_threads(threads)
+    st = lib.orc_pcg_csr(n, _ptr(rowptr), _ptr(col), _ptr(val), _ptr(B), k, tol, max_iter,
+                         _ptr(X), _ptr(its), _ptr(rel), _ptr(rs))
     return X, its, rel, rs, st
+
+
+def omp_threads() -> int:
+    """Threads the all-core build runs on (OMP_NUM_THREADS or all host cores)."""
+    return int(_load(omp=True).orc_threads(0))
 
 
 def bj_apply(rowptr, col, val, bs, r):

@@ -44,6 +44,9 @@
  *
  * Every function returns 0 on success and a negative code on failure.
  */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <math.h>
 #include <stdint.h>
 #include <stdio.h>
@@ -899,86 +902,110 @@ int orc_relres(const orc_system *s, const double *B, const double *X, int k, dou
     return 0;
 }
 
-/* Jacobi-PCG, one column at a time (Sect. 2.1 with M = diag(A); exit test
- * Eq. (2)).  B, X are [nfree][k]; X is overwritten (zero initial guess).
+/* Jacobi-PCG for column j of B (Sect. 2.1 with M = diag(A); exit test
+ * Eq. (2)), zero initial guess; w holds 6 work vectors of n doubles.
  * iters[j] = number of products A p; relres[j] = true residual of Eq. (2);
  * restarts[j] = restarts after a drifted recursive residual.
- * Returns 0, or 1 if some column hit max_iter, or ORC_EBREAK on p.Ap <= 0. */
-static int pcg_csr(const csr_view *A, const double *B, int k, double tol, int64_t max_iter,
-                   double *X, int64_t *iters, double *relres, int32_t *restarts)
+ * Returns 0, or 1 if the column misses Eq. (2) (iteration cap or last
+ * restart), or ORC_EBREAK on p.Ap <= 0. */
+static int pcg_column(const csr_view *A, const double *B, int k, int j, double tol, int64_t max_iter,
+                      double *w, double *X, int64_t *iters, double *relres, int32_t *restarts)
 {
     int64_t n = A->n;
     int status = 0;
-    size_t bytes = sizeof(double) * (n ? n : 1);
-    double *b = malloc(bytes), *x = malloc(bytes), *r = malloc(bytes), *z = malloc(bytes);
-    double *p = malloc(bytes), *q = malloc(bytes);
-    if (!b || !x || !r || !z || !p || !q) {
-        free(b); free(x); free(r); free(z); free(p); free(q);
-        return ORC_ENOMEM;
+    size_t stride = (size_t)(n ? n : 1);
+    double *b = w, *x = w + stride, *r = w + 2 * stride, *z = w + 3 * stride;
+    double *p = w + 4 * stride, *q = w + 5 * stride;
+    for (int64_t i = 0; i < n; i++) b[i] = B[i * k + j];
+    double bnorm = sqrt(dot1(n, b, b));
+    int64_t its = 0;
+    int rs = 0;
+    for (int64_t i = 0; i < n; i++) x[i] = 0.0;
+    if (bnorm == 0.0) {
+        iters[j] = 0;
+        relres[j] = 0.0;
+        if (restarts) restarts[j] = 0;
+        for (int64_t i = 0; i < n; i++) X[i * k + j] = 0.0;
+        return 0;
     }
+    double rel = 0.0;
+    for (;;) {
+        /* (re)start from x: r = b - A x, z = D^-1 r, p = z */
+        spmv1(A, x, q);
+        for (int64_t i = 0; i < n; i++) r[i] = b[i] - q[i];
+        for (int64_t i = 0; i < n; i++) z[i] = r[i] / A->diag[i];
+        for (int64_t i = 0; i < n; i++) p[i] = z[i];
+        double rho = dot1(n, r, z);
+        double rnorm = sqrt(dot1(n, r, r));
+        while (rnorm > tol * bnorm && its < max_iter) {
+            spmv1(A, p, q);
+            double pq = dot1(n, p, q);
+            if (!(pq > 0.0) || !isfinite(pq)) {
+                status = ORC_EBREAK;
+                break;
+            }
+            double alpha = rho / pq;
+            for (int64_t i = 0; i < n; i++) x[i] += alpha * p[i];
+            for (int64_t i = 0; i < n; i++) r[i] -= alpha * q[i];
+            its++;
+            rnorm = sqrt(dot1(n, r, r));
+            if (rnorm <= tol * bnorm) break;
+            for (int64_t i = 0; i < n; i++) z[i] = r[i] / A->diag[i];
+            double rho_new = dot1(n, r, z);
+            double beta = rho_new / rho;
+            rho = rho_new;
+            for (int64_t i = 0; i < n; i++) p[i] = z[i] + beta * p[i];
+        }
+        /* true residual */
+        spmv1(A, x, q);
+        double rr = 0.0;
+        for (int64_t i = 0; i < n; i++) {
+            double t = b[i] - q[i];
+            rr += t * t;
+        }
+        rel = sqrt(rr) / bnorm;
+        if (status == ORC_EBREAK || rel <= tol || its >= max_iter || rs >= 3) break;
+        rs++;
+    }
+    /* Eq. (2) not met, either at the iteration cap or after the last
+     * allowed restart: a warning, not success */
+    if (rel > tol && status == 0) status = 1;
+    iters[j] = its;
+    relres[j] = rel;
+    if (restarts) restarts[j] = rs;
+    for (int64_t i = 0; i < n; i++) X[i * k + j] = x[i];
+    return status;
+}
+
+/* Jacobi-PCG on the k columns of B, [nfree][k] (X is overwritten, zero
+ * initial guess).  The columns are independent solves (Sect. 4.3: an
+ * iterative solver treats each right-hand side on its own).  The default
+ * build runs them one after another.  Built with -fopenmp (the CPU-baseline
+ * timing build only) the columns run on separate threads; each column's
+ * arithmetic is the same, so the results are identical.
+ * Returns ORC_EBREAK if any column broke down, else 1 if any column missed
+ * Eq. (2), else 0. */
+static int pcg_csr(const csr_view *A, const double *B, int k, double tol, int64_t max_iter,
+                   double *X, int64_t *iters, double *relres, int32_t *restarts)
+{
+    size_t stride = (size_t)(A->n ? A->n : 1);
+    int worst = 0, broke = 0, nomem = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) reduction(max : worst) reduction(| : broke, nomem)
+#endif
     for (int j = 0; j < k; j++) {
-        for (int64_t i = 0; i < n; i++) b[i] = B[i * k + j];
-        double bnorm = sqrt(dot1(n, b, b));
-        int64_t its = 0;
-        int rs = 0;
-        for (int64_t i = 0; i < n; i++) x[i] = 0.0;
-        if (bnorm == 0.0) {
-            iters[j] = 0;
-            relres[j] = 0.0;
-            if (restarts) restarts[j] = 0;
-            for (int64_t i = 0; i < n; i++) X[i * k + j] = 0.0;
+        double *w = malloc(sizeof(double) * 6 * stride);
+        if (!w) {
+            nomem = 1;
             continue;
         }
-        double rel = 0.0;
-        for (;;) {
-            /* (re)start from x: r = b - A x, z = D^-1 r, p = z */
-            spmv1(A, x, q);
-            for (int64_t i = 0; i < n; i++) r[i] = b[i] - q[i];
-            for (int64_t i = 0; i < n; i++) z[i] = r[i] / A->diag[i];
-            for (int64_t i = 0; i < n; i++) p[i] = z[i];
-            double rho = dot1(n, r, z);
-            double rnorm = sqrt(dot1(n, r, r));
-            while (rnorm > tol * bnorm && its < max_iter) {
-                spmv1(A, p, q);
-                double pq = dot1(n, p, q);
-                if (!(pq > 0.0) || !isfinite(pq)) {
-                    status = ORC_EBREAK;
-                    break;
-                }
-                double alpha = rho / pq;
-                for (int64_t i = 0; i < n; i++) x[i] += alpha * p[i];
-                for (int64_t i = 0; i < n; i++) r[i] -= alpha * q[i];
-                its++;
-                rnorm = sqrt(dot1(n, r, r));
-                if (rnorm <= tol * bnorm) break;
-                for (int64_t i = 0; i < n; i++) z[i] = r[i] / A->diag[i];
-                double rho_new = dot1(n, r, z);
-                double beta = rho_new / rho;
-                rho = rho_new;
-                for (int64_t i = 0; i < n; i++) p[i] = z[i] + beta * p[i];
-            }
-            /* true residual */
-            spmv1(A, x, q);
-            double rr = 0.0;
-            for (int64_t i = 0; i < n; i++) {
-                double t = b[i] - q[i];
-                rr += t * t;
-            }
-            rel = sqrt(rr) / bnorm;
-            if (status == ORC_EBREAK || rel <= tol || its >= max_iter || rs >= 3) break;
-            rs++;
-        }
-        /* Eq. (2) not met, either at the iteration cap or after the last
-         * allowed restart: a warning, not success */
-        if (rel > tol && status == 0) status = 1;
-        iters[j] = its;
-        relres[j] = rel;
-        if (restarts) restarts[j] = rs;
-        for (int64_t i = 0; i < n; i++) X[i * k + j] = x[i];
-        if (status == ORC_EBREAK) break;
+        int st = pcg_column(A, B, k, j, tol, max_iter, w, X, iters, relres, restarts);
+        free(w);
+        if (st == ORC_EBREAK) broke = 1;
+        else if (st > worst) worst = st;
     }
-    free(b); free(x); free(r); free(z); free(p); free(q);
-    return status;
+    if (nomem) return ORC_ENOMEM;
+    return broke ? ORC_EBREAK : worst;
 }
 
 int orc_pcg(const orc_system *s, const double *B, int k, double tol, int64_t max_iter,
@@ -986,6 +1013,19 @@ int orc_pcg(const orc_system *s, const double *B, int k, double tol, int64_t max
 {
     csr_view A = view_A(s);
     return pcg_csr(&A, B, k, tol, max_iter, X, iters, relres, restarts);
+}
+
+/* Threads that pcg_csr runs columns on: 1 in the default build; in the
+ * -fopenmp timing build, `want` (if positive) becomes the thread count. */
+int orc_threads(int want)
+{
+#ifdef _OPENMP
+    if (want > 0) omp_set_num_threads(want);
+    return omp_get_max_threads();
+#else
+    (void)want;
+    return 1;
+#endif
 }
 
 /* The same PCG on a caller-given CSR matrix (used by tests that plant a

@@ -119,3 +119,23 @@ def test_unreachable_tol_warns_after_the_last_restart():
     g = meshgen.harmonic_eval(meshgen.random_coeffs(2, 1, 5), coords)
     X, its, rel, rs, st = s.pcg(s.rhs(g), 1e-17)
     assert st == 1 and rs[0] == 3 and rel[0] > 1e-17 and its[0] < oracle.default_max_iter(s.nfree)
+
+
+def test_all_core_build_gives_the_serial_results():
+    # the CPU baseline's all-core build runs the columns on separate threads;
+    # each column keeps its arithmetic, so X, iterations and residuals equal
+    # the one-thread oracle's bit for bit, a zero column included
+    mesh = meshgen.make_mesh(3, 9, 0.2, 21)
+    s = oracle.System(mesh, 1)
+    coords, _, _ = s.dofs()
+    g = meshgen.harmonic_eval(meshgen.random_coeffs(3, 7, 22), coords)
+    B = s.rhs(g)
+    B[:, 3] = 0.0
+    rp, col, val = s.A()
+    ref = oracle.pcg_csr(rp, col, val, B, 1e-10)
+    got = oracle.pcg_csr(rp, col, val, B, 1e-10, threads=4)
+    assert ref[4] == got[4] == 0
+    for a, b in zip(ref[:4], got[:4]):
+        assert np.array_equal(a, b)
+    assert ref[1][3] == 0 and np.all(ref[0][:, 3] == 0.0)
+    assert oracle.omp_threads() >= 1
