@@ -132,6 +132,10 @@ __device__ __forceinline__ void for_each_tile(int64_t T, F &&f)
 // reductions (fixed order everywhere)
 // ---------------------------------------------------------------------------
 
+// The cross-wave sums of write_tile_partials, write_tile_partials_vec and
+// reduce_partials add exactly four per-wave values in a fixed order.
+static_assert(kBlock / kWave == 4, "the fixed-order cross-wave sums assume four waves per block");
+
 // Lanes l and l' serve the same column iff l = l' (mod kp); sum them.
 __device__ __forceinline__ double wave_reduce_cols(double v, int kp)
 {
