@@ -221,6 +221,24 @@ int fem_rhs(const fem_matrix *A, const double *g_all, int32_t k, double *B, void
  * X, Y: device [n_free][k] FP64, public order.  Enqueued on stream. */
 int fem_spmv(fem_matrix *A, const double *X, double *Y, int32_t k, void *stream);
 
+/* fem_spmv without any allocation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, layout and result as fem_spmv (the same
+ * kernels and tiling: Y is identical bit for bit).  Every buffer beyond X and
+ * Y (launch table, state, per-tile partials, the permuted copies of X and Y)
+ * lives in one fixed device array of FEMCG_NOALLOC_SCRATCH_BYTES per device,
+ * which each device that runs it holds until the process ends.  Fully
+ * asynchronous on stream: the call enqueues four kernels and returns, with no
+ * host copy and no synchronisation.  All calls on one device share that
+ * array, so calls that overlap on one device (other streams, other threads)
+ * race: serialise them, e.g. on one stream.  A must have a device copy.
+ * Returns 0, FEMCG_EINVAL (NULL argument, host-only matrix, or a product
+ * needing more scratch than the limit: about n_free * pad(k) <= 4M, pad(k)
+ * = k rounded up to a power of two), FEMCG_EUNSUPPORTED (k outside
+ * 1..FEMCG_MAX_K), FEMCG_EDEVICE. */
+#define FEMCG_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int fem_spmv_noalloc(fem_matrix *A, const double *X, double *Y, int32_t k, void *stream);
+
 /* Solve A X = B column by column with Jacobi-preconditioned CG (Sect. 2.1's
  * preconditioned system with M = diag(A)), stopping each column when Eq. (2)
  * holds for its recursive residual and then confirming it with the true FP64

@@ -13,7 +13,8 @@ LIB = os.path.join(HERE, "libfemcg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "gpu_assemble.hip", "bicgstab.hip", "femcg.cpp", "assemble.cpp", "serve.cpp"]
+SOURCES = ["kernels.hip", "gpu_assemble.hip", "bicgstab.hip", "noalloc.hip", "femcg.cpp", "assemble.cpp",
+           "serve.cpp"]
 
 # Packed FP32 instructions are disabled for every device pass.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

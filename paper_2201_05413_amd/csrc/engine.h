@@ -173,6 +173,16 @@ int upload_solver_copy(fem_matrix *A);
 int upload_lifting(fem_matrix *A);
 int get_work(fem_matrix *A, int kp, int prec, Work **out);
 size_t work_bytes_estimate(int64_t n, int kp, int prec, int ntiles);
+// fem_spmv's tiling and SpMM descriptor without its workspace, for the
+// allocation-free product (noalloc.hip), which places the buffers itself:
+// spmv_plan fills kp, n, lpr, tile_rows, ntiles, ngroups and band of w (no
+// buffer); spmv_desc describes the product on caller-placed buffers; the
+// launch uses spmv_grid blocks and the class mask spmv_launch_mask.
+void spmv_plan(const fem_matrix *A, int kp, Work &w);
+SysDesc spmv_desc(const fem_matrix *A, const Work &w, int k, double *P, double *Q, double *part, double *gpart,
+                  uint32_t *gticket, SysState *st);
+int spmv_grid(const fem_matrix *A, const Work &w);
+unsigned spmv_launch_mask(const Work &w);
 size_t matrix_bytes_estimate(const SolverCopy &sc, const HostSystem &hs);
 int engine_create(int prec, int max_slots, int m, bool use_graph, std::unique_ptr<Engine> &out);
 int engine_admit(Engine *e, int s);

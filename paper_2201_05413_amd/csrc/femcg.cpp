@@ -884,6 +884,38 @@ int upload_lifting(fem_matrix *A)
     return FEMCG_OK;
 }
 
+void spmv_plan(const fem_matrix *A, int kp, Work &w)
+{
+    w.kp = kp;
+    w.prec = PCG_FP64;
+    w.n = A->dev.n;
+    w.lpr = choose_lpr(A, kp);
+    choose_tiles(A, kp, w.lpr, w.tile_rows, w.ntiles, w.band);
+    w.ngroups = (w.ntiles + kGroup - 1) / kGroup;
+}
+
+SysDesc spmv_desc(const fem_matrix *A, const Work &w, int k, double *P, double *Q, double *part, double *gpart,
+                  uint32_t *gticket, SysState *st)
+{
+    SysDesc D = make_desc_base(A, &w, false, nullptr, nullptr, nullptr, P, Q, part, st, k);
+    D.band = w.band;
+    D.lpr = w.lpr;
+    D.gpart = gpart;
+    D.gticket = gticket;
+    D.tile_base = 0;
+    return D;
+}
+
+int spmv_grid(const fem_matrix *A, const Work &w)
+{
+    return grid_for(w.ntiles, grid_cap(A, &w));
+}
+
+unsigned spmv_launch_mask(const Work &w)
+{
+    return launch_bit(w.kp, w.lpr);
+}
+
 }  // namespace femcg
 
 using namespace femcg;

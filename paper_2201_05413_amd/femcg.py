@@ -36,7 +36,8 @@ FEM_ASSEMBLE_HOST_ONLY = 0x200
 PCG_FP64 = 0
 PCG_MIXED = 1
 
-EXPORTS = ["pcg_default_opts", "fem_assemble", "fem_dofs", "fem_csr", "fem_rhs", "fem_spmv", "pcg_solve",
+EXPORTS = ["pcg_default_opts", "fem_assemble", "fem_dofs", "fem_csr", "fem_rhs", "fem_spmv", "fem_spmv_noalloc",
+           "pcg_solve",
            "pcg_solve_batch", "pcg_stats", "fem_tune", "fem_set_format", "fem_set_tiling", "pcg_time_kernel", "pcg_time_spmm_cold", "bicgstab_solve",
            "fem_free",
            "fem_last_error", "serve_create", "serve_submit", "serve_step", "serve_poll", "serve_clock",
@@ -111,6 +112,7 @@ def lib():
         "fem_csr": (C.c_int, [P, C.POINTER(I64), P, P, P]),
         "fem_rhs": (C.c_int, [P, P, I32, P, P]),
         "fem_spmv": (C.c_int, [P, P, P, I32, P]),
+        "fem_spmv_noalloc": (C.c_int, [P, P, P, I32, P]),
         "pcg_solve": (C.c_int, [P, P, P, I32, D, C.POINTER(pcg_opts), P]),
         "pcg_solve_batch": (C.c_int, [I32, P, P, P, P, P, C.POINTER(pcg_opts), P, P]),
         "pcg_stats": (C.c_int, [P, C.POINTER(pcg_stats_t)]),
@@ -245,6 +247,19 @@ def fem_spmv(A, X, Y, stream=None):
     k = X.shape[1]
     _check(lib().fem_spmv(A.h, _dev_ptr(X), _dev_ptr(Y), k, _stream(stream)))
     return Y
+
+
+def fem_spmv_noalloc(A, X, Y, stream=None):
+    """fem_spmv without allocation (the library's fixed scratch array);
+    asynchronous on the stream."""
+    k = X.shape[1]
+    if X.shape != (A.n_free, k) or Y.shape != X.shape:
+        raise ValueError("X and Y must be [n_free][k]")
+    _check(lib().fem_spmv_noalloc(A.h, _dev_ptr(X), _dev_ptr(Y), k, _stream(stream)))
+    return Y
+
+
+FEMCG_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def pcg_solve(A, B, X, tol, opts=None, stream=None):
