@@ -174,10 +174,16 @@ def run_single(args):
     femcg.fem_rhs(A, g, B)
     t0 = time.time()
     order = 0
+    tune = None
+    eta = args.eta
     if args.format == "auto":
-        fmt, cw, sg = femcg.fem_tune(A, k, femcg.PCG_FP64)
-        order = fmt & femcg.FEM_ORDER_SFC
-        fmt &= ~femcg.FEM_ORDER_SFC
+        # the whole solve tuned on this workload's B: format and row order,
+        # lanes per row, tiling, precision and inner tolerance
+        _, tune = femcg.pcg_tune(A, B, w.tol, femcg.default_opts(tol=w.tol, check_every=args.check_every))
+        fmt, cw, sg = tune["format"], tune["C"], tune["sigma"]
+        order = femcg.FEM_ORDER_SFC if tune["sfc"] else 0
+        if tune["inner_eta"] > 0:
+            eta = tune["inner_eta"]
     else:
         parts = args.format.split(":")
         fmt = femcg.FEM_FORMAT_CSR if parts[0] == "csr" else femcg.FEM_FORMAT_SELL
@@ -192,7 +198,7 @@ def run_single(args):
                                                                                "sfc" if order else "natural"))
     o64 = femcg.default_opts(tol=w.tol, precision=femcg.PCG_FP64, check_every=args.check_every)
     omx = femcg.default_opts(tol=w.tol, precision=femcg.PCG_MIXED, check_every=args.check_every,
-                             inner_eta=args.eta)
+                             inner_eta=eta)
     stream = torch.cuda.current_stream()
 
     def step():
@@ -287,6 +293,8 @@ def run_single(args):
             femcg.fem_set_format(Ac, fmt | order, cw, sg)
             if args.band is not None:
                 femcg.fem_set_tiling(Ac, args.band, args.tile)
+            elif tune is not None and tune["band"] in (0, 1):
+                femcg.fem_set_tiling(Ac, tune["band"], tune["tile"])
             mats.append(Ac)
         ms_c, by_c = femcg.pcg_time_spmm_cold(mats, k, femcg.PCG_FP64, reps=5)
         cold = {"copies": ncopy, "aggregate_mb": round(ncopy * by_c / 1e6, 1), "ms": round(ms_c, 5),
@@ -331,7 +339,13 @@ def run_single(args):
         },
         "time_to_tol_ms": {"fp64_p50": round(1e3 * percentile(lat64, 50), 3),
                            "mixed_p50": round(1e3 * percentile(latmx, 50), 3),
-                           "mixed_over_fp64": round(percentile(latmx, 50) / percentile(lat64, 50), 3)},
+                           "mixed_over_fp64": round(percentile(latmx, 50) / percentile(lat64, 50), 3),
+                           "mixed_inner_eta": eta,
+                           "tuned_choice": None if tune is None else ("fp64" if tune["fp64_fallback"] else "mixed"),
+                           "tuned_p50": round(1e3 * min(percentile(lat64, 50), percentile(latmx, 50))
+                                              if tune is None or not tune["fp64_fallback"]
+                                              else 1e3 * percentile(lat64, 50), 3)},
+        "tuner": tune,
         "latency_ms": {"fp64_p50": round(1e3 * percentile(lat64, 50), 3),
                        "fp64_p99": round(1e3 * percentile(lat64, 99), 3),
                        "mixed_p50": round(1e3 * percentile(latmx, 50), 3),
@@ -399,9 +413,18 @@ def run_serve(args):
     prec = femcg.PCG_MIXED if args.serve_mixed else femcg.PCG_FP64
     L = femcg.lib()
     meshes = [femcg.make_mesh_struct(w.mesh) for w in wls]
+    # free-DOF maps from the library's host-only assembly (no device memory)
+    f2ds = []
+    for w in wls:
+        H = femcg.Matrix(w.mesh, w.order, femcg.FEM_FORMAT_CSR | femcg.FEM_ASSEMBLE_HOST_ONLY)
+        f2ds.append(H.dofs()[2])
+        H.free()
+    nfree = [len(f) for f in f2ds]
+    xs = {}
 
-    def serve(t_arr):
-        """Replay arrival times t_arr (seconds) through a fresh server."""
+    def serve(t_arr, keep_x=False):
+        """Replay arrival times t_arr (seconds) through a fresh server; with
+        keep_x, return every served solution as well."""
         srv = C.c_void_p()
         femcg._check(L.serve_create(args.budget_gb * 1e9, args.slots, prec, args.check_every, C.byref(srv)))
         ids, done = {}, {}
@@ -420,10 +443,14 @@ def run_serve(args):
             femcg._check(open_)
             for rid in list(ids):
                 info = femcg.fem_request_info()
-                if L.serve_poll(srv, rid, None, C.byref(info)) == 1:
-                    i = ids.pop(rid)
+                i = ids[rid]
+                X = np.zeros((nfree[i], wls[i].k)) if keep_x else None
+                if L.serve_poll(srv, rid, femcg._np_ptr(X) if keep_x else None, C.byref(info)) == 1:
+                    ids.pop(rid)
                     done[i] = dict(status=info.status, t_arr=t_arr[i], t_ready=info.t_ready - t_start,
                                    t_done=info.t_done - t_start, relres=info.relres_max)
+                    if keep_x:
+                        xs[i] = X
             if open_ == 0 and nxt < len(wls):
                 time.sleep(max(0.0, min(0.01, t_arr[nxt] - (L.serve_clock(srv) - t_start))))
         L.serve_destroy(srv)
@@ -437,7 +464,7 @@ def run_serve(args):
                     p99_excl_assembly_ms=round(1e3 * percentile(lat_s, 99), 2), failed_or_above_tol=bad)
 
     base = np.array([r["t_arrival"] for r in reqs])
-    cap = serve(np.zeros(len(wls)))
+    cap = serve(np.zeros(len(wls)), keep_x=True)
     capacity = cap["solves_per_s"]
     log("capacity (all submitted at t=0): %.3f solves/s in %.2f s" % (capacity, cap["wall_s"]))
     sweep = []
@@ -451,7 +478,7 @@ def run_serve(args):
     ref = min(args.serve_fractions, key=lambda f: abs(f - 0.7))
     t_ref = base / (ref * capacity)
     # one-at-a-time FP64 PCG on the same trace
-    t_free, lat1 = 0.0, []
+    t_free, lat1, diff_fp64 = 0.0, [], []
     for i, w in enumerate(wls):
         ta = time.perf_counter()
         A = femcg.Matrix(w.mesh, w.order)
@@ -464,7 +491,29 @@ def run_serve(args):
         start = max(t_ref[i], t_free)
         t_free = start + dur
         lat1.append(t_free - t_ref[i])
+        x1 = X.cpu().numpy()
+        diff_fp64.append(float(np.linalg.norm(xs[i] - x1) / max(np.linalg.norm(x1), 1e-300)))
         del A, B, X
+    # accuracy of the served solutions (capacity run):
+    # (R) the oracle's Eq. (2) residual on a seeded random sample of the
+    #     requests the oracle assembles in seconds (n_free <= 1.5M);
+    # Eq. (1) error against the exact discrete solution where it is known
+    #     (structured P1: the nodal values of the harmonic cubic data)
+    import oracle
+    rng = np.random.default_rng(7)
+    eligible = [i for i in range(len(wls)) if nfree[i] <= 1500000]
+    sample = sorted(rng.choice(eligible, size=min(args.serve_oracle_sample, len(eligible)), replace=False).tolist())
+    t0 = time.time()
+    rel_sample = []
+    for i in sample:
+        orc = oracle.System(wls[i].mesh, wls[i].order)
+        rel_sample.append(float(orc.relres(orc.rhs(gs[i]), xs[i]).max()))
+        del orc
+    log("oracle residual of %d sampled served solutions in %.1f s: max %.3e"
+        % (len(sample), time.time() - t0, max(rel_sample) if rel_sample else float("nan")))
+    exact = [i for i in range(len(wls)) if wls[i].order == 1 and reqs[i]["jitter"] == 0.0]
+    xerr = [max(float(np.linalg.norm(gs[i][f2ds[i], j] - xs[i][:, j]) / np.linalg.norm(gs[i][f2ds[i], j]))
+                for j in range(wls[i].k)) for i in exact]
     main = [r for r in sweep if r["fraction"] == ref][0]
     line = {
         "metric": METRIC, "value": capacity, "unit": "solves/s", "n_gpus": 1,
@@ -482,6 +531,18 @@ def run_serve(args):
         "one_at_a_time_fp64": {"rate_per_s": main["rate_per_s"], "solves_per_s": round(len(wls) / t_free, 3),
                                "p50_ms": round(1e3 * percentile(lat1, 50), 2),
                                "p99_ms": round(1e3 * percentile(lat1, 99), 2)},
+        "accuracy": {
+            "oracle_relres": {"sample": len(sample), "of_eligible": len(eligible),
+                              "rule": "seeded random sample (numpy default_rng(7)) of the requests with "
+                                      "n_free <= 1.5M; the oracle's own Eq. (2) residual of the served X",
+                              "max": max(rel_sample) if rel_sample else None,
+                              "all_within_tol": all(r <= 1.0001e-8 for r in rel_sample)},
+            "x_err_vs_exact": {"requests": len(exact),
+                               "rule": "structured P1 requests, whose exact discrete solution is the nodal "
+                                       "harmonic data; Eq. (1), worst column per request",
+                               "p50": percentile(xerr, 50) if xerr else None, "max": max(xerr) if xerr else None},
+            "served_vs_one_at_a_time_fp64_rel_l2": {"p50": percentile(diff_fp64, 50), "max": max(diff_fp64)},
+        },
     }
     print(json.dumps(line), flush=True)
 
@@ -885,7 +946,9 @@ def main():
     ap.add_argument("--profile", type=int, default=0,
                     help="counter runs: FP64 solve capped at this many iterations, kernels timed, no JSON line")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--n-requests", type=int, default=40)
+    ap.add_argument("--n-requests", type=int, default=200)
+    ap.add_argument("--serve-oracle-sample", type=int, default=40,
+                    help="c5: served solutions checked by the oracle's residual (seeded random sample)")
     ap.add_argument("--asm-p2-sides", type=int, nargs="*", default=[48, 96],
                     help="assembly timing: sides of the extra 3D P2 meshes")
     ap.add_argument("--asm-oracle-max-n", type=int, default=3000000,

@@ -274,6 +274,37 @@ int pcg_stats(const fem_matrix *A, pcg_stats_t *out);
 int fem_tune(fem_matrix *A, int32_t k, int32_t precision, int32_t *C_out, int32_t *sigma_out,
              void *stream);
 
+/* What pcg_tune chose, and the times it compared. */
+typedef struct {
+    int32_t format, C, sigma, sfc; /* solver copy: FEM_FORMAT_CSR/SELL, slice height, sigma, Morton order */
+    int32_t lpr;                   /* SpMM lanes per row at one column (1, 2, 4 or 8) */
+    int32_t band;                  /* tiling mode: 0 tiles, 1 band, 2 single-workgroup loop */
+    int32_t tile;                  /* fem_set_tiling's tile argument chosen (0 for band 2) */
+    int32_t ntiles;                /* tiles per vector in that mode */
+    int32_t precision;             /* PCG_FP64 or PCG_MIXED: the faster to tol */
+    int32_t fp64_fallback;         /* 1: no mixed solve beat FP64 (or none reached tol) */
+    double inner_eta;              /* fastest mixed inner tolerance (0: none reached tol) */
+    double fp64_ms, mixed_ms;      /* time to tol: FP64, and the fastest mixed solve */
+} pcg_tune_report;
+
+/* Autotune the whole solve of k right-hand sides B (device [n_free][k],
+ * public order) to tol (Eq. (2)), for later solves of the same kind:
+ *  1. the solver-copy format and row order, as fem_tune (SpMM time);
+ *  2. at k = 1, the SpMM lanes per row (1, 2, 4, 8; SpMM time);
+ *  3. the tile size of the phase kernels in the automatic tiling mode: the
+ *     default, half and double (time of 128 capped FP64 iterations);
+ *  4. the precision and the mixed inner tolerance: one FP64 solve and
+ *     mixed solves with inner_eta in {1e-2, 1e-3, 1e-4, 1e-5}, each to tol,
+ *     timed from call to result.
+ * The matrix keeps the chosen format, tiling and lanes per row; opts (in:
+ * the caller's options; out: precision and inner_eta set to the fastest
+ * solve, FP64 when no mixed solve is faster) and report are filled.  Runs
+ * solves on stream and synchronises; allocates a temporary X.  Returns 0,
+ * FEMCG_EINVAL (arguments, or the FP64 solve misses tol), or the errors of
+ * fem_tune and pcg_solve. */
+int pcg_tune(fem_matrix *A, const double *B, int32_t k, double tol, pcg_opts *opts, pcg_tune_report *report,
+             void *stream);
+
 /* Rebuild the solver copy in an explicit format (SELL: slice height C in
  * {8,16,32,64}, sorting window sigma >= 1).  format may carry FEM_ORDER_SFC:
  * the internal row order then follows a Morton curve through the DOF

@@ -87,6 +87,7 @@ struct fem_matrix {
     int tile_target = 0;  // 0 = automatic
     int band_mode = -1;   // -1 automatic; 0 tile, 1 band, 2 single-workgroup loop forced
     int band_tile_bytes = 0;  // 0 = automatic
+    int lpr_force = 0;        // SpMM lanes per row at kp = 1 (pcg_tune); 0 = from the mean row length
     int max_grid = 2048;
     bool device_assembled = false;
     bool host_only = false;   // FEM_ASSEMBLE_HOST_ONLY: no device copy

@@ -147,6 +147,7 @@ static int choose_lpr(const fem_matrix *A, int kp)
     if (kp != 1) return 1;
     const double mean = A->sc.n ? (double)A->sc.nnz / (double)A->sc.n : 0.0;
     int lpr = mean >= 32.0 ? 8 : (mean >= 14.0 ? 4 : (mean >= 8.0 ? 2 : 1));
+    if (A->lpr_force > 0) lpr = A->lpr_force;                       // pcg_tune's choice
     if (const char *ev = std::getenv("FEMCG_LPR")) lpr = atoi(ev);  // tuning override
     return (lpr == 2 || lpr == 4 || lpr == 8) ? lpr : 1;
 }
@@ -1399,6 +1400,147 @@ static int fem_tune_impl(fem_matrix *A, int32_t k, int32_t precision, int32_t *C
     return bc.format;
 }
 
+static int fem_set_tiling_impl(fem_matrix *A, int32_t band, int32_t tile);
+
+// Wall time of one pcg_solve on the caller's stream, from zero (X is
+// overwritten); status of the solve in *status.
+static int timed_solve(fem_matrix *A, const double *B, double *X, int k, const pcg_opts &o, hipStream_t s,
+                       double *ms, int *status)
+{
+    HIPCHK(hipStreamSynchronize(s));
+    const double t0 = now_s();
+    *status = pcg_solve_impl(A, B, X, k, o.tol, &o, s);
+    *ms = 1e3 * (now_s() - t0);
+    return *status < 0 ? *status : FEMCG_OK;
+}
+
+static int pcg_tune_impl(fem_matrix *A, const double *B, int32_t k, double tol, pcg_opts *opts, pcg_tune_report *rep,
+                         void *stream)
+{
+    g_err.clear();
+    if (!A || !B || !opts || !rep) return fail(FEMCG_EINVAL, "NULL argument");
+    if (int rc = require_device(A)) return rc;
+    if (k < 1 || k > kMaxK) return fail(FEMCG_EUNSUPPORTED, "k=%d outside 1..%d", k, kMaxK);
+    if (!(tol > 0.0)) return fail(FEMCG_EINVAL, "tol must be > 0");
+    hipStream_t s = (hipStream_t)stream;
+    pcg_tune_report R{};
+    const int kp = pad_k(k);
+    // 1. solver-copy format and row order (SpMM time)
+    int32_t C = 0, sigma = 0;
+    const int fmt = fem_tune_impl(A, k, PCG_FP64, &C, &sigma, stream);
+    if (fmt < 0) return fmt;
+    R.format = fmt & ~FEM_ORDER_SFC;
+    R.sfc = (fmt & FEM_ORDER_SFC) ? 1 : 0;
+    R.C = C;
+    R.sigma = sigma;
+    // 2. lanes per row of the one-column SpMM (SpMM time)
+    A->lpr_force = 0;
+    if (kp == 1) {
+        float best = 1e30f;
+        int bl = 1;
+        for (int lpr : {1, 2, 4, 8}) {
+            A->lpr_force = lpr;
+            A->works.clear();
+            A->engines.clear();
+            SpmmProbe pr;
+            int rc = pr.init(A, k, PCG_FP64, s);
+            if (rc) return rc;
+            pr.launch(s);
+            pr.launch(s);
+            float t = 0;
+            if ((rc = time_launches(s, 10, [&]() { pr.launch(s); }, &t))) return rc;
+            if (t < best) {
+                best = t;
+                bl = lpr;
+            }
+        }
+        A->lpr_force = bl;
+        A->works.clear();
+        A->engines.clear();
+    }
+    R.lpr = choose_lpr(A, kp);
+    double *X = nullptr;
+    const size_t xbytes = sizeof(double) * (size_t)std::max<int64_t>(A->dev.n, 1) * k;
+    if (hipMalloc((void **)&X, xbytes) != hipSuccess)
+        return fail(FEMCG_ENOMEM, "tuner solution buffer of %zu bytes", xbytes);
+    struct FreeOnExit {
+        double *p;
+        ~FreeOnExit() { (void)hipFree(p); }
+    } free_x{X};
+    pcg_opts o = *opts;
+    o.tol = tol;
+    o.use_x0 = 0;
+    const int warm_iters = std::max(1, o.check_every > 0 ? o.check_every : 32);
+    int rc, st;
+    double ms;
+    // 3. tiling of the phase kernels: the automatic tile, half and double,
+    //    timed on capped FP64 solves, each after a warm-up solve that pays
+    //    its graph capture
+    Work *w;
+    if ((rc = get_work(A, kp, PCG_FP64, &w))) return rc;
+    R.band = w->small ? 2 : w->band;
+    if (!w->small) {
+        const int band = w->band;
+        const int auto_tile = band ? w->tile_rows * kp * 8 : w->ntiles;
+        std::vector<int> cands = {auto_tile};
+        for (int t : {auto_tile / 2, auto_tile * 2})
+            if (band ? (t >= 4096 && t <= 262144) : (t >= 64 && t <= 16384)) cands.push_back(t);
+        pcg_opts oc = o;
+        oc.precision = PCG_FP64;
+        double best = 1e30;
+        int bt = auto_tile;
+        for (int t : cands) {
+            if ((rc = fem_set_tiling_impl(A, band, t))) return rc;
+            oc.max_iter = warm_iters;
+            if ((rc = timed_solve(A, B, X, k, oc, s, &ms, &st))) return rc;
+            oc.max_iter = 128;
+            if ((rc = timed_solve(A, B, X, k, oc, s, &ms, &st))) return rc;
+            if (ms < best) {
+                best = ms;
+                bt = t;
+            }
+        }
+        if ((rc = fem_set_tiling_impl(A, band, bt))) return rc;
+        R.tile = bt;
+        if ((rc = get_work(A, kp, PCG_FP64, &w))) return rc;
+    }
+    R.ntiles = w->ntiles;
+    // 4. precision and inner tolerance: full solves to tol, after a short
+    //    warm-up solve of each precision (graph capture is not timed)
+    pcg_opts o64 = o, omx = o;
+    o64.precision = PCG_FP64;
+    omx.precision = PCG_MIXED;
+    {
+        pcg_opts wu = o64;
+        wu.max_iter = warm_iters;
+        if ((rc = timed_solve(A, B, X, k, wu, s, &ms, &st))) return rc;
+        wu.precision = PCG_MIXED;
+        wu.max_outer = 1;
+        if ((rc = timed_solve(A, B, X, k, wu, s, &ms, &st))) return rc;
+    }
+    if ((rc = timed_solve(A, B, X, k, o64, s, &R.fp64_ms, &st))) return rc;
+    if (st != FEMCG_OK) return fail(FEMCG_EINVAL, "FP64 solve did not reach tol (status %d)", st);
+    R.mixed_ms = 0.0;
+    for (double eta : {1e-2, 1e-3, 1e-4, 1e-5}) {
+        omx.inner_eta = eta;
+        // a mixed solve that fails or misses tol is not a candidate
+        if (timed_solve(A, B, X, k, omx, s, &ms, &st) == FEMCG_OK && st == FEMCG_OK &&
+            (R.inner_eta == 0.0 || ms < R.mixed_ms)) {
+            R.mixed_ms = ms;
+            R.inner_eta = eta;
+        }
+    }
+    g_err.clear();
+    const bool mixed_wins = R.inner_eta > 0.0 && R.mixed_ms < R.fp64_ms;
+    R.fp64_fallback = mixed_wins ? 0 : 1;
+    R.precision = mixed_wins ? PCG_MIXED : PCG_FP64;
+    *opts = o;
+    opts->precision = R.precision;
+    if (R.inner_eta > 0.0) opts->inner_eta = R.inner_eta;
+    *rep = R;
+    return FEMCG_OK;
+}
+
 static int fem_set_tiling_impl(fem_matrix *A, int32_t band, int32_t tile)
 {
     if (!A || band < -1 || band > 2 || tile < 0) return fail(FEMCG_EINVAL, "bad tiling arguments");
@@ -1596,6 +1738,18 @@ int fem_tune(fem_matrix *A, int32_t k, int32_t precision, int32_t *C_out, int32_
         return fail(FEMCG_ENOMEM, "fem_tune: host allocation failed");
     } catch (const std::exception &ex) {
         return fail(FEMCG_EDEVICE, "fem_tune: %s", ex.what());
+    }
+}
+
+int pcg_tune(fem_matrix *A, const double *B, int32_t k, double tol, pcg_opts *opts, pcg_tune_report *report,
+             void *stream)
+{
+    try {
+        return pcg_tune_impl(A, B, k, tol, opts, report, stream);
+    } catch (const std::bad_alloc &) {
+        return fail(FEMCG_ENOMEM, "pcg_tune: host allocation failed");
+    } catch (const std::exception &ex) {
+        return fail(FEMCG_EDEVICE, "pcg_tune: %s", ex.what());
     }
 }
 

@@ -38,7 +38,7 @@ PCG_MIXED = 1
 
 EXPORTS = ["pcg_default_opts", "fem_assemble", "fem_dofs", "fem_csr", "fem_rhs", "fem_spmv", "fem_spmv_noalloc",
            "pcg_solve",
-           "pcg_solve_batch", "pcg_stats", "fem_tune", "fem_set_format", "fem_set_tiling", "pcg_time_kernel", "pcg_time_spmm_cold", "bicgstab_solve",
+           "pcg_solve_batch", "pcg_stats", "fem_tune", "pcg_tune", "fem_set_format", "fem_set_tiling", "pcg_time_kernel", "pcg_time_spmm_cold", "bicgstab_solve",
            "fem_free",
            "fem_last_error", "serve_create", "serve_submit", "serve_step", "serve_poll", "serve_clock",
            "serve_destroy"]
@@ -59,6 +59,16 @@ class pcg_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int64), ("precision", C.c_int32),
                 ("inner_eta", C.c_double), ("check_every", C.c_int32), ("use_x0", C.c_int32),
                 ("max_restarts", C.c_int32), ("max_outer", C.c_int32), ("use_graph", C.c_int32)]
+
+
+class pcg_tune_report(C.Structure):
+    _fields_ = [("format", C.c_int32), ("C", C.c_int32), ("sigma", C.c_int32), ("sfc", C.c_int32),
+                ("lpr", C.c_int32), ("band", C.c_int32), ("tile", C.c_int32), ("ntiles", C.c_int32),
+                ("precision", C.c_int32), ("fp64_fallback", C.c_int32), ("inner_eta", C.c_double),
+                ("fp64_ms", C.c_double), ("mixed_ms", C.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class pcg_stats_t(C.Structure):
@@ -117,6 +127,7 @@ def lib():
         "pcg_solve_batch": (C.c_int, [I32, P, P, P, P, P, C.POINTER(pcg_opts), P, P]),
         "pcg_stats": (C.c_int, [P, C.POINTER(pcg_stats_t)]),
         "fem_tune": (C.c_int, [P, I32, I32, C.POINTER(I32), C.POINTER(I32), P]),
+        "pcg_tune": (C.c_int, [P, P, I32, D, C.POINTER(pcg_opts), C.POINTER(pcg_tune_report), P]),
         "fem_set_format": (C.c_int, [P, I32, I32, I32]),
         "fem_set_tiling": (C.c_int, [P, I32, I32]),
         "pcg_time_kernel": (C.c_int, [P, I32, I32, P, C.POINTER(D), C.POINTER(D)]),
@@ -317,6 +328,18 @@ def fem_tune(A, k, precision=PCG_FP64, stream=None):
     cw, sg = C.c_int32(), C.c_int32()
     f = _check(lib().fem_tune(A.h, k, precision, C.byref(cw), C.byref(sg), _stream(stream)))
     return f, cw.value, sg.value
+
+
+def pcg_tune(A, B, tol, opts=None, stream=None):
+    """Autotune format, lanes per row, tiling, precision and inner_eta on the
+    solve of B to tol; returns (tuned pcg_opts, report dict)."""
+    k = B.shape[1]
+    if B.shape[0] != A.n_free:
+        raise ValueError("B must be [n_free][k]")
+    o = opts if opts is not None else default_opts(tol=tol)
+    rep = pcg_tune_report()
+    _check(lib().pcg_tune(A.h, _dev_ptr(B), k, tol, C.byref(o), C.byref(rep), _stream(stream)))
+    return o, rep.as_dict()
 
 
 def pcg_time_spmm_cold(mats, k, precision=PCG_FP64, reps=5, stream=None):
