@@ -196,6 +196,60 @@ typedef struct {
 int bicgstab_solve(fem_matrix *A, const double *B, double *X, double tol, int32_t block_size,
                    const double *row_scale, int64_t max_iter, void *stream, bicgstab_stats_t *stats);
 
+/* ---- direct solver: sparse Cholesky of A = K_II (Sect. 4.3) ----
+ * Sect. 4.3 sets an iterative solver's time for t right-hand sides,
+ * T_IS_PC + t T_IS_SOLVE, against a direct solver's T_FACT + t T_SOLVE: the
+ * matrix is factorised once and each right-hand side costs a forward and a
+ * backward triangular solve (one at a time or as the block of Eq. (3)).
+ * A is symmetric positive definite, so the factorisation is Cholesky,
+ * A(perm, perm) = L L^T, by the multifrontal method on a nested-dissection
+ * order computed from the DOF coordinates (Sect. 3.1: the direct solvers
+ * reorder the matrix to limit the fill-in before factorising it). */
+typedef struct fem_chol fem_chol;   /* opaque: ordering, tree and factor (device) */
+
+typedef struct {
+    int64_t n;             /* rows of A */
+    int64_t nnz_l;         /* entries of L (lower triangle, diagonal included) */
+    int32_t nodes;         /* nested-dissection tree nodes (fronts) */
+    int32_t levels;        /* tree depth + 1 */
+    int32_t max_front;     /* largest frontal matrix (rows) */
+    int32_t pad;
+    double flops;          /* factorisation flops (POTRF + TRSM + SYRK of every front) */
+    double factor_mb;      /* device memory of the factor panels */
+    double work_mb;        /* peak device memory of two consecutive levels of fronts */
+    double order_s;        /* host: nested-dissection ordering */
+    double symbolic_s;     /* host: update sets, tree levels */
+    double factor_s;       /* numeric factorisation on the device (0 until chol_factor) */
+    double total_s;        /* chol_factor wall time: ordering, symbolic, set-up, numeric */
+    double solve_s;        /* last chol_solve, call to result */
+} chol_stats_t;
+
+/* Ordering and symbolic analysis only, on the host (works on a host-only
+ * matrix): fills out; perm_out (may be NULL) receives n_free entries, the
+ * free row at each position of the elimination order.  Returns 0,
+ * FEMCG_EINVAL (NULL), FEMCG_ENOMEM. */
+int chol_analyze(const fem_matrix *A, chol_stats_t *out, int32_t *perm_out);
+
+/* Factorise A = K_II (device copy needed): ordering and symbolic analysis on
+ * the host, numeric factorisation on stream (synchronised on return).  *out
+ * receives a library-owned factor, independent of A afterwards; free it with
+ * chol_free.  Returns 0, FEMCG_EINVAL (NULL, host-only matrix),
+ * FEMCG_EBREAKDOWN (a non-positive pivot: A not positive definite),
+ * FEMCG_ENOMEM, FEMCG_EDEVICE. */
+int chol_factor(fem_matrix *A, fem_chol **out, void *stream);
+
+/* X = A^-1 B for k right-hand sides as one block (Eq. (3)): B, X device
+ * [n_free][k] FP64 in the public order (X may not alias B); forward and
+ * backward substitution with the factor on stream (synchronised on return).
+ * Allocates its work vectors per call.  Returns 0, FEMCG_EINVAL,
+ * FEMCG_ENOMEM, FEMCG_EDEVICE. */
+int chol_solve(fem_chol *L, const double *B, double *X, int32_t k, void *stream);
+
+/* Statistics of the factor and of its last solve.  Returns 0 or FEMCG_EINVAL. */
+int chol_stats(const fem_chol *L, chol_stats_t *out);
+
+void chol_free(fem_chol *L);
+
 /* Sizes and DOF data of the discretisation (Sect. 2.2: P1 DOFs are the mesh
  * vertices; Table 7's degrees add p-1 DOFs per edge and (p-1)(p-2)/2 per
  * cell), in the public DOF order above.  Any output pointer may be NULL.

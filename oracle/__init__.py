@@ -84,6 +84,7 @@ def _load(omp: bool = False):
     lib.orc_fd7_identity_nnz.argtypes = [C.c_int64]
     lib.orc_fd7_identity_nnz.restype = C.c_int64
     lib.orc_threads.argtypes = [C.c_int]
+    lib.orc_dense_cholesky.argtypes = [C.c_int64, P, P, P, P, C.c_int, P, P]
     if omp:
         _omp = lib
     else:
@@ -306,6 +307,26 @@ def bicgstab_csr(rowptr, col, val, b, bs, tol, max_iter=None):
     st = _load().orc_bicgstab_csr(n, _ptr(rowptr), _ptr(col), _ptr(val), _ptr(b), bs, tol, max_iter, _ptr(x),
                                   _ptr(its), _ptr(rel), _ptr(rs))
     return x, int(its[0]), float(rel[0]), int(rs[0]), st
+
+
+def dense_cholesky(rowptr, col, val, B=None, want_L=False):
+    """Direct solve of the SPD system by dense Cholesky (Sect. 4.3's direct
+    solver: factorise once, forward and backward substitution per
+    right-hand side).  Returns (X or None, L or None, status)."""
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    n = len(rowptr) - 1
+    X = Bc = None
+    k = 0
+    if B is not None:
+        Bc = np.ascontiguousarray(B, dtype=np.float64).reshape(n, -1)
+        k = Bc.shape[1]
+        X = np.zeros_like(Bc)
+    L = np.zeros((n, n)) if want_L else None
+    st = _load().orc_dense_cholesky(n, _ptr(rowptr), _ptr(col), _ptr(val), _ptr(Bc) if Bc is not None else None, k,
+                                    _ptr(X) if X is not None else None, _ptr(L) if L is not None else None)
+    return X, L, st
 
 
 def default_max_iter(n: int) -> int:

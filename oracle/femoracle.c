@@ -1280,3 +1280,55 @@ int64_t orc_fd7_identity_nnz(int64_t m)
             }
     return nnz;
 }
+
+/* Dense Cholesky (Sect. 4.3: a direct solver factorises the matrix once and
+ * solves two triangular systems per right-hand side; A is symmetric
+ * positive definite, so A = L L^T).  A given in CSR (n rows) is expanded to
+ * a dense n x n array; L (row-major, lower triangle, zeros above) is written
+ * to L_out when it is not NULL, and X = A^-1 B for the k columns of B
+ * ([n][k]) when X is not NULL: forward substitution L y = b, then backward
+ * substitution L^T x = y.  Returns 0, ORC_ENOMEM, or ORC_EBREAK when a pivot
+ * is not positive (A not positive definite). */
+int orc_dense_cholesky(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                       const double *B, int k, double *X, double *L_out)
+{
+    double *L = calloc((size_t)(n ? n : 1) * (size_t)(n ? n : 1), sizeof(double));
+    if (!L) return ORC_ENOMEM;
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t t = rowptr[i]; t < rowptr[i + 1]; t++)
+            if (col[t] <= i) L[i * n + col[t]] += val[t];
+    /* column by column: L_jj = sqrt(a_jj - sum_m L_jm^2),
+     * L_ij = (a_ij - sum_m L_im L_jm) / L_jj for i > j */
+    for (int64_t j = 0; j < n; j++) {
+        double d = L[j * n + j];
+        for (int64_t m = 0; m < j; m++) d -= L[j * n + m] * L[j * n + m];
+        if (!(d > 0.0)) {
+            free(L);
+            return ORC_EBREAK;
+        }
+        double ljj = sqrt(d);
+        L[j * n + j] = ljj;
+        for (int64_t i = j + 1; i < n; i++) {
+            double s = L[i * n + j];
+            for (int64_t m = 0; m < j; m++) s -= L[i * n + m] * L[j * n + m];
+            L[i * n + j] = s / ljj;
+        }
+    }
+    if (X) {
+        for (int c = 0; c < k; c++) {
+            for (int64_t i = 0; i < n; i++) {
+                double s = B[i * k + c];
+                for (int64_t m = 0; m < i; m++) s -= L[i * n + m] * X[m * k + c];
+                X[i * k + c] = s / L[i * n + i];
+            }
+            for (int64_t i = n - 1; i >= 0; i--) {
+                double s = X[i * k + c];
+                for (int64_t m = i + 1; m < n; m++) s -= L[m * n + i] * X[m * k + c];
+                X[i * k + c] = s / L[i * n + i];
+            }
+        }
+    }
+    if (L_out) memcpy(L_out, L, sizeof(double) * (size_t)n * (size_t)n);
+    free(L);
+    return 0;
+}

@@ -13,8 +13,8 @@ LIB = os.path.join(HERE, "libfemcg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "gpu_assemble.hip", "bicgstab.hip", "noalloc.hip", "femcg.cpp", "assemble.cpp",
-           "serve.cpp"]
+SOURCES = ["kernels.hip", "gpu_assemble.hip", "bicgstab.hip", "noalloc.hip", "direct.hip", "femcg.cpp",
+           "assemble.cpp", "serve.cpp"]
 
 # Packed FP32 instructions are disabled for every device pass.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -41,7 +41,8 @@ def build(verbose: bool = False, out: str = LIB) -> str:
     with cf.ThreadPoolExecutor(max_workers=4) as ex:
         objs = list(ex.map(lambda s: _compile(s, build_dir), SOURCES))
     tmp = out + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + ["-lpthread"]
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + [
+        "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s" % r.stderr[-4000:])

@@ -1,0 +1,968 @@
+// direct.hip -- sparse Cholesky factorisation of A = K_II and its solves.
+//
+// The direct side of Sect. 4.3's multiple right-hand-side model: a direct
+// solver factorises the matrix once (T_FACT) and then solves two triangular
+// systems per right-hand side (T_SOLVE), one at a time or as a block
+// (Eq. (3)).  A is symmetric positive definite, so the factorisation is
+// Cholesky, A(perm, perm) = L L^T, computed by the multifrontal method:
+//
+//   ordering   geometric nested dissection on the DOF coordinates: a box is
+//              split at the median coordinate of its longest side, and the
+//              separator is the smaller of the two sets of DOFs that have a
+//              matrix neighbour across the cut; both halves recurse, down to
+//              leaves of at most kLeaf DOFs.  Positions follow the tree in
+//              postorder (children before their separator).
+//   symbolic   node k owns positions [b, e); its update set is every later
+//              position coupled to its subtree: the later neighbours of its
+//              own DOFs and the later entries of its children's update sets.
+//              Its frontal matrix F (f = no + nu square, column-major) is
+//              indexed by the own positions, then the update positions.
+//   numeric    level by level from the deepest: F = A entries of the own
+//              columns, plus the children's update matrices (extend-add, in
+//              child order); partial Cholesky of the own columns:
+//              L11 = chol(F11), L21 = F21 L11^-T, U = F22 - L21 L21^T.  The
+//              panel [L11; L21] is kept; U goes to the parent.
+//   solve      forward by levels from the deepest (y = L^-1 b, the update
+//              vectors passed up by extend-add in child order), backward from
+//              the root (x = L^-T y, reading the ancestors' x).
+//
+// Fronts up to kMidFront are factorised and solved by one workgroup each, in
+// panels of kPanel columns staged in LDS; larger fronts use rocSOLVER's
+// POTRF and rocBLAS's TRSM / SYRK / GEMM (dense FP64, matrix cores).  Every
+// sum has a fixed order, so the factor and the solution do not depend on
+// the launch configuration.
+#include "engine.h"
+
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+namespace femcg {
+
+constexpr int kLeaf = 64;         // nested-dissection leaves: at most this many DOFs
+constexpr int kMidFront = 1024;   // fronts up to this size: one workgroup each
+constexpr int kPanel = 8;         // columns per LDS panel in the workgroup kernels
+constexpr int kDBlock = 256;      // threads per workgroup of the direct kernels
+
+struct ChNode {
+    int64_t b = 0, e = 0;          // own positions [b, e)
+    int child[2] = {-1, -1};
+    int parent = -1, depth = 0;
+    std::vector<int64_t> upd;      // update positions, ascending, all >= e
+    int64_t f() const { return (e - b) + (int64_t)upd.size(); }
+    int64_t no() const { return e - b; }
+    int64_t nu() const { return (int64_t)upd.size(); }
+};
+
+// Device-side description of one node.  Its frontal matrix (f x f, lower
+// triangle) is stored in two parts: the panel columns 0..no-1 (f x no,
+// ld f) in the panel store, where they become [L11; L21], and the update
+// block U (rows and columns no..f-1; nu x nu, ld nu) in its level's buffer.
+struct DNode {
+    int64_t b;           // first own position
+    int32_t no, nu;      // own and update sizes (f = no + nu)
+    int64_t panel;       // offset of its panel in the panel store
+    int64_t u;           // offset of its update block in its level's buffer
+    int64_t wunit;       // solves: offset of its work block (f x t, ld f) in its level's buffer, in units of t
+    int64_t idx;         // offset of its update positions in the index store (nu entries)
+    int64_t rel[2];      // offsets of its children's relative indices in the index store
+    int32_t child[2];    // node ids, -1 if none
+};
+
+}  // namespace femcg
+
+struct fem_chol {
+    int64_t n = 0;
+    std::vector<int32_t> perm;                 // position -> free row
+    std::vector<femcg::ChNode> nodes;
+    std::vector<std::vector<int32_t>> levels;  // node ids by depth
+    std::vector<femcg::DNode> hnodes;
+    femcg::DNode *d_nodes = nullptr;
+    int32_t *d_perm = nullptr;                 // position -> free row
+    int64_t *d_index = nullptr;                // update positions and children's relative indices
+    double *d_panel = nullptr;                 // panels [L11; L21] of every node, level by level
+    char *d_lists = nullptr;                   // per-level work lists (one allocation)
+    struct Level {
+        int32_t *all = nullptr, *mid = nullptr;  // node ids: every node, fronts up to kMidFront
+        int32_t nall = 0, nmid = 0;
+        std::vector<int32_t> big;                // node ids of larger fronts (host loop)
+        int32_t *dbig = nullptr;                 // the same on the device
+        int64_t panel0 = 0, panel1 = 0;          // the level's range in the panel store
+        int64_t udoubles = 0;                    // update blocks of the level's nodes
+        int64_t wunits = 0;                      // sum of f over the level's nodes
+        int64_t *asm_dst = nullptr;              // A entries of the level's own columns
+        double *asm_val = nullptr;
+        int64_t nasm = 0;
+        int32_t *ea_cols[2] = {nullptr, nullptr};  // (node, child column) pairs per child slot
+        int64_t nea[2] = {0, 0};
+    };
+    std::vector<Level> lev;
+    int64_t max_udoubles = 0, max_wunits = 0;
+    int32_t *d_fail = nullptr;                 // nonzero: a non-positive pivot
+    chol_stats_t stats{};
+    rocblas_handle blas = nullptr;
+    ~fem_chol();
+};
+
+namespace femcg {
+namespace {
+
+// --------------------------------------------------------------------------
+// host: ordering and symbolic analysis
+// --------------------------------------------------------------------------
+
+struct Graph {
+    std::vector<int64_t> ptr;  // pruned pattern of A without the diagonal
+    std::vector<int32_t> adj;
+};
+
+// The solver copy's pruning: entries |a| <= 4 eps max_row |a| are dropped
+// (never the diagonal); they are zero in exact arithmetic (structural zeros
+// of the element matrices).
+static double prune_threshold(const HostSystem &hs, int64_t i)
+{
+    double mx = 0.0;
+    for (int64_t t = hs.a_rowptr[i]; t < hs.a_rowptr[i + 1]; ++t) mx = std::max(mx, std::fabs(hs.a_val[t]));
+    return 4.0 * 2.220446049250313e-16 * mx;
+}
+
+static void build_graph(const HostSystem &hs, Graph &G)
+{
+    const int64_t n = hs.nfree;
+    G.ptr.assign(n + 1, 0);
+    std::vector<int64_t> cnt(n, 0);
+    parallel_for(n, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i) {
+            const double thr = prune_threshold(hs, i);
+            int64_t c = 0;
+            for (int64_t t = hs.a_rowptr[i]; t < hs.a_rowptr[i + 1]; ++t)
+                c += hs.a_col[t] != i && std::fabs(hs.a_val[t]) > thr;
+            cnt[i] = c;
+        }
+    });
+    for (int64_t i = 0; i < n; ++i) G.ptr[i + 1] = G.ptr[i] + cnt[i];
+    G.adj.resize(G.ptr[n]);
+    parallel_for(n, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i) {
+            const double thr = prune_threshold(hs, i);
+            int64_t o = G.ptr[i];
+            for (int64_t t = hs.a_rowptr[i]; t < hs.a_rowptr[i + 1]; ++t)
+                if (hs.a_col[t] != i && std::fabs(hs.a_val[t]) > thr) G.adj[o++] = hs.a_col[t];
+        }
+    });
+}
+
+struct NdState {
+    const HostSystem *hs;
+    const Graph *G;
+    std::vector<int32_t> mark;  // stamps
+    int32_t stamp = 0;
+    int64_t next = 0;           // next free position
+    std::vector<int32_t> perm;
+    std::vector<ChNode> nodes;
+};
+
+static double coord(const NdState &S, int32_t i, int r)
+{
+    const HostSystem &hs = *S.hs;
+    return hs.dof_coords[hs.free2dof[i] * hs.dim + r];
+}
+
+static int new_node(NdState &S, const std::vector<int32_t> &own, int depth)
+{
+    ChNode nd;
+    nd.b = S.next;
+    for (int32_t i : own) S.perm[S.next++] = i;
+    nd.e = S.next;
+    nd.depth = depth;
+    S.nodes.push_back(std::move(nd));
+    return (int)S.nodes.size() - 1;
+}
+
+// Nested dissection of the free rows `ids`; returns the node id.
+static int dissect(NdState &S, std::vector<int32_t> &ids, int depth)
+{
+    if ((int64_t)ids.size() <= kLeaf) return new_node(S, ids, depth);
+    const int dim = S.hs->dim;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int32_t i : ids)
+        for (int r = 0; r < dim; ++r) {
+            lo[r] = std::min(lo[r], coord(S, i, r));
+            hi[r] = std::max(hi[r], coord(S, i, r));
+        }
+    int ax = 0;
+    for (int r = 1; r < dim; ++r)
+        if (hi[r] - lo[r] > hi[ax] - lo[ax]) ax = r;
+    // split at the median coordinate; ties on the median value go right
+    std::vector<int32_t> ord(ids);
+    const size_t mid = ord.size() / 2;
+    std::nth_element(ord.begin(), ord.begin() + mid, ord.end(), [&](int32_t a, int32_t c) {
+        const double ca = coord(S, a, ax), cc = coord(S, c, ax);
+        return ca < cc || (ca == cc && a < c);
+    });
+    const double vm = coord(S, ord[mid], ax);
+    std::vector<int32_t> L, R;
+    for (int32_t i : ids) (coord(S, i, ax) < vm ? L : R).push_back(i);
+    if (L.empty() || R.empty()) {
+        // every coordinate equal along the axis: split by the order above
+        L.assign(ord.begin(), ord.begin() + mid);
+        R.assign(ord.begin() + mid, ord.end());
+    }
+    // the two boundary sets; the smaller one is the separator
+    const Graph &G = *S.G;
+    auto boundary = [&](const std::vector<int32_t> &side, const std::vector<int32_t> &other) {
+        ++S.stamp;
+        for (int32_t j : other) S.mark[j] = S.stamp;
+        std::vector<int32_t> bnd;
+        for (int32_t i : side)
+            for (int64_t t = G.ptr[i]; t < G.ptr[i + 1]; ++t)
+                if (S.mark[G.adj[t]] == S.stamp) {
+                    bnd.push_back(i);
+                    break;
+                }
+        return bnd;
+    };
+    std::vector<int32_t> BL = boundary(L, R), BR = boundary(R, L);
+    const bool left = BL.size() <= BR.size();
+    std::vector<int32_t> sep = left ? BL : BR;
+    std::vector<int32_t> &cut = left ? L : R;
+    ++S.stamp;
+    for (int32_t i : sep) S.mark[i] = S.stamp;
+    cut.erase(std::remove_if(cut.begin(), cut.end(), [&](int32_t i) { return S.mark[i] == S.stamp; }), cut.end());
+    ids.clear();
+    ids.shrink_to_fit();
+    const int c0 = L.empty() ? -1 : dissect(S, L, depth + 1);
+    const int c1 = R.empty() ? -1 : dissect(S, R, depth + 1);
+    const int k = new_node(S, sep, depth);
+    S.nodes[k].child[0] = c0;
+    S.nodes[k].child[1] = c1;
+    if (c0 >= 0) S.nodes[c0].parent = k;
+    if (c1 >= 0) S.nodes[c1].parent = k;
+    return k;
+}
+
+}  // namespace
+
+// Ordering, tree, update sets and the statistics of the factorisation.
+int chol_symbolic(const HostSystem &hs, fem_chol &C)
+{
+    const double t0 = now_s();
+    Graph G;
+    build_graph(hs, G);
+    NdState S;
+    S.hs = &hs;
+    S.G = &G;
+    S.mark.assign(hs.nfree, 0);
+    S.perm.assign(hs.nfree, 0);
+    std::vector<int32_t> all(hs.nfree);
+    std::iota(all.begin(), all.end(), 0);
+    if (hs.nfree > 0) dissect(S, all, 0);
+    C.n = hs.nfree;
+    C.perm = std::move(S.perm);
+    C.nodes = std::move(S.nodes);
+    const double t1 = now_s();
+    std::vector<int32_t> ipos(C.n);
+    for (int64_t p = 0; p < C.n; ++p) ipos[C.perm[p]] = (int32_t)p;
+    // update sets, children first (the node list is in postorder)
+    std::vector<int64_t> mark(C.n, -1);
+    for (size_t k = 0; k < C.nodes.size(); ++k) {
+        ChNode &nd = C.nodes[k];
+        std::vector<int64_t> u;
+        auto add = [&](int64_t q) {
+            if (q >= nd.e && mark[q] != (int64_t)k) {
+                mark[q] = (int64_t)k;
+                u.push_back(q);
+            }
+        };
+        for (int64_t p = nd.b; p < nd.e; ++p) {
+            const int32_t i = C.perm[p];
+            for (int64_t t = G.ptr[i]; t < G.ptr[i + 1]; ++t) add(ipos[G.adj[t]]);
+        }
+        for (int c : nd.child)
+            if (c >= 0) {
+                for (int64_t q : C.nodes[c].upd) add(q);
+            }
+        std::sort(u.begin(), u.end());
+        nd.upd = std::move(u);
+    }
+    // levels and statistics
+    int maxd = 0;
+    for (const ChNode &nd : C.nodes) maxd = std::max(maxd, nd.depth);
+    C.levels.assign(maxd + 1, {});
+    for (size_t k = 0; k < C.nodes.size(); ++k) C.levels[C.nodes[k].depth].push_back((int32_t)k);
+    chol_stats_t &st = C.stats;
+    st.n = C.n;
+    st.nodes = (int32_t)C.nodes.size();
+    st.levels = maxd + 1;
+    double nnzl = 0, flops = 0, panel = 0, peak = 0;
+    int64_t maxf = 0;
+    std::vector<double> lev(maxd + 1, 0.0);
+    for (const ChNode &nd : C.nodes) {
+        const double no = (double)nd.no(), nu = (double)nd.nu(), f = no + nu;
+        nnzl += no * (no + 1) / 2 + nu * no;
+        flops += no * no * no / 3.0 + nu * no * no + nu * nu * no;
+        panel += f * no;
+        maxf = std::max<int64_t>(maxf, nd.f());
+        lev[nd.depth] += f * f;
+    }
+    for (int d = 0; d < maxd; ++d) peak = std::max(peak, lev[d] + lev[d + 1]);
+    if (maxd == 0) peak = lev[0];
+    st.nnz_l = (int64_t)nnzl;
+    st.flops = flops;
+    st.max_front = (int32_t)maxf;
+    st.factor_mb = (panel * 8.0) * 1e-6;
+    st.work_mb = (peak * 8.0) * 1e-6;
+    st.order_s = t1 - t0;
+    st.symbolic_s = now_s() - t1;
+    return FEMCG_OK;
+}
+
+
+// --------------------------------------------------------------------------
+// device kernels
+// --------------------------------------------------------------------------
+
+namespace {
+
+// Element (r, c), r >= c, of a frontal matrix stored as panel + update block.
+struct Front {
+    double *panel, *u;
+    int no, nu, f;
+    __device__ double &at(int r, int c) const
+    {
+        return c < no ? panel[r + (int64_t)c * f] : u[(r - no) + (int64_t)(c - no) * nu];
+    }
+};
+
+__device__ inline Front front_of(const DNode &D, double *panel, double *ubuf)
+{
+    return Front{panel + D.panel, ubuf + D.u, D.no, D.nu, D.no + D.nu};
+}
+
+// A's entries of the level's own columns (every frontal position written by
+// exactly one entry; the panels were zeroed before).
+__global__ __launch_bounds__(kDBlock) void k_assemble(const int64_t *dst, const double *val, int64_t n, double *panel)
+{
+    for (int64_t e = (int64_t)blockIdx.x * kDBlock + threadIdx.x; e < n; e += (int64_t)gridDim.x * kDBlock)
+        panel[dst[e]] = val[e];
+}
+
+// Extend-add of child slot s: block = one (node, child column b) pair; the
+// child's update column b is added into the node's front at the child's
+// relative indices (rows rel[a] >= rel[b], since rel increases).
+__global__ __launch_bounds__(kDBlock) void k_extend_add(const DNode *nodes, const int32_t *pairs, int s,
+                                                        const int64_t *index, double *panel, double *ubuf,
+                                                        const double *uchild)
+{
+    const int k = pairs[2 * blockIdx.x], b = pairs[2 * blockIdx.x + 1];
+    const DNode D = nodes[k];
+    const DNode Cn = nodes[D.child[s]];
+    const Front F = front_of(D, panel, ubuf);
+    const int64_t *rel = index + D.rel[s];
+    const double *U = uchild + Cn.u;
+    const int nuc = Cn.nu;
+    const int cb = (int)rel[b];
+    for (int a = b + threadIdx.x; a < nuc; a += kDBlock) F.at((int)rel[a], cb) += U[a + (int64_t)b * nuc];
+}
+
+// Partial Cholesky of one front (f <= kMidFront) per workgroup, right-looking
+// in panels of kPanel columns staged in LDS: factor the panel's columns,
+// write them back, then update every later column (panel and update block)
+// with the panel, each entry once per panel in a fixed order.
+__global__ __launch_bounds__(kDBlock) void k_mid_factor(const DNode *nodes, const int32_t *list, double *panel,
+                                                        double *ubuf, int32_t *fail)
+{
+    __shared__ double P[kMidFront * kPanel];  // P[(r - k0) * kPanel + j] = F(r, k0 + j)
+    __shared__ int s_bad;
+    const DNode D = nodes[list[blockIdx.x]];
+    const Front F = front_of(D, panel, ubuf);
+    const int f = F.f, no = F.no, tid = threadIdx.x;
+    if (tid == 0) s_bad = 0;
+    for (int k0 = 0; k0 < no; k0 += kPanel) {
+        const int kw = min(kPanel, no - k0), rows = f - k0;
+        for (int i = tid; i < rows * kw; i += kDBlock) {
+            const int r = i / kw, j = i - r * kw;
+            P[r * kPanel + j] = F.panel[(k0 + r) + (int64_t)(k0 + j) * f];
+        }
+        __syncthreads();
+        for (int j = 0; j < kw; ++j) {
+            const double d = P[j * kPanel + j];
+            if (!(d > 0.0) && tid == 0) s_bad = 1;
+            const double sq = sqrt(d > 0.0 ? d : 1.0);
+            __syncthreads();
+            for (int r = j + tid; r < rows; r += kDBlock) P[r * kPanel + j] = r == j ? sq : P[r * kPanel + j] / sq;
+            __syncthreads();
+            for (int j2 = j + 1; j2 < kw; ++j2) {
+                const double pj = P[j2 * kPanel + j];
+                for (int r = j2 + tid; r < rows; r += kDBlock) P[r * kPanel + j2] -= P[r * kPanel + j] * pj;
+            }
+            __syncthreads();
+        }
+        for (int i = tid; i < rows * kw; i += kDBlock) {
+            const int r = i / kw, j = i - r * kw;
+            F.panel[(k0 + r) + (int64_t)(k0 + j) * f] = P[r * kPanel + j];
+        }
+        for (int c = k0 + kw; c < f; ++c) {
+            double pc[kPanel];
+#pragma unroll
+            for (int j = 0; j < kPanel; ++j) pc[j] = j < kw ? P[(c - k0) * kPanel + j] : 0.0;
+            for (int r = c + tid; r < f; r += kDBlock) {
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < kPanel; ++j)
+                    if (j < kw) acc += P[(r - k0) * kPanel + j] * pc[j];
+                F.at(r, c) -= acc;
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0 && s_bad) fail[0] = 1;
+}
+
+// ---- solves: z holds the right-hand sides in elimination order, [n][t] ----
+
+// z[p][c] = B[perm[p]][c]   /   X[perm[p]][c] = z[p][c]
+__global__ __launch_bounds__(kDBlock) void k_permute(const int32_t *perm, int64_t n, int t, const double *src,
+                                                     double *dst, int to_positions)
+{
+    const int64_t tot = n * t;
+    for (int64_t e = (int64_t)blockIdx.x * kDBlock + threadIdx.x; e < tot; e += (int64_t)gridDim.x * kDBlock) {
+        const int64_t p = e / t, c = e - p * t;
+        const int64_t i = perm[p];
+        if (to_positions) dst[e] = src[i * t + c];
+        else dst[i * t + c] = src[e];
+    }
+}
+
+// Forward gather of one node into its work block W (f x t, ld f): its own
+// right-hand-side rows, zeros below, then the children's update vectors
+// (rows no_c..f_c of their blocks) added at their relative indices, child 0
+// first.  One workgroup per node; the block is complete on return.
+__device__ void fwd_gather(const DNode &D, const DNode *nodes, const int64_t *index, const double *z, int t,
+                           double *W, const double *wchild)
+{
+    const int f = D.no + D.nu;
+    for (int64_t e = threadIdx.x; e < (int64_t)f * t; e += kDBlock) {
+        const int c = (int)(e / f), r = (int)(e - (int64_t)c * f);
+        W[e] = r < D.no ? z[(D.b + r) * t + c] : 0.0;
+    }
+    for (int s = 0; s < 2; ++s) {
+        __syncthreads();
+        if (D.child[s] < 0) continue;
+        const DNode Cn = nodes[D.child[s]];
+        const int fc = Cn.no + Cn.nu;
+        const double *V = wchild + Cn.wunit * t;
+        const int64_t *rel = index + D.rel[s];
+        for (int64_t e = threadIdx.x; e < (int64_t)Cn.nu * t; e += kDBlock) {
+            const int c = (int)(e / Cn.nu), a = (int)(e - (int64_t)c * Cn.nu);
+            W[rel[a] + (int64_t)c * f] += V[(Cn.no + a) + (int64_t)c * fc];
+        }
+    }
+    __syncthreads();
+}
+
+// Backward gather: own rows from z (y), update rows from z at the update
+// positions (the ancestors' x).
+__device__ void bwd_gather(const DNode &D, const int64_t *index, const double *z, int t, double *W)
+{
+    const int f = D.no + D.nu;
+    const int64_t *upd = index + D.idx;
+    for (int64_t e = threadIdx.x; e < (int64_t)f * t; e += kDBlock) {
+        const int c = (int)(e / f), r = (int)(e - (int64_t)c * f);
+        W[e] = r < D.no ? z[(D.b + r) * t + c] : z[upd[r - D.no] * t + c];
+    }
+    __syncthreads();
+}
+
+__device__ void own_store(const DNode &D, const double *W, int t, double *z)
+{
+    const int f = D.no + D.nu;
+    for (int64_t e = threadIdx.x; e < (int64_t)D.no * t; e += kDBlock) {
+        const int c = (int)(e / D.no), r = (int)(e - (int64_t)c * D.no);
+        z[(D.b + r) * t + c] = W[r + (int64_t)c * f];
+    }
+}
+
+// Whole forward step of a front up to kMidFront: gather, y = L11^-1 w
+// (column by column), w_upd -= L21 y, store y.
+__global__ __launch_bounds__(kDBlock) void k_mid_fwd(const DNode *nodes, const int32_t *list, const int64_t *index,
+                                                     const double *panel, double *z, int t, double *wbuf,
+                                                     const double *wchild)
+{
+    const DNode D = nodes[list[blockIdx.x]];
+    const int f = D.no + D.nu;
+    double *W = wbuf + D.wunit * t;
+    const double *L = panel + D.panel;
+    fwd_gather(D, nodes, index, z, t, W, wchild);
+    for (int k = 0; k < D.no; ++k) {
+        const double dk = L[k + (int64_t)k * f];
+        for (int c = threadIdx.x; c < t; c += kDBlock) W[k + (int64_t)c * f] /= dk;
+        __syncthreads();
+        const int rows = f - k - 1;
+        for (int64_t e = threadIdx.x; e < (int64_t)rows * t; e += kDBlock) {
+            const int c = (int)(e / rows), r = k + 1 + (int)(e - (int64_t)c * rows);
+            W[r + (int64_t)c * f] -= L[r + (int64_t)k * f] * W[k + (int64_t)c * f];
+        }
+        __syncthreads();
+    }
+    own_store(D, W, t, z);
+}
+
+// Whole backward step of a front up to kMidFront: gather, w -= L21^T x_upd,
+// x = L11^-T w (from the last column), store x.
+__global__ __launch_bounds__(kDBlock) void k_mid_bwd(const DNode *nodes, const int32_t *list, const int64_t *index,
+                                                     const double *panel, double *z, int t, double *wbuf)
+{
+    const DNode D = nodes[list[blockIdx.x]];
+    const int f = D.no + D.nu;
+    double *W = wbuf + D.wunit * t;
+    const double *L = panel + D.panel;
+    bwd_gather(D, index, z, t, W);
+    for (int64_t e = threadIdx.x; e < (int64_t)D.no * t; e += kDBlock) {
+        const int c = (int)(e / D.no), i = (int)(e - (int64_t)c * D.no);
+        double acc = 0.0;
+        for (int a = 0; a < D.nu; ++a) acc += L[(D.no + a) + (int64_t)i * f] * W[(D.no + a) + (int64_t)c * f];
+        W[i + (int64_t)c * f] -= acc;
+    }
+    __syncthreads();
+    for (int k = D.no - 1; k >= 0; --k) {
+        const double dk = L[k + (int64_t)k * f];
+        for (int c = threadIdx.x; c < t; c += kDBlock) W[k + (int64_t)c * f] /= dk;
+        __syncthreads();
+        for (int64_t e = threadIdx.x; e < (int64_t)k * t; e += kDBlock) {
+            const int c = (int)(e / k), r = (int)(e - (int64_t)c * k);
+            W[r + (int64_t)c * f] -= L[k + (int64_t)r * f] * W[k + (int64_t)c * f];
+        }
+        __syncthreads();
+    }
+    own_store(D, W, t, z);
+}
+
+// Gather / store around the rocBLAS steps of the larger fronts.
+__global__ __launch_bounds__(kDBlock) void k_big_fwd_gather(const DNode *nodes, const int32_t *list,
+                                                            const int64_t *index, const double *z, int t,
+                                                            double *wbuf, const double *wchild)
+{
+    const DNode D = nodes[list[blockIdx.x]];
+    fwd_gather(D, nodes, index, z, t, wbuf + D.wunit * t, wchild);
+}
+__global__ __launch_bounds__(kDBlock) void k_big_bwd_gather(const DNode *nodes, const int32_t *list,
+                                                            const int64_t *index, const double *z, int t,
+                                                            double *wbuf)
+{
+    const DNode D = nodes[list[blockIdx.x]];
+    bwd_gather(D, index, z, t, wbuf + D.wunit * t);
+}
+__global__ __launch_bounds__(kDBlock) void k_big_store(const DNode *nodes, const int32_t *list, int t,
+                                                       const double *wbuf, double *z)
+{
+    const DNode D = nodes[list[blockIdx.x]];
+    own_store(D, wbuf + D.wunit * t, t, z);
+}
+
+}  // namespace
+
+// --------------------------------------------------------------------------
+// host: numeric set-up, factorisation and solves
+// --------------------------------------------------------------------------
+
+#define DCHK(call)                                                                          \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess) return fail(FEMCG_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+#define BCHK(call)                                                                          \
+    do {                                                                                    \
+        rocblas_status b_ = (call);                                                         \
+        if (b_ != rocblas_status_success) return fail(FEMCG_EDEVICE, "%s: rocBLAS status %d", #call, (int)b_); \
+    } while (0)
+
+static int dgrid(int64_t work)
+{
+    return (int)std::max<int64_t>(1, std::min<int64_t>((work + kDBlock - 1) / kDBlock, 8192));
+}
+
+// Index of position q in node nd's front (own positions, then the update
+// positions), or -1 if q is not in it (which the nested-dissection
+// separators rule out; checked so that no kernel can index past a front).
+static int64_t front_index(const ChNode &nd, int64_t q)
+{
+    if (q >= nd.b && q < nd.e) return q - nd.b;
+    auto it = std::lower_bound(nd.upd.begin(), nd.upd.end(), q);
+    if (it == nd.upd.end() || *it != q) return -1;
+    return nd.no() + (it - nd.upd.begin());
+}
+
+// Offsets, index store, per-level lists and the assembly map; uploads them.
+int chol_setup(const HostSystem &hs, fem_chol &C)
+{
+    const int64_t n = C.n;
+    const size_t nn = C.nodes.size();
+    std::vector<int32_t> ipos(n);
+    for (int64_t p = 0; p < n; ++p) ipos[C.perm[p]] = (int32_t)p;
+    C.hnodes.assign(nn, DNode{});
+    std::vector<int64_t> index;
+    const int nlev = (int)C.levels.size();
+    C.lev.assign(nlev, fem_chol::Level{});
+    int64_t panel = 0;
+    // deepest level first: panels in factorisation order
+    for (int d = nlev - 1; d >= 0; --d) {
+        fem_chol::Level &L = C.lev[d];
+        L.panel0 = panel;
+        int64_t u = 0, w = 0;
+        for (int32_t k : C.levels[d]) {
+            const ChNode &nd = C.nodes[k];
+            DNode &D = C.hnodes[k];
+            D.b = nd.b;
+            D.no = (int32_t)nd.no();
+            D.nu = (int32_t)nd.nu();
+            D.panel = panel;
+            panel += nd.f() * nd.no();
+            D.u = u;
+            u += nd.nu() * nd.nu();
+            D.wunit = w;
+            w += nd.f();
+            D.idx = (int64_t)index.size();
+            index.insert(index.end(), nd.upd.begin(), nd.upd.end());
+            for (int s = 0; s < 2; ++s) {
+                D.child[s] = nd.child[s];
+                D.rel[s] = 0;
+                if (nd.child[s] < 0) continue;
+                D.rel[s] = (int64_t)index.size();
+                for (int64_t q : C.nodes[nd.child[s]].upd) {
+                    const int64_t r = front_index(nd, q);
+                    if (r < 0) return fail(FEMCG_EINVAL, "chol: update position %lld outside the parent front", (long long)q);
+                    index.push_back(r);
+                }
+            }
+        }
+        L.panel1 = panel;
+        L.udoubles = u;
+        L.wunits = w;
+        C.max_udoubles = std::max(C.max_udoubles, u);
+        C.max_wunits = std::max(C.max_wunits, w);
+    }
+    // assembly map: A entries (q >= p) of every own column p
+    std::vector<std::vector<int64_t>> adst(nlev);
+    std::vector<std::vector<double>> aval(nlev);
+    for (int d = 0; d < nlev; ++d)
+        for (int32_t k : C.levels[d]) {
+            const ChNode &nd = C.nodes[k];
+            const DNode &D = C.hnodes[k];
+            const int64_t f = nd.f();
+            for (int64_t p = nd.b; p < nd.e; ++p) {
+                const int64_t i = C.perm[p];
+                const double thr = prune_threshold(hs, i);
+                for (int64_t t = hs.a_rowptr[i]; t < hs.a_rowptr[i + 1]; ++t) {
+                    const int64_t j = hs.a_col[t];
+                    const int64_t q = ipos[j];
+                    if (q < p || (j != i && !(std::fabs(hs.a_val[t]) > thr))) continue;
+                    const int64_t r = front_index(nd, q);
+                    if (r < 0) return fail(FEMCG_EINVAL, "chol: matrix entry (%lld, %lld) outside its front", (long long)p, (long long)q);
+                    adst[d].push_back(D.panel + r + (p - nd.b) * f);
+                    aval[d].push_back(hs.a_val[t]);
+                }
+            }
+        }
+    // device lists: per level node ids (all, mid, big), extend-add pairs, assembly
+    size_t bytes = 0;
+    auto reserve = [&](size_t b) {
+        const size_t off = (bytes + 255) & ~(size_t)255;
+        bytes = off + b;
+        return off;
+    };
+    struct Off {
+        size_t all, mid, big, ea[2], dst, val;
+    };
+    std::vector<Off> off(nlev);
+    std::vector<std::vector<int32_t>> mid(nlev), big(nlev), ea0(nlev), ea1(nlev);
+    for (int d = 0; d < nlev; ++d) {
+        for (int32_t k : C.levels[d]) {
+            (C.nodes[k].f() <= kMidFront ? mid[d] : big[d]).push_back(k);
+            for (int s = 0; s < 2; ++s) {
+                const int c = C.nodes[k].child[s];
+                if (c < 0) continue;
+                auto &v = s == 0 ? ea0[d] : ea1[d];
+                for (int64_t b = 0; b < C.nodes[c].nu(); ++b) {
+                    v.push_back(k);
+                    v.push_back((int32_t)b);
+                }
+            }
+        }
+        off[d].all = reserve(C.levels[d].size() * 4);
+        off[d].mid = reserve(mid[d].size() * 4);
+        off[d].big = reserve(big[d].size() * 4);
+        off[d].ea[0] = reserve(ea0[d].size() * 4);
+        off[d].ea[1] = reserve(ea1[d].size() * 4);
+        off[d].dst = reserve(adst[d].size() * 8);
+        off[d].val = reserve(aval[d].size() * 8);
+    }
+    DCHK(hipMalloc((void **)&C.d_lists, std::max<size_t>(bytes, 256)));
+    DCHK(hipMalloc((void **)&C.d_nodes, sizeof(DNode) * std::max<size_t>(nn, 1)));
+    DCHK(hipMalloc((void **)&C.d_perm, sizeof(int32_t) * std::max<int64_t>(n, 1)));
+    DCHK(hipMalloc((void **)&C.d_index, sizeof(int64_t) * std::max<size_t>(index.size(), 1)));
+    DCHK(hipMalloc((void **)&C.d_fail, sizeof(int32_t)));
+    DCHK(hipMemcpy(C.d_nodes, C.hnodes.data(), sizeof(DNode) * nn, hipMemcpyHostToDevice));
+    DCHK(hipMemcpy(C.d_perm, C.perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
+    if (!index.empty()) DCHK(hipMemcpy(C.d_index, index.data(), sizeof(int64_t) * index.size(), hipMemcpyHostToDevice));
+    auto put = [&](size_t o, const void *src, size_t b) -> int {
+        if (b) DCHK(hipMemcpy(C.d_lists + o, src, b, hipMemcpyHostToDevice));
+        return FEMCG_OK;
+    };
+    for (int d = 0; d < nlev; ++d) {
+        fem_chol::Level &L = C.lev[d];
+        int rc;
+        if ((rc = put(off[d].all, C.levels[d].data(), C.levels[d].size() * 4)) ||
+            (rc = put(off[d].mid, mid[d].data(), mid[d].size() * 4)) ||
+            (rc = put(off[d].big, big[d].data(), big[d].size() * 4)) ||
+            (rc = put(off[d].ea[0], ea0[d].data(), ea0[d].size() * 4)) ||
+            (rc = put(off[d].ea[1], ea1[d].data(), ea1[d].size() * 4)) ||
+            (rc = put(off[d].dst, adst[d].data(), adst[d].size() * 8)) ||
+            (rc = put(off[d].val, aval[d].data(), aval[d].size() * 8)))
+            return rc;
+        L.all = (int32_t *)(C.d_lists + off[d].all);
+        L.mid = (int32_t *)(C.d_lists + off[d].mid);
+        L.nall = (int32_t)C.levels[d].size();
+        L.nmid = (int32_t)mid[d].size();
+        L.big = big[d];
+        L.dbig = (int32_t *)(C.d_lists + off[d].big);
+        L.ea_cols[0] = (int32_t *)(C.d_lists + off[d].ea[0]);
+        L.ea_cols[1] = (int32_t *)(C.d_lists + off[d].ea[1]);
+        L.nea[0] = (int64_t)ea0[d].size() / 2;
+        L.nea[1] = (int64_t)ea1[d].size() / 2;
+        L.asm_dst = (int64_t *)(C.d_lists + off[d].dst);
+        L.asm_val = (double *)(C.d_lists + off[d].val);
+        L.nasm = (int64_t)adst[d].size();
+    }
+    DCHK(hipMalloc((void **)&C.d_panel, sizeof(double) * std::max<int64_t>(panel, 1)));
+    C.stats.factor_mb = panel * 8e-6;
+    return FEMCG_OK;
+}
+
+// Numeric factorisation on stream s (panels and update blocks zeroed level by
+// level, A entries, extend-add, partial Cholesky); synchronises.
+int chol_numeric(fem_chol &C, hipStream_t s)
+{
+    double *ubuf[2] = {nullptr, nullptr};
+    int32_t *info = nullptr;
+    struct Release {
+        double **u;
+        int32_t **i;
+        ~Release()
+        {
+            if (u[0]) (void)hipFree(u[0]);
+            if (u[1]) (void)hipFree(u[1]);
+            if (*i) (void)hipFree(*i);
+        }
+    } release{ubuf, &info};
+    for (int b = 0; b < 2; ++b) DCHK(hipMalloc((void **)&ubuf[b], sizeof(double) * std::max<int64_t>(C.max_udoubles, 1)));
+    int64_t nbig = 0;
+    for (const auto &L : C.lev) nbig += (int64_t)L.big.size();
+    DCHK(hipMalloc((void **)&info, sizeof(int32_t) * std::max<int64_t>(nbig, 1)));
+    DCHK(hipMemsetAsync(info, 0, sizeof(int32_t) * std::max<int64_t>(nbig, 1), s));
+    DCHK(hipMemsetAsync(C.d_fail, 0, sizeof(int32_t), s));
+    BCHK(rocblas_set_stream(C.blas, s));
+    BCHK(rocblas_set_pointer_mode(C.blas, rocblas_pointer_mode_host));
+    const int nlev = (int)C.lev.size();
+    int64_t ib = 0;
+    for (int d = nlev - 1; d >= 0; --d) {
+        const fem_chol::Level &L = C.lev[d];
+        double *u = ubuf[d & 1];
+        const double *uc = ubuf[(d + 1) & 1];
+        DCHK(hipMemsetAsync(C.d_panel + L.panel0, 0, sizeof(double) * (L.panel1 - L.panel0), s));
+        if (L.udoubles) DCHK(hipMemsetAsync(u, 0, sizeof(double) * L.udoubles, s));
+        if (L.nasm) hipLaunchKernelGGL(k_assemble, dim3(dgrid(L.nasm)), dim3(kDBlock), 0, s, L.asm_dst, L.asm_val, L.nasm, C.d_panel);
+        for (int sl = 0; sl < 2; ++sl)
+            if (L.nea[sl])
+                hipLaunchKernelGGL(k_extend_add, dim3((unsigned)L.nea[sl]), dim3(kDBlock), 0, s, C.d_nodes, L.ea_cols[sl],
+                                   sl, C.d_index, C.d_panel, u, uc);
+        if (L.nmid) hipLaunchKernelGGL(k_mid_factor, dim3(L.nmid), dim3(kDBlock), 0, s, C.d_nodes, L.mid, C.d_panel, u, C.d_fail);
+        DCHK(hipGetLastError());
+        for (int32_t k : L.big) {
+            const DNode &D = C.hnodes[k];
+            const int f = D.no + D.nu;
+            double *P = C.d_panel + D.panel;
+            if (D.no > 0) BCHK(rocsolver_dpotrf(C.blas, rocblas_fill_lower, D.no, P, f, info + ib));
+            ++ib;
+            if (D.no > 0 && D.nu > 0) {
+                const double one = 1.0, mone = -1.0;
+                BCHK(rocblas_dtrsm(C.blas, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
+                                   rocblas_diagonal_non_unit, D.nu, D.no, &one, P, f, P + D.no, f));
+                BCHK(rocblas_dsyrk(C.blas, rocblas_fill_lower, rocblas_operation_none, D.nu, D.no, &mone, P + D.no, f,
+                                   &one, u + D.u, D.nu));
+            }
+        }
+    }
+    DCHK(hipStreamSynchronize(s));
+    int32_t bad = 0;
+    DCHK(hipMemcpy(&bad, C.d_fail, sizeof bad, hipMemcpyDeviceToHost));
+    if (nbig) {
+        std::vector<int32_t> h(nbig);
+        DCHK(hipMemcpy(h.data(), info, sizeof(int32_t) * nbig, hipMemcpyDeviceToHost));
+        for (int32_t v : h) bad |= v != 0;
+    }
+    if (bad) return fail(FEMCG_EBREAKDOWN, "chol_factor: non-positive pivot (A not positive definite)");
+    return FEMCG_OK;
+}
+
+// Forward and backward solve of t right-hand sides (device [n][t], public
+// order) on stream s; synchronises.
+int chol_solve_impl(fem_chol &C, const double *B, double *X, int t, hipStream_t s)
+{
+    const int64_t n = C.n;
+    double *z = nullptr, *wb[2] = {nullptr, nullptr};
+    struct Release {
+        double **z, **w;
+        ~Release()
+        {
+            if (*z) (void)hipFree(*z);
+            if (w[0]) (void)hipFree(w[0]);
+            if (w[1]) (void)hipFree(w[1]);
+        }
+    } release{&z, wb};
+    DCHK(hipMalloc((void **)&z, sizeof(double) * std::max<int64_t>(n * t, 1)));
+    for (int b = 0; b < 2; ++b) DCHK(hipMalloc((void **)&wb[b], sizeof(double) * std::max<int64_t>(C.max_wunits * t, 1)));
+    BCHK(rocblas_set_stream(C.blas, s));
+    BCHK(rocblas_set_pointer_mode(C.blas, rocblas_pointer_mode_host));
+    const double one = 1.0, mone = -1.0;
+    hipLaunchKernelGGL(k_permute, dim3(dgrid(n * t)), dim3(kDBlock), 0, s, C.d_perm, n, t, B, z, 1);
+    const int nlev = (int)C.lev.size();
+    for (int d = nlev - 1; d >= 0; --d) {
+        const fem_chol::Level &L = C.lev[d];
+        double *w = wb[d & 1];
+        const double *wc = wb[(d + 1) & 1];
+        if (L.nmid)
+            hipLaunchKernelGGL(k_mid_fwd, dim3(L.nmid), dim3(kDBlock), 0, s, C.d_nodes, L.mid, C.d_index, C.d_panel, z, t, w, wc);
+        if (!L.big.empty()) {
+            hipLaunchKernelGGL(k_big_fwd_gather, dim3((unsigned)L.big.size()), dim3(kDBlock), 0, s, C.d_nodes, L.dbig,
+                               C.d_index, z, t, w, wc);
+            for (int32_t k : L.big) {
+                const DNode &D = C.hnodes[k];
+                const int f = D.no + D.nu;
+                const double *P = C.d_panel + D.panel;
+                double *W = w + D.wunit * t;
+                if (D.no == 0) continue;
+                BCHK(rocblas_dtrsm(C.blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
+                                   rocblas_diagonal_non_unit, D.no, t, &one, P, f, W, f));
+                if (D.nu > 0)
+                    BCHK(rocblas_dgemm(C.blas, rocblas_operation_none, rocblas_operation_none, D.nu, t, D.no, &mone,
+                                       P + D.no, f, W, f, &one, W + D.no, f));
+            }
+            hipLaunchKernelGGL(k_big_store, dim3((unsigned)L.big.size()), dim3(kDBlock), 0, s, C.d_nodes, L.dbig, t, w, z);
+        }
+        DCHK(hipGetLastError());
+    }
+    for (int d = 0; d < nlev; ++d) {
+        const fem_chol::Level &L = C.lev[d];
+        double *w = wb[0];
+        if (L.nmid) hipLaunchKernelGGL(k_mid_bwd, dim3(L.nmid), dim3(kDBlock), 0, s, C.d_nodes, L.mid, C.d_index, C.d_panel, z, t, w);
+        if (!L.big.empty()) {
+            hipLaunchKernelGGL(k_big_bwd_gather, dim3((unsigned)L.big.size()), dim3(kDBlock), 0, s, C.d_nodes, L.dbig,
+                               C.d_index, z, t, w);
+            for (int32_t k : L.big) {
+                const DNode &D = C.hnodes[k];
+                const int f = D.no + D.nu;
+                const double *P = C.d_panel + D.panel;
+                double *W = w + D.wunit * t;
+                if (D.no == 0) continue;
+                if (D.nu > 0)
+                    BCHK(rocblas_dgemm(C.blas, rocblas_operation_transpose, rocblas_operation_none, D.no, t, D.nu, &mone,
+                                       P + D.no, f, W + D.no, f, &one, W, f));
+                BCHK(rocblas_dtrsm(C.blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_transpose,
+                                   rocblas_diagonal_non_unit, D.no, t, &one, P, f, W, f));
+            }
+            hipLaunchKernelGGL(k_big_store, dim3((unsigned)L.big.size()), dim3(kDBlock), 0, s, C.d_nodes, L.dbig, t, w, z);
+        }
+        DCHK(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_permute, dim3(dgrid(n * t)), dim3(kDBlock), 0, s, C.d_perm, n, t, z, X, 0);
+    DCHK(hipGetLastError());
+    DCHK(hipStreamSynchronize(s));
+    return FEMCG_OK;
+}
+
+}  // namespace femcg
+
+using namespace femcg;
+
+fem_chol::~fem_chol()
+{
+    if (d_nodes) (void)hipFree(d_nodes);
+    if (d_perm) (void)hipFree(d_perm);
+    if (d_index) (void)hipFree(d_index);
+    if (d_panel) (void)hipFree(d_panel);
+    if (d_lists) (void)hipFree(d_lists);
+    if (d_fail) (void)hipFree(d_fail);
+    if (blas) (void)rocblas_destroy_handle(blas);
+}
+
+extern "C" int chol_analyze(const fem_matrix *A, chol_stats_t *out, int32_t *perm_out)
+{
+    if (!A || !out) return fail(FEMCG_EINVAL, "NULL argument");
+    try {
+        fem_chol C;
+        int rc = chol_symbolic(A->hs, C);
+        if (rc) return rc;
+        *out = C.stats;
+        if (perm_out) std::copy(C.perm.begin(), C.perm.end(), perm_out);
+        return FEMCG_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(FEMCG_ENOMEM, "chol_analyze: host allocation failed");
+    }
+}
+
+extern "C" int chol_factor(fem_matrix *A, fem_chol **out, void *stream)
+{
+    if (!A || !out) return fail(FEMCG_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (int rc = require_device(A)) return rc;
+    try {
+        const double t0 = now_s();
+        auto C = std::make_unique<fem_chol>();
+        int rc = chol_symbolic(A->hs, *C);
+        if (rc) return rc;
+        const double t1 = now_s();
+        if ((rc = chol_setup(A->hs, *C))) return rc;
+        if (rocblas_create_handle(&C->blas) != rocblas_status_success)
+            return fail(FEMCG_EDEVICE, "rocblas_create_handle failed");
+        const double t2 = now_s();
+        if ((rc = chol_numeric(*C, (hipStream_t)stream))) return rc;
+        const double t3 = now_s();
+        C->stats.symbolic_s += t2 - t1;  // host set-up and uploads belong to the symbolic phase
+        C->stats.factor_s = t3 - t2;
+        C->stats.total_s = t3 - t0;
+        *out = C.release();
+        return FEMCG_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(FEMCG_ENOMEM, "chol_factor: host allocation failed");
+    }
+}
+
+extern "C" int chol_solve(fem_chol *L, const double *B, double *X, int32_t k, void *stream)
+{
+    if (!L || !B || !X) return fail(FEMCG_EINVAL, "NULL argument");
+    if (k < 1) return fail(FEMCG_EINVAL, "k=%d", k);
+    try {
+        const double t0 = now_s();
+        int rc = chol_solve_impl(*L, B, X, k, (hipStream_t)stream);
+        L->stats.solve_s = now_s() - t0;
+        return rc;
+    } catch (const std::bad_alloc &) {
+        return fail(FEMCG_ENOMEM, "chol_solve: host allocation failed");
+    }
+}
+
+extern "C" int chol_stats(const fem_chol *L, chol_stats_t *out)
+{
+    if (!L || !out) return fail(FEMCG_EINVAL, "NULL argument");
+    *out = L->stats;
+    return FEMCG_OK;
+}
+
+extern "C" void chol_free(fem_chol *L)
+{
+    delete L;
+}

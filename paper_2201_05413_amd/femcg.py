@@ -41,7 +41,7 @@ EXPORTS = ["pcg_default_opts", "fem_assemble", "fem_dofs", "fem_csr", "fem_rhs",
            "pcg_solve_batch", "pcg_stats", "fem_tune", "pcg_tune", "fem_set_format", "fem_set_tiling", "pcg_time_kernel", "pcg_time_spmm_cold", "bicgstab_solve",
            "fem_free",
            "fem_last_error", "serve_create", "serve_submit", "serve_step", "serve_poll", "serve_clock",
-           "serve_destroy"]
+           "serve_destroy", "chol_analyze", "chol_factor", "chol_solve", "chol_stats", "chol_free"]
 
 
 class FemcgError(RuntimeError):
@@ -59,6 +59,16 @@ class pcg_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int64), ("precision", C.c_int32),
                 ("inner_eta", C.c_double), ("check_every", C.c_int32), ("use_x0", C.c_int32),
                 ("max_restarts", C.c_int32), ("max_outer", C.c_int32), ("use_graph", C.c_int32)]
+
+
+class chol_stats_t(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz_l", C.c_int64), ("nodes", C.c_int32), ("levels", C.c_int32),
+                ("max_front", C.c_int32), ("pad", C.c_int32), ("flops", C.c_double), ("factor_mb", C.c_double),
+                ("work_mb", C.c_double), ("order_s", C.c_double), ("symbolic_s", C.c_double),
+                ("factor_s", C.c_double), ("total_s", C.c_double), ("solve_s", C.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "pad"}
 
 
 class pcg_tune_report(C.Structure):
@@ -128,6 +138,11 @@ def lib():
         "pcg_stats": (C.c_int, [P, C.POINTER(pcg_stats_t)]),
         "fem_tune": (C.c_int, [P, I32, I32, C.POINTER(I32), C.POINTER(I32), P]),
         "pcg_tune": (C.c_int, [P, P, I32, D, C.POINTER(pcg_opts), C.POINTER(pcg_tune_report), P]),
+        "chol_analyze": (C.c_int, [P, C.POINTER(chol_stats_t), P]),
+        "chol_factor": (C.c_int, [P, C.POINTER(P), P]),
+        "chol_solve": (C.c_int, [P, P, P, I32, P]),
+        "chol_stats": (C.c_int, [P, C.POINTER(chol_stats_t)]),
+        "chol_free": (None, [P]),
         "fem_set_format": (C.c_int, [P, I32, I32, I32]),
         "fem_set_tiling": (C.c_int, [P, I32, I32]),
         "pcg_time_kernel": (C.c_int, [P, I32, I32, P, C.POINTER(D), C.POINTER(D)]),
@@ -340,6 +355,47 @@ def pcg_tune(A, B, tol, opts=None, stream=None):
     rep = pcg_tune_report()
     _check(lib().pcg_tune(A.h, _dev_ptr(B), k, tol, C.byref(o), C.byref(rep), _stream(stream)))
     return o, rep.as_dict()
+
+
+def chol_analyze(A):
+    """Nested-dissection ordering and symbolic analysis of A (host only):
+    returns (stats dict, perm), perm[p] = free row at elimination position p."""
+    import numpy as np
+    st = chol_stats_t()
+    perm = np.zeros(max(A.n_free, 1), dtype=np.int32)
+    _check(lib().chol_analyze(A.h, C.byref(st), _np_ptr(perm)))
+    return st.as_dict(), perm[: A.n_free]
+
+
+class Chol:
+    """Sparse Cholesky factor of A = K_II on the device (chol_factor)."""
+
+    def __init__(self, A, stream=None):
+        self.h = C.c_void_p()
+        self.n = A.n_free
+        _check(lib().chol_factor(A.h, C.byref(self.h), _stream(stream)))
+
+    def solve(self, B, X, stream=None):
+        if B.shape != X.shape or B.shape[0] != self.n:
+            raise ValueError("B and X must be [n_free][k]")
+        _check(lib().chol_solve(self.h, _dev_ptr(B), _dev_ptr(X), B.shape[1], _stream(stream)))
+        return X
+
+    def stats(self):
+        st = chol_stats_t()
+        _check(lib().chol_stats(self.h, C.byref(st)))
+        return st.as_dict()
+
+    def free(self):
+        if self.h:
+            lib().chol_free(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def pcg_time_spmm_cold(mats, k, precision=PCG_FP64, reps=5, stream=None):

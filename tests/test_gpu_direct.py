@@ -1,0 +1,90 @@
+"""The direct solver (sparse Cholesky, Sect. 4.3) through the C ABI against
+the oracle: the dense Cholesky solve on small systems, the PCG solution at
+1e-14 on larger ones (fronts beyond the one-workgroup size included), and
+the oracle's own Eq. (2) residual everywhere; a block of right-hand sides
+against one-column solves; full-size C2."""
+import numpy as np
+import pytest
+
+import meshgen
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2201_05413_amd import femcg  # noqa: E402
+
+
+def _setup(dim, m, jit, order, k, seed):
+    mesh = meshgen.make_mesh(dim, m, jit, seed)
+    orc = oracle.System(mesh, order)
+    A = femcg.Matrix(mesh, order, femcg.FEM_FORMAT_SELL)
+    g = meshgen.harmonic_eval(meshgen.random_coeffs(dim, k, seed + 1), A.dofs()[0])
+    B = torch.empty((A.n_free, k), dtype=torch.float64, device="cuda")
+    femcg.fem_rhs(A, g, B)
+    return orc, A, g, B
+
+
+def _solve(L, B):
+    X = torch.full_like(B, np.nan)
+    L.solve(B, X)
+    torch.cuda.synchronize()
+    return X.cpu().numpy()
+
+
+@pytest.mark.parametrize("dim,m,jit,order,k", [(2, 30, 0.3, 1, 1), (2, 14, 0.25, 2, 3), (2, 9, 0.3, 3, 2),
+                                               (2, 8, 0.2, 4, 1), (3, 9, 0.3, 1, 4), (3, 6, 0.25, 2, 2)])
+def test_small_systems_match_dense_cholesky(dim, m, jit, order, k):
+    orc, A, g, B = _setup(dim, m, jit, order, k, 50 + m)
+    assert A.n_free <= 3000
+    L = femcg.Chol(A)
+    x = _solve(L, B)
+    rp, col, val = orc.A()
+    Bo = orc.rhs(g)
+    xd, _, st = oracle.dense_cholesky(rp, col, val, Bo)
+    assert st == 0
+    for j in range(k):
+        assert np.linalg.norm(x[:, j] - xd[:, j]) <= 1e-11 * np.linalg.norm(xd[:, j])
+    assert np.all(orc.relres(Bo, x) <= 1e-13)
+    s = L.stats()
+    assert s["n"] == A.n_free and s["factor_s"] > 0 and s["solve_s"] > 0
+
+
+@pytest.mark.parametrize("dim,m,jit,order,k", [(2, 160, 0.3, 1, 2), (3, 40, 0.0, 1, 3), (3, 16, 0.3, 2, 2)])
+def test_larger_systems_match_oracle_pcg(dim, m, jit, order, k):
+    orc, A, g, B = _setup(dim, m, jit, order, k, 60 + m)
+    L = femcg.Chol(A)
+    st = L.stats()
+    x = _solve(L, B)
+    Bo = orc.rhs(g)
+    assert np.all(orc.relres(Bo, x) <= 1e-12)
+    xs, _, _, _, sp = orc.pcg(Bo, 1e-14)
+    assert sp == 0
+    for j in range(k):
+        assert np.linalg.norm(x[:, j] - xs[:, j]) <= 1e-9 * np.linalg.norm(xs[:, j])
+    if dim == 3 and order == 1:
+        assert st["max_front"] > 1024  # the rocBLAS / rocSOLVER path ran
+    # the block of k right-hand sides against one column at a time
+    for j in range(k):
+        xj = _solve(L, B[:, j:j + 1].contiguous())
+        assert np.linalg.norm(xj[:, 0] - x[:, j]) <= 1e-13 * np.linalg.norm(x[:, j])
+
+
+def test_factor_rejects_host_only_matrix():
+    mesh = meshgen.make_mesh(2, 12, 0.2, 70)
+    H = femcg.Matrix(mesh, 1, femcg.FEM_FORMAT_CSR | femcg.FEM_ASSEMBLE_HOST_ONLY)
+    with pytest.raises(femcg.FemcgError) as e:
+        femcg.Chol(H)
+    assert e.value.code == femcg.FEMCG_EINVAL
+
+
+def test_full_size_c2_residual():
+    w = meshgen.c2()
+    A = femcg.Matrix(w.mesh, w.order, femcg.FEM_FORMAT_SELL)
+    g = w.dirichlet(A.dofs()[0])
+    B = torch.empty((A.n_free, 1), dtype=torch.float64, device="cuda")
+    femcg.fem_rhs(A, g, B)
+    L = femcg.Chol(A)
+    x = _solve(L, B)
+    orc = oracle.System(w.mesh, w.order)
+    assert orc.relres(orc.rhs(g), x)[0] <= 1e-12
