@@ -46,6 +46,7 @@ constexpr int kLeaf = 64;         // nested-dissection leaves: at most this many
 constexpr int kMidFront = 1024;   // fronts up to this size: one workgroup each
 constexpr int kPanel = 8;         // columns per LDS panel in the workgroup kernels
 constexpr int kDBlock = 256;      // threads per workgroup of the direct kernels
+constexpr int kSolveLds = 8192;   // doubles of LDS per solve workgroup (64 KB)
 
 struct ChNode {
     int64_t b = 0, e = 0;          // own positions [b, e)
@@ -90,6 +91,9 @@ struct fem_chol {
         int32_t nall = 0, nmid = 0;
         std::vector<int32_t> big;                // node ids of larger fronts (host loop)
         int32_t *dbig = nullptr;                 // the same on the device
+        int32_t *dbigtri = nullptr;              // larger fronts whose own block has <= kMidFront columns
+        int32_t nbigtri = 0;
+        int32_t mid_rows = 0, tri_rows = 0;      // LDS rows of the factor launches (largest f, largest no)
         int64_t panel0 = 0, panel1 = 0;          // the level's range in the panel store
         int64_t udoubles = 0;                    // update blocks of the level's nodes
         int64_t wunits = 0;                      // sum of f over the level's nodes
@@ -371,21 +375,26 @@ __global__ __launch_bounds__(kDBlock) void k_extend_add(const DNode *nodes, cons
 // Partial Cholesky of one front (f <= kMidFront) per workgroup, right-looking
 // in panels of kPanel columns staged in LDS: factor the panel's columns,
 // write them back, then update every later column (panel and update block)
-// with the panel, each entry once per panel in a fixed order.
+// with the panel, each entry once per panel in a fixed order.  With
+// diag_only, only the own block F11 (no <= kMidFront) is factorised, in
+// place in the panel (ld f): the larger fronts' L21 and U then come from
+// TRSM and SYRK.  Dynamic LDS: (rows of the largest front of the launch) x
+// kPanel doubles.
 __global__ __launch_bounds__(kDBlock) void k_mid_factor(const DNode *nodes, const int32_t *list, double *panel,
-                                                        double *ubuf, int32_t *fail)
+                                                        double *ubuf, int32_t *fail, int diag_only)
 {
-    __shared__ double P[kMidFront * kPanel];  // P[(r - k0) * kPanel + j] = F(r, k0 + j)
+    extern __shared__ double P[];  // P[(r - k0) * kPanel + j] = F(r, k0 + j)
     __shared__ int s_bad;
     const DNode D = nodes[list[blockIdx.x]];
     const Front F = front_of(D, panel, ubuf);
-    const int f = F.f, no = F.no, tid = threadIdx.x;
+    const int ld = F.f, no = F.no, tid = threadIdx.x;
+    const int f = diag_only ? no : ld;  // rows and columns processed
     if (tid == 0) s_bad = 0;
     for (int k0 = 0; k0 < no; k0 += kPanel) {
         const int kw = min(kPanel, no - k0), rows = f - k0;
         for (int i = tid; i < rows * kw; i += kDBlock) {
             const int r = i / kw, j = i - r * kw;
-            P[r * kPanel + j] = F.panel[(k0 + r) + (int64_t)(k0 + j) * f];
+            P[r * kPanel + j] = F.panel[(k0 + r) + (int64_t)(k0 + j) * ld];
         }
         __syncthreads();
         for (int j = 0; j < kw; ++j) {
@@ -403,7 +412,7 @@ __global__ __launch_bounds__(kDBlock) void k_mid_factor(const DNode *nodes, cons
         }
         for (int i = tid; i < rows * kw; i += kDBlock) {
             const int r = i / kw, j = i - r * kw;
-            F.panel[(k0 + r) + (int64_t)(k0 + j) * f] = P[r * kPanel + j];
+            F.panel[(k0 + r) + (int64_t)(k0 + j) * ld] = P[r * kPanel + j];
         }
         for (int c = k0 + kw; c < f; ++c) {
             double pc[kPanel];
@@ -486,58 +495,185 @@ __device__ void own_store(const DNode &D, const double *W, int t, double *z)
     }
 }
 
-// Whole forward step of a front up to kMidFront: gather, y = L11^-1 w
-// (column by column), w_upd -= L21 y, store y.
+// The panel's diagonal block, T[j][i] = L(k0 + j, k0 + i) for i <= j < kw,
+// read by all threads at once (one round trip), then a barrier.
+__device__ void stage_triangle(const double *L, int f, int k0, int kw, double *T)
+{
+    for (int e = threadIdx.x; e < kPanel * kPanel; e += kDBlock) {
+        const int j = e / kPanel, i = e - j * kPanel;
+        T[e] = (j < kw && i <= j) ? L[(k0 + j) + (int64_t)(k0 + i) * f] : 0.0;
+    }
+    __syncthreads();
+}
+
+// Forward substitution with L11 on the own rows [0, no) of W (f x t, ld f),
+// applying L21 to the rows [no, rend) as well when rend = f (rend = no: L11
+// only).  Chunks of tc right-hand sides are staged in LDS (rend x tc, S), and
+// L11 is walked in panels of kPanel columns: lane c solves the panel's
+// triangle for column c on its own, then every later row loses the panel's
+// contribution (sum over the panel's columns in order) in one pass.
+__device__ void fwd_lds(const double *L, int f, int no, int rend, double *W, int t, double *S)
+{
+    __shared__ double T[kPanel * kPanel];
+    const int tid = threadIdx.x;
+    const int tcm = max(1, min(t, kSolveLds / max(rend, 1)));
+    for (int c0 = 0; c0 < t; c0 += tcm) {
+        const int tc = min(tcm, t - c0);
+        for (int64_t e = tid; e < (int64_t)rend * tc; e += kDBlock) {
+            const int c = (int)(e / rend), r = (int)(e - (int64_t)c * rend);
+            S[r * tc + c] = W[r + (int64_t)(c0 + c) * f];
+        }
+        __syncthreads();
+        for (int k0 = 0; k0 < no; k0 += kPanel) {
+            const int kw = min(kPanel, no - k0);
+            stage_triangle(L, f, k0, kw, T);
+            for (int c = tid; c < tc; c += kDBlock) {
+                double x[kPanel];
+#pragma unroll
+                for (int j = 0; j < kPanel; ++j) {
+                    if (j >= kw) break;
+                    double v = S[(k0 + j) * tc + c];
+#pragma unroll
+                    for (int i = 0; i < j; ++i) v -= T[j * kPanel + i] * x[i];
+                    x[j] = v / T[j * kPanel + j];
+                    S[(k0 + j) * tc + c] = x[j];
+                }
+            }
+            __syncthreads();
+            const int r0 = k0 + kw, nr = rend - r0;
+            for (int64_t e = tid; e < (int64_t)nr * tc; e += kDBlock) {
+                const int c = (int)(e / nr), r = r0 + (int)(e - (int64_t)c * nr);
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < kPanel; ++j)
+                    if (j < kw) acc += L[r + (int64_t)(k0 + j) * f] * S[(k0 + j) * tc + c];
+                S[r * tc + c] -= acc;
+            }
+            __syncthreads();
+        }
+        for (int64_t e = tid; e < (int64_t)rend * tc; e += kDBlock) {
+            const int c = (int)(e / rend), r = (int)(e - (int64_t)c * rend);
+            W[r + (int64_t)(c0 + c) * f] = S[r * tc + c];
+        }
+        __syncthreads();
+    }
+}
+
+// Backward: with apply21 the own rows first lose L21^T w_upd (rows no..f-1
+// of W, the ancestors' x), then L11^T back substitution in panels from the
+// last (lane c solves the panel's triangle for column c; earlier rows then
+// lose the panel's contribution).  Chunks of right-hand sides in LDS.
+__device__ void bwd_lds(const double *L, int f, int no, int apply21, double *W, int t, double *S)
+{
+    __shared__ double T[kPanel * kPanel];
+    const int tid = threadIdx.x;
+    const int rows = apply21 ? f : no, nu = f - no;
+    const int tcm = max(1, min(t, kSolveLds / max(rows, 1)));
+    for (int c0 = 0; c0 < t; c0 += tcm) {
+        const int tc = min(tcm, t - c0);
+        for (int64_t e = tid; e < (int64_t)rows * tc; e += kDBlock) {
+            const int c = (int)(e / rows), r = (int)(e - (int64_t)c * rows);
+            S[r * tc + c] = W[r + (int64_t)(c0 + c) * f];
+        }
+        __syncthreads();
+        if (apply21 && nu > 0) {
+            for (int64_t e = tid; e < (int64_t)no * tc; e += kDBlock) {
+                const int i = (int)(e / tc), c = (int)(e - (int64_t)i * tc);
+                const double *Li = L + no + (int64_t)i * f;
+                const double *Sa = S + no * tc + c;
+                // four interleaved partial sums, combined in a fixed order
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                int a = 0;
+                for (; a + 4 <= nu; a += 4) {
+                    a0 += Li[a] * Sa[(int64_t)a * tc];
+                    a1 += Li[a + 1] * Sa[(int64_t)(a + 1) * tc];
+                    a2 += Li[a + 2] * Sa[(int64_t)(a + 2) * tc];
+                    a3 += Li[a + 3] * Sa[(int64_t)(a + 3) * tc];
+                }
+                for (; a < nu; ++a) a0 += Li[a] * Sa[(int64_t)a * tc];
+                S[i * tc + c] -= (a0 + a1) + (a2 + a3);
+            }
+            __syncthreads();
+        }
+        for (int k0 = ((no - 1) / kPanel) * kPanel; k0 >= 0 && no > 0; k0 -= kPanel) {
+            const int kw = min(kPanel, no - k0);
+            stage_triangle(L, f, k0, kw, T);
+            for (int c = tid; c < tc; c += kDBlock) {
+                double x[kPanel];
+#pragma unroll
+                for (int j = kPanel - 1; j >= 0; --j) {
+                    if (j >= kw) continue;
+                    double v = S[(k0 + j) * tc + c];
+#pragma unroll
+                    for (int i = j + 1; i < kPanel; ++i)
+                        if (i < kw) v -= T[i * kPanel + j] * x[i];
+                    x[j] = v / T[j * kPanel + j];
+                    S[(k0 + j) * tc + c] = x[j];
+                }
+            }
+            __syncthreads();
+            for (int64_t e = tid; e < (int64_t)k0 * tc; e += kDBlock) {
+                const int c = (int)(e / k0), r = (int)(e - (int64_t)c * k0);
+                const double *Lr = L + k0 + (int64_t)r * f;
+                double acc = 0.0;
+#pragma unroll
+                for (int j = 0; j < kPanel; ++j)
+                    if (j < kw) acc += Lr[j] * S[(k0 + j) * tc + c];
+                S[r * tc + c] -= acc;
+            }
+            __syncthreads();
+        }
+        for (int64_t e = tid; e < (int64_t)no * tc; e += kDBlock) {
+            const int c = (int)(e / no), r = (int)(e - (int64_t)c * no);
+            W[r + (int64_t)(c0 + c) * f] = S[r * tc + c];
+        }
+        __syncthreads();
+    }
+}
+
+// Whole forward step of a front up to kMidFront: gather, y = L11^-1 w,
+// w_upd -= L21 y, store y.  Dynamic LDS: kSolveLds doubles.
 __global__ __launch_bounds__(kDBlock) void k_mid_fwd(const DNode *nodes, const int32_t *list, const int64_t *index,
                                                      const double *panel, double *z, int t, double *wbuf,
                                                      const double *wchild)
 {
+    extern __shared__ double S[];
     const DNode D = nodes[list[blockIdx.x]];
     const int f = D.no + D.nu;
     double *W = wbuf + D.wunit * t;
-    const double *L = panel + D.panel;
     fwd_gather(D, nodes, index, z, t, W, wchild);
-    for (int k = 0; k < D.no; ++k) {
-        const double dk = L[k + (int64_t)k * f];
-        for (int c = threadIdx.x; c < t; c += kDBlock) W[k + (int64_t)c * f] /= dk;
-        __syncthreads();
-        const int rows = f - k - 1;
-        for (int64_t e = threadIdx.x; e < (int64_t)rows * t; e += kDBlock) {
-            const int c = (int)(e / rows), r = k + 1 + (int)(e - (int64_t)c * rows);
-            W[r + (int64_t)c * f] -= L[r + (int64_t)k * f] * W[k + (int64_t)c * f];
-        }
-        __syncthreads();
-    }
+    fwd_lds(panel + D.panel, f, D.no, f, W, t, S);
     own_store(D, W, t, z);
 }
 
+// The L11 parts of larger fronts (no <= kMidFront; their L21 products run as
+// GEMMs): forward and backward substitution on the own rows of W.
+__global__ __launch_bounds__(kDBlock) void k_tri_fwd(const DNode *nodes, const int32_t *list, const double *panel,
+                                                     int t, double *wbuf)
+{
+    extern __shared__ double S[];
+    const DNode D = nodes[list[blockIdx.x]];
+    fwd_lds(panel + D.panel, D.no + D.nu, D.no, D.no, wbuf + D.wunit * t, t, S);
+}
+__global__ __launch_bounds__(kDBlock) void k_tri_bwd(const DNode *nodes, const int32_t *list, const double *panel,
+                                                     int t, double *wbuf)
+{
+    extern __shared__ double S[];
+    const DNode D = nodes[list[blockIdx.x]];
+    bwd_lds(panel + D.panel, D.no + D.nu, D.no, 0, wbuf + D.wunit * t, t, S);
+}
+
 // Whole backward step of a front up to kMidFront: gather, w -= L21^T x_upd,
-// x = L11^-T w (from the last column), store x.
+// x = L11^-T w, store x.
 __global__ __launch_bounds__(kDBlock) void k_mid_bwd(const DNode *nodes, const int32_t *list, const int64_t *index,
                                                      const double *panel, double *z, int t, double *wbuf)
 {
+    extern __shared__ double S[];
     const DNode D = nodes[list[blockIdx.x]];
     const int f = D.no + D.nu;
     double *W = wbuf + D.wunit * t;
-    const double *L = panel + D.panel;
     bwd_gather(D, index, z, t, W);
-    for (int64_t e = threadIdx.x; e < (int64_t)D.no * t; e += kDBlock) {
-        const int c = (int)(e / D.no), i = (int)(e - (int64_t)c * D.no);
-        double acc = 0.0;
-        for (int a = 0; a < D.nu; ++a) acc += L[(D.no + a) + (int64_t)i * f] * W[(D.no + a) + (int64_t)c * f];
-        W[i + (int64_t)c * f] -= acc;
-    }
-    __syncthreads();
-    for (int k = D.no - 1; k >= 0; --k) {
-        const double dk = L[k + (int64_t)k * f];
-        for (int c = threadIdx.x; c < t; c += kDBlock) W[k + (int64_t)c * f] /= dk;
-        __syncthreads();
-        for (int64_t e = threadIdx.x; e < (int64_t)k * t; e += kDBlock) {
-            const int c = (int)(e / k), r = (int)(e - (int64_t)c * k);
-            W[r + (int64_t)c * f] -= L[k + (int64_t)r * f] * W[k + (int64_t)c * f];
-        }
-        __syncthreads();
-    }
+    bwd_lds(panel + D.panel, f, D.no, 1, W, t, S);
     own_store(D, W, t, z);
 }
 
@@ -675,13 +811,23 @@ int chol_setup(const HostSystem &hs, fem_chol &C)
         return off;
     };
     struct Off {
-        size_t all, mid, big, ea[2], dst, val;
+        size_t all, mid, big, bigtri, ea[2], dst, val;
     };
     std::vector<Off> off(nlev);
-    std::vector<std::vector<int32_t>> mid(nlev), big(nlev), ea0(nlev), ea1(nlev);
+    std::vector<std::vector<int32_t>> mid(nlev), big(nlev), bigtri(nlev), ea0(nlev), ea1(nlev);
     for (int d = 0; d < nlev; ++d) {
         for (int32_t k : C.levels[d]) {
-            (C.nodes[k].f() <= kMidFront ? mid[d] : big[d]).push_back(k);
+            const ChNode &nd = C.nodes[k];
+            if (nd.f() <= kMidFront) {
+                mid[d].push_back(k);
+                C.lev[d].mid_rows = std::max<int32_t>(C.lev[d].mid_rows, (int32_t)nd.f());
+            } else {
+                big[d].push_back(k);
+                if (nd.no() > 0 && nd.no() <= kMidFront) {
+                    bigtri[d].push_back(k);
+                    C.lev[d].tri_rows = std::max<int32_t>(C.lev[d].tri_rows, (int32_t)nd.no());
+                }
+            }
             for (int s = 0; s < 2; ++s) {
                 const int c = C.nodes[k].child[s];
                 if (c < 0) continue;
@@ -695,6 +841,7 @@ int chol_setup(const HostSystem &hs, fem_chol &C)
         off[d].all = reserve(C.levels[d].size() * 4);
         off[d].mid = reserve(mid[d].size() * 4);
         off[d].big = reserve(big[d].size() * 4);
+        off[d].bigtri = reserve(bigtri[d].size() * 4);
         off[d].ea[0] = reserve(ea0[d].size() * 4);
         off[d].ea[1] = reserve(ea1[d].size() * 4);
         off[d].dst = reserve(adst[d].size() * 8);
@@ -718,6 +865,7 @@ int chol_setup(const HostSystem &hs, fem_chol &C)
         if ((rc = put(off[d].all, C.levels[d].data(), C.levels[d].size() * 4)) ||
             (rc = put(off[d].mid, mid[d].data(), mid[d].size() * 4)) ||
             (rc = put(off[d].big, big[d].data(), big[d].size() * 4)) ||
+            (rc = put(off[d].bigtri, bigtri[d].data(), bigtri[d].size() * 4)) ||
             (rc = put(off[d].ea[0], ea0[d].data(), ea0[d].size() * 4)) ||
             (rc = put(off[d].ea[1], ea1[d].data(), ea1[d].size() * 4)) ||
             (rc = put(off[d].dst, adst[d].data(), adst[d].size() * 8)) ||
@@ -729,6 +877,8 @@ int chol_setup(const HostSystem &hs, fem_chol &C)
         L.nmid = (int32_t)mid[d].size();
         L.big = big[d];
         L.dbig = (int32_t *)(C.d_lists + off[d].big);
+        L.dbigtri = (int32_t *)(C.d_lists + off[d].bigtri);
+        L.nbigtri = (int32_t)bigtri[d].size();
         L.ea_cols[0] = (int32_t *)(C.d_lists + off[d].ea[0]);
         L.ea_cols[1] = (int32_t *)(C.d_lists + off[d].ea[1]);
         L.nea[0] = (int64_t)ea0[d].size() / 2;
@@ -766,6 +916,8 @@ int chol_numeric(fem_chol &C, hipStream_t s)
     DCHK(hipMemsetAsync(C.d_fail, 0, sizeof(int32_t), s));
     BCHK(rocblas_set_stream(C.blas, s));
     BCHK(rocblas_set_pointer_mode(C.blas, rocblas_pointer_mode_host));
+    DCHK(hipFuncSetAttribute((const void *)k_mid_factor, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(sizeof(double) * kMidFront * kPanel)));
     const int nlev = (int)C.lev.size();
     int64_t ib = 0;
     for (int d = nlev - 1; d >= 0; --d) {
@@ -779,13 +931,18 @@ int chol_numeric(fem_chol &C, hipStream_t s)
             if (L.nea[sl])
                 hipLaunchKernelGGL(k_extend_add, dim3((unsigned)L.nea[sl]), dim3(kDBlock), 0, s, C.d_nodes, L.ea_cols[sl],
                                    sl, C.d_index, C.d_panel, u, uc);
-        if (L.nmid) hipLaunchKernelGGL(k_mid_factor, dim3(L.nmid), dim3(kDBlock), 0, s, C.d_nodes, L.mid, C.d_panel, u, C.d_fail);
+        if (L.nmid)
+            hipLaunchKernelGGL(k_mid_factor, dim3(L.nmid), dim3(kDBlock), sizeof(double) * L.mid_rows * kPanel, s,
+                               C.d_nodes, L.mid, C.d_panel, u, C.d_fail, 0);
+        if (L.nbigtri)
+            hipLaunchKernelGGL(k_mid_factor, dim3(L.nbigtri), dim3(kDBlock), sizeof(double) * L.tri_rows * kPanel, s,
+                               C.d_nodes, L.dbigtri, C.d_panel, u, C.d_fail, 1);
         DCHK(hipGetLastError());
         for (int32_t k : L.big) {
             const DNode &D = C.hnodes[k];
             const int f = D.no + D.nu;
             double *P = C.d_panel + D.panel;
-            if (D.no > 0) BCHK(rocsolver_dpotrf(C.blas, rocblas_fill_lower, D.no, P, f, info + ib));
+            if (D.no > kMidFront) BCHK(rocsolver_dpotrf(C.blas, rocblas_fill_lower, D.no, P, f, info + ib));
             ++ib;
             if (D.no > 0 && D.nu > 0) {
                 const double one = 1.0, mone = -1.0;
@@ -828,6 +985,9 @@ int chol_solve_impl(fem_chol &C, const double *B, double *X, int t, hipStream_t 
     BCHK(rocblas_set_stream(C.blas, s));
     BCHK(rocblas_set_pointer_mode(C.blas, rocblas_pointer_mode_host));
     const double one = 1.0, mone = -1.0;
+    const size_t kSolveBytes = sizeof(double) * kSolveLds;
+    for (const void *fn : {(const void *)k_mid_fwd, (const void *)k_mid_bwd, (const void *)k_tri_fwd, (const void *)k_tri_bwd})
+        DCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSolveBytes));
     hipLaunchKernelGGL(k_permute, dim3(dgrid(n * t)), dim3(kDBlock), 0, s, C.d_perm, n, t, B, z, 1);
     const int nlev = (int)C.lev.size();
     for (int d = nlev - 1; d >= 0; --d) {
@@ -835,19 +995,27 @@ int chol_solve_impl(fem_chol &C, const double *B, double *X, int t, hipStream_t 
         double *w = wb[d & 1];
         const double *wc = wb[(d + 1) & 1];
         if (L.nmid)
-            hipLaunchKernelGGL(k_mid_fwd, dim3(L.nmid), dim3(kDBlock), 0, s, C.d_nodes, L.mid, C.d_index, C.d_panel, z, t, w, wc);
+            hipLaunchKernelGGL(k_mid_fwd, dim3(L.nmid), dim3(kDBlock), kSolveBytes, s, C.d_nodes, L.mid, C.d_index, C.d_panel, z,
+                               t, w, wc);
         if (!L.big.empty()) {
             hipLaunchKernelGGL(k_big_fwd_gather, dim3((unsigned)L.big.size()), dim3(kDBlock), 0, s, C.d_nodes, L.dbig,
                                C.d_index, z, t, w, wc);
+            if (L.nbigtri)
+                hipLaunchKernelGGL(k_tri_fwd, dim3(L.nbigtri), dim3(kDBlock), kSolveBytes, s, C.d_nodes, L.dbigtri, C.d_panel,
+                                   t, w);
             for (int32_t k : L.big) {
                 const DNode &D = C.hnodes[k];
                 const int f = D.no + D.nu;
                 const double *P = C.d_panel + D.panel;
                 double *W = w + D.wunit * t;
                 if (D.no == 0) continue;
-                BCHK(rocblas_dtrsm(C.blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
-                                   rocblas_diagonal_non_unit, D.no, t, &one, P, f, W, f));
-                if (D.nu > 0)
+                if (D.no > kMidFront)
+                    BCHK(rocblas_dtrsm(C.blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
+                                       rocblas_diagonal_non_unit, D.no, t, &one, P, f, W, f));
+                if (D.nu > 0 && t == 1)
+                    BCHK(rocblas_dgemv(C.blas, rocblas_operation_none, D.nu, D.no, &mone, P + D.no, f, W, 1, &one,
+                                       W + D.no, 1));
+                else if (D.nu > 0)
                     BCHK(rocblas_dgemm(C.blas, rocblas_operation_none, rocblas_operation_none, D.nu, t, D.no, &mone,
                                        P + D.no, f, W, f, &one, W + D.no, f));
             }
@@ -858,7 +1026,9 @@ int chol_solve_impl(fem_chol &C, const double *B, double *X, int t, hipStream_t 
     for (int d = 0; d < nlev; ++d) {
         const fem_chol::Level &L = C.lev[d];
         double *w = wb[0];
-        if (L.nmid) hipLaunchKernelGGL(k_mid_bwd, dim3(L.nmid), dim3(kDBlock), 0, s, C.d_nodes, L.mid, C.d_index, C.d_panel, z, t, w);
+        if (L.nmid)
+            hipLaunchKernelGGL(k_mid_bwd, dim3(L.nmid), dim3(kDBlock), kSolveBytes, s, C.d_nodes, L.mid, C.d_index, C.d_panel,
+                               z, t, w);
         if (!L.big.empty()) {
             hipLaunchKernelGGL(k_big_bwd_gather, dim3((unsigned)L.big.size()), dim3(kDBlock), 0, s, C.d_nodes, L.dbig,
                                C.d_index, z, t, w);
@@ -868,12 +1038,19 @@ int chol_solve_impl(fem_chol &C, const double *B, double *X, int t, hipStream_t 
                 const double *P = C.d_panel + D.panel;
                 double *W = w + D.wunit * t;
                 if (D.no == 0) continue;
-                if (D.nu > 0)
+                if (D.nu > 0 && t == 1)
+                    BCHK(rocblas_dgemv(C.blas, rocblas_operation_transpose, D.nu, D.no, &mone, P + D.no, f, W + D.no, 1,
+                                       &one, W, 1));
+                else if (D.nu > 0)
                     BCHK(rocblas_dgemm(C.blas, rocblas_operation_transpose, rocblas_operation_none, D.no, t, D.nu, &mone,
                                        P + D.no, f, W + D.no, f, &one, W, f));
-                BCHK(rocblas_dtrsm(C.blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_transpose,
-                                   rocblas_diagonal_non_unit, D.no, t, &one, P, f, W, f));
+                if (D.no > kMidFront)
+                    BCHK(rocblas_dtrsm(C.blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_transpose,
+                                       rocblas_diagonal_non_unit, D.no, t, &one, P, f, W, f));
             }
+            if (L.nbigtri)
+                hipLaunchKernelGGL(k_tri_bwd, dim3(L.nbigtri), dim3(kDBlock), kSolveBytes, s, C.d_nodes, L.dbigtri, C.d_panel,
+                                   t, w);
             hipLaunchKernelGGL(k_big_store, dim3((unsigned)L.big.size()), dim3(kDBlock), 0, s, C.d_nodes, L.dbig, t, w, z);
         }
         DCHK(hipGetLastError());
