@@ -839,78 +839,128 @@ def run_bicgstab(args):
 
 
 def run_rhs(args):
-    """The iterative side of the multiple right-hand-side model of Sect. 4.3,
-    T_IS(t) = T_IS_PC + t T_IS_SOLVE: Jacobi-PCG on C3's 128^3 Kuhn cube (the
-    paper's Cube 1 grid) and on the C2 system, t = 1, 2, 4, ..., 64 random
-    harmonic right-hand sides (seed 3 / 8), tol 1e-8, solved one at a time
-    (t solves of one column) and as one block of t interleaved columns.
-    T_IS_PC is the preconditioner set-up (Jacobi: D^-1, inside the solver
-    copy) plus the tuner; T_IS_SOLVE is the least-squares slope of T_IS(t)
-    in t.  With a direct solver's factorisation and per-column solve times,
+    """The multiple right-hand-side model of Sect. 4.3 on one GPU: the
+    iterative side T_IS(t) = T_IS_PC + t T_IS_SOLVE (Jacobi-PCG) against the
+    direct side T_DS(t) = T_DS_FACT + t T_DS_SOLVE (sparse Cholesky,
+    chol_factor / chol_solve), on C3's 128^3 Kuhn cube (the paper's Cube 1
+    grid) and on the C2 system, t = 1, 2, 4, ..., 64 random harmonic
+    right-hand sides (seed 3 / 8), PCG tolerances 1e-8 and 1e-12, each side
+    solved one right-hand side at a time and as one block of t columns
+    (Eq. (3)).  T_IS_PC is the Jacobi set-up (the solver copy with D^-1,
+    rebuilt and uploaded); T_DS_FACT is the whole chol_factor (ordering,
+    symbolic analysis, numeric factorisation); FEM assembly is common to both
+    and left out.  T_IS_SOLVE and T_DS_SOLVE are least-squares slopes in t
+    (blocks) or the one-column times (one at a time), and
     t_0 = (T_DS_FACT - T_IS_PC) / (T_IS_SOLVE - T_DS_SOLVE)."""
     import numpy as np
     import torch
 
     import meshgen
+    import oracle
     from paper_2201_05413_amd import femcg
 
     torch.cuda.set_device(0)
     ts_all = [1, 2, 4, 8, 16, 32, 64]
+    tols = args.rhs_tols
     systems = [("c3_3d_p1_128", meshgen.mesh3d(128), 3, 3), ("c2_2d_p1_jit_1024", meshgen.c2().mesh, 2, 8)]
+    reps = max(1, args.steps)
     out = []
+
+    def timed(fn):
+        tt = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            tt.append(time.perf_counter() - ta)
+        return percentile(tt, 50)
+
+    def slope(rows, key):
+        tv = np.array([r["t"] for r in rows], dtype=float)
+        yv = np.array([r[key] for r in rows])
+        return float(np.polyfit(tv, yv, 1)[0])
+
+    def t0_of(fact_s, pc_s, it_ms, ds_ms):
+        den = it_ms - ds_ms
+        return round((fact_s - pc_s) * 1e3 / den, 1) if den > 0 else None
+
     for name, mesh, dim, seed in systems:
-        t0 = time.perf_counter()
         A = femcg.Matrix(mesh, 1, femcg.FEM_FORMAT_SELL)
-        t_asm = time.perf_counter() - t0
         coords, _, _ = A.dofs()
         G = meshgen.harmonic_eval(meshgen.random_coeffs(dim, max(ts_all), seed), coords)
         n = A.n_free
-        rows = []
-
-        def solve(k, reps):
-            B = torch.empty((n, k), dtype=torch.float64, device="cuda")
-            femcg.fem_rhs(A, np.ascontiguousarray(G[:, :k]), B)
-            X = torch.zeros_like(B)
-            o = femcg.default_opts(tol=1e-8, check_every=args.check_every)
-            femcg.pcg_solve(A, B, X, 1e-8, o)  # warm-up (workspace, graph)
-            tt = []
-            for _ in range(reps):
-                X.zero_()
-                torch.cuda.synchronize()
-                ta = time.perf_counter()
-                rc = femcg.pcg_solve(A, B, X, 1e-8, o)
-                torch.cuda.synchronize()
-                tt.append(time.perf_counter() - ta)
-                if rc != 0:
-                    raise RuntimeError("%s k %d status %d" % (name, k, rc))
-            st = A.stats()
-            return percentile(tt, 50), int(max(st["iters"][:k]))
-
+        Ball = torch.empty((n, max(ts_all)), dtype=torch.float64, device="cuda")
+        femcg.fem_rhs(A, np.ascontiguousarray(G), Ball)
+        fmt, cw, sg = femcg.fem_tune(A, 1, femcg.PCG_FP64)
+        # T_IS_PC: the Jacobi preconditioner lives in the solver copy (D^-1)
         t0 = time.perf_counter()
-        femcg.fem_tune(A, 1, femcg.PCG_FP64)
-        t_tune1 = time.perf_counter() - t0
-        t1, it1 = solve(1, max(1, args.steps))
+        femcg.fem_set_format(A, fmt, cw, sg)
+        t_pc = time.perf_counter() - t0
+        iterative = []
+        for tol in tols:
+            o = femcg.default_opts(tol=tol, check_every=args.check_every)
+
+            def pcg(k):
+                B = Ball[:, :k].contiguous()
+                X = torch.zeros_like(B)
+                femcg.pcg_solve(A, B, X, tol, o)  # warm-up (workspace, graph)
+
+                def run():
+                    X.zero_()
+                    rc = femcg.pcg_solve(A, B, X, tol, o)
+                    if rc != 0:
+                        raise RuntimeError("%s k %d status %d" % (name, k, rc))
+                return timed(run), int(max(A.stats()["iters"][:k]))
+
+            t1, it1 = pcg(1)
+            rows = []
+            for t in ts_all:
+                tb, itb = pcg(t)
+                rows.append(dict(t=t, block_ms=round(1e3 * tb, 3), block_ms_per_rhs=round(1e3 * tb / t, 3),
+                                 block_iters_max=itb, one_at_a_time_ms=round(1e3 * t1 * t, 3)))
+                log("%s tol %.0e t=%d: PCG block %.2f ms (%.2f per rhs, %d its), one at a time %.2f ms"
+                    % (name, tol, t, 1e3 * tb, 1e3 * tb / t, itb, 1e3 * t1 * t))
+            iterative.append(dict(tol=tol, iters_k1=it1, one_at_a_time_ms_per_rhs=round(1e3 * t1, 3),
+                                  T_IS_SOLVE_block_ms=round(slope(rows, "block_ms"), 3), rows=rows))
+        # the direct side
+        L = femcg.Chol(A)
+        cst = L.stats()
+        log("%s: chol_factor %.3f s (ordering %.3f, symbolic and set-up %.3f, numeric %.3f), nnz(L) %.3g, %.3g flops"
+            % (name, cst["total_s"], cst["order_s"], cst["symbolic_s"], cst["factor_s"], cst["nnz_l"], cst["flops"]))
+        drows = []
         for t in ts_all:
-            t0 = time.perf_counter()
-            femcg.fem_tune(A, t, femcg.PCG_FP64)
-            t_tune = time.perf_counter() - t0
-            tb, itb = solve(t, max(1, args.steps))
-            rows.append(dict(t=t, block_ms=round(1e3 * tb, 3), block_ms_per_rhs=round(1e3 * tb / t, 3),
-                             block_iters_max=itb, one_at_a_time_ms=round(1e3 * t1 * t, 3), tune_s=round(t_tune, 3)))
-            log("%s t=%d: block %.2f ms (%.2f ms per rhs, %d its), one at a time %.2f ms"
-                % (name, t, 1e3 * tb, 1e3 * tb / t, itb, 1e3 * t1 * t))
-        tv = np.array([r["t"] for r in rows], dtype=float)
-        yv = np.array([r["block_ms"] for r in rows])
-        slope, icept = np.polyfit(tv, yv, 1)
-        out.append(dict(system=name, n=n, setup_s=round(A.stats()["setup_s"], 3), assembly_wall_s=round(t_asm, 3),
-                        tune_s_k1=round(t_tune1, 3), one_at_a_time_ms_per_rhs=round(1e3 * t1, 3), iters_k1=it1,
-                        T_IS_PC_s=round(A.stats()["setup_s"] + t_tune1, 3),
-                        T_IS_SOLVE_block_ms=round(float(slope), 3), block_fit_intercept_ms=round(float(icept), 3),
-                        rows=rows))
+            B = Ball[:, :t].contiguous()
+            X = torch.empty_like(B)
+            L.solve(B, X)
+            td = timed(lambda: L.solve(B, X))
+            drows.append(dict(t=t, block_ms=round(1e3 * td, 3), block_ms_per_rhs=round(1e3 * td / t, 3)))
+            log("%s t=%d: direct block solve %.2f ms (%.3f per rhs)" % (name, t, 1e3 * td, 1e3 * td / t))
+        d1 = drows[0]["block_ms"]
+        for r in drows:
+            r["one_at_a_time_ms"] = round(d1 * r["t"], 3)
+        # parity: the oracle's Eq. (2) residual of the largest direct block
+        orc = oracle.System(mesh, 1)
+        rel = orc.relres(orc.rhs(G), X.cpu().numpy())
+        T_fact = cst["total_s"]
+        T_ds_block = slope(drows, "block_ms")
+        for it in iterative:
+            it["t0_block"] = t0_of(T_fact, t_pc, it["T_IS_SOLVE_block_ms"], T_ds_block)
+            it["t0_one_at_a_time"] = t0_of(T_fact, t_pc, it["one_at_a_time_ms_per_rhs"], d1)
+        out.append(dict(system=name, n=n, T_IS_PC_s=round(t_pc, 3), iterative=iterative,
+                        direct=dict(T_DS_FACT_s=round(T_fact, 3), order_s=round(cst["order_s"], 3),
+                                    symbolic_s=round(cst["symbolic_s"], 3), numeric_s=round(cst["factor_s"], 3),
+                                    nnz_l=cst["nnz_l"], flops=cst["flops"], max_front=cst["max_front"],
+                                    factor_mb=round(cst["factor_mb"], 1),
+                                    numeric_tflops=round(cst["flops"] / cst["factor_s"] / 1e12, 2),
+                                    T_DS_SOLVE_block_ms=round(T_ds_block, 3), one_column_ms=d1,
+                                    oracle_relres_max=float(rel.max()), rows=drows)))
+        L.free()
         A.free()
     line = {
-        "metric": "T_IS(t) = T_IS_PC + t T_IS_SOLVE (Sect. 4.3), Jacobi-PCG, blocks of t right-hand sides",
-        "value": out[0]["T_IS_SOLVE_block_ms"], "unit": "ms per right-hand side", "n_gpus": 1,
+        "metric": "t_0 = (T_DS_FACT - T_IS_PC) / (T_IS_SOLVE - T_DS_SOLVE) (Sect. 4.3): Jacobi-PCG against sparse "
+                  "Cholesky, blocks and one at a time",
+        "value": out[0]["iterative"][0]["t0_block"], "unit": "right-hand sides", "n_gpus": 1,
         "steps": args.steps, "warmup": 1, "ms_per_step": None, "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "multi_rhs", "recipe": " ".join((run_rhs.__doc__ or "").split())},
@@ -947,6 +997,8 @@ def main():
                     help="counter runs: FP64 solve capped at this many iterations, kernels timed, no JSON line")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--n-requests", type=int, default=200)
+    ap.add_argument("--rhs-tols", type=float, nargs="+", default=[1e-8, 1e-12],
+                    help="rhs workload: PCG tolerances")
     ap.add_argument("--serve-oracle-sample", type=int, default=40,
                     help="c5: served solutions checked by the oracle's residual (seeded random sample)")
     ap.add_argument("--asm-p2-sides", type=int, nargs="*", default=[48, 96],
