@@ -390,7 +390,11 @@ def run_serve(args):
     # arrival times at rate 1; a trace at rate r divides them by r
     reqs = meshgen.request_stream(args.n_requests, 1.0, seed=6, max2d=args.max2d, max3d=args.max3d)
     t0 = time.time()
-    wls = [meshgen.build_request(r) for r in reqs]
+    wls = []
+    for r in reqs:
+        wls.append(meshgen.build_request(r))
+        if len(wls) % 50 == 0:
+            log("generated %d of %d requests" % (len(wls), len(reqs)))
     log("generated %d requests in %.1f s" % (len(wls), time.time() - t0))
     # DOF coordinates (public order) of every request, for its Dirichlet data:
     # P1 = vertices; P2 = vertices then edge midpoints in (min, max) order
@@ -494,6 +498,8 @@ def run_serve(args):
         x1 = X.cpu().numpy()
         diff_fp64.append(float(np.linalg.norm(xs[i] - x1) / max(np.linalg.norm(x1), 1e-300)))
         del A, B, X
+        if (i + 1) % 25 == 0:
+            log("one at a time: %d of %d requests" % (i + 1, len(wls)))
     # accuracy of the served solutions (capacity run):
     # (R) the oracle's Eq. (2) residual on a seeded random sample of the
     #     requests the oracle assembles in seconds (n_free <= 1.5M);
@@ -509,6 +515,8 @@ def run_serve(args):
         orc = oracle.System(wls[i].mesh, wls[i].order)
         rel_sample.append(float(orc.relres(orc.rhs(gs[i]), xs[i]).max()))
         del orc
+        if len(rel_sample) % 10 == 0:
+            log("oracle check: %d of %d sampled requests" % (len(rel_sample), len(sample)))
     log("oracle residual of %d sampled served solutions in %.1f s: max %.3e"
         % (len(sample), time.time() - t0, max(rel_sample) if rel_sample else float("nan")))
     exact = [i for i in range(len(wls)) if wls[i].order == 1 and reqs[i]["jitter"] == 0.0]
