@@ -376,8 +376,9 @@ def run_serve(args):
     """Serving stream: Poisson arrivals of mixed 2D/3D, P1/P2, structured/jittered
     requests with 1..16 random harmonic right-hand sides, tol 1e-8.  First the
     server's capacity (every request submitted at once), then the same requests
-    replayed as Poisson arrivals at fractions of that capacity; one-at-a-time
-    FP64 PCG replays the trace at 0.7x capacity for comparison."""
+    replayed as Poisson arrivals at fractions of that capacity (0.5x and 1x by
+    default); one-at-a-time FP64 PCG replays the trace nearest 0.7x capacity
+    for comparison."""
     import ctypes as C
 
     import numpy as np
@@ -426,7 +427,7 @@ def run_serve(args):
     nfree = [len(f) for f in f2ds]
     xs = {}
 
-    def serve(t_arr, keep_x=False):
+    def serve(t_arr, keep_x=False, what=""):
         """Replay arrival times t_arr (seconds) through a fresh server; with
         keep_x, return every served solution as well."""
         srv = C.c_void_p()
@@ -455,6 +456,8 @@ def run_serve(args):
                                    t_done=info.t_done - t_start, relres=info.relres_max)
                     if keep_x:
                         xs[i] = X
+                    if len(done) % 25 == 0:
+                        log("%s: %d of %d requests done at %.1f s" % (what, len(done), len(wls), now))
             if open_ == 0 and nxt < len(wls):
                 time.sleep(max(0.0, min(0.01, t_arr[nxt] - (L.serve_clock(srv) - t_start))))
         L.serve_destroy(srv)
@@ -468,13 +471,13 @@ def run_serve(args):
                     p99_excl_assembly_ms=round(1e3 * percentile(lat_s, 99), 2), failed_or_above_tol=bad)
 
     base = np.array([r["t_arrival"] for r in reqs])
-    cap = serve(np.zeros(len(wls)), keep_x=True)
+    cap = serve(np.zeros(len(wls)), keep_x=True, what="capacity run")
     capacity = cap["solves_per_s"]
     log("capacity (all submitted at t=0): %.3f solves/s in %.2f s" % (capacity, cap["wall_s"]))
     sweep = []
     for f in args.serve_fractions:
         rate = f * capacity
-        r = serve(base / rate)
+        r = serve(base / rate, what="trace at %.2fx capacity" % f)
         r.update(fraction=f, rate_per_s=round(rate, 3))
         sweep.append(r)
         log("rate %.2f/s (%.1fx capacity): %.3f solves/s, p50 %.0f ms, p99 %.0f ms"
@@ -868,9 +871,12 @@ def run_rhs(args):
     from paper_2201_05413_amd import femcg
 
     torch.cuda.set_device(0)
-    ts_all = [1, 2, 4, 8, 16, 32, 64]
+    ts_all = sorted(set(args.rhs_ts) | {1})
+    if ts_all[-1] > 64:
+        raise SystemExit("--rhs-ts: at most 64 right-hand sides per block")
     tols = args.rhs_tols
-    systems = [("c3_3d_p1_128", meshgen.mesh3d(128), 3, 3), ("c2_2d_p1_jit_1024", meshgen.c2().mesh, 2, 8)]
+    systems = [("c3_3d_p1_128", meshgen.mesh3d, 128, 3, 3), ("c2_2d_p1_jit_1024", lambda m: meshgen.c2().mesh, 0, 2, 8)]
+    systems = [(nm, mk(m), d, sd) for nm, mk, m, d, sd in systems if nm[:2] in args.rhs_systems]
     reps = max(1, args.steps)
     out = []
 
@@ -1005,6 +1011,10 @@ def main():
                     help="counter runs: FP64 solve capped at this many iterations, kernels timed, no JSON line")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--n-requests", type=int, default=200)
+    ap.add_argument("--rhs-systems", nargs="+", default=["c3", "c2"], choices=["c3", "c2"],
+                    help="rhs workload: the systems (the 128^3 cube, the C2 system)")
+    ap.add_argument("--rhs-ts", type=int, nargs="+", default=[1, 2, 4, 8, 16, 32, 64],
+                    help="rhs workload: block sizes t (1 is always run)")
     ap.add_argument("--rhs-tols", type=float, nargs="+", default=[1e-8, 1e-12],
                     help="rhs workload: PCG tolerances")
     ap.add_argument("--serve-oracle-sample", type=int, default=40,
@@ -1015,7 +1025,7 @@ def main():
                     help="assembly timing: time the oracle's assembly up to this many free DOFs")
     ap.add_argument("--degrees", type=int, nargs="+", default=[1, 2, 3, 4], help="deg workload: FEM degrees")
     ap.add_argument("--deg-fp64-only", action="store_true", help="deg workload: skip the mixed solves (counter runs)")
-    ap.add_argument("--serve-fractions", type=float, nargs="+", default=[0.3, 0.7, 1.0],
+    ap.add_argument("--serve-fractions", type=float, nargs="+", default=[0.5, 1.0],
                     help="serving: arrival rates as fractions of the measured capacity")
     ap.add_argument("--slots", type=int, default=32)
     ap.add_argument("--budget-gb", type=float, default=64.0)

@@ -27,16 +27,20 @@
 //              the root (x = L^-T y, reading the ancestors' x).
 //
 // Fronts up to kMidFront are factorised and solved by one workgroup each, in
-// panels of kPanel columns staged in LDS; larger fronts use rocSOLVER's
-// POTRF and rocBLAS's TRSM / SYRK / GEMM (dense FP64, matrix cores).  Every
-// sum has a fixed order, so the factor and the solution do not depend on
-// the launch configuration.
+// panels of kPanel columns staged in LDS.  Larger fronts are factorised with
+// rocSOLVER's POTRF (own blocks above kMidFront; smaller ones by the
+// workgroup kernel) and rocBLAS's TRSM / SYRK (dense FP64, matrix cores);
+// TRTRI then replaces their L11 by L11^-1, so that their solves are matrix
+// products spread over many workgroups instead of sequential substitutions.
+// Every sum has a fixed order, so the factor and the solution do not depend
+// on the launch configuration or on the number of right-hand sides.
 #include "engine.h"
 
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <numeric>
 
@@ -47,6 +51,11 @@ constexpr int kMidFront = 1024;   // fronts up to this size: one workgroup each
 constexpr int kPanel = 8;         // columns per LDS panel in the workgroup kernels
 constexpr int kDBlock = 256;      // threads per workgroup of the direct kernels
 constexpr int kSolveLds = 8192;   // doubles of LDS per solve workgroup (64 KB)
+constexpr int kWaveLanes = 64;    // lanes per wavefront
+constexpr int kBigRows = 64;      // rows per workgroup of the larger fronts' row products (one per lane)
+constexpr int kBigCols = kDBlock / kWaveLanes;  // columns per workgroup of their column products (one per wave)
+static_assert(kDBlock / kWaveLanes == 4, "the row products add four wave partials");
+static_assert(kBigRows == kWaveLanes, "one row per lane");
 
 struct ChNode {
     int64_t b = 0, e = 0;          // own positions [b, e)
@@ -93,6 +102,10 @@ struct fem_chol {
         int32_t *dbig = nullptr;                 // the same on the device
         int32_t *dbigtri = nullptr;              // larger fronts whose own block has <= kMidFront columns
         int32_t nbigtri = 0;
+        // product-form solve items of the larger fronts, (node, first row or column) pairs:
+        // rows of L11^-1, rows of L21, columns of L21, columns of L11^-1
+        int32_t *prod[4] = {nullptr, nullptr, nullptr, nullptr};
+        int32_t nprod[4] = {0, 0, 0, 0};
         int32_t mid_rows = 0, tri_rows = 0;      // LDS rows of the factor launches (largest f, largest no)
         int64_t panel0 = 0, panel1 = 0;          // the level's range in the panel store
         int64_t udoubles = 0;                    // update blocks of the level's nodes
@@ -646,23 +659,6 @@ __global__ __launch_bounds__(kDBlock) void k_mid_fwd(const DNode *nodes, const i
     own_store(D, W, t, z);
 }
 
-// The L11 parts of larger fronts (no <= kMidFront; their L21 products run as
-// GEMMs): forward and backward substitution on the own rows of W.
-__global__ __launch_bounds__(kDBlock) void k_tri_fwd(const DNode *nodes, const int32_t *list, const double *panel,
-                                                     int t, double *wbuf)
-{
-    extern __shared__ double S[];
-    const DNode D = nodes[list[blockIdx.x]];
-    fwd_lds(panel + D.panel, D.no + D.nu, D.no, D.no, wbuf + D.wunit * t, t, S);
-}
-__global__ __launch_bounds__(kDBlock) void k_tri_bwd(const DNode *nodes, const int32_t *list, const double *panel,
-                                                     int t, double *wbuf)
-{
-    extern __shared__ double S[];
-    const DNode D = nodes[list[blockIdx.x]];
-    bwd_lds(panel + D.panel, D.no + D.nu, D.no, 0, wbuf + D.wunit * t, t, S);
-}
-
 // Whole backward step of a front up to kMidFront: gather, w -= L21^T x_upd,
 // x = L11^-T w, store x.
 __global__ __launch_bounds__(kDBlock) void k_mid_bwd(const DNode *nodes, const int32_t *list, const int64_t *index,
@@ -677,7 +673,7 @@ __global__ __launch_bounds__(kDBlock) void k_mid_bwd(const DNode *nodes, const i
     own_store(D, W, t, z);
 }
 
-// Gather / store around the rocBLAS steps of the larger fronts.
+// Gathers around the product-form steps of the larger fronts.
 __global__ __launch_bounds__(kDBlock) void k_big_fwd_gather(const DNode *nodes, const int32_t *list,
                                                             const int64_t *index, const double *z, int t,
                                                             double *wbuf, const double *wchild)
@@ -692,11 +688,98 @@ __global__ __launch_bounds__(kDBlock) void k_big_bwd_gather(const DNode *nodes, 
     const DNode D = nodes[list[blockIdx.x]];
     bwd_gather(D, index, z, t, wbuf + D.wunit * t);
 }
-__global__ __launch_bounds__(kDBlock) void k_big_store(const DNode *nodes, const int32_t *list, int t,
-                                                       const double *wbuf, double *z)
+
+// ---- larger fronts: solves in product form ----
+// A front above kMidFront keeps L11^-1 (lower triangle, from TRTRI after
+// its factorisation) in place of L11, so that both of its triangular solves
+// are matrix products with no sequential dependence:
+//   forward   y = L11^-1 w_own (to z),   w_upd -= L21 y
+//   backward  w_own -= L21^T x_upd,      x = L11^-T w_own (to z)
+// Right-hand-side columns come in chunks of TC (blockIdx.y); every column's
+// sums run in the same order whatever t is.
+
+// Row products: one workgroup per (node, chunk of 64 rows), one row per
+// lane; the four waves take contiguous quarters of the columns and their
+// partial sums are added in wave order.  own: rows of L11^-1 (columns
+// j <= r) times W's own rows, result y written to z; otherwise rows of L21
+// times y (z's own rows), subtracted from W's update rows.
+template <int TC>
+__global__ __launch_bounds__(kDBlock) void k_big_rows(const DNode *nodes, const int32_t *items, int own,
+                                                      const double *panel, double *z, int t, double *wbuf)
 {
-    const DNode D = nodes[list[blockIdx.x]];
-    own_store(D, wbuf + D.wunit * t, t, z);
+    __shared__ double part[kDBlock / kWaveLanes][TC][kWaveLanes];
+    const DNode D = nodes[items[2 * blockIdx.x]];
+    const int r0 = items[2 * blockIdx.x + 1];
+    const int f = D.no + D.nu;
+    const int c0 = blockIdx.y * TC, tcn = min(TC, t - c0);
+    const int lane = threadIdx.x & (kWaveLanes - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWaveLanes);
+    const int nrow = own ? D.no : D.nu;
+    const int r = r0 + lane;
+    const bool ok = r < nrow;
+    const int64_t prow = (own ? 0 : D.no) + (ok ? r : nrow - 1);
+    const int jend = own ? min(D.no, r0 + kWaveLanes) : D.no;
+    const int per = (jend + 3) / 4;
+    const int js = min(jend, wave * per), je = min(jend, js + per);
+    const double *P = panel + D.panel;
+    double *W = wbuf + D.wunit * t;
+    double acc[TC];
+#pragma unroll
+    for (int c = 0; c < TC; ++c) acc[c] = 0.0;
+#pragma unroll 4
+    for (int j = js; j < je; ++j) {
+        double a = P[prow + (int64_t)j * f];
+        if (own && j > r) a = 0.0;  // L11^-1 is lower triangular
+#pragma unroll
+        for (int c = 0; c < TC; ++c)
+            if (c < tcn) acc[c] += a * (own ? W[j + (int64_t)(c0 + c) * f] : z[(D.b + j) * t + c0 + c]);
+    }
+#pragma unroll
+    for (int c = 0; c < TC; ++c) part[wave][c][lane] = acc[c];
+    __syncthreads();
+    if (threadIdx.x < kWaveLanes && ok)
+        for (int c = 0; c < tcn; ++c) {
+            const double v = (part[0][c][lane] + part[1][c][lane]) + (part[2][c][lane] + part[3][c][lane]);
+            if (own) z[(D.b + r) * t + c0 + c] = v;
+            else W[D.no + r + (int64_t)(c0 + c) * f] -= v;
+        }
+}
+
+// Column products: one wave per column j (four per workgroup); lanes stride
+// the rows, then a fixed xor tree adds the lanes.  own: column j of L11^-1
+// (rows r >= j) against W's own rows, x_j written to z; otherwise column j
+// of L21 against W's update rows, subtracted from W's own row j.
+template <int TC>
+__global__ __launch_bounds__(kDBlock) void k_big_cols(const DNode *nodes, const int32_t *items, int own,
+                                                      const double *panel, double *z, int t, double *wbuf)
+{
+    const DNode D = nodes[items[2 * blockIdx.x]];
+    const int lane = threadIdx.x & (kWaveLanes - 1);
+    const int j = items[2 * blockIdx.x + 1] + (int)(threadIdx.x / kWaveLanes);
+    if (j >= D.no) return;  // whole waves only; no barrier below
+    const int f = D.no + D.nu;
+    const int c0 = blockIdx.y * TC, tcn = min(TC, t - c0);
+    const int rs = own ? j : D.no, re = own ? D.no : f;
+    const double *Pj = panel + D.panel + (int64_t)j * f;
+    double *W = wbuf + D.wunit * t;
+    double acc[TC];
+#pragma unroll
+    for (int c = 0; c < TC; ++c) acc[c] = 0.0;
+#pragma unroll 2
+    for (int r = rs + lane; r < re; r += kWaveLanes) {
+        const double a = Pj[r];
+#pragma unroll
+        for (int c = 0; c < TC; ++c)
+            if (c < tcn) acc[c] += a * W[r + (int64_t)(c0 + c) * f];
+    }
+#pragma unroll
+    for (int c = 0; c < TC; ++c)
+        for (int off = kWaveLanes / 2; off >= 1; off >>= 1) acc[c] += __shfl_xor(acc[c], off, kWaveLanes);
+    if (lane == 0)
+        for (int c = 0; c < tcn; ++c) {
+            if (own) z[(D.b + j) * t + c0 + c] = acc[c];
+            else W[j + (int64_t)(c0 + c) * f] -= acc[c];
+        }
 }
 
 }  // namespace
@@ -811,10 +894,11 @@ int chol_setup(const HostSystem &hs, fem_chol &C)
         return off;
     };
     struct Off {
-        size_t all, mid, big, bigtri, ea[2], dst, val;
+        size_t all, mid, big, bigtri, ea[2], dst, val, prod[4];
     };
     std::vector<Off> off(nlev);
     std::vector<std::vector<int32_t>> mid(nlev), big(nlev), bigtri(nlev), ea0(nlev), ea1(nlev);
+    std::vector<std::array<std::vector<int32_t>, 4>> prod(nlev);
     for (int d = 0; d < nlev; ++d) {
         for (int32_t k : C.levels[d]) {
             const ChNode &nd = C.nodes[k];
@@ -827,6 +911,13 @@ int chol_setup(const HostSystem &hs, fem_chol &C)
                     bigtri[d].push_back(k);
                     C.lev[d].tri_rows = std::max<int32_t>(C.lev[d].tri_rows, (int32_t)nd.no());
                 }
+                auto &pr = prod[d];
+                for (int32_t r = 0; r < (int32_t)nd.no(); r += kBigRows) pr[0].insert(pr[0].end(), {k, r});
+                if (nd.no() > 0)
+                    for (int32_t r = 0; r < (int32_t)nd.nu(); r += kBigRows) pr[1].insert(pr[1].end(), {k, r});
+                if (nd.nu() > 0)
+                    for (int32_t j = 0; j < (int32_t)nd.no(); j += kBigCols) pr[2].insert(pr[2].end(), {k, j});
+                for (int32_t j = 0; j < (int32_t)nd.no(); j += kBigCols) pr[3].insert(pr[3].end(), {k, j});
             }
             for (int s = 0; s < 2; ++s) {
                 const int c = C.nodes[k].child[s];
@@ -846,6 +937,7 @@ int chol_setup(const HostSystem &hs, fem_chol &C)
         off[d].ea[1] = reserve(ea1[d].size() * 4);
         off[d].dst = reserve(adst[d].size() * 8);
         off[d].val = reserve(aval[d].size() * 8);
+        for (int q = 0; q < 4; ++q) off[d].prod[q] = reserve(prod[d][q].size() * 4);
     }
     DCHK(hipMalloc((void **)&C.d_lists, std::max<size_t>(bytes, 256)));
     DCHK(hipMalloc((void **)&C.d_nodes, sizeof(DNode) * std::max<size_t>(nn, 1)));
@@ -871,6 +963,11 @@ int chol_setup(const HostSystem &hs, fem_chol &C)
             (rc = put(off[d].dst, adst[d].data(), adst[d].size() * 8)) ||
             (rc = put(off[d].val, aval[d].data(), aval[d].size() * 8)))
             return rc;
+        for (int q = 0; q < 4; ++q) {
+            if ((rc = put(off[d].prod[q], prod[d][q].data(), prod[d][q].size() * 4))) return rc;
+            L.prod[q] = (int32_t *)(C.d_lists + off[d].prod[q]);
+            L.nprod[q] = (int32_t)(prod[d][q].size() / 2);
+        }
         L.all = (int32_t *)(C.d_lists + off[d].all);
         L.mid = (int32_t *)(C.d_lists + off[d].mid);
         L.nall = (int32_t)C.levels[d].size();
@@ -911,8 +1008,9 @@ int chol_numeric(fem_chol &C, hipStream_t s)
     for (int b = 0; b < 2; ++b) DCHK(hipMalloc((void **)&ubuf[b], sizeof(double) * std::max<int64_t>(C.max_udoubles, 1)));
     int64_t nbig = 0;
     for (const auto &L : C.lev) nbig += (int64_t)L.big.size();
-    DCHK(hipMalloc((void **)&info, sizeof(int32_t) * std::max<int64_t>(nbig, 1)));
-    DCHK(hipMemsetAsync(info, 0, sizeof(int32_t) * std::max<int64_t>(nbig, 1), s));
+    // info[i]: POTRF of the i-th larger front, info[nbig + i]: its TRTRI
+    DCHK(hipMalloc((void **)&info, sizeof(int32_t) * std::max<int64_t>(2 * nbig, 1)));
+    DCHK(hipMemsetAsync(info, 0, sizeof(int32_t) * std::max<int64_t>(2 * nbig, 1), s));
     DCHK(hipMemsetAsync(C.d_fail, 0, sizeof(int32_t), s));
     BCHK(rocblas_set_stream(C.blas, s));
     BCHK(rocblas_set_pointer_mode(C.blas, rocblas_pointer_mode_host));
@@ -943,7 +1041,6 @@ int chol_numeric(fem_chol &C, hipStream_t s)
             const int f = D.no + D.nu;
             double *P = C.d_panel + D.panel;
             if (D.no > kMidFront) BCHK(rocsolver_dpotrf(C.blas, rocblas_fill_lower, D.no, P, f, info + ib));
-            ++ib;
             if (D.no > 0 && D.nu > 0) {
                 const double one = 1.0, mone = -1.0;
                 BCHK(rocblas_dtrsm(C.blas, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
@@ -951,22 +1048,52 @@ int chol_numeric(fem_chol &C, hipStream_t s)
                 BCHK(rocblas_dsyrk(C.blas, rocblas_fill_lower, rocblas_operation_none, D.nu, D.no, &mone, P + D.no, f,
                                    &one, u + D.u, D.nu));
             }
+            // L11 -> L11^-1 for the product-form solves (L21 and U no longer need L11)
+            if (D.no > 0)
+                BCHK(rocsolver_dtrtri(C.blas, rocblas_fill_lower, rocblas_diagonal_non_unit, D.no, P, f, info + nbig + ib));
+            ++ib;
         }
     }
     DCHK(hipStreamSynchronize(s));
     int32_t bad = 0;
     DCHK(hipMemcpy(&bad, C.d_fail, sizeof bad, hipMemcpyDeviceToHost));
     if (nbig) {
-        std::vector<int32_t> h(nbig);
-        DCHK(hipMemcpy(h.data(), info, sizeof(int32_t) * nbig, hipMemcpyDeviceToHost));
+        std::vector<int32_t> h(2 * nbig);
+        DCHK(hipMemcpy(h.data(), info, sizeof(int32_t) * 2 * nbig, hipMemcpyDeviceToHost));
         for (int32_t v : h) bad |= v != 0;
     }
     if (bad) return fail(FEMCG_EBREAKDOWN, "chol_factor: non-positive pivot (A not positive definite)");
     return FEMCG_OK;
 }
 
+// One product-form step of the larger fronts of a level: q = 0..3 as in
+// Level::prod, right-hand-side columns in chunks of TC.
+template <int TC>
+static void launch_prod(const fem_chol &C, const fem_chol::Level &L, int q, double *z, int t, double *w, hipStream_t s)
+{
+    if (!L.nprod[q]) return;
+    const dim3 grid((unsigned)L.nprod[q], (unsigned)((t + TC - 1) / TC));
+    if (q < 2)
+        hipLaunchKernelGGL(k_big_rows<TC>, grid, dim3(kDBlock), 0, s, C.d_nodes, L.prod[q], q == 0 ? 1 : 0, C.d_panel,
+                           z, t, w);
+    else
+        hipLaunchKernelGGL(k_big_cols<TC>, grid, dim3(kDBlock), 0, s, C.d_nodes, L.prod[q], q == 3 ? 1 : 0, C.d_panel,
+                           z, t, w);
+}
+
+static void prod_step(const fem_chol &C, const fem_chol::Level &L, int q, double *z, int t, double *w, hipStream_t s)
+{
+    if (t == 1) launch_prod<1>(C, L, q, z, t, w, s);
+    else if (t == 2) launch_prod<2>(C, L, q, z, t, w, s);
+    else if (t <= 4) launch_prod<4>(C, L, q, z, t, w, s);
+    else if (t <= 8) launch_prod<8>(C, L, q, z, t, w, s);
+    else launch_prod<16>(C, L, q, z, t, w, s);
+}
+
 // Forward and backward solve of t right-hand sides (device [n][t], public
-// order) on stream s; synchronises.
+// order) on stream s; synchronises.  Per level, fronts up to kMidFront take
+// one workgroup each (gather, triangular solve in LDS panels, store); the
+// larger fronts are gathered, then go through the four product steps.
 int chol_solve_impl(fem_chol &C, const double *B, double *X, int t, hipStream_t s)
 {
     const int64_t n = C.n;
@@ -982,11 +1109,8 @@ int chol_solve_impl(fem_chol &C, const double *B, double *X, int t, hipStream_t 
     } release{&z, wb};
     DCHK(hipMalloc((void **)&z, sizeof(double) * std::max<int64_t>(n * t, 1)));
     for (int b = 0; b < 2; ++b) DCHK(hipMalloc((void **)&wb[b], sizeof(double) * std::max<int64_t>(C.max_wunits * t, 1)));
-    BCHK(rocblas_set_stream(C.blas, s));
-    BCHK(rocblas_set_pointer_mode(C.blas, rocblas_pointer_mode_host));
-    const double one = 1.0, mone = -1.0;
     const size_t kSolveBytes = sizeof(double) * kSolveLds;
-    for (const void *fn : {(const void *)k_mid_fwd, (const void *)k_mid_bwd, (const void *)k_tri_fwd, (const void *)k_tri_bwd})
+    for (const void *fn : {(const void *)k_mid_fwd, (const void *)k_mid_bwd})
         DCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSolveBytes));
     hipLaunchKernelGGL(k_permute, dim3(dgrid(n * t)), dim3(kDBlock), 0, s, C.d_perm, n, t, B, z, 1);
     const int nlev = (int)C.lev.size();
@@ -1000,26 +1124,8 @@ int chol_solve_impl(fem_chol &C, const double *B, double *X, int t, hipStream_t 
         if (!L.big.empty()) {
             hipLaunchKernelGGL(k_big_fwd_gather, dim3((unsigned)L.big.size()), dim3(kDBlock), 0, s, C.d_nodes, L.dbig,
                                C.d_index, z, t, w, wc);
-            if (L.nbigtri)
-                hipLaunchKernelGGL(k_tri_fwd, dim3(L.nbigtri), dim3(kDBlock), kSolveBytes, s, C.d_nodes, L.dbigtri, C.d_panel,
-                                   t, w);
-            for (int32_t k : L.big) {
-                const DNode &D = C.hnodes[k];
-                const int f = D.no + D.nu;
-                const double *P = C.d_panel + D.panel;
-                double *W = w + D.wunit * t;
-                if (D.no == 0) continue;
-                if (D.no > kMidFront)
-                    BCHK(rocblas_dtrsm(C.blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
-                                       rocblas_diagonal_non_unit, D.no, t, &one, P, f, W, f));
-                if (D.nu > 0 && t == 1)
-                    BCHK(rocblas_dgemv(C.blas, rocblas_operation_none, D.nu, D.no, &mone, P + D.no, f, W, 1, &one,
-                                       W + D.no, 1));
-                else if (D.nu > 0)
-                    BCHK(rocblas_dgemm(C.blas, rocblas_operation_none, rocblas_operation_none, D.nu, t, D.no, &mone,
-                                       P + D.no, f, W, f, &one, W + D.no, f));
-            }
-            hipLaunchKernelGGL(k_big_store, dim3((unsigned)L.big.size()), dim3(kDBlock), 0, s, C.d_nodes, L.dbig, t, w, z);
+            prod_step(C, L, 0, z, t, w, s);  // y = L11^-1 w_own -> z
+            prod_step(C, L, 1, z, t, w, s);  // w_upd -= L21 y
         }
         DCHK(hipGetLastError());
     }
@@ -1032,26 +1138,8 @@ int chol_solve_impl(fem_chol &C, const double *B, double *X, int t, hipStream_t 
         if (!L.big.empty()) {
             hipLaunchKernelGGL(k_big_bwd_gather, dim3((unsigned)L.big.size()), dim3(kDBlock), 0, s, C.d_nodes, L.dbig,
                                C.d_index, z, t, w);
-            for (int32_t k : L.big) {
-                const DNode &D = C.hnodes[k];
-                const int f = D.no + D.nu;
-                const double *P = C.d_panel + D.panel;
-                double *W = w + D.wunit * t;
-                if (D.no == 0) continue;
-                if (D.nu > 0 && t == 1)
-                    BCHK(rocblas_dgemv(C.blas, rocblas_operation_transpose, D.nu, D.no, &mone, P + D.no, f, W + D.no, 1,
-                                       &one, W, 1));
-                else if (D.nu > 0)
-                    BCHK(rocblas_dgemm(C.blas, rocblas_operation_transpose, rocblas_operation_none, D.no, t, D.nu, &mone,
-                                       P + D.no, f, W + D.no, f, &one, W, f));
-                if (D.no > kMidFront)
-                    BCHK(rocblas_dtrsm(C.blas, rocblas_side_left, rocblas_fill_lower, rocblas_operation_transpose,
-                                       rocblas_diagonal_non_unit, D.no, t, &one, P, f, W, f));
-            }
-            if (L.nbigtri)
-                hipLaunchKernelGGL(k_tri_bwd, dim3(L.nbigtri), dim3(kDBlock), kSolveBytes, s, C.d_nodes, L.dbigtri, C.d_panel,
-                                   t, w);
-            hipLaunchKernelGGL(k_big_store, dim3((unsigned)L.big.size()), dim3(kDBlock), 0, s, C.d_nodes, L.dbig, t, w, z);
+            prod_step(C, L, 2, z, t, w, s);  // w_own -= L21^T x_upd
+            prod_step(C, L, 3, z, t, w, s);  // x = L11^-T w_own -> z
         }
         DCHK(hipGetLastError());
     }
