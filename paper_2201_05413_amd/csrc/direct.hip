@@ -54,6 +54,7 @@ constexpr int kSolveLds = 8192;   // doubles of LDS per solve workgroup (64 KB)
 constexpr int kWaveLanes = 64;    // lanes per wavefront
 constexpr int kBigRows = 64;      // rows per workgroup of the larger fronts' row products (one per lane)
 constexpr int kBigCols = kDBlock / kWaveLanes;  // columns per workgroup of their column products (one per wave)
+constexpr int kGatherRows = 256;  // rows of W per workgroup of the larger fronts' gathers
 static_assert(kDBlock / kWaveLanes == 4, "the row products add four wave partials");
 static_assert(kBigRows == kWaveLanes, "one row per lane");
 
@@ -102,10 +103,10 @@ struct fem_chol {
         int32_t *dbig = nullptr;                 // the same on the device
         int32_t *dbigtri = nullptr;              // larger fronts whose own block has <= kMidFront columns
         int32_t nbigtri = 0;
-        // product-form solve items of the larger fronts, (node, first row or column) pairs:
-        // rows of L11^-1, rows of L21, columns of L21, columns of L11^-1
-        int32_t *prod[4] = {nullptr, nullptr, nullptr, nullptr};
-        int32_t nprod[4] = {0, 0, 0, 0};
+        // solve items of the larger fronts, (node, first row or column) pairs:
+        // rows of L11^-1, rows of L21, columns of L21, columns of L11^-1, rows of W (gathers)
+        int32_t *prod[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+        int32_t nprod[5] = {0, 0, 0, 0, 0};
         int32_t mid_rows = 0, tri_rows = 0;      // LDS rows of the factor launches (largest f, largest no)
         int64_t panel0 = 0, panel1 = 0;          // the level's range in the panel store
         int64_t udoubles = 0;                    // update blocks of the level's nodes
@@ -459,17 +460,17 @@ __global__ __launch_bounds__(kDBlock) void k_permute(const int32_t *perm, int64_
     }
 }
 
-// Forward gather of one node into its work block W (f x t, ld f): its own
-// right-hand-side rows, zeros below, then the children's update vectors
-// (rows no_c..f_c of their blocks) added at their relative indices, child 0
-// first.  One workgroup per node; the block is complete on return.
+// Forward gather of one node into its work block W (f x t, ld f), columns
+// [c0, c0 + tc): its own right-hand-side rows, zeros below, then the
+// children's update vectors (rows no_c..f_c of their blocks) added at their
+// relative indices, child 0 first.  One workgroup; complete on return.
 __device__ void fwd_gather(const DNode &D, const DNode *nodes, const int64_t *index, const double *z, int t,
-                           double *W, const double *wchild)
+                           double *W, const double *wchild, int c0, int tc)
 {
     const int f = D.no + D.nu;
-    for (int64_t e = threadIdx.x; e < (int64_t)f * t; e += kDBlock) {
-        const int c = (int)(e / f), r = (int)(e - (int64_t)c * f);
-        W[e] = r < D.no ? z[(D.b + r) * t + c] : 0.0;
+    for (int64_t e = threadIdx.x; e < (int64_t)f * tc; e += kDBlock) {
+        const int c = c0 + (int)(e / f), r = (int)(e % f);
+        W[r + (int64_t)c * f] = r < D.no ? z[(D.b + r) * t + c] : 0.0;
     }
     for (int s = 0; s < 2; ++s) {
         __syncthreads();
@@ -478,32 +479,32 @@ __device__ void fwd_gather(const DNode &D, const DNode *nodes, const int64_t *in
         const int fc = Cn.no + Cn.nu;
         const double *V = wchild + Cn.wunit * t;
         const int64_t *rel = index + D.rel[s];
-        for (int64_t e = threadIdx.x; e < (int64_t)Cn.nu * t; e += kDBlock) {
-            const int c = (int)(e / Cn.nu), a = (int)(e - (int64_t)c * Cn.nu);
+        for (int64_t e = threadIdx.x; e < (int64_t)Cn.nu * tc; e += kDBlock) {
+            const int c = c0 + (int)(e / Cn.nu), a = (int)(e % Cn.nu);
             W[rel[a] + (int64_t)c * f] += V[(Cn.no + a) + (int64_t)c * fc];
         }
     }
     __syncthreads();
 }
 
-// Backward gather: own rows from z (y), update rows from z at the update
-// positions (the ancestors' x).
-__device__ void bwd_gather(const DNode &D, const int64_t *index, const double *z, int t, double *W)
+// Backward gather, columns [c0, c0 + tc): own rows from z (y), update rows
+// from z at the update positions (the ancestors' x).
+__device__ void bwd_gather(const DNode &D, const int64_t *index, const double *z, int t, double *W, int c0, int tc)
 {
     const int f = D.no + D.nu;
     const int64_t *upd = index + D.idx;
-    for (int64_t e = threadIdx.x; e < (int64_t)f * t; e += kDBlock) {
-        const int c = (int)(e / f), r = (int)(e - (int64_t)c * f);
-        W[e] = r < D.no ? z[(D.b + r) * t + c] : z[upd[r - D.no] * t + c];
+    for (int64_t e = threadIdx.x; e < (int64_t)f * tc; e += kDBlock) {
+        const int c = c0 + (int)(e / f), r = (int)(e % f);
+        W[r + (int64_t)c * f] = r < D.no ? z[(D.b + r) * t + c] : z[upd[r - D.no] * t + c];
     }
     __syncthreads();
 }
 
-__device__ void own_store(const DNode &D, const double *W, int t, double *z)
+__device__ void own_store(const DNode &D, const double *W, int t, double *z, int c0, int tc)
 {
     const int f = D.no + D.nu;
-    for (int64_t e = threadIdx.x; e < (int64_t)D.no * t; e += kDBlock) {
-        const int c = (int)(e / D.no), r = (int)(e - (int64_t)c * D.no);
+    for (int64_t e = threadIdx.x; e < (int64_t)D.no * tc; e += kDBlock) {
+        const int c = c0 + (int)(e / D.no), r = (int)(e % D.no);
         z[(D.b + r) * t + c] = W[r + (int64_t)c * f];
     }
 }
@@ -644,49 +645,94 @@ __device__ void bwd_lds(const double *L, int f, int no, int apply21, double *W, 
     }
 }
 
-// Whole forward step of a front up to kMidFront: gather, y = L11^-1 w,
-// w_upd -= L21 y, store y.  Dynamic LDS: kSolveLds doubles.
+// Whole forward step of a front up to kMidFront, for the right-hand-side
+// columns [c0, c0 + cw) of chunk blockIdx.y: gather, y = L11^-1 w,
+// w_upd -= L21 y, store y.  Dynamic LDS: kSolveLds doubles (cw rows of the
+// largest front of the launch fit).
 __global__ __launch_bounds__(kDBlock) void k_mid_fwd(const DNode *nodes, const int32_t *list, const int64_t *index,
-                                                     const double *panel, double *z, int t, double *wbuf,
+                                                     const double *panel, double *z, int t, int cw, double *wbuf,
                                                      const double *wchild)
 {
     extern __shared__ double S[];
     const DNode D = nodes[list[blockIdx.x]];
     const int f = D.no + D.nu;
+    const int c0 = blockIdx.y * cw, tc = min(cw, t - c0);
     double *W = wbuf + D.wunit * t;
-    fwd_gather(D, nodes, index, z, t, W, wchild);
-    fwd_lds(panel + D.panel, f, D.no, f, W, t, S);
-    own_store(D, W, t, z);
+    fwd_gather(D, nodes, index, z, t, W, wchild, c0, tc);
+    fwd_lds(panel + D.panel, f, D.no, f, W + (int64_t)c0 * f, tc, S);
+    own_store(D, W, t, z, c0, tc);
 }
 
-// Whole backward step of a front up to kMidFront: gather, w -= L21^T x_upd,
-// x = L11^-T w, store x.
+// Whole backward step of a front up to kMidFront, columns [c0, c0 + cw) of
+// chunk blockIdx.y: gather, w -= L21^T x_upd, x = L11^-T w, store x.
 __global__ __launch_bounds__(kDBlock) void k_mid_bwd(const DNode *nodes, const int32_t *list, const int64_t *index,
-                                                     const double *panel, double *z, int t, double *wbuf)
+                                                     const double *panel, double *z, int t, int cw, double *wbuf)
 {
     extern __shared__ double S[];
     const DNode D = nodes[list[blockIdx.x]];
     const int f = D.no + D.nu;
+    const int c0 = blockIdx.y * cw, tc = min(cw, t - c0);
     double *W = wbuf + D.wunit * t;
-    bwd_gather(D, index, z, t, W);
-    bwd_lds(panel + D.panel, f, D.no, 1, W, t, S);
-    own_store(D, W, t, z);
+    bwd_gather(D, index, z, t, W, c0, tc);
+    bwd_lds(panel + D.panel, f, D.no, 1, W + (int64_t)c0 * f, tc, S);
+    own_store(D, W, t, z, c0, tc);
 }
 
-// Gathers around the product-form steps of the larger fronts.
-__global__ __launch_bounds__(kDBlock) void k_big_fwd_gather(const DNode *nodes, const int32_t *list,
+// Gathers of the larger fronts, one workgroup per (node, chunk of
+// kGatherRows rows of W), every column.  Forward: own right-hand-side rows
+// or zeros, then the children's update rows that land in the chunk (the
+// relative indices increase, so they form one range), child 0 first.
+__device__ inline int lower_index(const int64_t *rel, int n, int64_t v)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (rel[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kDBlock) void k_big_fwd_gather(const DNode *nodes, const int32_t *items,
                                                             const int64_t *index, const double *z, int t,
                                                             double *wbuf, const double *wchild)
 {
-    const DNode D = nodes[list[blockIdx.x]];
-    fwd_gather(D, nodes, index, z, t, wbuf + D.wunit * t, wchild);
+    const DNode D = nodes[items[2 * blockIdx.x]];
+    const int f = D.no + D.nu;
+    const int r0 = items[2 * blockIdx.x + 1], r1 = min(f, r0 + kGatherRows), nr = r1 - r0;
+    double *W = wbuf + D.wunit * t;
+    for (int64_t e = threadIdx.x; e < (int64_t)nr * t; e += kDBlock) {
+        const int c = (int)(e / nr), r = r0 + (int)(e % nr);
+        W[r + (int64_t)c * f] = r < D.no ? z[(D.b + r) * t + c] : 0.0;
+    }
+    for (int s = 0; s < 2; ++s) {
+        __syncthreads();
+        if (D.child[s] < 0) continue;
+        const DNode Cn = nodes[D.child[s]];
+        const int fc = Cn.no + Cn.nu;
+        const double *V = wchild + Cn.wunit * t;
+        const int64_t *rel = index + D.rel[s];
+        const int a0 = lower_index(rel, Cn.nu, r0), na = lower_index(rel, Cn.nu, r1) - a0;
+        for (int64_t e = threadIdx.x; e < (int64_t)na * t; e += kDBlock) {
+            const int c = (int)(e / na), a = a0 + (int)(e % na);
+            W[rel[a] + (int64_t)c * f] += V[(Cn.no + a) + (int64_t)c * fc];
+        }
+    }
 }
-__global__ __launch_bounds__(kDBlock) void k_big_bwd_gather(const DNode *nodes, const int32_t *list,
+
+__global__ __launch_bounds__(kDBlock) void k_big_bwd_gather(const DNode *nodes, const int32_t *items,
                                                             const int64_t *index, const double *z, int t,
                                                             double *wbuf)
 {
-    const DNode D = nodes[list[blockIdx.x]];
-    bwd_gather(D, index, z, t, wbuf + D.wunit * t);
+    const DNode D = nodes[items[2 * blockIdx.x]];
+    const int f = D.no + D.nu;
+    const int r0 = items[2 * blockIdx.x + 1], r1 = min(f, r0 + kGatherRows), nr = r1 - r0;
+    const int64_t *upd = index + D.idx;
+    double *W = wbuf + D.wunit * t;
+    for (int64_t e = threadIdx.x; e < (int64_t)nr * t; e += kDBlock) {
+        const int c = (int)(e / nr), r = r0 + (int)(e % nr);
+        W[r + (int64_t)c * f] = r < D.no ? z[(D.b + r) * t + c] : z[upd[r - D.no] * t + c];
+    }
 }
 
 // ---- larger fronts: solves in product form ----
@@ -894,11 +940,11 @@ int chol_setup(const HostSystem &hs, fem_chol &C)
         return off;
     };
     struct Off {
-        size_t all, mid, big, bigtri, ea[2], dst, val, prod[4];
+        size_t all, mid, big, bigtri, ea[2], dst, val, prod[5];
     };
     std::vector<Off> off(nlev);
     std::vector<std::vector<int32_t>> mid(nlev), big(nlev), bigtri(nlev), ea0(nlev), ea1(nlev);
-    std::vector<std::array<std::vector<int32_t>, 4>> prod(nlev);
+    std::vector<std::array<std::vector<int32_t>, 5>> prod(nlev);
     for (int d = 0; d < nlev; ++d) {
         for (int32_t k : C.levels[d]) {
             const ChNode &nd = C.nodes[k];
@@ -918,6 +964,7 @@ int chol_setup(const HostSystem &hs, fem_chol &C)
                 if (nd.nu() > 0)
                     for (int32_t j = 0; j < (int32_t)nd.no(); j += kBigCols) pr[2].insert(pr[2].end(), {k, j});
                 for (int32_t j = 0; j < (int32_t)nd.no(); j += kBigCols) pr[3].insert(pr[3].end(), {k, j});
+                for (int32_t r = 0; r < (int32_t)nd.f(); r += kGatherRows) pr[4].insert(pr[4].end(), {k, r});
             }
             for (int s = 0; s < 2; ++s) {
                 const int c = C.nodes[k].child[s];
@@ -937,7 +984,7 @@ int chol_setup(const HostSystem &hs, fem_chol &C)
         off[d].ea[1] = reserve(ea1[d].size() * 4);
         off[d].dst = reserve(adst[d].size() * 8);
         off[d].val = reserve(aval[d].size() * 8);
-        for (int q = 0; q < 4; ++q) off[d].prod[q] = reserve(prod[d][q].size() * 4);
+        for (int q = 0; q < 5; ++q) off[d].prod[q] = reserve(prod[d][q].size() * 4);
     }
     DCHK(hipMalloc((void **)&C.d_lists, std::max<size_t>(bytes, 256)));
     DCHK(hipMalloc((void **)&C.d_nodes, sizeof(DNode) * std::max<size_t>(nn, 1)));
@@ -963,7 +1010,7 @@ int chol_setup(const HostSystem &hs, fem_chol &C)
             (rc = put(off[d].dst, adst[d].data(), adst[d].size() * 8)) ||
             (rc = put(off[d].val, aval[d].data(), aval[d].size() * 8)))
             return rc;
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < 5; ++q) {
             if ((rc = put(off[d].prod[q], prod[d][q].data(), prod[d][q].size() * 4))) return rc;
             L.prod[q] = (int32_t *)(C.d_lists + off[d].prod[q]);
             L.nprod[q] = (int32_t)(prod[d][q].size() / 2);
@@ -1081,6 +1128,13 @@ static void launch_prod(const fem_chol &C, const fem_chol::Level &L, int q, doub
                            z, t, w);
 }
 
+// Right-hand-side columns per workgroup of a level's fronts up to
+// kMidFront: as many as the LDS holds for its largest front.
+static int mid_chunk(const fem_chol::Level &L, int t)
+{
+    return std::max(1, std::min(t, kSolveLds / std::max<int>(L.mid_rows, 1)));
+}
+
 static void prod_step(const fem_chol &C, const fem_chol::Level &L, int q, double *z, int t, double *w, hipStream_t s)
 {
     if (t == 1) launch_prod<1>(C, L, q, z, t, w, s);
@@ -1118,11 +1172,13 @@ int chol_solve_impl(fem_chol &C, const double *B, double *X, int t, hipStream_t 
         const fem_chol::Level &L = C.lev[d];
         double *w = wb[d & 1];
         const double *wc = wb[(d + 1) & 1];
-        if (L.nmid)
-            hipLaunchKernelGGL(k_mid_fwd, dim3(L.nmid), dim3(kDBlock), kSolveBytes, s, C.d_nodes, L.mid, C.d_index, C.d_panel, z,
-                               t, w, wc);
+        if (L.nmid) {
+            const int cw = mid_chunk(L, t);
+            hipLaunchKernelGGL(k_mid_fwd, dim3(L.nmid, (t + cw - 1) / cw), dim3(kDBlock), kSolveBytes, s, C.d_nodes, L.mid,
+                               C.d_index, C.d_panel, z, t, cw, w, wc);
+        }
         if (!L.big.empty()) {
-            hipLaunchKernelGGL(k_big_fwd_gather, dim3((unsigned)L.big.size()), dim3(kDBlock), 0, s, C.d_nodes, L.dbig,
+            hipLaunchKernelGGL(k_big_fwd_gather, dim3((unsigned)L.nprod[4]), dim3(kDBlock), 0, s, C.d_nodes, L.prod[4],
                                C.d_index, z, t, w, wc);
             prod_step(C, L, 0, z, t, w, s);  // y = L11^-1 w_own -> z
             prod_step(C, L, 1, z, t, w, s);  // w_upd -= L21 y
@@ -1132,11 +1188,13 @@ int chol_solve_impl(fem_chol &C, const double *B, double *X, int t, hipStream_t 
     for (int d = 0; d < nlev; ++d) {
         const fem_chol::Level &L = C.lev[d];
         double *w = wb[0];
-        if (L.nmid)
-            hipLaunchKernelGGL(k_mid_bwd, dim3(L.nmid), dim3(kDBlock), kSolveBytes, s, C.d_nodes, L.mid, C.d_index, C.d_panel,
-                               z, t, w);
+        if (L.nmid) {
+            const int cw = mid_chunk(L, t);
+            hipLaunchKernelGGL(k_mid_bwd, dim3(L.nmid, (t + cw - 1) / cw), dim3(kDBlock), kSolveBytes, s, C.d_nodes, L.mid,
+                               C.d_index, C.d_panel, z, t, cw, w);
+        }
         if (!L.big.empty()) {
-            hipLaunchKernelGGL(k_big_bwd_gather, dim3((unsigned)L.big.size()), dim3(kDBlock), 0, s, C.d_nodes, L.dbig,
+            hipLaunchKernelGGL(k_big_bwd_gather, dim3((unsigned)L.nprod[4]), dim3(kDBlock), 0, s, C.d_nodes, L.prod[4],
                                C.d_index, z, t, w);
             prod_step(C, L, 2, z, t, w, s);  // w_own -= L21^T x_upd
             prod_step(C, L, 3, z, t, w, s);  // x = L11^-T w_own -> z
