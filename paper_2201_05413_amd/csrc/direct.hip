@@ -55,6 +55,7 @@ constexpr int kWaveLanes = 64;    // lanes per wavefront
 constexpr int kBigRows = 64;      // rows per workgroup of the larger fronts' row products (one per lane)
 constexpr int kBigCols = kDBlock / kWaveLanes;  // columns per workgroup of their column products (one per wave)
 constexpr int kGatherRows = 256;  // rows of W per workgroup of the larger fronts' gathers
+constexpr int kMirrorTile = 64;   // tile edge of the L11^-1 mirror
 static_assert(kDBlock / kWaveLanes == 4, "the row products add four wave partials");
 static_assert(kBigRows == kWaveLanes, "one row per lane");
 
@@ -104,7 +105,7 @@ struct fem_chol {
         int32_t *dbigtri = nullptr;              // larger fronts whose own block has <= kMidFront columns
         int32_t nbigtri = 0;
         // solve items of the larger fronts, (node, first row or column) pairs:
-        // rows of L11^-1, rows of L21, columns of L21, columns of L11^-1, rows of W (gathers)
+        // columns of L11^-T (mirror), rows of L21, columns of L21, columns of L11^-1, rows of W (gathers)
         int32_t *prod[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
         int32_t nprod[5] = {0, 0, 0, 0, 0};
         int32_t mid_rows = 0, tri_rows = 0;      // LDS rows of the factor launches (largest f, largest no)
@@ -119,6 +120,8 @@ struct fem_chol {
     };
     std::vector<Level> lev;
     int64_t max_udoubles = 0, max_wunits = 0;
+    int32_t *d_mir = nullptr;                  // mirror tiles of the larger fronts (node, tile code)
+    int64_t nmir = 0;
     int32_t *d_fail = nullptr;                 // nonzero: a non-positive pivot
     chol_stats_t stats{};
     rocblas_handle blas = nullptr;
@@ -744,14 +747,13 @@ __global__ __launch_bounds__(kDBlock) void k_big_bwd_gather(const DNode *nodes, 
 // Right-hand-side columns come in chunks of TC (blockIdx.y); every column's
 // sums run in the same order whatever t is.
 
-// Row products: one workgroup per (node, chunk of 64 rows), one row per
-// lane; the four waves take contiguous quarters of the columns and their
-// partial sums are added in wave order.  own: rows of L11^-1 (columns
-// j <= r) times W's own rows, result y written to z; otherwise rows of L21
-// times y (z's own rows), subtracted from W's update rows.
+// Row products: one workgroup per (node, chunk of 64 rows of L21), one row
+// per lane; the four waves take contiguous quarters of the columns and their
+// partial sums are added in wave order.  Rows of L21 times y (z's own
+// rows), subtracted from W's update rows.
 template <int TC>
-__global__ __launch_bounds__(kDBlock) void k_big_rows(const DNode *nodes, const int32_t *items, int own,
-                                                      const double *panel, double *z, int t, double *wbuf)
+__global__ __launch_bounds__(kDBlock) void k_big_rows(const DNode *nodes, const int32_t *items, const double *panel,
+                                                      const double *z, int t, double *wbuf)
 {
     __shared__ double part[kDBlock / kWaveLanes][TC][kWaveLanes];
     const DNode D = nodes[items[2 * blockIdx.x]];
@@ -760,13 +762,11 @@ __global__ __launch_bounds__(kDBlock) void k_big_rows(const DNode *nodes, const 
     const int c0 = blockIdx.y * TC, tcn = min(TC, t - c0);
     const int lane = threadIdx.x & (kWaveLanes - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWaveLanes);
-    const int nrow = own ? D.no : D.nu;
     const int r = r0 + lane;
-    const bool ok = r < nrow;
-    const int64_t prow = (own ? 0 : D.no) + (ok ? r : nrow - 1);
-    const int jend = own ? min(D.no, r0 + kWaveLanes) : D.no;
-    const int per = (jend + 3) / 4;
-    const int js = min(jend, wave * per), je = min(jend, js + per);
+    const bool ok = r < D.nu;
+    const int64_t prow = D.no + (ok ? r : D.nu - 1);
+    const int per = (D.no + 3) / 4;
+    const int js = min(D.no, wave * per), je = min(D.no, js + per);
     const double *P = panel + D.panel;
     double *W = wbuf + D.wunit * t;
     double acc[TC];
@@ -774,11 +774,10 @@ __global__ __launch_bounds__(kDBlock) void k_big_rows(const DNode *nodes, const 
     for (int c = 0; c < TC; ++c) acc[c] = 0.0;
 #pragma unroll 4
     for (int j = js; j < je; ++j) {
-        double a = P[prow + (int64_t)j * f];
-        if (own && j > r) a = 0.0;  // L11^-1 is lower triangular
+        const double a = P[prow + (int64_t)j * f];
 #pragma unroll
         for (int c = 0; c < TC; ++c)
-            if (c < tcn) acc[c] += a * (own ? W[j + (int64_t)(c0 + c) * f] : z[(D.b + j) * t + c0 + c]);
+            if (c < tcn) acc[c] += a * z[(D.b + j) * t + c0 + c];
     }
 #pragma unroll
     for (int c = 0; c < TC; ++c) part[wave][c][lane] = acc[c];
@@ -786,17 +785,19 @@ __global__ __launch_bounds__(kDBlock) void k_big_rows(const DNode *nodes, const 
     if (threadIdx.x < kWaveLanes && ok)
         for (int c = 0; c < tcn; ++c) {
             const double v = (part[0][c][lane] + part[1][c][lane]) + (part[2][c][lane] + part[3][c][lane]);
-            if (own) z[(D.b + r) * t + c0 + c] = v;
-            else W[D.no + r + (int64_t)(c0 + c) * f] -= v;
+            W[D.no + r + (int64_t)(c0 + c) * f] -= v;
         }
 }
 
 // Column products: one wave per column j (four per workgroup); lanes stride
-// the rows, then a fixed xor tree adds the lanes.  own: column j of L11^-1
-// (rows r >= j) against W's own rows, x_j written to z; otherwise column j
-// of L21 against W's update rows, subtracted from W's own row j.
+// the rows, then a fixed xor tree adds the lanes.
+//   kL21   column j of L21 against W's update rows, subtracted from W's own row j
+//   kLow   column j of L11^-1 (rows j..no-1) against W's own rows: x_j, to z
+//   kUp    column j of L11^-T (rows 0..j, the mirror in the upper triangle)
+//          against W's own rows: y_j = (L11^-1 w)_j, to z
+enum ColForm { kL21 = 0, kLow = 1, kUp = 2 };
 template <int TC>
-__global__ __launch_bounds__(kDBlock) void k_big_cols(const DNode *nodes, const int32_t *items, int own,
+__global__ __launch_bounds__(kDBlock) void k_big_cols(const DNode *nodes, const int32_t *items, int form,
                                                       const double *panel, double *z, int t, double *wbuf)
 {
     const DNode D = nodes[items[2 * blockIdx.x]];
@@ -805,7 +806,8 @@ __global__ __launch_bounds__(kDBlock) void k_big_cols(const DNode *nodes, const 
     if (j >= D.no) return;  // whole waves only; no barrier below
     const int f = D.no + D.nu;
     const int c0 = blockIdx.y * TC, tcn = min(TC, t - c0);
-    const int rs = own ? j : D.no, re = own ? D.no : f;
+    const int rs = form == kL21 ? D.no : (form == kLow ? j : 0);
+    const int re = form == kL21 ? f : (form == kLow ? D.no : j + 1);
     const double *Pj = panel + D.panel + (int64_t)j * f;
     double *W = wbuf + D.wunit * t;
     double acc[TC];
@@ -823,9 +825,34 @@ __global__ __launch_bounds__(kDBlock) void k_big_cols(const DNode *nodes, const 
         for (int off = kWaveLanes / 2; off >= 1; off >>= 1) acc[c] += __shfl_xor(acc[c], off, kWaveLanes);
     if (lane == 0)
         for (int c = 0; c < tcn; ++c) {
-            if (own) z[(D.b + j) * t + c0 + c] = acc[c];
-            else W[j + (int64_t)(c0 + c) * f] -= acc[c];
+            if (form == kL21) W[j + (int64_t)(c0 + c) * f] -= acc[c];
+            else z[(D.b + j) * t + c0 + c] = acc[c];
         }
+}
+
+// After TRTRI: the strictly lower triangle of L11^-1 copied, transposed,
+// into the strictly upper triangle of the own block, one 64 x 64 tile per
+// workgroup (items: node, tile row << 16 | tile column, tile row >= tile
+// column), so that the forward product reads contiguous columns.
+__global__ __launch_bounds__(kDBlock) void k_mirror(const DNode *nodes, const int32_t *items, double *panel)
+{
+    __shared__ double T[kMirrorTile][kMirrorTile + 1];
+    const DNode D = nodes[items[2 * blockIdx.x]];
+    const int code = items[2 * blockIdx.x + 1];
+    const int r0 = (code >> 16) * kMirrorTile, c0 = (code & 0xffff) * kMirrorTile;
+    const int f = D.no + D.nu;
+    double *P = panel + D.panel;
+    for (int e = threadIdx.x; e < kMirrorTile * kMirrorTile; e += kDBlock) {
+        const int c = e / kMirrorTile, r = e % kMirrorTile;  // rows fastest: contiguous loads
+        const int gr = r0 + r, gc = c0 + c;
+        T[c][r] = (gr < D.no && gr > gc) ? P[gr + (int64_t)gc * f] : 0.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kMirrorTile * kMirrorTile; e += kDBlock) {
+        const int r = e / kMirrorTile, c = e % kMirrorTile;  // target rows fastest: contiguous stores
+        const int gr = r0 + r, gc = c0 + c;
+        if (gr < D.no && gr > gc) P[gc + (int64_t)gr * f] = T[c][r];
+    }
 }
 
 }  // namespace
@@ -945,6 +972,7 @@ int chol_setup(const HostSystem &hs, fem_chol &C)
     std::vector<Off> off(nlev);
     std::vector<std::vector<int32_t>> mid(nlev), big(nlev), bigtri(nlev), ea0(nlev), ea1(nlev);
     std::vector<std::array<std::vector<int32_t>, 5>> prod(nlev);
+    std::vector<int32_t> mir;  // mirror tiles of every larger front
     for (int d = 0; d < nlev; ++d) {
         for (int32_t k : C.levels[d]) {
             const ChNode &nd = C.nodes[k];
@@ -958,7 +986,11 @@ int chol_setup(const HostSystem &hs, fem_chol &C)
                     C.lev[d].tri_rows = std::max<int32_t>(C.lev[d].tri_rows, (int32_t)nd.no());
                 }
                 auto &pr = prod[d];
-                for (int32_t r = 0; r < (int32_t)nd.no(); r += kBigRows) pr[0].insert(pr[0].end(), {k, r});
+                for (int32_t j = 0; j < (int32_t)nd.no(); j += kBigCols) pr[0].insert(pr[0].end(), {k, j});
+                const int32_t nt = (int32_t)((nd.no() + kMirrorTile - 1) / kMirrorTile);
+                if (nt >= (1 << 15)) return fail(FEMCG_EINVAL, "chol: separator of %lld DOFs is too large", (long long)nd.no());
+                for (int32_t ti = 0; ti < nt; ++ti)
+                    for (int32_t tj = 0; tj <= ti; ++tj) mir.insert(mir.end(), {k, (ti << 16) | tj});
                 if (nd.no() > 0)
                     for (int32_t r = 0; r < (int32_t)nd.nu(); r += kBigRows) pr[1].insert(pr[1].end(), {k, r});
                 if (nd.nu() > 0)
@@ -986,6 +1018,7 @@ int chol_setup(const HostSystem &hs, fem_chol &C)
         off[d].val = reserve(aval[d].size() * 8);
         for (int q = 0; q < 5; ++q) off[d].prod[q] = reserve(prod[d][q].size() * 4);
     }
+    const size_t off_mir = reserve(mir.size() * 4);
     DCHK(hipMalloc((void **)&C.d_lists, std::max<size_t>(bytes, 256)));
     DCHK(hipMalloc((void **)&C.d_nodes, sizeof(DNode) * std::max<size_t>(nn, 1)));
     DCHK(hipMalloc((void **)&C.d_perm, sizeof(int32_t) * std::max<int64_t>(n, 1)));
@@ -998,6 +1031,12 @@ int chol_setup(const HostSystem &hs, fem_chol &C)
         if (b) DCHK(hipMemcpy(C.d_lists + o, src, b, hipMemcpyHostToDevice));
         return FEMCG_OK;
     };
+    {
+        const int rc = put(off_mir, mir.data(), mir.size() * 4);
+        if (rc) return rc;
+        C.d_mir = (int32_t *)(C.d_lists + off_mir);
+        C.nmir = (int64_t)mir.size() / 2;
+    }
     for (int d = 0; d < nlev; ++d) {
         fem_chol::Level &L = C.lev[d];
         int rc;
@@ -1101,6 +1140,13 @@ int chol_numeric(fem_chol &C, hipStream_t s)
             ++ib;
         }
     }
+    // the larger fronts' L11^-1 mirrored into their upper triangles (the
+    // grid walks the tile list in slices of at most 2^20 workgroups)
+    for (int64_t m0 = 0; m0 < C.nmir; m0 += (int64_t)1 << 20) {
+        const int64_t m = std::min<int64_t>(C.nmir - m0, (int64_t)1 << 20);
+        hipLaunchKernelGGL(k_mirror, dim3((unsigned)m), dim3(kDBlock), 0, s, C.d_nodes, C.d_mir + 2 * m0, C.d_panel);
+    }
+    DCHK(hipGetLastError());
     DCHK(hipStreamSynchronize(s));
     int32_t bad = 0;
     DCHK(hipMemcpy(&bad, C.d_fail, sizeof bad, hipMemcpyDeviceToHost));
@@ -1120,12 +1166,11 @@ static void launch_prod(const fem_chol &C, const fem_chol::Level &L, int q, doub
 {
     if (!L.nprod[q]) return;
     const dim3 grid((unsigned)L.nprod[q], (unsigned)((t + TC - 1) / TC));
-    if (q < 2)
-        hipLaunchKernelGGL(k_big_rows<TC>, grid, dim3(kDBlock), 0, s, C.d_nodes, L.prod[q], q == 0 ? 1 : 0, C.d_panel,
-                           z, t, w);
+    if (q == 1)
+        hipLaunchKernelGGL(k_big_rows<TC>, grid, dim3(kDBlock), 0, s, C.d_nodes, L.prod[q], C.d_panel, z, t, w);
     else
-        hipLaunchKernelGGL(k_big_cols<TC>, grid, dim3(kDBlock), 0, s, C.d_nodes, L.prod[q], q == 3 ? 1 : 0, C.d_panel,
-                           z, t, w);
+        hipLaunchKernelGGL(k_big_cols<TC>, grid, dim3(kDBlock), 0, s, C.d_nodes, L.prod[q],
+                           q == 0 ? kUp : (q == 2 ? kL21 : kLow), C.d_panel, z, t, w);
 }
 
 // Right-hand-side columns per workgroup of a level's fronts up to
@@ -1180,7 +1225,7 @@ int chol_solve_impl(fem_chol &C, const double *B, double *X, int t, hipStream_t 
         if (!L.big.empty()) {
             hipLaunchKernelGGL(k_big_fwd_gather, dim3((unsigned)L.nprod[4]), dim3(kDBlock), 0, s, C.d_nodes, L.prod[4],
                                C.d_index, z, t, w, wc);
-            prod_step(C, L, 0, z, t, w, s);  // y = L11^-1 w_own -> z
+            prod_step(C, L, 0, z, t, w, s);  // y = L11^-1 w_own -> z (columns of the mirror)
             prod_step(C, L, 1, z, t, w, s);  // w_upd -= L21 y
         }
         DCHK(hipGetLastError());
