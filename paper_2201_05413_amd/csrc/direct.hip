@@ -53,9 +53,14 @@ constexpr int kDBlock = 256;      // threads per workgroup of the direct kernels
 constexpr int kSolveLds = 8192;   // doubles of LDS per solve workgroup (64 KB)
 constexpr int kWaveLanes = 64;    // lanes per wavefront
 constexpr int kBigRows = 64;      // rows per workgroup of the larger fronts' row products (one per lane)
-constexpr int kBigCols = kDBlock / kWaveLanes;  // columns per workgroup of their column products (one per wave)
+constexpr int kBigCols = 4;       // columns per workgroup of their column products
 constexpr int kGatherRows = 256;  // rows of W per workgroup of the larger fronts' gathers
 constexpr int kMirrorTile = 64;   // tile edge of the L11^-1 mirror
+#ifndef FEMCG_CHOL_CHUNK
+#define FEMCG_CHOL_CHUNK 8
+#endif
+constexpr int kProdChunk = FEMCG_CHOL_CHUNK;  // right-hand-side columns per product launch chunk beyond 8 (8 or 16)
+static_assert(kProdChunk == 8 || kProdChunk == 16, "product chunks of 8 or 16 columns");
 static_assert(kDBlock / kWaveLanes == 4, "the row products add four wave partials");
 static_assert(kBigRows == kWaveLanes, "one row per lane");
 
@@ -789,45 +794,66 @@ __global__ __launch_bounds__(kDBlock) void k_big_rows(const DNode *nodes, const 
         }
 }
 
-// Column products: one wave per column j (four per workgroup); lanes stride
-// the rows, then a fixed xor tree adds the lanes.
-//   kL21   column j of L21 against W's update rows, subtracted from W's own row j
-//   kLow   column j of L11^-1 (rows j..no-1) against W's own rows: x_j, to z
-//   kUp    column j of L11^-T (rows 0..j, the mirror in the upper triangle)
+// Column products: one workgroup per (node, kBigCols consecutive columns);
+// the four waves take contiguous quarters of the rows, each lane strides its
+// quarter and reads every right-hand-side row once for all the workgroup's
+// columns; lanes are added by a fixed xor tree, then the waves in order.
+//   kL21   columns j of L21 against W's update rows, subtracted from W's own rows j
+//   kLow   columns j of L11^-1 (rows j..no-1) against W's own rows: x_j, to z
+//   kUp    columns j of L11^-T (rows 0..j, the mirror in the upper triangle)
 //          against W's own rows: y_j = (L11^-1 w)_j, to z
 enum ColForm { kL21 = 0, kLow = 1, kUp = 2 };
 template <int TC>
 __global__ __launch_bounds__(kDBlock) void k_big_cols(const DNode *nodes, const int32_t *items, int form,
                                                       const double *panel, double *z, int t, double *wbuf)
 {
+    __shared__ double part[kDBlock / kWaveLanes][kBigCols][TC];
     const DNode D = nodes[items[2 * blockIdx.x]];
+    const int j0 = items[2 * blockIdx.x + 1], ncol = min(kBigCols, D.no - j0);
     const int lane = threadIdx.x & (kWaveLanes - 1);
-    const int j = items[2 * blockIdx.x + 1] + (int)(threadIdx.x / kWaveLanes);
-    if (j >= D.no) return;  // whole waves only; no barrier below
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWaveLanes);
     const int f = D.no + D.nu;
     const int c0 = blockIdx.y * TC, tcn = min(TC, t - c0);
-    const int rs = form == kL21 ? D.no : (form == kLow ? j : 0);
-    const int re = form == kL21 ? f : (form == kLow ? D.no : j + 1);
-    const double *Pj = panel + D.panel + (int64_t)j * f;
+    // the rows any of the columns reads, split in four
+    const int rs = form == kL21 ? D.no : (form == kLow ? j0 : 0);
+    const int re = form == kL21 ? f : (form == kLow ? D.no : j0 + ncol);
+    const int per = (re - rs + 3) / 4;
+    const int ws = min(re, rs + wave * per), we = min(re, ws + per);
+    const double *P = panel + D.panel + (int64_t)j0 * f;
     double *W = wbuf + D.wunit * t;
-    double acc[TC];
+    double acc[kBigCols][TC];
 #pragma unroll
-    for (int c = 0; c < TC; ++c) acc[c] = 0.0;
-#pragma unroll 2
-    for (int r = rs + lane; r < re; r += kWaveLanes) {
-        const double a = Pj[r];
+    for (int q = 0; q < kBigCols; ++q)
 #pragma unroll
-        for (int c = 0; c < TC; ++c)
-            if (c < tcn) acc[c] += a * W[r + (int64_t)(c0 + c) * f];
+        for (int c = 0; c < TC; ++c) acc[q][c] = 0.0;
+    for (int r = ws + lane; r < we; r += kWaveLanes) {
+        double wv[TC];
+#pragma unroll
+        for (int c = 0; c < TC; ++c) wv[c] = c < tcn ? W[r + (int64_t)(c0 + c) * f] : 0.0;
+#pragma unroll
+        for (int q = 0; q < kBigCols; ++q) {
+            if (q >= ncol) break;
+            double a = P[r + (int64_t)q * f];
+            if ((form == kLow && r < j0 + q) || (form == kUp && r > j0 + q)) a = 0.0;
+#pragma unroll
+            for (int c = 0; c < TC; ++c) acc[q][c] += a * wv[c];
+        }
     }
 #pragma unroll
-    for (int c = 0; c < TC; ++c)
-        for (int off = kWaveLanes / 2; off >= 1; off >>= 1) acc[c] += __shfl_xor(acc[c], off, kWaveLanes);
-    if (lane == 0)
-        for (int c = 0; c < tcn; ++c) {
-            if (form == kL21) W[j + (int64_t)(c0 + c) * f] -= acc[c];
-            else z[(D.b + j) * t + c0 + c] = acc[c];
+    for (int q = 0; q < kBigCols; ++q)
+#pragma unroll
+        for (int c = 0; c < TC; ++c) {
+            double v = acc[q][c];
+            for (int off = kWaveLanes / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWaveLanes);
+            if (lane == 0) part[wave][q][c] = v;
         }
+    __syncthreads();
+    for (int e = threadIdx.x; e < ncol * tcn; e += kDBlock) {
+        const int q = e / tcn, c = e % tcn, j = j0 + q;
+        const double v = (part[0][q][c] + part[1][q][c]) + (part[2][q][c] + part[3][q][c]);
+        if (form == kL21) W[j + (int64_t)(c0 + c) * f] -= v;
+        else z[(D.b + j) * t + c0 + c] = v;
+    }
 }
 
 // After TRTRI: the strictly lower triangle of L11^-1 copied, transposed,
@@ -1185,7 +1211,7 @@ static void prod_step(const fem_chol &C, const fem_chol::Level &L, int q, double
     if (t == 1) launch_prod<1>(C, L, q, z, t, w, s);
     else if (t == 2) launch_prod<2>(C, L, q, z, t, w, s);
     else if (t <= 4) launch_prod<4>(C, L, q, z, t, w, s);
-    else if (t <= 8) launch_prod<8>(C, L, q, z, t, w, s);
+    else if (t <= 8 || kProdChunk == 8) launch_prod<8>(C, L, q, z, t, w, s);
     else launch_prod<16>(C, L, q, z, t, w, s);
 }
 
