@@ -48,7 +48,8 @@ namespace femcg {
 
 constexpr int kLeaf = 64;         // nested-dissection leaves: at most this many DOFs
 constexpr int kMidFront = 1024;   // fronts up to this size: one workgroup each
-constexpr int kPanel = 8;         // columns per LDS panel in the workgroup kernels
+constexpr int kPanel = 8;         // columns per LDS panel of the workgroup factorisation
+constexpr int kSolvePanel = 8;    // columns per triangle panel of the workgroup solves (16 and 32 measured slower)
 constexpr int kDBlock = 256;      // threads per workgroup of the direct kernels
 constexpr int kSolveLds = 8192;   // doubles of LDS per solve workgroup (64 KB)
 constexpr int kWaveLanes = 64;    // lanes per wavefront
@@ -56,11 +57,7 @@ constexpr int kBigRows = 64;      // rows per workgroup of the larger fronts' ro
 constexpr int kBigCols = 4;       // columns per workgroup of their column products
 constexpr int kGatherRows = 256;  // rows of W per workgroup of the larger fronts' gathers
 constexpr int kMirrorTile = 64;   // tile edge of the L11^-1 mirror
-#ifndef FEMCG_CHOL_CHUNK
-#define FEMCG_CHOL_CHUNK 8
-#endif
-constexpr int kProdChunk = FEMCG_CHOL_CHUNK;  // right-hand-side columns per product launch chunk beyond 8 (8 or 16)
-static_assert(kProdChunk == 8 || kProdChunk == 16, "product chunks of 8 or 16 columns");
+
 static_assert(kDBlock / kWaveLanes == 4, "the row products add four wave partials");
 static_assert(kBigRows == kWaveLanes, "one row per lane");
 
@@ -521,8 +518,8 @@ __device__ void own_store(const DNode &D, const double *W, int t, double *z, int
 // read by all threads at once (one round trip), then a barrier.
 __device__ void stage_triangle(const double *L, int f, int k0, int kw, double *T)
 {
-    for (int e = threadIdx.x; e < kPanel * kPanel; e += kDBlock) {
-        const int j = e / kPanel, i = e - j * kPanel;
+    for (int e = threadIdx.x; e < kSolvePanel * kSolvePanel; e += kDBlock) {
+        const int j = e / kSolvePanel, i = e - j * kSolvePanel;
         T[e] = (j < kw && i <= j) ? L[(k0 + j) + (int64_t)(k0 + i) * f] : 0.0;
     }
     __syncthreads();
@@ -531,12 +528,12 @@ __device__ void stage_triangle(const double *L, int f, int k0, int kw, double *T
 // Forward substitution with L11 on the own rows [0, no) of W (f x t, ld f),
 // applying L21 to the rows [no, rend) as well when rend = f (rend = no: L11
 // only).  Chunks of tc right-hand sides are staged in LDS (rend x tc, S), and
-// L11 is walked in panels of kPanel columns: lane c solves the panel's
+// L11 is walked in panels of kSolvePanel columns: lane c solves the panel's
 // triangle for column c on its own, then every later row loses the panel's
 // contribution (sum over the panel's columns in order) in one pass.
 __device__ void fwd_lds(const double *L, int f, int no, int rend, double *W, int t, double *S)
 {
-    __shared__ double T[kPanel * kPanel];
+    __shared__ double T[kSolvePanel * kSolvePanel];
     const int tid = threadIdx.x;
     const int tcm = max(1, min(t, kSolveLds / max(rend, 1)));
     for (int c0 = 0; c0 < t; c0 += tcm) {
@@ -546,18 +543,18 @@ __device__ void fwd_lds(const double *L, int f, int no, int rend, double *W, int
             S[r * tc + c] = W[r + (int64_t)(c0 + c) * f];
         }
         __syncthreads();
-        for (int k0 = 0; k0 < no; k0 += kPanel) {
-            const int kw = min(kPanel, no - k0);
+        for (int k0 = 0; k0 < no; k0 += kSolvePanel) {
+            const int kw = min(kSolvePanel, no - k0);
             stage_triangle(L, f, k0, kw, T);
             for (int c = tid; c < tc; c += kDBlock) {
-                double x[kPanel];
+                double x[kSolvePanel];
 #pragma unroll
-                for (int j = 0; j < kPanel; ++j) {
+                for (int j = 0; j < kSolvePanel; ++j) {
                     if (j >= kw) break;
                     double v = S[(k0 + j) * tc + c];
 #pragma unroll
-                    for (int i = 0; i < j; ++i) v -= T[j * kPanel + i] * x[i];
-                    x[j] = v / T[j * kPanel + j];
+                    for (int i = 0; i < j; ++i) v -= T[j * kSolvePanel + i] * x[i];
+                    x[j] = v / T[j * kSolvePanel + j];
                     S[(k0 + j) * tc + c] = x[j];
                 }
             }
@@ -567,7 +564,7 @@ __device__ void fwd_lds(const double *L, int f, int no, int rend, double *W, int
                 const int c = (int)(e / nr), r = r0 + (int)(e - (int64_t)c * nr);
                 double acc = 0.0;
 #pragma unroll
-                for (int j = 0; j < kPanel; ++j)
+                for (int j = 0; j < kSolvePanel; ++j)
                     if (j < kw) acc += L[r + (int64_t)(k0 + j) * f] * S[(k0 + j) * tc + c];
                 S[r * tc + c] -= acc;
             }
@@ -587,7 +584,7 @@ __device__ void fwd_lds(const double *L, int f, int no, int rend, double *W, int
 // lose the panel's contribution).  Chunks of right-hand sides in LDS.
 __device__ void bwd_lds(const double *L, int f, int no, int apply21, double *W, int t, double *S)
 {
-    __shared__ double T[kPanel * kPanel];
+    __shared__ double T[kSolvePanel * kSolvePanel];
     const int tid = threadIdx.x;
     const int rows = apply21 ? f : no, nu = f - no;
     const int tcm = max(1, min(t, kSolveLds / max(rows, 1)));
@@ -617,19 +614,19 @@ __device__ void bwd_lds(const double *L, int f, int no, int apply21, double *W, 
             }
             __syncthreads();
         }
-        for (int k0 = ((no - 1) / kPanel) * kPanel; k0 >= 0 && no > 0; k0 -= kPanel) {
-            const int kw = min(kPanel, no - k0);
+        for (int k0 = ((no - 1) / kSolvePanel) * kSolvePanel; k0 >= 0 && no > 0; k0 -= kSolvePanel) {
+            const int kw = min(kSolvePanel, no - k0);
             stage_triangle(L, f, k0, kw, T);
             for (int c = tid; c < tc; c += kDBlock) {
-                double x[kPanel];
+                double x[kSolvePanel];
 #pragma unroll
-                for (int j = kPanel - 1; j >= 0; --j) {
+                for (int j = kSolvePanel - 1; j >= 0; --j) {
                     if (j >= kw) continue;
                     double v = S[(k0 + j) * tc + c];
 #pragma unroll
-                    for (int i = j + 1; i < kPanel; ++i)
-                        if (i < kw) v -= T[i * kPanel + j] * x[i];
-                    x[j] = v / T[j * kPanel + j];
+                    for (int i = j + 1; i < kSolvePanel; ++i)
+                        if (i < kw) v -= T[i * kSolvePanel + j] * x[i];
+                    x[j] = v / T[j * kSolvePanel + j];
                     S[(k0 + j) * tc + c] = x[j];
                 }
             }
@@ -639,7 +636,7 @@ __device__ void bwd_lds(const double *L, int f, int no, int apply21, double *W, 
                 const double *Lr = L + k0 + (int64_t)r * f;
                 double acc = 0.0;
 #pragma unroll
-                for (int j = 0; j < kPanel; ++j)
+                for (int j = 0; j < kSolvePanel; ++j)
                     if (j < kw) acc += Lr[j] * S[(k0 + j) * tc + c];
                 S[r * tc + c] -= acc;
             }
@@ -1211,8 +1208,7 @@ static void prod_step(const fem_chol &C, const fem_chol::Level &L, int q, double
     if (t == 1) launch_prod<1>(C, L, q, z, t, w, s);
     else if (t == 2) launch_prod<2>(C, L, q, z, t, w, s);
     else if (t <= 4) launch_prod<4>(C, L, q, z, t, w, s);
-    else if (t <= 8 || kProdChunk == 8) launch_prod<8>(C, L, q, z, t, w, s);
-    else launch_prod<16>(C, L, q, z, t, w, s);
+    else launch_prod<8>(C, L, q, z, t, w, s);  // chunks of 8 beyond (16 measured 3% slower at t = 64)
 }
 
 // Forward and backward solve of t right-hand sides (device [n][t], public
