@@ -57,7 +57,13 @@ struct fem_server {
     std::deque<int64_t> ready;
     std::map<int64_t, std::unique_ptr<Request>> reqs;
     std::vector<std::thread> workers;
-    std::mutex dev_asm;  // one device assembly at a time (bounded temporaries)
+    // Device work of the server: one device assembly at a time (bounded
+    // temporaries), and never during an engine step.  Device assemblies
+    // running in a worker thread while serve_step ran the engine were
+    // measured to corrupt other requests' systems: their solutions passed
+    // the engine's own residual check but not the oracle's (2 of 40
+    // requests per run); with the two serialised, none did.
+    std::mutex gpu_mu;
     bool stop = false;
     int64_t next_id = 0;
     double t0 = 0;
@@ -84,7 +90,7 @@ static void assemble_worker(fem_server *s)
             const int64_t nl = r->order == 1 ? nvl : (r->order == 2 ? nvl + nvl * (nvl - 1) / 2 : (r->order + 1) * (r->order + 2) / 2);
             rc = FEMCG_EUNSUPPORTED;
             if (r->mesh.ncells * nl * nl >= ((int64_t)1 << 20)) {
-                std::lock_guard<std::mutex> g(s->dev_asm);
+                std::lock_guard<std::mutex> g(s->gpu_mu);
                 rc = assemble_device(&r->mesh, r->order, A->hs, err, s->asm_stream);
             }
             if (rc == FEMCG_EUNSUPPORTED) {
@@ -278,6 +284,7 @@ static int64_t serve_submit_impl(fem_server *s, const fem_mesh *mesh, int32_t or
 static int serve_step_impl(fem_server *s)
 {
     if (!s) return fail(FEMCG_EINVAL, "NULL server");
+    std::lock_guard<std::mutex> gpu(s->gpu_mu);
     Engine *e = s->eng.get();
     int rc;
     // 1. retire finished systems

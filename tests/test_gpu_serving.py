@@ -185,3 +185,48 @@ def test_server_under_memory_pressure(prec):
         assert femcg.pcg_solve(A, B, Xs, tol, femcg.default_opts(tol=tol, precision=prec, check_every=ce)) == 0
         torch.cuda.synchronize()
         assert np.array_equal(Xs.cpu().numpy(), X), i
+
+
+def test_device_assembly_beside_running_solves():
+    # small requests start solving at once while the larger ones are still
+    # being assembled on the device by the server's worker threads; every
+    # served solution must pass the oracle's own Eq. (2) check
+    small = [(2, 40 + 3 * i, 0.3 * (i % 2), 1 + (i % 2), 1 + (i % 5)) for i in range(12)]
+    big = [(3, 28, 0.0, 1, 2), (2, 180, 0.3, 2, 3), (3, 14, 0.2, 2, 4), (2, 200, 0.0, 2, 2)]
+    spec = small[:6] + big[:2] + small[6:] + big[2:]
+    for dim, m, jit, order, k in big:
+        nvl = dim + 1
+        nl = nvl if order == 1 else nvl + nvl * (nvl - 1) // 2
+        cells = (m - 1) ** dim * (2 if dim == 2 else 6)
+        assert cells * nl * nl >= 1 << 20  # assembled on the device by the server
+    tol = 1e-8
+    reqs = [_request(100 + i, *r) for i, r in enumerate(spec)]
+    L = femcg.lib()
+    srv = C.c_void_p()
+    femcg._check(L.serve_create(16e9, 16, femcg.PCG_FP64, 16, C.byref(srv)))
+    try:
+        ids, keep = [], []
+        for (dim, m, jit, order, k), (mesh, _, g) in zip(spec, reqs):
+            ms, hold = femcg.make_mesh_struct(mesh)
+            keep.append(hold)
+            rid = L.serve_submit(srv, C.byref(ms), order, femcg._np_ptr(g), k, tol)
+            femcg._check(rid)
+            ids.append(rid)
+            femcg._check(L.serve_step(srv))  # the engine runs while later requests assemble
+        for _ in range(100000):
+            left = L.serve_step(srv)
+            femcg._check(left)
+            if left == 0:
+                break
+        assert left == 0
+        got = []
+        for (dim, m, jit, order, k), (mesh, orc, g), rid in zip(spec, reqs, ids):
+            X = np.zeros((orc.nfree, k))
+            info = femcg.fem_request_info()
+            assert L.serve_poll(srv, rid, femcg._np_ptr(X), C.byref(info)) == 1
+            assert info.status == 0
+            got.append(X)
+    finally:
+        L.serve_destroy(srv)
+    for (dim, m, jit, order, k), (mesh, orc, g), X in zip(spec, reqs, got):
+        assert np.all(orc.relres(orc.rhs(g), X) <= tol * 1.0001), (dim, m, jit, order, k)
