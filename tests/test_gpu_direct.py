@@ -88,3 +88,18 @@ def test_full_size_c2_residual():
     x = _solve(L, B)
     orc = oracle.System(w.mesh, w.order)
     assert orc.relres(orc.rhs(g), x)[0] <= 1e-12
+
+
+@pytest.mark.parametrize("dim,m,jit,order,k", [(3, 40, 0.0, 1, 20), (2, 160, 0.3, 1, 13)])
+def test_many_columns_in_chunks(dim, m, jit, order, k):
+    # more right-hand sides than one chunk of the large fronts' products (8)
+    # and of the small fronts' LDS stage: the block equals column-at-a-time
+    # solves and passes the oracle's residual check
+    orc, A, g, B = _setup(dim, m, jit, order, k, 80 + m)
+    L = femcg.Chol(A)
+    x = _solve(L, B)
+    Bo = orc.rhs(g)
+    assert np.all(orc.relres(Bo, x) <= 1e-12)
+    for j in (0, 7, 8, k - 1):
+        xj = _solve(L, B[:, j:j + 1].contiguous())
+        assert np.linalg.norm(xj[:, 0] - x[:, j]) <= 1e-13 * np.linalg.norm(x[:, j])
