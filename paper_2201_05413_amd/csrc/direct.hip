@@ -41,8 +41,10 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cmath>
 #include <numeric>
+#include <thread>
 
 namespace femcg {
 
@@ -178,15 +180,39 @@ static void build_graph(const HostSystem &hs, Graph &G)
     });
 }
 
+// One dissection context: its own marks and nodes, positions written from
+// `next` into the shared permutation (disjoint ranges per context).
 struct NdState {
     const HostSystem *hs;
     const Graph *G;
     std::vector<int32_t> mark;  // stamps
     int32_t stamp = 0;
     int64_t next = 0;           // next free position
-    std::vector<int32_t> perm;
+    std::vector<int32_t> *perm;
     std::vector<ChNode> nodes;
 };
+
+// Subtrees above this depth are dissected on threads of their own (the
+// result is the serial one: nodes and positions in the same postorder).
+constexpr int kNdThreadDepth = 3;
+
+// Run fn(i) for i in [0, count) on up to 16 threads, items taken in turn.
+static void par_items(int64_t count, const std::function<void(int64_t)> &fn)
+{
+    unsigned hw = std::thread::hardware_concurrency();
+    const int nt = (int)std::min<int64_t>(count, std::min<unsigned>(hw ? hw : 1, 16));
+    if (nt <= 1) {
+        for (int64_t i = 0; i < count; ++i) fn(i);
+        return;
+    }
+    std::atomic<int64_t> next{0};
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&] {
+            for (int64_t i = next++; i < count; i = next++) fn(i);
+        });
+    for (auto &x : th) x.join();
+}
 
 static double coord(const NdState &S, int32_t i, int r)
 {
@@ -198,7 +224,7 @@ static int new_node(NdState &S, const std::vector<int32_t> &own, int depth)
 {
     ChNode nd;
     nd.b = S.next;
-    for (int32_t i : own) S.perm[S.next++] = i;
+    for (int32_t i : own) (*S.perm)[S.next++] = i;
     nd.e = S.next;
     nd.depth = depth;
     S.nodes.push_back(std::move(nd));
@@ -257,8 +283,48 @@ static int dissect(NdState &S, std::vector<int32_t> &ids, int depth)
     cut.erase(std::remove_if(cut.begin(), cut.end(), [&](int32_t i) { return S.mark[i] == S.stamp; }), cut.end());
     ids.clear();
     ids.shrink_to_fit();
-    const int c0 = L.empty() ? -1 : dissect(S, L, depth + 1);
-    const int c1 = R.empty() ? -1 : dissect(S, R, depth + 1);
+    int c0 = -1, c1 = -1;
+    if (depth < kNdThreadDepth && !L.empty() && !R.empty()) {
+        // the left subtree on a thread of its own, into positions
+        // [next, next + |L|), with its own marks; its nodes are then
+        // appended before the right subtree's, as the serial order has them
+        NdState SL;
+        SL.hs = S.hs;
+        SL.G = S.G;
+        SL.mark.assign(S.mark.size(), 0);
+        SL.perm = S.perm;
+        SL.next = S.next;
+        S.next += (int64_t)L.size();
+        std::thread tl([&] { dissect(SL, L, depth + 1); });
+        NdState SR;
+        SR.hs = S.hs;
+        SR.G = S.G;
+        SR.perm = S.perm;
+        SR.next = S.next;
+        SR.mark.swap(S.mark);  // the right subtree reuses this context's marks
+        SR.stamp = S.stamp;
+        dissect(SR, R, depth + 1);
+        tl.join();
+        S.mark.swap(SR.mark);
+        S.stamp = SR.stamp;
+        S.next = SR.next;
+        const int off = (int)S.nodes.size();
+        auto append = [&](std::vector<ChNode> &v, int base) {
+            for (ChNode &nd : v) {
+                for (int &c : nd.child)
+                    if (c >= 0) c += base;
+                if (nd.parent >= 0) nd.parent += base;
+                S.nodes.push_back(std::move(nd));
+            }
+        };
+        append(SL.nodes, off);
+        c0 = (int)S.nodes.size() - 1;
+        append(SR.nodes, (int)S.nodes.size());
+        c1 = (int)S.nodes.size() - 1;
+    } else {
+        c0 = L.empty() ? -1 : dissect(S, L, depth + 1);
+        c1 = R.empty() ? -1 : dissect(S, R, depth + 1);
+    }
     const int k = new_node(S, sep, depth);
     S.nodes[k].child[0] = c0;
     S.nodes[k].child[1] = c1;
@@ -279,43 +345,46 @@ int chol_symbolic(const HostSystem &hs, fem_chol &C)
     S.hs = &hs;
     S.G = &G;
     S.mark.assign(hs.nfree, 0);
-    S.perm.assign(hs.nfree, 0);
+    std::vector<int32_t> perm(hs.nfree, 0);
+    S.perm = &perm;
     std::vector<int32_t> all(hs.nfree);
     std::iota(all.begin(), all.end(), 0);
     if (hs.nfree > 0) dissect(S, all, 0);
     C.n = hs.nfree;
-    C.perm = std::move(S.perm);
+    C.perm = std::move(perm);
     C.nodes = std::move(S.nodes);
     const double t1 = now_s();
     std::vector<int32_t> ipos(C.n);
     for (int64_t p = 0; p < C.n; ++p) ipos[C.perm[p]] = (int32_t)p;
-    // update sets, children first (the node list is in postorder)
-    std::vector<int64_t> mark(C.n, -1);
-    for (size_t k = 0; k < C.nodes.size(); ++k) {
-        ChNode &nd = C.nodes[k];
-        std::vector<int64_t> u;
-        auto add = [&](int64_t q) {
-            if (q >= nd.e && mark[q] != (int64_t)k) {
-                mark[q] = (int64_t)k;
-                u.push_back(q);
-            }
-        };
-        for (int64_t p = nd.b; p < nd.e; ++p) {
-            const int32_t i = C.perm[p];
-            for (int64_t t = G.ptr[i]; t < G.ptr[i + 1]; ++t) add(ipos[G.adj[t]]);
-        }
-        for (int c : nd.child)
-            if (c >= 0) {
-                for (int64_t q : C.nodes[c].upd) add(q);
-            }
-        std::sort(u.begin(), u.end());
-        nd.upd = std::move(u);
-    }
-    // levels and statistics
+    // levels (a node's children are one level deeper)
     int maxd = 0;
     for (const ChNode &nd : C.nodes) maxd = std::max(maxd, nd.depth);
     C.levels.assign(maxd + 1, {});
     for (size_t k = 0; k < C.nodes.size(); ++k) C.levels[C.nodes[k].depth].push_back((int32_t)k);
+    // update sets, deepest level first; the nodes of a level in parallel:
+    // the later neighbours of the own rows and the children's update
+    // positions, sorted and made unique
+    for (int d = maxd; d >= 0; --d) {
+        const std::vector<int32_t> &lv = C.levels[d];
+        par_items((int64_t)lv.size(), [&](int64_t li) {
+            ChNode &nd = C.nodes[lv[li]];
+            std::vector<int64_t> u;
+            for (int64_t p = nd.b; p < nd.e; ++p) {
+                const int32_t i = C.perm[p];
+                for (int64_t t = G.ptr[i]; t < G.ptr[i + 1]; ++t) {
+                    const int64_t q = ipos[G.adj[t]];
+                    if (q >= nd.e) u.push_back(q);
+                }
+            }
+            for (int c : nd.child)
+                if (c >= 0)
+                    for (int64_t q : C.nodes[c].upd)
+                        if (q >= nd.e) u.push_back(q);
+            std::sort(u.begin(), u.end());
+            u.erase(std::unique(u.begin(), u.end()), u.end());
+            nd.upd = std::move(u);
+        });
+    }
     chol_stats_t &st = C.stats;
     st.n = C.n;
     st.nodes = (int32_t)C.nodes.size();
@@ -919,11 +988,12 @@ int chol_setup(const HostSystem &hs, fem_chol &C)
     std::vector<int32_t> ipos(n);
     for (int64_t p = 0; p < n; ++p) ipos[C.perm[p]] = (int32_t)p;
     C.hnodes.assign(nn, DNode{});
-    std::vector<int64_t> index;
     const int nlev = (int)C.levels.size();
     C.lev.assign(nlev, fem_chol::Level{});
-    int64_t panel = 0;
-    // deepest level first: panels in factorisation order
+    int64_t panel = 0, nindex = 0;
+    // offsets, deepest level first: panels in factorisation order; in the
+    // index store each node's update positions, then its children's
+    // relative indices
     for (int d = nlev - 1; d >= 0; --d) {
         fem_chol::Level &L = C.lev[d];
         L.panel0 = panel;
@@ -940,18 +1010,14 @@ int chol_setup(const HostSystem &hs, fem_chol &C)
             u += nd.nu() * nd.nu();
             D.wunit = w;
             w += nd.f();
-            D.idx = (int64_t)index.size();
-            index.insert(index.end(), nd.upd.begin(), nd.upd.end());
+            D.idx = nindex;
+            nindex += nd.nu();
             for (int s = 0; s < 2; ++s) {
                 D.child[s] = nd.child[s];
                 D.rel[s] = 0;
                 if (nd.child[s] < 0) continue;
-                D.rel[s] = (int64_t)index.size();
-                for (int64_t q : C.nodes[nd.child[s]].upd) {
-                    const int64_t r = front_index(nd, q);
-                    if (r < 0) return fail(FEMCG_EINVAL, "chol: update position %lld outside the parent front", (long long)q);
-                    index.push_back(r);
-                }
+                D.rel[s] = nindex;
+                nindex += C.nodes[nd.child[s]].nu();
             }
         }
         L.panel1 = panel;
@@ -960,28 +1026,66 @@ int chol_setup(const HostSystem &hs, fem_chol &C)
         C.max_udoubles = std::max(C.max_udoubles, u);
         C.max_wunits = std::max(C.max_wunits, w);
     }
-    // assembly map: A entries (q >= p) of every own column p
-    std::vector<std::vector<int64_t>> adst(nlev);
-    std::vector<std::vector<double>> aval(nlev);
-    for (int d = 0; d < nlev; ++d)
-        for (int32_t k : C.levels[d]) {
-            const ChNode &nd = C.nodes[k];
-            const DNode &D = C.hnodes[k];
-            const int64_t f = nd.f();
-            for (int64_t p = nd.b; p < nd.e; ++p) {
-                const int64_t i = C.perm[p];
-                const double thr = prune_threshold(hs, i);
-                for (int64_t t = hs.a_rowptr[i]; t < hs.a_rowptr[i + 1]; ++t) {
-                    const int64_t j = hs.a_col[t];
-                    const int64_t q = ipos[j];
-                    if (q < p || (j != i && !(std::fabs(hs.a_val[t]) > thr))) continue;
-                    const int64_t r = front_index(nd, q);
-                    if (r < 0) return fail(FEMCG_EINVAL, "chol: matrix entry (%lld, %lld) outside its front", (long long)p, (long long)q);
-                    adst[d].push_back(D.panel + r + (p - nd.b) * f);
-                    aval[d].push_back(hs.a_val[t]);
-                }
+    // the index store, nodes in parallel (binary searches in the fronts)
+    std::vector<int64_t> index(nindex);
+    std::atomic<int64_t> bad_upd{-1};
+    par_items((int64_t)nn, [&](int64_t k) {
+        const ChNode &nd = C.nodes[k];
+        const DNode &D = C.hnodes[k];
+        std::copy(nd.upd.begin(), nd.upd.end(), index.begin() + D.idx);
+        for (int s = 0; s < 2; ++s) {
+            if (nd.child[s] < 0) continue;
+            int64_t o = D.rel[s];
+            for (int64_t q : C.nodes[nd.child[s]].upd) {
+                const int64_t r = front_index(nd, q);
+                if (r < 0) bad_upd = q;
+                index[o++] = r;
             }
         }
+    });
+    if (bad_upd >= 0)
+        return fail(FEMCG_EINVAL, "chol: update position %lld outside the parent front", (long long)bad_upd.load());
+    // assembly map: A entries (q >= p) of every own column p; nodes in
+    // parallel, then concatenated level by level in node order
+    std::vector<std::vector<int64_t>> adst(nlev);
+    std::vector<std::vector<double>> aval(nlev);
+    std::vector<std::vector<int64_t>> ndst(nn);
+    std::vector<std::vector<double>> nval(nn);
+    std::atomic<int64_t> bad_p{-1};
+    par_items((int64_t)nn, [&](int64_t k) {
+        const ChNode &nd = C.nodes[k];
+        const DNode &D = C.hnodes[k];
+        const int64_t f = nd.f();
+        for (int64_t p = nd.b; p < nd.e; ++p) {
+            const int64_t i = C.perm[p];
+            const double thr = prune_threshold(hs, i);
+            for (int64_t t = hs.a_rowptr[i]; t < hs.a_rowptr[i + 1]; ++t) {
+                const int64_t j = hs.a_col[t];
+                const int64_t q = ipos[j];
+                if (q < p || (j != i && !(std::fabs(hs.a_val[t]) > thr))) continue;
+                const int64_t r = front_index(nd, q);
+                if (r < 0) {
+                    bad_p = p;
+                    continue;
+                }
+                ndst[k].push_back(D.panel + r + (p - nd.b) * f);
+                nval[k].push_back(hs.a_val[t]);
+            }
+        }
+    });
+    if (bad_p >= 0) return fail(FEMCG_EINVAL, "chol: a matrix entry of row %lld lies outside its front", (long long)bad_p.load());
+    for (int d = 0; d < nlev; ++d) {
+        size_t tot = 0;
+        for (int32_t k : C.levels[d]) tot += ndst[k].size();
+        adst[d].reserve(tot);
+        aval[d].reserve(tot);
+        for (int32_t k : C.levels[d]) {
+            adst[d].insert(adst[d].end(), ndst[k].begin(), ndst[k].end());
+            aval[d].insert(aval[d].end(), nval[k].begin(), nval[k].end());
+            std::vector<int64_t>().swap(ndst[k]);
+            std::vector<double>().swap(nval[k]);
+        }
+    }
     // device lists: per level node ids (all, mid, big), extend-add pairs, assembly
     size_t bytes = 0;
     auto reserve = [&](size_t b) {
@@ -1301,6 +1405,8 @@ extern "C" int chol_analyze(const fem_matrix *A, chol_stats_t *out, int32_t *per
         return FEMCG_OK;
     } catch (const std::bad_alloc &) {
         return fail(FEMCG_ENOMEM, "chol_analyze: host allocation failed");
+    } catch (const std::exception &ex) {  // e.g. no host thread for the ordering
+        return fail(FEMCG_ENOMEM, "chol_analyze: %s", ex.what());
     }
 }
 
@@ -1328,6 +1434,8 @@ extern "C" int chol_factor(fem_matrix *A, fem_chol **out, void *stream)
         return FEMCG_OK;
     } catch (const std::bad_alloc &) {
         return fail(FEMCG_ENOMEM, "chol_factor: host allocation failed");
+    } catch (const std::exception &ex) {  // e.g. no host thread for the ordering
+        return fail(FEMCG_ENOMEM, "chol_factor: %s", ex.what());
     }
 }
 
@@ -1342,6 +1450,8 @@ extern "C" int chol_solve(fem_chol *L, const double *B, double *X, int32_t k, vo
         return rc;
     } catch (const std::bad_alloc &) {
         return fail(FEMCG_ENOMEM, "chol_solve: host allocation failed");
+    } catch (const std::exception &ex) {  // e.g. no host thread for the ordering
+        return fail(FEMCG_ENOMEM, "chol_solve: %s", ex.what());
     }
 }
 

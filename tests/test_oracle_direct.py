@@ -96,3 +96,17 @@ def test_host_analysis_orders_and_bounds_fill(dim, m, jit, order):
     exact = _exact_fill(Ap | Ap.T)
     assert exact <= st["nnz_l"] <= n * (n + 1) // 2
     assert st["max_front"] <= n and st["nodes"] >= 1 and st["flops"] > 0
+
+
+def test_host_analysis_is_deterministic():
+    # the ordering runs its top subtrees on threads of their own and the
+    # update sets level by level in parallel: repeated analyses agree
+    from paper_2201_05413_amd import femcg
+    mesh = meshgen.make_mesh(3, 30, 0.2, 46)
+    H = femcg.Matrix(mesh, 1, femcg.FEM_FORMAT_CSR | femcg.FEM_ASSEMBLE_HOST_ONLY)
+    st0, p0 = femcg.chol_analyze(H)
+    for _ in range(3):
+        st, p = femcg.chol_analyze(H)
+        assert np.array_equal(p, p0)
+        assert (st["nnz_l"], st["nodes"], st["levels"], st["max_front"], st["flops"]) == \
+            (st0["nnz_l"], st0["nodes"], st0["levels"], st0["max_front"], st0["flops"])
