@@ -54,7 +54,6 @@ constexpr int kPanel = 8;         // columns per LDS panel of the workgroup fact
 constexpr int kSolvePanel = 8;    // columns per triangle panel of the workgroup solves (16 and 32 measured slower)
 constexpr int kDBlock = 256;      // threads per workgroup of the direct kernels
 constexpr int kSolveLds = 8192;   // doubles of LDS per solve workgroup (64 KB)
-constexpr int kAuxStreams = 3;    // extra streams for the larger fronts' library calls in a level
 constexpr int kWaveLanes = 64;    // lanes per wavefront
 constexpr int kBigRows = 64;      // rows per workgroup of the larger fronts' row products (one per lane)
 constexpr int kBigCols = 4;       // columns per workgroup of their column products
@@ -1209,24 +1208,6 @@ int chol_numeric(fem_chol &C, hipStream_t s)
 {
     double *ubuf[2] = {nullptr, nullptr};
     int32_t *info = nullptr;
-    // the larger fronts of a level are independent: their library calls go
-    // round-robin to the main stream and kAuxStreams more, joined by events
-    // at the end of the level
-    struct Aux {
-        hipStream_t st[kAuxStreams] = {};
-        rocblas_handle h[kAuxStreams] = {};
-        hipEvent_t ready = nullptr, done[kAuxStreams] = {};
-        ~Aux()
-        {
-            for (int a = 0; a < kAuxStreams; ++a) {
-                if (st[a]) (void)hipStreamSynchronize(st[a]);
-                if (h[a]) (void)rocblas_destroy_handle(h[a]);
-                if (st[a]) (void)hipStreamDestroy(st[a]);
-                if (done[a]) (void)hipEventDestroy(done[a]);
-            }
-            if (ready) (void)hipEventDestroy(ready);
-        }
-    } aux;
     struct Release {
         double **u;
         int32_t **i;
@@ -1237,14 +1218,6 @@ int chol_numeric(fem_chol &C, hipStream_t s)
             if (*i) (void)hipFree(*i);
         }
     } release{ubuf, &info};
-    DCHK(hipEventCreateWithFlags(&aux.ready, hipEventDisableTiming));
-    for (int a = 0; a < kAuxStreams; ++a) {
-        DCHK(hipStreamCreateWithFlags(&aux.st[a], hipStreamNonBlocking));
-        DCHK(hipEventCreateWithFlags(&aux.done[a], hipEventDisableTiming));
-        BCHK(rocblas_create_handle(&aux.h[a]));
-        BCHK(rocblas_set_stream(aux.h[a], aux.st[a]));
-        BCHK(rocblas_set_pointer_mode(aux.h[a], rocblas_pointer_mode_host));
-    }
     for (int b = 0; b < 2; ++b) DCHK(hipMalloc((void **)&ubuf[b], sizeof(double) * std::max<int64_t>(C.max_udoubles, 1)));
     int64_t nbig = 0;
     for (const auto &L : C.lev) nbig += (int64_t)L.big.size();
@@ -1276,33 +1249,22 @@ int chol_numeric(fem_chol &C, hipStream_t s)
             hipLaunchKernelGGL(k_mid_factor, dim3(L.nbigtri), dim3(kDBlock), sizeof(double) * L.tri_rows * kPanel, s,
                                C.d_nodes, L.dbigtri, C.d_panel, u, C.d_fail, 1);
         DCHK(hipGetLastError());
-        const int nuse = (int)std::min<size_t>(L.big.size(), kAuxStreams + 1);  // streams this level uses
-        if (nuse > 1) {
-            DCHK(hipEventRecord(aux.ready, s));
-            for (int a = 0; a + 1 < nuse; ++a) DCHK(hipStreamWaitEvent(aux.st[a], aux.ready, 0));
-        }
-        for (size_t bi = 0; bi < L.big.size(); ++bi, ++ib) {
-            const int32_t k = L.big[bi];
-            const int a = (int)(bi % (size_t)nuse);  // 0: the main stream
-            rocblas_handle hb = a == 0 ? C.blas : aux.h[a - 1];
+        for (int32_t k : L.big) {
             const DNode &D = C.hnodes[k];
             const int f = D.no + D.nu;
             double *P = C.d_panel + D.panel;
-            if (D.no > kMidFront) BCHK(rocsolver_dpotrf(hb, rocblas_fill_lower, D.no, P, f, info + ib));
+            if (D.no > kMidFront) BCHK(rocsolver_dpotrf(C.blas, rocblas_fill_lower, D.no, P, f, info + ib));
             if (D.no > 0 && D.nu > 0) {
                 const double one = 1.0, mone = -1.0;
-                BCHK(rocblas_dtrsm(hb, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
+                BCHK(rocblas_dtrsm(C.blas, rocblas_side_right, rocblas_fill_lower, rocblas_operation_transpose,
                                    rocblas_diagonal_non_unit, D.nu, D.no, &one, P, f, P + D.no, f));
-                BCHK(rocblas_dsyrk(hb, rocblas_fill_lower, rocblas_operation_none, D.nu, D.no, &mone, P + D.no, f,
+                BCHK(rocblas_dsyrk(C.blas, rocblas_fill_lower, rocblas_operation_none, D.nu, D.no, &mone, P + D.no, f,
                                    &one, u + D.u, D.nu));
             }
             // L11 -> L11^-1 for the product-form solves (L21 and U no longer need L11)
             if (D.no > 0)
-                BCHK(rocsolver_dtrtri(hb, rocblas_fill_lower, rocblas_diagonal_non_unit, D.no, P, f, info + nbig + ib));
-        }
-        for (int a = 0; a + 1 < nuse; ++a) {
-            DCHK(hipEventRecord(aux.done[a], aux.st[a]));
-            DCHK(hipStreamWaitEvent(s, aux.done[a], 0));
+                BCHK(rocsolver_dtrtri(C.blas, rocblas_fill_lower, rocblas_diagonal_non_unit, D.no, P, f, info + nbig + ib));
+            ++ib;
         }
     }
     // the larger fronts' L11^-1 mirrored into their upper triangles (the
