@@ -103,3 +103,19 @@ def test_many_columns_in_chunks(dim, m, jit, order, k):
     for j in (0, 7, 8, k - 1):
         xj = _solve(L, B[:, j:j + 1].contiguous())
         assert np.linalg.norm(xj[:, 0] - x[:, j]) <= 1e-13 * np.linalg.norm(x[:, j])
+
+
+def test_full_size_cube_residual():
+    # the 128^3 cube: 47,127 fronts up to 23,814 rows, a 25 GB factor; a
+    # block of 3 harmonic right-hand sides against the oracle's own residual
+    w = meshgen.c3()
+    A = femcg.Matrix(w.mesh, w.order, femcg.FEM_FORMAT_SELL)
+    g = np.ascontiguousarray(w.dirichlet(A.dofs()[0])[:, :3])
+    B = torch.empty((A.n_free, 3), dtype=torch.float64, device="cuda")
+    femcg.fem_rhs(A, g, B)
+    L = femcg.Chol(A)
+    assert L.stats()["max_front"] > 20000
+    x = _solve(L, B)
+    L.free()
+    orc = oracle.System(w.mesh, w.order)
+    assert np.all(orc.relres(orc.rhs(g), x) <= 1e-12)
