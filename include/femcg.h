@@ -231,10 +231,10 @@ typedef struct {
 int chol_analyze(const fem_matrix *A, chol_stats_t *out, int32_t *perm_out);
 
 /* Factorise A = K_II (device copy needed): ordering and symbolic analysis on
- * the host, numeric factorisation on stream (synchronised on return).  The
- * fronts above 1,024 rows keep their diagonal blocks inverted (L11^-1, also
- * stored transposed), so that chol_solve applies them as matrix products;
- * the factor is otherwise the Cholesky factor L of A(perm, perm).  *out
+ * the host, numeric factorisation on stream (synchronised on return).  Every
+ * front keeps its diagonal block inverted (L11^-1, also stored transposed),
+ * so that chol_solve applies them as matrix products; the factor is
+ * otherwise the Cholesky factor L of A(perm, perm).  *out
  * receives a library-owned factor, independent of A afterwards; free it with
  * chol_free.  Returns 0, FEMCG_EINVAL (NULL, host-only matrix),
  * FEMCG_EBREAKDOWN (a non-positive pivot: A not positive definite),

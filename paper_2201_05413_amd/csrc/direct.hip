@@ -51,7 +51,6 @@ namespace femcg {
 constexpr int kLeaf = 64;         // nested-dissection leaves: at most this many DOFs
 constexpr int kMidFront = 1024;   // fronts up to this size: one workgroup each
 constexpr int kPanel = 8;         // columns per LDS panel of the workgroup factorisation
-constexpr int kSolvePanel = 8;    // columns per triangle panel of the workgroup solves (16 and 32 measured slower)
 constexpr int kDBlock = 256;      // threads per workgroup of the direct kernels
 constexpr int kSolveLds = 8192;   // doubles of LDS per solve workgroup (64 KB)
 constexpr int kWaveLanes = 64;    // lanes per wavefront
@@ -113,6 +112,7 @@ struct fem_chol {
         int32_t *prod[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
         int32_t nprod[5] = {0, 0, 0, 0, 0};
         int32_t mid_rows = 0, tri_rows = 0;      // LDS rows of the factor launches (largest f, largest no)
+        int32_t solve_rows = 0;                  // LDS rows of the mid-front solves (largest f + no)
         int64_t panel0 = 0, panel1 = 0;          // the level's range in the panel store
         int64_t udoubles = 0;                    // update blocks of the level's nodes
         int64_t wunits = 0;                      // sum of f over the level's nodes
@@ -561,195 +561,176 @@ __device__ void fwd_gather(const DNode &D, const DNode *nodes, const int64_t *in
     __syncthreads();
 }
 
-// Backward gather, columns [c0, c0 + tc): own rows from z (y), update rows
-// from z at the update positions (the ancestors' x).
-__device__ void bwd_gather(const DNode &D, const int64_t *index, const double *z, int t, double *W, int c0, int tc)
-{
-    const int f = D.no + D.nu;
-    const int64_t *upd = index + D.idx;
-    for (int64_t e = threadIdx.x; e < (int64_t)f * tc; e += kDBlock) {
-        const int c = c0 + (int)(e / f), r = (int)(e % f);
-        W[r + (int64_t)c * f] = r < D.no ? z[(D.b + r) * t + c] : z[upd[r - D.no] * t + c];
-    }
-    __syncthreads();
-}
+// Solves of a front up to kMidFront, whose own block holds L11^-1 (lower
+// triangle, diagonal included) and its transpose (strictly upper
+// triangle), so that both triangular solves are products.  One workgroup
+// per (front, chunk of cw right-hand-side columns, blockIdx.y); the chunk
+// of W is staged in LDS as S (f x tc) with the product in T (no x tc).
+// Threads take (row, column) pairs with the rows fastest, so that the
+// factor's loads of a wave are contiguous; every sum runs over its index
+// in one fixed order.  Dynamic LDS: kSolveLds doubles, (f + no) x cw fit.
 
-__device__ void own_store(const DNode &D, const double *W, int t, double *z, int c0, int tc)
-{
-    const int f = D.no + D.nu;
-    for (int64_t e = threadIdx.x; e < (int64_t)D.no * tc; e += kDBlock) {
-        const int c = c0 + (int)(e / D.no), r = (int)(e % D.no);
-        z[(D.b + r) * t + c] = W[r + (int64_t)c * f];
-    }
-}
-
-// The panel's diagonal block, T[j][i] = L(k0 + j, k0 + i) for i <= j < kw,
-// read by all threads at once (one round trip), then a barrier.
-__device__ void stage_triangle(const double *L, int f, int k0, int kw, double *T)
-{
-    for (int e = threadIdx.x; e < kSolvePanel * kSolvePanel; e += kDBlock) {
-        const int j = e / kSolvePanel, i = e - j * kSolvePanel;
-        T[e] = (j < kw && i <= j) ? L[(k0 + j) + (int64_t)(k0 + i) * f] : 0.0;
-    }
-    __syncthreads();
-}
-
-// Forward substitution with L11 on the own rows [0, no) of W (f x t, ld f),
-// applying L21 to the rows [no, rend) as well when rend = f (rend = no: L11
-// only).  Chunks of tc right-hand sides are staged in LDS (rend x tc, S), and
-// L11 is walked in panels of kSolvePanel columns: lane c solves the panel's
-// triangle for column c on its own, then every later row loses the panel's
-// contribution (sum over the panel's columns in order) in one pass.
-__device__ void fwd_lds(const double *L, int f, int no, int rend, double *W, int t, double *S)
-{
-    __shared__ double T[kSolvePanel * kSolvePanel];
-    const int tid = threadIdx.x;
-    const int tcm = max(1, min(t, kSolveLds / max(rend, 1)));
-    for (int c0 = 0; c0 < t; c0 += tcm) {
-        const int tc = min(tcm, t - c0);
-        for (int64_t e = tid; e < (int64_t)rend * tc; e += kDBlock) {
-            const int c = (int)(e / rend), r = (int)(e - (int64_t)c * rend);
-            S[r * tc + c] = W[r + (int64_t)(c0 + c) * f];
-        }
-        __syncthreads();
-        for (int k0 = 0; k0 < no; k0 += kSolvePanel) {
-            const int kw = min(kSolvePanel, no - k0);
-            stage_triangle(L, f, k0, kw, T);
-            for (int c = tid; c < tc; c += kDBlock) {
-                double x[kSolvePanel];
-#pragma unroll
-                for (int j = 0; j < kSolvePanel; ++j) {
-                    if (j >= kw) break;
-                    double v = S[(k0 + j) * tc + c];
-#pragma unroll
-                    for (int i = 0; i < j; ++i) v -= T[j * kSolvePanel + i] * x[i];
-                    x[j] = v / T[j * kSolvePanel + j];
-                    S[(k0 + j) * tc + c] = x[j];
-                }
-            }
-            __syncthreads();
-            const int r0 = k0 + kw, nr = rend - r0;
-            for (int64_t e = tid; e < (int64_t)nr * tc; e += kDBlock) {
-                const int c = (int)(e / nr), r = r0 + (int)(e - (int64_t)c * nr);
-                double acc = 0.0;
-#pragma unroll
-                for (int j = 0; j < kSolvePanel; ++j)
-                    if (j < kw) acc += L[r + (int64_t)(k0 + j) * f] * S[(k0 + j) * tc + c];
-                S[r * tc + c] -= acc;
-            }
-            __syncthreads();
-        }
-        for (int64_t e = tid; e < (int64_t)rend * tc; e += kDBlock) {
-            const int c = (int)(e / rend), r = (int)(e - (int64_t)c * rend);
-            W[r + (int64_t)(c0 + c) * f] = S[r * tc + c];
-        }
-        __syncthreads();
-    }
-}
-
-// Backward: with apply21 the own rows first lose L21^T w_upd (rows no..f-1
-// of W, the ancestors' x), then L11^T back substitution in panels from the
-// last (lane c solves the panel's triangle for column c; earlier rows then
-// lose the panel's contribution).  Chunks of right-hand sides in LDS.
-__device__ void bwd_lds(const double *L, int f, int no, int apply21, double *W, int t, double *S)
-{
-    __shared__ double T[kSolvePanel * kSolvePanel];
-    const int tid = threadIdx.x;
-    const int rows = apply21 ? f : no, nu = f - no;
-    const int tcm = max(1, min(t, kSolveLds / max(rows, 1)));
-    for (int c0 = 0; c0 < t; c0 += tcm) {
-        const int tc = min(tcm, t - c0);
-        for (int64_t e = tid; e < (int64_t)rows * tc; e += kDBlock) {
-            const int c = (int)(e / rows), r = (int)(e - (int64_t)c * rows);
-            S[r * tc + c] = W[r + (int64_t)(c0 + c) * f];
-        }
-        __syncthreads();
-        if (apply21 && nu > 0) {
-            for (int64_t e = tid; e < (int64_t)no * tc; e += kDBlock) {
-                const int i = (int)(e / tc), c = (int)(e - (int64_t)i * tc);
-                const double *Li = L + no + (int64_t)i * f;
-                const double *Sa = S + no * tc + c;
-                // four interleaved partial sums, combined in a fixed order
-                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-                int a = 0;
-                for (; a + 4 <= nu; a += 4) {
-                    a0 += Li[a] * Sa[(int64_t)a * tc];
-                    a1 += Li[a + 1] * Sa[(int64_t)(a + 1) * tc];
-                    a2 += Li[a + 2] * Sa[(int64_t)(a + 2) * tc];
-                    a3 += Li[a + 3] * Sa[(int64_t)(a + 3) * tc];
-                }
-                for (; a < nu; ++a) a0 += Li[a] * Sa[(int64_t)a * tc];
-                S[i * tc + c] -= (a0 + a1) + (a2 + a3);
-            }
-            __syncthreads();
-        }
-        for (int k0 = ((no - 1) / kSolvePanel) * kSolvePanel; k0 >= 0 && no > 0; k0 -= kSolvePanel) {
-            const int kw = min(kSolvePanel, no - k0);
-            stage_triangle(L, f, k0, kw, T);
-            for (int c = tid; c < tc; c += kDBlock) {
-                double x[kSolvePanel];
-#pragma unroll
-                for (int j = kSolvePanel - 1; j >= 0; --j) {
-                    if (j >= kw) continue;
-                    double v = S[(k0 + j) * tc + c];
-#pragma unroll
-                    for (int i = j + 1; i < kSolvePanel; ++i)
-                        if (i < kw) v -= T[i * kSolvePanel + j] * x[i];
-                    x[j] = v / T[j * kSolvePanel + j];
-                    S[(k0 + j) * tc + c] = x[j];
-                }
-            }
-            __syncthreads();
-            for (int64_t e = tid; e < (int64_t)k0 * tc; e += kDBlock) {
-                const int c = (int)(e / k0), r = (int)(e - (int64_t)c * k0);
-                const double *Lr = L + k0 + (int64_t)r * f;
-                double acc = 0.0;
-#pragma unroll
-                for (int j = 0; j < kSolvePanel; ++j)
-                    if (j < kw) acc += Lr[j] * S[(k0 + j) * tc + c];
-                S[r * tc + c] -= acc;
-            }
-            __syncthreads();
-        }
-        for (int64_t e = tid; e < (int64_t)no * tc; e += kDBlock) {
-            const int c = (int)(e / no), r = (int)(e - (int64_t)c * no);
-            W[r + (int64_t)(c0 + c) * f] = S[r * tc + c];
-        }
-        __syncthreads();
-    }
-}
-
-// Whole forward step of a front up to kMidFront, for the right-hand-side
-// columns [c0, c0 + cw) of chunk blockIdx.y: gather, y = L11^-1 w,
-// w_upd -= L21 y, store y.  Dynamic LDS: kSolveLds doubles (cw rows of the
-// largest front of the launch fit).
+// Forward: gather, y = L11^-1 w (rows of L11^-1), w_upd -= L21 y; y to z,
+// w_upd back to W for the parent's gather.
 __global__ __launch_bounds__(kDBlock) void k_mid_fwd(const DNode *nodes, const int32_t *list, const int64_t *index,
                                                      const double *panel, double *z, int t, int cw, double *wbuf,
                                                      const double *wchild)
 {
     extern __shared__ double S[];
     const DNode D = nodes[list[blockIdx.x]];
-    const int f = D.no + D.nu;
+    const int no = D.no, nu = D.nu, f = no + nu, tid = threadIdx.x;
     const int c0 = blockIdx.y * cw, tc = min(cw, t - c0);
     double *W = wbuf + D.wunit * t;
-    fwd_gather(D, nodes, index, z, t, W, wchild, c0, tc);
-    fwd_lds(panel + D.panel, f, D.no, f, W + (int64_t)c0 * f, tc, S);
-    own_store(D, W, t, z, c0, tc);
+    const double *P = panel + D.panel;
+    double *T = S + (int64_t)f * tc;
+    fwd_gather(D, nodes, index, z, t, W, wchild, c0, tc);  // ends with a barrier
+    for (int64_t e = tid; e < (int64_t)f * tc; e += kDBlock) {
+        const int c = (int)(e / f), r = (int)(e % f);
+        S[r * tc + c] = W[r + (int64_t)(c0 + c) * f];
+    }
+    __syncthreads();
+    for (int64_t e = tid; e < (int64_t)no * tc; e += kDBlock) {
+        const int c = (int)(e / no), i = (int)(e % no);
+        double acc = 0.0;
+        for (int j = 0; j <= i; ++j) acc += P[i + (int64_t)j * f] * S[j * tc + c];
+        T[i * tc + c] = acc;
+    }
+    __syncthreads();
+    for (int64_t e = tid; e < (int64_t)nu * tc; e += kDBlock) {
+        const int c = (int)(e / nu), r = no + (int)(e % nu);
+        double acc = 0.0;
+        for (int j = 0; j < no; ++j) acc += P[r + (int64_t)j * f] * T[j * tc + c];
+        W[r + (int64_t)(c0 + c) * f] = S[r * tc + c] - acc;
+    }
+    for (int64_t e = tid; e < (int64_t)no * tc; e += kDBlock) {
+        const int c = (int)(e / no), i = (int)(e % no);
+        z[(D.b + i) * t + c0 + c] = T[i * tc + c];
+    }
 }
 
-// Whole backward step of a front up to kMidFront, columns [c0, c0 + cw) of
-// chunk blockIdx.y: gather, w -= L21^T x_upd, x = L11^-T w, store x.
+// Backward: own rows (y) and update rows (the ancestors' x) from z,
+// w = y - L21^T x_upd (columns of L21), x = L11^-T w (columns of the
+// transpose in the upper triangle); x to z.
 __global__ __launch_bounds__(kDBlock) void k_mid_bwd(const DNode *nodes, const int32_t *list, const int64_t *index,
-                                                     const double *panel, double *z, int t, int cw, double *wbuf)
+                                                     const double *panel, double *z, int t, int cw)
 {
     extern __shared__ double S[];
     const DNode D = nodes[list[blockIdx.x]];
-    const int f = D.no + D.nu;
+    const int no = D.no, nu = D.nu, f = no + nu, tid = threadIdx.x;
     const int c0 = blockIdx.y * cw, tc = min(cw, t - c0);
-    double *W = wbuf + D.wunit * t;
-    bwd_gather(D, index, z, t, W, c0, tc);
-    bwd_lds(panel + D.panel, f, D.no, 1, W + (int64_t)c0 * f, tc, S);
-    own_store(D, W, t, z, c0, tc);
+    const double *P = panel + D.panel;
+    const int64_t *upd = index + D.idx;
+    double *T = S + (int64_t)f * tc;
+    for (int64_t e = tid; e < (int64_t)f * tc; e += kDBlock) {
+        const int c = (int)(e / f), r = (int)(e % f);
+        S[r * tc + c] = r < no ? z[(D.b + r) * t + c0 + c] : z[upd[r - no] * t + c0 + c];
+    }
+    __syncthreads();
+    for (int64_t e = tid; e < (int64_t)no * tc; e += kDBlock) {
+        const int c = (int)(e / no), i = (int)(e % no);
+        const double *Li = P + no + (int64_t)i * f;
+        const double *Sa = S + (int64_t)no * tc + c;
+        // four interleaved partial sums, combined in a fixed order
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int a = 0;
+        for (; a + 4 <= nu; a += 4) {
+            a0 += Li[a] * Sa[(int64_t)a * tc];
+            a1 += Li[a + 1] * Sa[(int64_t)(a + 1) * tc];
+            a2 += Li[a + 2] * Sa[(int64_t)(a + 2) * tc];
+            a3 += Li[a + 3] * Sa[(int64_t)(a + 3) * tc];
+        }
+        for (; a < nu; ++a) a0 += Li[a] * Sa[(int64_t)a * tc];
+        T[i * tc + c] = S[i * tc + c] - ((a0 + a1) + (a2 + a3));
+    }
+    __syncthreads();
+    for (int64_t e = tid; e < (int64_t)no * tc; e += kDBlock) {
+        const int c = (int)(e / no), j = (int)(e % no);
+        double acc = 0.0;
+        for (int i = j; i < no; ++i) acc += P[j + (int64_t)i * f] * T[i * tc + c];
+        z[(D.b + j) * t + c0 + c] = acc;
+    }
+}
+
+// In-place inversion of the own block of fronts up to kMidFront (after the
+// factorisation), one workgroup per front, then its transpose into the
+// strictly upper triangle.  Panels of kPanel columns from the last: with
+// the panel's diagonal block Dp, the rows below it L21p and the already
+// inverted trailing block X22, the rows below become -X22 L21p Dp^-1 and the
+// diagonal block Dp^-1.  Dynamic LDS: max(no * kPanel, transpose tile)
+// doubles.
+__global__ __launch_bounds__(kDBlock) void k_mid_inv(const DNode *nodes, const int32_t *list, double *panel)
+{
+    extern __shared__ double S[];
+    __shared__ double Dm[kPanel][kPanel], Di[kPanel][kPanel];
+    const DNode D = nodes[list[blockIdx.x]];
+    const int no = D.no, f = no + D.nu, tid = threadIdx.x;
+    double *P = panel + D.panel;
+    for (int k0 = ((no - 1) / kPanel) * kPanel; k0 >= 0 && no > 0; k0 -= kPanel) {
+        const int kw = min(kPanel, no - k0), r0 = k0 + kw, m = no - r0;
+        for (int e = tid; e < kPanel * kPanel; e += kDBlock) {
+            const int i = e / kPanel, j = e % kPanel;  // Dm[i][j] = L(k0 + i, k0 + j)
+            Dm[i][j] = (i < kw && j <= i) ? P[(k0 + i) + (int64_t)(k0 + j) * f] : 0.0;
+        }
+        for (int e = tid; e < m * kw; e += kDBlock) {
+            const int r = e / kw, c = e % kw;
+            S[r * kPanel + c] = P[(r0 + r) + (int64_t)(k0 + c) * f];
+        }
+        __syncthreads();
+        if (tid < kw) {  // column c of Dp^-1 by forward substitution
+            const int c = tid;
+            double x[kPanel];
+#pragma unroll
+            for (int i = 0; i < kPanel; ++i) {
+                double v = i == c ? 1.0 : 0.0;
+#pragma unroll
+                for (int j = 0; j < i; ++j) v -= Dm[i][j] * x[j];
+                x[i] = (i < kw && i >= c) ? v / Dm[i][i] : 0.0;
+            }
+#pragma unroll
+            for (int i = 0; i < kPanel; ++i) Di[i][c] = x[i];
+        }
+        __syncthreads();
+        for (int r = tid; r < m; r += kDBlock) {
+            const int gi = r0 + r;
+            double acc[kPanel];
+#pragma unroll
+            for (int c = 0; c < kPanel; ++c) acc[c] = 0.0;
+            for (int j = r0; j <= gi; ++j) {
+                const double x = P[gi + (int64_t)j * f];
+#pragma unroll
+                for (int c = 0; c < kPanel; ++c) acc[c] += x * S[(j - r0) * kPanel + c];
+            }
+            for (int c = 0; c < kw; ++c) {
+                double v = 0.0;
+                for (int q = c; q < kw; ++q) v += acc[q] * Di[q][c];
+                P[gi + (int64_t)(k0 + c) * f] = -v;
+            }
+        }
+        for (int e = tid; e < kw * kw; e += kDBlock) {
+            const int i = e / kw, c = e % kw;
+            if (i >= c) P[(k0 + i) + (int64_t)(k0 + c) * f] = Di[i][c];
+        }
+        __syncthreads();
+    }
+    // the transpose into the strictly upper triangle, one tile at a time
+    constexpr int TT = kMirrorTile / 2;
+    const int nt = (no + TT - 1) / TT;
+    for (int ti = 0; ti < nt; ++ti)
+        for (int tj = 0; tj <= ti; ++tj) {
+            const int ro = ti * TT, co = tj * TT;
+            for (int e = tid; e < TT * TT; e += kDBlock) {
+                const int c = e / TT, r = e % TT;
+                const int gr = ro + r, gc = co + c;
+                S[c * (TT + 1) + r] = (gr < no && gr > gc) ? P[gr + (int64_t)gc * f] : 0.0;
+            }
+            __syncthreads();
+            for (int e = tid; e < TT * TT; e += kDBlock) {
+                const int r = e / TT, c = e % TT;
+                const int gr = ro + r, gc = co + c;
+                if (gr < no && gr > gc) P[gc + (int64_t)gr * f] = S[c * (TT + 1) + r];
+            }
+            __syncthreads();
+        }
 }
 
 // Gathers of the larger fronts, one workgroup per (node, chunk of
@@ -1106,6 +1087,7 @@ int chol_setup(const HostSystem &hs, fem_chol &C)
             if (nd.f() <= kMidFront) {
                 mid[d].push_back(k);
                 C.lev[d].mid_rows = std::max<int32_t>(C.lev[d].mid_rows, (int32_t)nd.f());
+                C.lev[d].solve_rows = std::max<int32_t>(C.lev[d].solve_rows, (int32_t)(nd.f() + nd.no()));
             } else {
                 big[d].push_back(k);
                 if (nd.no() > 0 && nd.no() <= kMidFront) {
@@ -1267,6 +1249,15 @@ int chol_numeric(fem_chol &C, hipStream_t s)
             ++ib;
         }
     }
+    // the own blocks of the fronts up to kMidFront inverted in place
+    DCHK(hipFuncSetAttribute((const void *)k_mid_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(sizeof(double) * kMidFront * kPanel)));
+    for (const auto &L : C.lev)
+        if (L.nmid) {
+            const int lds = std::max(L.mid_rows * kPanel, (kMirrorTile / 2) * (kMirrorTile / 2 + 1));
+            hipLaunchKernelGGL(k_mid_inv, dim3(L.nmid), dim3(kDBlock), sizeof(double) * lds, s, C.d_nodes, L.mid,
+                               C.d_panel);
+        }
     // the larger fronts' L11^-1 mirrored into their upper triangles (the
     // grid walks the tile list in slices of at most 2^20 workgroups)
     for (int64_t m0 = 0; m0 < C.nmir; m0 += (int64_t)1 << 20) {
@@ -1304,7 +1295,7 @@ static void launch_prod(const fem_chol &C, const fem_chol::Level &L, int q, doub
 // kMidFront: as many as the LDS holds for its largest front.
 static int mid_chunk(const fem_chol::Level &L, int t)
 {
-    return std::max(1, std::min(t, kSolveLds / std::max<int>(L.mid_rows, 1)));
+    return std::max(1, std::min(t, kSolveLds / std::max<int>(L.solve_rows, 1)));
 }
 
 static void prod_step(const fem_chol &C, const fem_chol::Level &L, int q, double *z, int t, double *w, hipStream_t s)
@@ -1317,8 +1308,9 @@ static void prod_step(const fem_chol &C, const fem_chol::Level &L, int q, double
 
 // Forward and backward solve of t right-hand sides (device [n][t], public
 // order) on stream s; synchronises.  Per level, fronts up to kMidFront take
-// one workgroup each (gather, triangular solve in LDS panels, store); the
-// larger fronts are gathered, then go through the four product steps.
+// one workgroup per column chunk (gather, products with L11^-1 and L21,
+// store); the larger fronts are gathered, then go through the four
+// product steps.
 int chol_solve_impl(fem_chol &C, const double *B, double *X, int t, hipStream_t s)
 {
     const int64_t n = C.n;
@@ -1362,7 +1354,7 @@ int chol_solve_impl(fem_chol &C, const double *B, double *X, int t, hipStream_t 
         if (L.nmid) {
             const int cw = mid_chunk(L, t);
             hipLaunchKernelGGL(k_mid_bwd, dim3(L.nmid, (t + cw - 1) / cw), dim3(kDBlock), kSolveBytes, s, C.d_nodes, L.mid,
-                               C.d_index, C.d_panel, z, t, cw, w);
+                               C.d_index, C.d_panel, z, t, cw);
         }
         if (!L.big.empty()) {
             hipLaunchKernelGGL(k_big_bwd_gather, dim3((unsigned)L.nprod[4]), dim3(kDBlock), 0, s, C.d_nodes, L.prod[4],
