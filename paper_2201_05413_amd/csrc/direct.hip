@@ -26,8 +26,10 @@
 //              vectors passed up by extend-add in child order), backward from
 //              the root (x = L^-T y, reading the ancestors' x).
 //
-// Fronts up to kMidFront are factorised and solved by one workgroup each, in
-// panels of kPanel columns staged in LDS.  Larger fronts are factorised with
+// Fronts up to kMidFront are factorised by one workgroup each (left-looking
+// blocks of kFB columns, then the update block as one tiled product), their
+// own blocks inverted in place, and solved by one workgroup per column
+// chunk as matrix products.  Larger fronts are factorised with
 // rocSOLVER's POTRF (own blocks above kMidFront; smaller ones by the
 // workgroup kernel) and rocBLAS's TRSM / SYRK (dense FP64, matrix cores);
 // TRTRI then replaces their L11 by L11^-1, so that their solves are matrix
@@ -50,7 +52,12 @@ namespace femcg {
 
 constexpr int kLeaf = 64;         // nested-dissection leaves: at most this many DOFs
 constexpr int kMidFront = 1024;   // fronts up to this size: one workgroup each
-constexpr int kPanel = 8;         // columns per LDS panel of the workgroup factorisation
+constexpr int kPanel = 8;         // columns per panel of the workgroup inversion of L11
+constexpr int kFB = 16;           // columns per block column of the workgroup factorisation
+constexpr int kFK = 256;          // finished columns per LDS stage of a block column's rows
+constexpr int kRowsPT = 4;        // front rows per thread of the workgroup factorisation
+constexpr int kSyT = 64;          // tile edge of the workgroup update-block product
+constexpr int kSyK = 32;          // columns of L21 per LDS stage of that product
 constexpr int kDBlock = 256;      // threads per workgroup of the direct kernels
 constexpr int kSolveLds = 8192;   // doubles of LDS per solve workgroup (64 KB)
 constexpr int kWaveLanes = 64;    // lanes per wavefront
@@ -111,7 +118,8 @@ struct fem_chol {
         // columns of L11^-T (mirror), rows of L21, columns of L21, columns of L11^-1, rows of W (gathers)
         int32_t *prod[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
         int32_t nprod[5] = {0, 0, 0, 0, 0};
-        int32_t mid_rows = 0, tri_rows = 0;      // LDS rows of the factor launches (largest f, largest no)
+        int32_t mid_rows = 0;                    // largest f of the level's fronts up to kMidFront
+        int32_t mid_tiles = 0;                   // most update-block tiles (k_mid_update) of those fronts
         int32_t solve_rows = 0;                  // LDS rows of the mid-front solves (largest f + no)
         int64_t panel0 = 0, panel1 = 0;          // the level's range in the panel store
         int64_t udoubles = 0;                    // update blocks of the level's nodes
@@ -460,63 +468,152 @@ __global__ __launch_bounds__(kDBlock) void k_extend_add(const DNode *nodes, cons
     for (int a = b + threadIdx.x; a < nuc; a += kDBlock) F.at((int)rel[a], cb) += U[a + (int64_t)b * nuc];
 }
 
-// Partial Cholesky of one front (f <= kMidFront) per workgroup, right-looking
-// in panels of kPanel columns staged in LDS: factor the panel's columns,
-// write them back, then update every later column (panel and update block)
-// with the panel, each entry once per panel in a fixed order.  With
-// diag_only, only the own block F11 (no <= kMidFront) is factorised, in
-// place in the panel (ld f): the larger fronts' L21 and U then come from
-// TRSM and SYRK.  Dynamic LDS: (rows of the largest front of the launch) x
-// kPanel doubles.
+// Own columns of one front (f <= kMidFront) per workgroup, left-looking in
+// blocks of kFB columns: each thread holds up to kRowsPT rows r >= J of the
+// block column and subtracts sum_k L(r, k) L(J + q, k) over the finished
+// columns k < J (the block's rows L(J.., k) staged in LDS in chunks of kFK);
+// the block's diagonal part is then factorised in LDS and the rows below
+// (L21 included) solve against it.  The update block U = F22 - L21 L21^T
+// follows in k_mid_update.  With diag_only, only the own block F11
+// (no <= kMidFront) is factorised, in place in the panel (ld f): the larger
+// fronts' L21 and U then come from TRSM and SYRK.  Every sum runs over k in
+// one fixed order.
 __global__ __launch_bounds__(kDBlock) void k_mid_factor(const DNode *nodes, const int32_t *list, double *panel,
-                                                        double *ubuf, int32_t *fail, int diag_only)
+                                                        int32_t *fail, int diag_only)
 {
-    extern __shared__ double P[];  // P[(r - k0) * kPanel + j] = F(r, k0 + j)
+    __shared__ double S[kFK * kFB];
+    __shared__ double Dg[kFB][kFB + 1];
     __shared__ int s_bad;
+    static_assert(kRowsPT * kDBlock >= kMidFront, "every row of a front has a thread");
     const DNode D = nodes[list[blockIdx.x]];
-    const Front F = front_of(D, panel, ubuf);
-    const int ld = F.f, no = F.no, tid = threadIdx.x;
-    const int f = diag_only ? no : ld;  // rows and columns processed
+    const int ld = D.no + D.nu, no = D.no, tid = threadIdx.x;
+    const int f = diag_only ? no : ld;  // rows processed
+    double *A = panel + D.panel;
     if (tid == 0) s_bad = 0;
-    for (int k0 = 0; k0 < no; k0 += kPanel) {
-        const int kw = min(kPanel, no - k0), rows = f - k0;
-        for (int i = tid; i < rows * kw; i += kDBlock) {
-            const int r = i / kw, j = i - r * kw;
-            P[r * kPanel + j] = F.panel[(k0 + r) + (int64_t)(k0 + j) * ld];
+    for (int J = 0; J < no; J += kFB) {
+        const int jw = min(kFB, no - J);
+        double acc[kRowsPT][kFB];
+#pragma unroll
+        for (int i = 0; i < kRowsPT; ++i) {
+            const int r = J + tid + i * kDBlock;
+#pragma unroll
+            for (int q = 0; q < kFB; ++q) acc[i][q] = (r < f && q < jw) ? A[r + (int64_t)(J + q) * ld] : 0.0;
         }
-        __syncthreads();
-        for (int j = 0; j < kw; ++j) {
-            const double d = P[j * kPanel + j];
-            if (!(d > 0.0) && tid == 0) s_bad = 1;
-            const double sq = sqrt(d > 0.0 ? d : 1.0);
+        for (int kc = 0; kc < J; kc += kFK) {
+            const int kw = min(kFK, J - kc);
             __syncthreads();
-            for (int r = j + tid; r < rows; r += kDBlock) P[r * kPanel + j] = r == j ? sq : P[r * kPanel + j] / sq;
-            __syncthreads();
-            for (int j2 = j + 1; j2 < kw; ++j2) {
-                const double pj = P[j2 * kPanel + j];
-                for (int r = j2 + tid; r < rows; r += kDBlock) P[r * kPanel + j2] -= P[r * kPanel + j] * pj;
+            for (int e = tid; e < kw * kFB; e += kDBlock) {
+                const int kk = e / kFB, q = e % kFB;
+                S[e] = q < jw ? A[(J + q) + (int64_t)(kc + kk) * ld] : 0.0;
             }
             __syncthreads();
-        }
-        for (int i = tid; i < rows * kw; i += kDBlock) {
-            const int r = i / kw, j = i - r * kw;
-            F.panel[(k0 + r) + (int64_t)(k0 + j) * ld] = P[r * kPanel + j];
-        }
-        for (int c = k0 + kw; c < f; ++c) {
-            double pc[kPanel];
+#pragma unroll 4
+            for (int kk = 0; kk < kw; ++kk) {
+                const double *sk = S + kk * kFB;
+                double l[kRowsPT];
 #pragma unroll
-            for (int j = 0; j < kPanel; ++j) pc[j] = j < kw ? P[(c - k0) * kPanel + j] : 0.0;
-            for (int r = c + tid; r < f; r += kDBlock) {
-                double acc = 0.0;
+                for (int i = 0; i < kRowsPT; ++i) {
+                    const int r = J + tid + i * kDBlock;
+                    l[i] = r < f ? A[r + (int64_t)(kc + kk) * ld] : 0.0;
+                }
 #pragma unroll
-                for (int j = 0; j < kPanel; ++j)
-                    if (j < kw) acc += P[(r - k0) * kPanel + j] * pc[j];
-                F.at(r, c) -= acc;
+                for (int q = 0; q < kFB; ++q) {
+                    const double sq = sk[q];
+#pragma unroll
+                    for (int i = 0; i < kRowsPT; ++i) acc[i][q] -= l[i] * sq;
+                }
+            }
+        }
+        // the block's diagonal part: rows J..J+jw-1 are threads 0..jw-1, first row slot
+        if (tid < jw)
+#pragma unroll
+            for (int q = 0; q < kFB; ++q) Dg[tid][q] = acc[0][q];
+        __syncthreads();
+        for (int j = 0; j < jw; ++j) {
+            if (tid == 0) {
+                const double d = Dg[j][j];
+                if (!(d > 0.0)) s_bad = 1;
+                Dg[j][j] = sqrt(d > 0.0 ? d : 1.0);
+            }
+            __syncthreads();
+            if (tid > j && tid < jw) Dg[tid][j] /= Dg[j][j];
+            __syncthreads();
+            if (tid > j && tid < jw)
+                for (int q = j + 1; q <= tid; ++q) Dg[tid][q] -= Dg[tid][j] * Dg[q][j];
+            __syncthreads();
+        }
+        if (tid < jw)
+            for (int q = 0; q <= tid; ++q) A[(J + tid) + (int64_t)(J + q) * ld] = Dg[tid][q];
+        // the rows below: x L_JJ^T = acc, by forward substitution over q
+#pragma unroll
+        for (int i = 0; i < kRowsPT; ++i) {
+            const int r = J + tid + i * kDBlock;
+            if (r < J + jw || r >= f) continue;
+            double x[kFB];
+#pragma unroll
+            for (int q = 0; q < kFB; ++q) {
+                double v = acc[i][q];
+#pragma unroll
+                for (int p = 0; p < q; ++p) v -= x[p] * Dg[q][p];
+                x[q] = q < jw ? v / Dg[q][q] : 0.0;
+                if (q < jw) A[r + (int64_t)(J + q) * ld] = x[q];
             }
         }
         __syncthreads();
     }
     if (tid == 0 && s_bad) fail[0] = 1;
+}
+
+// U = F22 - L21 L21^T of the fronts up to kMidFront, after their own
+// columns: one workgroup per (front, kSyT x kSyT tile of U's lower triangle,
+// blockIdx.y in row order), L21 staged in LDS in chunks of kSyK columns;
+// each thread sums a 4 x 4 block of the tile over k in order.
+__global__ __launch_bounds__(kDBlock) void k_mid_update(const DNode *nodes, const int32_t *list, const double *panel,
+                                                        double *ubuf)
+{
+    __shared__ double Ar[kSyK * kSyT], Bc[kSyK * kSyT];  // [kk][m] = L21(tile row m, k0 + kk)
+    const DNode D = nodes[list[blockIdx.x]];
+    const int no = D.no, nu = D.nu, ld = no + nu, tid = threadIdx.x;
+    int ti = 0, tj = (int)blockIdx.y;
+    while (tj > ti) tj -= ++ti;  // row ti holds tiles 0..ti
+    if (no == 0 || ti * kSyT >= nu) return;  // the same for the whole workgroup
+    const double *A = panel + D.panel;
+    double *U = ubuf + D.u;
+    const int tx = tid % 16, ty = tid / 16;
+    const int R0 = ti * kSyT, C0 = tj * kSyT;
+    double c[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c[i][j] = 0.0;
+    for (int k0 = 0; k0 < no; k0 += kSyK) {
+        const int kw = min(kSyK, no - k0);
+        __syncthreads();
+        for (int e = tid; e < kSyK * kSyT; e += kDBlock) {
+            const int kk = e / kSyT, m = e % kSyT;
+            Ar[e] = (kk < kw && R0 + m < nu) ? A[(no + R0 + m) + (int64_t)(k0 + kk) * ld] : 0.0;
+            Bc[e] = (kk < kw && C0 + m < nu) ? A[(no + C0 + m) + (int64_t)(k0 + kk) * ld] : 0.0;
+        }
+        __syncthreads();
+        for (int kk = 0; kk < kw; ++kk) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) av[i] = Ar[kk * kSyT + tx + 16 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bv[j] = Bc[kk * kSyT + ty + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) c[i][j] += av[i] * bv[j];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int ra = R0 + tx + 16 * i, cb = C0 + ty + 16 * j;
+            if (ra < nu && cb <= ra) U[ra + (int64_t)cb * nu] -= c[i][j];
+        }
 }
 
 // ---- solves: z holds the right-hand sides in elimination order, [n][t] ----
@@ -1087,13 +1184,14 @@ int chol_setup(const HostSystem &hs, fem_chol &C)
             if (nd.f() <= kMidFront) {
                 mid[d].push_back(k);
                 C.lev[d].mid_rows = std::max<int32_t>(C.lev[d].mid_rows, (int32_t)nd.f());
+                if (nd.no() > 0) {
+                    const int32_t nt = (int32_t)((nd.nu() + kSyT - 1) / kSyT);
+                    C.lev[d].mid_tiles = std::max<int32_t>(C.lev[d].mid_tiles, nt * (nt + 1) / 2);
+                }
                 C.lev[d].solve_rows = std::max<int32_t>(C.lev[d].solve_rows, (int32_t)(nd.f() + nd.no()));
             } else {
                 big[d].push_back(k);
-                if (nd.no() > 0 && nd.no() <= kMidFront) {
-                    bigtri[d].push_back(k);
-                    C.lev[d].tri_rows = std::max<int32_t>(C.lev[d].tri_rows, (int32_t)nd.no());
-                }
+                if (nd.no() > 0 && nd.no() <= kMidFront) bigtri[d].push_back(k);
                 auto &pr = prod[d];
                 for (int32_t j = 0; j < (int32_t)nd.no(); j += kBigCols) pr[0].insert(pr[0].end(), {k, j});
                 const int32_t nt = (int32_t)((nd.no() + kMirrorTile - 1) / kMirrorTile);
@@ -1209,8 +1307,6 @@ int chol_numeric(fem_chol &C, hipStream_t s)
     DCHK(hipMemsetAsync(C.d_fail, 0, sizeof(int32_t), s));
     BCHK(rocblas_set_stream(C.blas, s));
     BCHK(rocblas_set_pointer_mode(C.blas, rocblas_pointer_mode_host));
-    DCHK(hipFuncSetAttribute((const void *)k_mid_factor, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)(sizeof(double) * kMidFront * kPanel)));
     const int nlev = (int)C.lev.size();
     int64_t ib = 0;
     for (int d = nlev - 1; d >= 0; --d) {
@@ -1224,12 +1320,15 @@ int chol_numeric(fem_chol &C, hipStream_t s)
             if (L.nea[sl])
                 hipLaunchKernelGGL(k_extend_add, dim3((unsigned)L.nea[sl]), dim3(kDBlock), 0, s, C.d_nodes, L.ea_cols[sl],
                                    sl, C.d_index, C.d_panel, u, uc);
-        if (L.nmid)
-            hipLaunchKernelGGL(k_mid_factor, dim3(L.nmid), dim3(kDBlock), sizeof(double) * L.mid_rows * kPanel, s,
-                               C.d_nodes, L.mid, C.d_panel, u, C.d_fail, 0);
+        if (L.nmid) {
+            hipLaunchKernelGGL(k_mid_factor, dim3(L.nmid), dim3(kDBlock), 0, s, C.d_nodes, L.mid, C.d_panel, C.d_fail, 0);
+            if (L.mid_tiles)
+                hipLaunchKernelGGL(k_mid_update, dim3(L.nmid, L.mid_tiles), dim3(kDBlock), 0, s, C.d_nodes, L.mid,
+                                   C.d_panel, u);
+        }
         if (L.nbigtri)
-            hipLaunchKernelGGL(k_mid_factor, dim3(L.nbigtri), dim3(kDBlock), sizeof(double) * L.tri_rows * kPanel, s,
-                               C.d_nodes, L.dbigtri, C.d_panel, u, C.d_fail, 1);
+            hipLaunchKernelGGL(k_mid_factor, dim3(L.nbigtri), dim3(kDBlock), 0, s, C.d_nodes, L.dbigtri, C.d_panel,
+                               C.d_fail, 1);
         DCHK(hipGetLastError());
         for (int32_t k : L.big) {
             const DNode &D = C.hnodes[k];
