@@ -56,8 +56,10 @@ constexpr int kPanel = 8;         // columns per panel of the workgroup inversio
 constexpr int kFB = 16;           // columns per block column of the workgroup factorisation
 constexpr int kFK = 256;          // finished columns per LDS stage of a block column's rows
 constexpr int kRowsPT = 4;        // front rows per thread of the workgroup factorisation
-constexpr int kSyT = 64;          // tile edge of the workgroup update-block product
-constexpr int kSyK = 32;          // columns of L21 per LDS stage of that product
+constexpr int kSyT = 64;          // tile edge of the update-block product of the small fronts and of k_mid_l21
+constexpr int kSyK = 32;          // columns of L21 per LDS stage of those
+constexpr int kTriT = 128;        // tile edge of the update-block product of the larger fronts
+constexpr int kTriK = 16;         // columns of L21 per LDS stage of that one
 constexpr int kDBlock = 256;      // threads per workgroup of the direct kernels
 constexpr int kSolveLds = 8192;   // doubles of LDS per solve workgroup (64 KB)
 constexpr int kWaveLanes = 64;    // lanes per wavefront
@@ -68,6 +70,15 @@ constexpr int kMirrorTile = 64;   // tile edge of the L11^-1 mirror
 
 static_assert(kDBlock / kWaveLanes == 4, "the row products add four wave partials");
 static_assert(kBigRows == kWaveLanes, "one row per lane");
+
+// Larger fronts whose own block has at most kMidFront columns are factorised
+// by the workgroup kernels rather than by per-front library calls (their
+// update block's tiles must fit the grid's second dimension).
+inline bool own_path(int64_t no, int64_t nu)
+{
+    const int64_t rt = (nu + kSyT - 1) / kSyT;
+    return no > 0 && no <= kMidFront && rt * (rt + 1) / 2 <= 65535;
+}
 
 struct ChNode {
     int64_t b = 0, e = 0;          // own positions [b, e)
@@ -112,8 +123,10 @@ struct fem_chol {
         int32_t nall = 0, nmid = 0;
         std::vector<int32_t> big;                // node ids of larger fronts (host loop)
         int32_t *dbig = nullptr;                 // the same on the device
-        int32_t *dbigtri = nullptr;              // larger fronts whose own block has <= kMidFront columns
+        // larger fronts factorised by the workgroup kernels (own_path)
+        int32_t *dbigtri = nullptr;
         int32_t nbigtri = 0;
+        int32_t tri_rowtiles = 0, tri_tiles = 0;  // most F21 row tiles (k_mid_l21) and U tiles (k_mid_update)
         // solve items of the larger fronts, (node, first row or column) pairs:
         // columns of L11^-T (mirror), rows of L21, columns of L21, columns of L11^-1, rows of W (gathers)
         int32_t *prod[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -564,56 +577,123 @@ __global__ __launch_bounds__(kDBlock) void k_mid_factor(const DNode *nodes, cons
     if (tid == 0 && s_bad) fail[0] = 1;
 }
 
-// U = F22 - L21 L21^T of the fronts up to kMidFront, after their own
-// columns: one workgroup per (front, kSyT x kSyT tile of U's lower triangle,
-// blockIdx.y in row order), L21 staged in LDS in chunks of kSyK columns;
-// each thread sums a 4 x 4 block of the tile over k in order.
+// U = F22 - L21 L21^T after the own columns: one workgroup per (front,
+// TT x TT tile of U's lower triangle, blockIdx.y in row order).  L21 goes
+// through LDS in chunks of KS columns; the next chunk is loaded into
+// registers while the current one is summed.  Each thread sums a
+// (TT / 16) x (TT / 16) block of the tile over k in order.
+template <int TT, int KS>
 __global__ __launch_bounds__(kDBlock) void k_mid_update(const DNode *nodes, const int32_t *list, const double *panel,
                                                         double *ubuf)
 {
-    __shared__ double Ar[kSyK * kSyT], Bc[kSyK * kSyT];  // [kk][m] = L21(tile row m, k0 + kk)
+    constexpr int RT = TT / 16;                  // rows and columns per thread
+    constexpr int NL = 2 * KS * TT / kDBlock;    // staged values per thread and chunk
+    static_assert(NL * kDBlock == 2 * KS * TT && TT % 16 == 0, "whole chunks per thread");
+    __shared__ double St[2 * KS * TT];           // [0]: L21 rows of the tile rows, [1]: of its columns; [kk][m]
     const DNode D = nodes[list[blockIdx.x]];
     const int no = D.no, nu = D.nu, ld = no + nu, tid = threadIdx.x;
     int ti = 0, tj = (int)blockIdx.y;
     while (tj > ti) tj -= ++ti;  // row ti holds tiles 0..ti
-    if (no == 0 || ti * kSyT >= nu) return;  // the same for the whole workgroup
+    if (no == 0 || ti * TT >= nu) return;  // the same for the whole workgroup
     const double *A = panel + D.panel;
     double *U = ubuf + D.u;
     const int tx = tid % 16, ty = tid / 16;
-    const int R0 = ti * kSyT, C0 = tj * kSyT;
-    double c[4][4];
+    const int R0 = ti * TT, C0 = tj * TT;
+    double c[RT][RT], pf[NL];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < RT; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) c[i][j] = 0.0;
-    for (int k0 = 0; k0 < no; k0 += kSyK) {
-        const int kw = min(kSyK, no - k0);
-        __syncthreads();
-        for (int e = tid; e < kSyK * kSyT; e += kDBlock) {
-            const int kk = e / kSyT, m = e % kSyT;
-            Ar[e] = (kk < kw && R0 + m < nu) ? A[(no + R0 + m) + (int64_t)(k0 + kk) * ld] : 0.0;
-            Bc[e] = (kk < kw && C0 + m < nu) ? A[(no + C0 + m) + (int64_t)(k0 + kk) * ld] : 0.0;
+        for (int j = 0; j < RT; ++j) c[i][j] = 0.0;
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int v = 0; v < NL; ++v) {
+            const int e = tid + v * kDBlock, h = e / (KS * TT), e2 = e % (KS * TT);
+            const int k = k0 + e2 / TT, row = (h ? C0 : R0) + e2 % TT;
+            pf[v] = (k < no && row < nu) ? A[(no + row) + (int64_t)k * ld] : 0.0;
         }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < no; k0 += KS) {
         __syncthreads();
+#pragma unroll
+        for (int v = 0; v < NL; ++v) St[tid + v * kDBlock] = pf[v];
+        __syncthreads();
+        if (k0 + KS < no) fetch(k0 + KS);
+        const int kw = min(KS, no - k0);
         for (int kk = 0; kk < kw; ++kk) {
-            double av[4], bv[4];
+            double av[RT], bv[RT];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) av[i] = Ar[kk * kSyT + tx + 16 * i];
+            for (int i = 0; i < RT; ++i) av[i] = St[kk * TT + tx + 16 * i];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) bv[j] = Bc[kk * kSyT + ty + 16 * j];
+            for (int j = 0; j < RT; ++j) bv[j] = St[KS * TT + kk * TT + ty + 16 * j];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < RT; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) c[i][j] += av[i] * bv[j];
+                for (int j = 0; j < RT; ++j) c[i][j] += av[i] * bv[j];
         }
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < RT; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < RT; ++j) {
             const int ra = R0 + tx + 16 * i, cb = C0 + ty + 16 * j;
             if (ra < nu && cb <= ra) U[ra + (int64_t)cb * nu] -= c[i][j];
         }
+}
+
+// L21 = F21 L11^-T of the larger fronts whose own block has at most
+// kMidFront columns, once k_mid_inv has left L11^-1 in the own block: one
+// workgroup per (front, kSyT rows of F21, blockIdx.y), in place.  Column
+// tiles of kSyT go from the last to the first: the entries of a tile's
+// columns c are sum_{k <= c} F21(r, k) L11^-1(c, k), and only columns left
+// of the tile are read after it is written.  L11^-1(c, k) is read from the
+// lower triangle (k <= c) only.
+__global__ __launch_bounds__(kDBlock) void k_mid_l21(const DNode *nodes, const int32_t *list, double *panel)
+{
+    __shared__ double Ar[kSyK * kSyT], Bc[kSyK * kSyT];  // F21(tile row m, k), L11^-1(tile column m, k)
+    const DNode D = nodes[list[blockIdx.x]];
+    const int no = D.no, nu = D.nu, ld = no + nu, tid = threadIdx.x;
+    const int R0 = (int)blockIdx.y * kSyT;
+    if (no == 0 || R0 >= nu) return;  // the same for the whole workgroup
+    double *A = panel + D.panel;
+    const int tx = tid % 16, ty = tid / 16;
+    for (int C0 = ((no - 1) / kSyT) * kSyT; C0 >= 0; C0 -= kSyT) {
+        const int kend = min(no, C0 + kSyT);
+        double c[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) c[i][j] = 0.0;
+        for (int k0 = 0; k0 < kend; k0 += kSyK) {
+            const int kw = min(kSyK, kend - k0);
+            __syncthreads();
+            for (int e = tid; e < kSyK * kSyT; e += kDBlock) {
+                const int kk = e / kSyT, m = e % kSyT, k = k0 + kk;
+                Ar[e] = (kk < kw && R0 + m < nu) ? A[(no + R0 + m) + (int64_t)k * ld] : 0.0;
+                Bc[e] = (kk < kw && C0 + m < no && k <= C0 + m) ? A[(C0 + m) + (int64_t)k * ld] : 0.0;
+            }
+            __syncthreads();
+            for (int kk = 0; kk < kw; ++kk) {
+                double av[4], bv[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) av[i] = Ar[kk * kSyT + tx + 16 * i];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) bv[j] = Bc[kk * kSyT + ty + 16 * j];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) c[i][j] += av[i] * bv[j];
+            }
+        }
+        __syncthreads();  // every read of the tile's columns precedes its stores
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int ra = R0 + tx + 16 * i, cb = C0 + ty + 16 * j;
+                if (ra < nu && cb < no) A[(no + ra) + (int64_t)cb * ld] = c[i][j];
+            }
+    }
 }
 
 // ---- solves: z holds the right-hand sides in elimination order, [n][t] ----
@@ -1191,13 +1271,21 @@ int chol_setup(const HostSystem &hs, fem_chol &C)
                 C.lev[d].solve_rows = std::max<int32_t>(C.lev[d].solve_rows, (int32_t)(nd.f() + nd.no()));
             } else {
                 big[d].push_back(k);
-                if (nd.no() > 0 && nd.no() <= kMidFront) bigtri[d].push_back(k);
+                if (own_path(nd.no(), nd.nu())) {
+                    bigtri[d].push_back(k);
+                    const int32_t rt = (int32_t)((nd.nu() + kSyT - 1) / kSyT);
+                    const int32_t ut = (int32_t)((nd.nu() + kTriT - 1) / kTriT);
+                    C.lev[d].tri_rowtiles = std::max(C.lev[d].tri_rowtiles, rt);
+                    C.lev[d].tri_tiles = std::max(C.lev[d].tri_tiles, ut * (ut + 1) / 2);
+                } else {
+                    const int32_t nt = (int32_t)((nd.no() + kMirrorTile - 1) / kMirrorTile);
+                    if (nt >= (1 << 15))
+                        return fail(FEMCG_EINVAL, "chol: separator of %lld DOFs is too large", (long long)nd.no());
+                    for (int32_t ti = 0; ti < nt; ++ti)
+                        for (int32_t tj = 0; tj <= ti; ++tj) mir.insert(mir.end(), {k, (ti << 16) | tj});
+                }
                 auto &pr = prod[d];
                 for (int32_t j = 0; j < (int32_t)nd.no(); j += kBigCols) pr[0].insert(pr[0].end(), {k, j});
-                const int32_t nt = (int32_t)((nd.no() + kMirrorTile - 1) / kMirrorTile);
-                if (nt >= (1 << 15)) return fail(FEMCG_EINVAL, "chol: separator of %lld DOFs is too large", (long long)nd.no());
-                for (int32_t ti = 0; ti < nt; ++ti)
-                    for (int32_t tj = 0; tj <= ti; ++tj) mir.insert(mir.end(), {k, (ti << 16) | tj});
                 if (nd.no() > 0)
                     for (int32_t r = 0; r < (int32_t)nd.nu(); r += kBigRows) pr[1].insert(pr[1].end(), {k, r});
                 if (nd.nu() > 0)
@@ -1307,6 +1395,8 @@ int chol_numeric(fem_chol &C, hipStream_t s)
     DCHK(hipMemsetAsync(C.d_fail, 0, sizeof(int32_t), s));
     BCHK(rocblas_set_stream(C.blas, s));
     BCHK(rocblas_set_pointer_mode(C.blas, rocblas_pointer_mode_host));
+    DCHK(hipFuncSetAttribute((const void *)k_mid_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(sizeof(double) * kMidFront * kPanel)));
     const int nlev = (int)C.lev.size();
     int64_t ib = 0;
     for (int d = nlev - 1; d >= 0; --d) {
@@ -1323,17 +1413,31 @@ int chol_numeric(fem_chol &C, hipStream_t s)
         if (L.nmid) {
             hipLaunchKernelGGL(k_mid_factor, dim3(L.nmid), dim3(kDBlock), 0, s, C.d_nodes, L.mid, C.d_panel, C.d_fail, 0);
             if (L.mid_tiles)
-                hipLaunchKernelGGL(k_mid_update, dim3(L.nmid, L.mid_tiles), dim3(kDBlock), 0, s, C.d_nodes, L.mid,
-                                   C.d_panel, u);
+                hipLaunchKernelGGL((k_mid_update<kSyT, kSyK>), dim3(L.nmid, L.mid_tiles), dim3(kDBlock), 0, s,
+                                   C.d_nodes, L.mid, C.d_panel, u);
         }
-        if (L.nbigtri)
+        if (L.nbigtri) {
+            // own block, L11^-1 (and its transpose), L21 = F21 L11^-T, U -= L21 L21^T
             hipLaunchKernelGGL(k_mid_factor, dim3(L.nbigtri), dim3(kDBlock), 0, s, C.d_nodes, L.dbigtri, C.d_panel,
                                C.d_fail, 1);
+            hipLaunchKernelGGL(k_mid_inv, dim3(L.nbigtri), dim3(kDBlock), sizeof(double) * kMidFront * kPanel, s,
+                               C.d_nodes, L.dbigtri, C.d_panel);
+            if (L.tri_rowtiles)
+                hipLaunchKernelGGL(k_mid_l21, dim3(L.nbigtri, L.tri_rowtiles), dim3(kDBlock), 0, s, C.d_nodes, L.dbigtri,
+                                   C.d_panel);
+            if (L.tri_tiles)
+                hipLaunchKernelGGL((k_mid_update<kTriT, kTriK>), dim3(L.nbigtri, L.tri_tiles), dim3(kDBlock), 0, s,
+                                   C.d_nodes, L.dbigtri, C.d_panel, u);
+        }
         DCHK(hipGetLastError());
         for (int32_t k : L.big) {
             const DNode &D = C.hnodes[k];
             const int f = D.no + D.nu;
             double *P = C.d_panel + D.panel;
+            if (own_path(D.no, D.nu)) {
+                ++ib;
+                continue;
+            }
             if (D.no > kMidFront) BCHK(rocsolver_dpotrf(C.blas, rocblas_fill_lower, D.no, P, f, info + ib));
             if (D.no > 0 && D.nu > 0) {
                 const double one = 1.0, mone = -1.0;
@@ -1349,8 +1453,6 @@ int chol_numeric(fem_chol &C, hipStream_t s)
         }
     }
     // the own blocks of the fronts up to kMidFront inverted in place
-    DCHK(hipFuncSetAttribute((const void *)k_mid_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)(sizeof(double) * kMidFront * kPanel)));
     for (const auto &L : C.lev)
         if (L.nmid) {
             const int lds = std::max(L.mid_rows * kPanel, (kMirrorTile / 2) * (kMirrorTile / 2 + 1));
