@@ -53,6 +53,7 @@ namespace femcg {
 constexpr int kLeaf = 64;         // nested-dissection leaves: at most this many DOFs
 constexpr int kMidFront = 1024;   // fronts up to this size: one workgroup each
 constexpr int kPanel = 8;         // columns per panel of the workgroup inversion of L11
+constexpr int kInvLoads = 8;      // loads in flight per thread in that inversion's row products
 constexpr int kFB = 16;           // columns per block column of the workgroup factorisation
 constexpr int kFK = 256;          // finished columns per LDS stage of a block column's rows
 constexpr int kRowsPT = 4;        // front rows per thread of the workgroup factorisation
@@ -647,16 +648,28 @@ __global__ __launch_bounds__(kDBlock) void k_mid_update(const DNode *nodes, cons
 // tiles of kSyT go from the last to the first: the entries of a tile's
 // columns c are sum_{k <= c} F21(r, k) L11^-1(c, k), and only columns left
 // of the tile are read after it is written.  L11^-1(c, k) is read from the
-// lower triangle (k <= c) only.
+// lower triangle (k <= c) only.  Chunks of kSyK go through LDS, the next one
+// loaded into registers while the current one is summed.
 __global__ __launch_bounds__(kDBlock) void k_mid_l21(const DNode *nodes, const int32_t *list, double *panel)
 {
-    __shared__ double Ar[kSyK * kSyT], Bc[kSyK * kSyT];  // F21(tile row m, k), L11^-1(tile column m, k)
+    constexpr int NL = 2 * kSyK * kSyT / kDBlock;  // staged values per thread and chunk
+    __shared__ double St[2 * kSyK * kSyT];          // [0]: F21(tile row m, k), [1]: L11^-1(tile column m, k); [kk][m]
     const DNode D = nodes[list[blockIdx.x]];
     const int no = D.no, nu = D.nu, ld = no + nu, tid = threadIdx.x;
     const int R0 = (int)blockIdx.y * kSyT;
     if (no == 0 || R0 >= nu) return;  // the same for the whole workgroup
     double *A = panel + D.panel;
     const int tx = tid % 16, ty = tid / 16;
+    double pf[NL];
+    auto fetch = [&](int C0, int k0, int kend) {
+#pragma unroll
+        for (int v = 0; v < NL; ++v) {
+            const int e = tid + v * kDBlock, h = e / (kSyK * kSyT), e2 = e % (kSyK * kSyT);
+            const int k = k0 + e2 / kSyT, m = e2 % kSyT;
+            if (h == 0) pf[v] = (k < kend && R0 + m < nu) ? A[(no + R0 + m) + (int64_t)k * ld] : 0.0;
+            else pf[v] = (k < kend && C0 + m < no && k <= C0 + m) ? A[(C0 + m) + (int64_t)k * ld] : 0.0;
+        }
+    };
     for (int C0 = ((no - 1) / kSyT) * kSyT; C0 >= 0; C0 -= kSyT) {
         const int kend = min(no, C0 + kSyT);
         double c[4][4];
@@ -664,21 +677,20 @@ __global__ __launch_bounds__(kDBlock) void k_mid_l21(const DNode *nodes, const i
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j) c[i][j] = 0.0;
+        fetch(C0, 0, kend);
         for (int k0 = 0; k0 < kend; k0 += kSyK) {
+            __syncthreads();
+#pragma unroll
+            for (int v = 0; v < NL; ++v) St[tid + v * kDBlock] = pf[v];
+            __syncthreads();
+            if (k0 + kSyK < kend) fetch(C0, k0 + kSyK, kend);
             const int kw = min(kSyK, kend - k0);
-            __syncthreads();
-            for (int e = tid; e < kSyK * kSyT; e += kDBlock) {
-                const int kk = e / kSyT, m = e % kSyT, k = k0 + kk;
-                Ar[e] = (kk < kw && R0 + m < nu) ? A[(no + R0 + m) + (int64_t)k * ld] : 0.0;
-                Bc[e] = (kk < kw && C0 + m < no && k <= C0 + m) ? A[(C0 + m) + (int64_t)k * ld] : 0.0;
-            }
-            __syncthreads();
             for (int kk = 0; kk < kw; ++kk) {
                 double av[4], bv[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) av[i] = Ar[kk * kSyT + tx + 16 * i];
+                for (int i = 0; i < 4; ++i) av[i] = St[kk * kSyT + tx + 16 * i];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) bv[j] = Bc[kk * kSyT + ty + 16 * j];
+                for (int j = 0; j < 4; ++j) bv[j] = St[kSyK * kSyT + kk * kSyT + ty + 16 * j];
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -872,7 +884,18 @@ __global__ __launch_bounds__(kDBlock) void k_mid_inv(const DNode *nodes, const i
             double acc[kPanel];
 #pragma unroll
             for (int c = 0; c < kPanel; ++c) acc[c] = 0.0;
-            for (int j = r0; j <= gi; ++j) {
+            // X22's row in groups of kInvLoads loads, summed in order of j
+            int j = r0;
+            for (; j + kInvLoads <= gi + 1; j += kInvLoads) {
+                double x[kInvLoads];
+#pragma unroll
+                for (int u = 0; u < kInvLoads; ++u) x[u] = P[gi + (int64_t)(j + u) * f];
+#pragma unroll
+                for (int u = 0; u < kInvLoads; ++u)
+#pragma unroll
+                    for (int c = 0; c < kPanel; ++c) acc[c] += x[u] * S[(j + u - r0) * kPanel + c];
+            }
+            for (; j <= gi; ++j) {
                 const double x = P[gi + (int64_t)j * f];
 #pragma unroll
                 for (int c = 0; c < kPanel; ++c) acc[c] += x * S[(j - r0) * kPanel + c];
