@@ -1024,12 +1024,14 @@ __global__ __launch_bounds__(kDBlock) void k_big_rows(const DNode *nodes, const 
     double acc[TC];
 #pragma unroll
     for (int c = 0; c < TC; ++c) acc[c] = 0.0;
-#pragma unroll 4
+    // branch-free body (columns past tcn repeat the last one and are not
+    // stored), so that the unrolled loads are all in flight together
+#pragma unroll 16
     for (int j = js; j < je; ++j) {
         const double a = P[prow + (int64_t)j * f];
+        const double *zj = z + (D.b + j) * t + c0;
 #pragma unroll
-        for (int c = 0; c < TC; ++c)
-            if (c < tcn) acc[c] += a * z[(D.b + j) * t + c0 + c];
+        for (int c = 0; c < TC; ++c) acc[c] += a * zj[min(c, tcn - 1)];
     }
 #pragma unroll
     for (int c = 0; c < TC; ++c) part[wave][c][lane] = acc[c];
@@ -1073,15 +1075,19 @@ __global__ __launch_bounds__(kDBlock) void k_big_cols(const DNode *nodes, const 
     for (int q = 0; q < kBigCols; ++q)
 #pragma unroll
         for (int c = 0; c < TC; ++c) acc[q][c] = 0.0;
+    // branch-free body (columns past ncol and tcn repeat the last ones and
+    // are not stored), so that the unrolled loads are all in flight together
+#pragma unroll 4
     for (int r = ws + lane; r < we; r += kWaveLanes) {
         double wv[TC];
 #pragma unroll
-        for (int c = 0; c < TC; ++c) wv[c] = c < tcn ? W[r + (int64_t)(c0 + c) * f] : 0.0;
+        for (int c = 0; c < TC; ++c) wv[c] = W[r + (int64_t)(c0 + min(c, tcn - 1)) * f];
 #pragma unroll
         for (int q = 0; q < kBigCols; ++q) {
-            if (q >= ncol) break;
-            double a = P[r + (int64_t)q * f];
-            if ((form == kLow && r < j0 + q) || (form == kUp && r > j0 + q)) a = 0.0;
+            // a 0/1 factor rather than a select, which the compiler turns
+            // into a branch around the load (the factor's entries are finite)
+            const bool skip = q >= ncol || (form == kLow && r < j0 + q) || (form == kUp && r > j0 + q);
+            const double a = P[r + (int64_t)min(q, ncol - 1) * f] * (skip ? 0.0 : 1.0);
 #pragma unroll
             for (int c = 0; c < TC; ++c) acc[q][c] += a * wv[c];
         }
