@@ -63,6 +63,7 @@ constexpr int kTriT = 128;        // tile edge of the update-block product of th
 constexpr int kTriK = 16;         // columns of L21 per LDS stage of that one
 constexpr int kDBlock = 256;      // threads per workgroup of the direct kernels
 constexpr int kSolveLds = 8192;   // doubles of LDS per solve workgroup (64 KB)
+constexpr int kSolveLoads = 8;    // loads in flight per thread in the small fronts' solve products
 constexpr int kWaveLanes = 64;    // lanes per wavefront
 constexpr int kBigRows = 64;      // rows per workgroup of the larger fronts' row products (one per lane)
 constexpr int kBigCols = 4;       // columns per workgroup of their column products
@@ -750,6 +751,24 @@ __device__ void fwd_gather(const DNode &D, const DNode *nodes, const int64_t *in
     __syncthreads();
 }
 
+// sum over k in [k0, k1) of P[k * ps] * S[k * ss], in order of k, with
+// kSolveLoads loads of P in flight (the trip counts vary, so the compiler
+// does not unroll these loops by itself)
+__device__ __forceinline__ double strided_dot(const double *P, int64_t ps, const double *S, int ss, int k0, int k1)
+{
+    double acc = 0.0;
+    int k = k0;
+    for (; k + kSolveLoads <= k1; k += kSolveLoads) {
+        double x[kSolveLoads];
+#pragma unroll
+        for (int u = 0; u < kSolveLoads; ++u) x[u] = P[(int64_t)(k + u) * ps];
+#pragma unroll
+        for (int u = 0; u < kSolveLoads; ++u) acc += x[u] * S[(k + u) * ss];
+    }
+    for (; k < k1; ++k) acc += P[(int64_t)k * ps] * S[k * ss];
+    return acc;
+}
+
 // Solves of a front up to kMidFront, whose own block holds L11^-1 (lower
 // triangle, diagonal included) and its transpose (strictly upper
 // triangle), so that both triangular solves are products.  One workgroup
@@ -780,16 +799,12 @@ __global__ __launch_bounds__(kDBlock) void k_mid_fwd(const DNode *nodes, const i
     __syncthreads();
     for (int64_t e = tid; e < (int64_t)no * tc; e += kDBlock) {
         const int c = (int)(e / no), i = (int)(e % no);
-        double acc = 0.0;
-        for (int j = 0; j <= i; ++j) acc += P[i + (int64_t)j * f] * S[j * tc + c];
-        T[i * tc + c] = acc;
+        T[i * tc + c] = strided_dot(P + i, f, S + c, tc, 0, i + 1);
     }
     __syncthreads();
     for (int64_t e = tid; e < (int64_t)nu * tc; e += kDBlock) {
         const int c = (int)(e / nu), r = no + (int)(e % nu);
-        double acc = 0.0;
-        for (int j = 0; j < no; ++j) acc += P[r + (int64_t)j * f] * T[j * tc + c];
-        W[r + (int64_t)(c0 + c) * f] = S[r * tc + c] - acc;
+        W[r + (int64_t)(c0 + c) * f] = S[r * tc + c] - strided_dot(P + r, f, T + c, tc, 0, no);
     }
     for (int64_t e = tid; e < (int64_t)no * tc; e += kDBlock) {
         const int c = (int)(e / no), i = (int)(e % no);
@@ -834,9 +849,7 @@ __global__ __launch_bounds__(kDBlock) void k_mid_bwd(const DNode *nodes, const i
     __syncthreads();
     for (int64_t e = tid; e < (int64_t)no * tc; e += kDBlock) {
         const int c = (int)(e / no), j = (int)(e % no);
-        double acc = 0.0;
-        for (int i = j; i < no; ++i) acc += P[j + (int64_t)i * f] * T[i * tc + c];
-        z[(D.b + j) * t + c0 + c] = acc;
+        z[(D.b + j) * t + c0 + c] = strided_dot(P + j, f, T + c, tc, j, no);
     }
 }
 
