@@ -50,6 +50,7 @@ namespace {
 
 constexpr int kB = 256;          // threads per block
 constexpr int kGridMax = 1024;   // blocks, i.e. partials per dot
+constexpr int kRowLoads = 8;     // entries per batch of a row product (even)
 enum { SL_B = 0, SL_C = 1, SL_D = 2, SL_E = 3, SL_X = 4, kSlots = 5 };
 
 struct BcgState {
@@ -80,28 +81,40 @@ struct BcgArgs {
     BcgState *st;
 };
 
+// Entries alternate between two sums (even and odd positions of the row,
+// each in order).  A batch loads kRowLoads indices and values at once, then
+// their gathers: entries past the row's end take its last index and a zero
+// value, so every load is in bounds and none waits on a branch.
 __device__ __forceinline__ double row_dot(const BcgArgs &a, int64_t row, const double *__restrict__ x)
 {
     double acc0 = 0.0, acc1 = 0.0;
+    int64_t base, stride;
+    int len;
     if (a.format == FEM_FORMAT_SELL) {
-        const int64_t C = (int64_t)1 << a.sell_shift;
-        const int64_t base = a.slice_ptr[row >> a.sell_shift] + (row & (C - 1));
-        const int len = a.rowlen[row];
-        int e = 0;
-        for (; e + 1 < len; e += 2) {
-            const int64_t i0 = base + e * C, i1 = i0 + C;
-            acc0 += a.val[i0] * x[a.col[i0]];
-            acc1 += a.val[i1] * x[a.col[i1]];
-        }
-        if (e < len) acc0 += a.val[base + e * C] * x[a.col[base + e * C]];
+        stride = (int64_t)1 << a.sell_shift;
+        base = a.slice_ptr[row >> a.sell_shift] + (row & (stride - 1));
+        len = a.rowlen[row];
     } else {
-        const int32_t e0 = a.rowptr[row], e1 = a.rowptr[row + 1];
-        int32_t e = e0;
-        for (; e + 1 < e1; e += 2) {
-            acc0 += a.val[e] * x[a.col[e]];
-            acc1 += a.val[e + 1] * x[a.col[e + 1]];
+        stride = 1;
+        base = a.rowptr[row];
+        len = a.rowptr[row + 1] - (int32_t)base;
+    }
+    for (int e = 0; e < len; e += kRowLoads) {
+        int32_t c[kRowLoads];
+        double v[kRowLoads], xv[kRowLoads];
+#pragma unroll
+        for (int u = 0; u < kRowLoads; ++u) {
+            const int64_t i = base + (int64_t)min(e + u, len - 1) * stride;
+            c[u] = a.col[i];
+            v[u] = a.val[i] * (e + u < len ? 1.0 : 0.0);  // a factor, not a select (no branch round the load)
         }
-        if (e < e1) acc0 += a.val[e] * x[a.col[e]];
+#pragma unroll
+        for (int u = 0; u < kRowLoads; ++u) xv[u] = x[c[u]];
+#pragma unroll
+        for (int u = 0; u < kRowLoads; u += 2) {
+            acc0 += v[u] * xv[u];
+            acc1 += v[u + 1] * xv[u + 1];
+        }
     }
     return acc0 + acc1;
 }
