@@ -29,13 +29,16 @@
 // Fronts up to kMidFront are factorised by one workgroup each (left-looking
 // blocks of kFB columns, then the update block as one tiled product), their
 // own blocks inverted in place, and solved by one workgroup per column
-// chunk as matrix products.  Larger fronts are factorised with
-// rocSOLVER's POTRF (own blocks above kMidFront; smaller ones by the
-// workgroup kernel) and rocBLAS's TRSM / SYRK (dense FP64, matrix cores);
-// TRTRI then replaces their L11 by L11^-1, so that their solves are matrix
-// products spread over many workgroups instead of sequential substitutions.
-// Every sum has a fixed order, so the factor and the solution do not depend
-// on the launch configuration or on the number of right-hand sides.
+// chunk as matrix products.  Larger fronts whose own block has at most
+// kMidFront columns go through level-wide kernels too: the own block by one
+// workgroup, its inverse, then L21 = F21 L11^-T and U as tiled products.
+// Only the fronts with larger own blocks call the libraries: rocSOLVER's
+// POTRF and rocBLAS's TRSM / SYRK (dense FP64), then TRTRI for L11^-1.
+// Every front thus keeps L11^-1 (and its transpose), so that the solves of
+// the larger fronts are products spread over many workgroups instead of
+// sequential substitutions.  Every sum has a fixed order, so the factor and
+// the solution do not depend on the launch configuration or on the number
+// of right-hand sides.
 #include "engine.h"
 
 #include <rocblas/rocblas.h>
