@@ -1248,47 +1248,58 @@ int chol_setup(const HostSystem &hs, fem_chol &C)
     });
     if (bad_upd >= 0)
         return fail(FEMCG_EINVAL, "chol: update position %lld outside the parent front", (long long)bad_upd.load());
-    // assembly map: A entries (q >= p) of every own column p; nodes in
-    // parallel, then concatenated level by level in node order
+    // assembly map: A entries (q >= p) of every own column p, level by
+    // level in node order.  Nodes in parallel: a count, the offsets of the
+    // nodes in their level's arrays, then each node writes its own range.
+    std::vector<int32_t> lev_of(nn);
+    for (int d = 0; d < nlev; ++d)
+        for (int32_t k : C.levels[d]) lev_of[k] = d;
+    auto kept = [&](int64_t p, int64_t i, int64_t t, double thr) {
+        const int64_t j = hs.a_col[t];
+        return !(ipos[j] < p || (j != i && !(std::fabs(hs.a_val[t]) > thr)));
+    };
+    std::vector<int64_t> acount(nn, 0), aoff(nn, 0);
+    par_items((int64_t)nn, [&](int64_t k) {
+        const ChNode &nd = C.nodes[k];
+        int64_t c = 0;
+        for (int64_t p = nd.b; p < nd.e; ++p) {
+            const int64_t i = C.perm[p];
+            const double thr = prune_threshold(hs, i);
+            for (int64_t t = hs.a_rowptr[i]; t < hs.a_rowptr[i + 1]; ++t) c += kept(p, i, t, thr);
+        }
+        acount[k] = c;
+    });
     std::vector<std::vector<int64_t>> adst(nlev);
     std::vector<std::vector<double>> aval(nlev);
-    std::vector<std::vector<int64_t>> ndst(nn);
-    std::vector<std::vector<double>> nval(nn);
+    for (int d = 0; d < nlev; ++d) {
+        int64_t tot = 0;
+        for (int32_t k : C.levels[d]) {
+            aoff[k] = tot;
+            tot += acount[k];
+        }
+        adst[d].resize(tot);
+        aval[d].resize(tot);
+    }
     std::atomic<int64_t> bad_p{-1};
     par_items((int64_t)nn, [&](int64_t k) {
         const ChNode &nd = C.nodes[k];
         const DNode &D = C.hnodes[k];
         const int64_t f = nd.f();
+        int64_t *dst = adst[lev_of[k]].data() + aoff[k];
+        double *val = aval[lev_of[k]].data() + aoff[k];
         for (int64_t p = nd.b; p < nd.e; ++p) {
             const int64_t i = C.perm[p];
             const double thr = prune_threshold(hs, i);
             for (int64_t t = hs.a_rowptr[i]; t < hs.a_rowptr[i + 1]; ++t) {
-                const int64_t j = hs.a_col[t];
-                const int64_t q = ipos[j];
-                if (q < p || (j != i && !(std::fabs(hs.a_val[t]) > thr))) continue;
-                const int64_t r = front_index(nd, q);
-                if (r < 0) {
-                    bad_p = p;
-                    continue;
-                }
-                ndst[k].push_back(D.panel + r + (p - nd.b) * f);
-                nval[k].push_back(hs.a_val[t]);
+                if (!kept(p, i, t, thr)) continue;
+                const int64_t r = front_index(nd, ipos[hs.a_col[t]]);
+                if (r < 0) bad_p = p;  // the call fails below
+                *dst++ = D.panel + r + (p - nd.b) * f;
+                *val++ = hs.a_val[t];
             }
         }
     });
     if (bad_p >= 0) return fail(FEMCG_EINVAL, "chol: a matrix entry of row %lld lies outside its front", (long long)bad_p.load());
-    for (int d = 0; d < nlev; ++d) {
-        size_t tot = 0;
-        for (int32_t k : C.levels[d]) tot += ndst[k].size();
-        adst[d].reserve(tot);
-        aval[d].reserve(tot);
-        for (int32_t k : C.levels[d]) {
-            adst[d].insert(adst[d].end(), ndst[k].begin(), ndst[k].end());
-            aval[d].insert(aval[d].end(), nval[k].begin(), nval[k].end());
-            std::vector<int64_t>().swap(ndst[k]);
-            std::vector<double>().swap(nval[k]);
-        }
-    }
     // device lists: per level node ids (all, mid, big), extend-add pairs, assembly
     size_t bytes = 0;
     auto reserve = [&](size_t b) {
@@ -1303,6 +1314,8 @@ int chol_setup(const HostSystem &hs, fem_chol &C)
     std::vector<std::vector<int32_t>> mid(nlev), big(nlev), bigtri(nlev), ea0(nlev), ea1(nlev);
     std::vector<std::array<std::vector<int32_t>, 5>> prod(nlev);
     std::vector<int32_t> mir;  // mirror tiles of every larger front
+    std::vector<int64_t> eoff[2] = {std::vector<int64_t>(nn, 0), std::vector<int64_t>(nn, 0)};  // first pair of a node
+    std::vector<int64_t> esz[2] = {std::vector<int64_t>(nlev, 0), std::vector<int64_t>(nlev, 0)};  // pairs per level
     for (int d = 0; d < nlev; ++d) {
         for (int32_t k : C.levels[d]) {
             const ChNode &nd = C.nodes[k];
@@ -1338,27 +1351,41 @@ int chol_setup(const HostSystem &hs, fem_chol &C)
                 for (int32_t j = 0; j < (int32_t)nd.no(); j += kBigCols) pr[3].insert(pr[3].end(), {k, j});
                 for (int32_t r = 0; r < (int32_t)nd.f(); r += kGatherRows) pr[4].insert(pr[4].end(), {k, r});
             }
-            for (int s = 0; s < 2; ++s) {
+            for (int s = 0; s < 2; ++s) {  // extend-add pairs: counted here, written below
                 const int c = C.nodes[k].child[s];
                 if (c < 0) continue;
-                auto &v = s == 0 ? ea0[d] : ea1[d];
-                for (int64_t b = 0; b < C.nodes[c].nu(); ++b) {
-                    v.push_back(k);
-                    v.push_back((int32_t)b);
-                }
+                eoff[s][k] = esz[s][d];
+                esz[s][d] += C.nodes[c].nu();
             }
         }
         off[d].all = reserve(C.levels[d].size() * 4);
         off[d].mid = reserve(mid[d].size() * 4);
         off[d].big = reserve(big[d].size() * 4);
         off[d].bigtri = reserve(bigtri[d].size() * 4);
-        off[d].ea[0] = reserve(ea0[d].size() * 4);
-        off[d].ea[1] = reserve(ea1[d].size() * 4);
+        off[d].ea[0] = reserve(esz[0][d] * 8);
+        off[d].ea[1] = reserve(esz[1][d] * 8);
         off[d].dst = reserve(adst[d].size() * 8);
         off[d].val = reserve(aval[d].size() * 8);
         for (int q = 0; q < 5; ++q) off[d].prod[q] = reserve(prod[d][q].size() * 4);
     }
     const size_t off_mir = reserve(mir.size() * 4);
+    // the extend-add pairs (node, child column b), nodes in parallel, in the
+    // order of the level's nodes
+    for (int d = 0; d < nlev; ++d) {
+        ea0[d].resize(2 * esz[0][d]);
+        ea1[d].resize(2 * esz[1][d]);
+    }
+    par_items((int64_t)nn, [&](int64_t k) {
+        for (int s = 0; s < 2; ++s) {
+            const int c = C.nodes[k].child[s];
+            if (c < 0) continue;
+            int32_t *v = (s == 0 ? ea0 : ea1)[lev_of[k]].data() + 2 * eoff[s][k];
+            for (int64_t b = 0; b < C.nodes[c].nu(); ++b) {
+                v[2 * b] = (int32_t)k;
+                v[2 * b + 1] = (int32_t)b;
+            }
+        }
+    });
     DCHK(hipMalloc((void **)&C.d_lists, std::max<size_t>(bytes, 256)));
     DCHK(hipMalloc((void **)&C.d_nodes, sizeof(DNode) * std::max<size_t>(nn, 1)));
     DCHK(hipMalloc((void **)&C.d_perm, sizeof(int32_t) * std::max<int64_t>(n, 1)));
