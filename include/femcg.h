@@ -218,7 +218,8 @@ typedef struct {
     double factor_mb;      /* device memory of the factor panels */
     double work_mb;        /* peak device memory of two consecutive levels of fronts */
     double order_s;        /* host: nested-dissection ordering */
-    double symbolic_s;     /* host: update sets, tree levels */
+    double symbolic_s;     /* host: update sets, tree levels (after chol_factor also the
+                              factor's host set-up and its uploads) */
     double factor_s;       /* numeric factorisation on the device (0 until chol_factor) */
     double total_s;        /* chol_factor wall time: ordering, symbolic, set-up, numeric */
     double solve_s;        /* last chol_solve, call to result */
